@@ -1,0 +1,154 @@
+"""Point sets in conventional order, written from their definitions.
+
+Test infrastructure (see the package docstring): never imported by the
+product path.
+
+* Rank-1 lattice rule with prime N and generator g in (Z_N^*)^s
+  (Section 2.1): x_{n,j} = { n g_j / N } for n = 0..N-1.  With an equal shift
+  Delta = num/den in every coordinate (Remark 2) the coordinate is
+  { n g_j / N + Delta }.  Computed from exact integers:
+  x = ((n g_j mod N) den + num N) mod (N den) / (N den), one rounding.
+* Polynomial lattice rule over GF(2) with N = 2^m (Remark 1; the paper gives
+  no formulas, so the standard construction of Niederreiter is used): the
+  index n is the polynomial n(x) = sum_i n_i x^i (bit i of n is the
+  coefficient of x^i), r(x) = n(x) q_j(x) mod p(x), and the coordinate is
+  nu_m(r/p) = sum_{l=1}^m u_l 2^-l where r(x)/p(x) = sum_{l>=1} u_l x^-l.
+  Equivalently u_1..u_m are the bits (most significant first) of the
+  quotient floor(r(x) x^m / p(x)).  An equal shift is applied as for lattices.
+* phi (Section 2.1): identity, the tent transform 1 - |2x - 1|, the inverse
+  normal CDF; and x - 1/2 (Experiment 2).
+"""
+from __future__ import annotations
+
+import numpy as np
+from scipy.special import ndtri
+
+PHI_IDENTITY = 0
+PHI_CENTERED = 1
+PHI_INVNORM = 2
+PHI_TENT = 3
+
+RULE_LATTICE = 0
+RULE_POLY_GF2 = 1
+
+
+def phi_apply(kind: int, x: np.ndarray) -> np.ndarray:
+    """The univariate map phi applied to coordinates x in [0, 1)."""
+    x = np.asarray(x, dtype=np.float64)
+    if kind == PHI_IDENTITY:
+        return x.copy()
+    if kind == PHI_CENTERED:
+        return x - 0.5
+    if kind == PHI_INVNORM:
+        return ndtri(x)
+    if kind == PHI_TENT:
+        return 1.0 - np.abs(2.0 * x - 1.0)
+    raise ValueError(f"unknown phi kind {kind}")
+
+
+def _shifted_fraction(numer: np.ndarray, N: int, shift) -> np.ndarray:
+    """{ numer/N + num/den } for integer numer in [0, N), exactly rounded."""
+    num, den = int(shift[0]), int(shift[1])
+    big = N * den
+    k = (numer.astype(object) * den + num * N) % big if big >= (1 << 62) else \
+        (numer.astype(np.int64) * den + num * N) % big
+    return np.asarray(k, dtype=np.float64) / float(big)
+
+
+def lattice_coords(N: int, gen, shift=(0, 1), rows=None) -> np.ndarray:
+    """Coordinates {n g_j / N + Delta} for the given rows n (default 0..N-1)."""
+    g = np.asarray(gen, dtype=np.int64)
+    n = np.arange(N, dtype=np.int64) if rows is None else np.asarray(rows, dtype=np.int64)
+    resid = (n[:, None] * g[None, :]) % N
+    return _shifted_fraction(resid, N, shift)
+
+
+# ---- GF(2) polynomial arithmetic, vectorised over numpy uint64 arrays ------
+
+def _clmul(a: np.ndarray, b: np.ndarray, nbits: int) -> np.ndarray:
+    """Carry-less (GF(2)[x]) product of a and b, where b has < nbits bits."""
+    a = a.astype(np.uint64)
+    b = b.astype(np.uint64)
+    r = np.zeros(np.broadcast(a, b).shape, dtype=np.uint64)
+    for i in range(nbits):
+        bit = (b >> np.uint64(i)) & np.uint64(1)
+        r ^= np.where(bit == 1, a << np.uint64(i), np.uint64(0))
+    return r
+
+
+def _poly_divmod(a: np.ndarray, p: int, abits: int):
+    """Quotient and remainder of a(x) by p(x) over GF(2); a has < abits bits."""
+    m = int(p).bit_length() - 1
+    a = a.astype(np.uint64).copy()
+    q = np.zeros_like(a)
+    pp = np.uint64(p)
+    for k in range(abits - 1 - m, -1, -1):
+        top = (a >> np.uint64(m + k)) & np.uint64(1)
+        a ^= np.where(top == 1, pp << np.uint64(k), np.uint64(0))
+        q |= np.where(top == 1, np.uint64(1) << np.uint64(k), np.uint64(0))
+    return q, a
+
+
+def gf2_residues(m: int, p: int, gen, rows=None) -> np.ndarray:
+    """r = n(x) q_j(x) mod p(x) for the given rows n (default 0..2^m-1)."""
+    N = 1 << m
+    q = np.asarray(gen, dtype=np.uint64)
+    n = np.arange(N, dtype=np.uint64) if rows is None else np.asarray(rows, dtype=np.uint64)
+    prod = _clmul(n[:, None], q[None, :], m)
+    _, r = _poly_divmod(prod, p, 2 * m)
+    return r
+
+
+def gf2_value_of_residue(m: int, p: int, r: np.ndarray) -> np.ndarray:
+    """Integer Q with Q/2^m = nu_m(r/p): the quotient floor(r(x) x^m / p(x))."""
+    q, _ = _poly_divmod(np.asarray(r, dtype=np.uint64) << np.uint64(m), p, 2 * m)
+    return q
+
+
+def gf2_coords(m: int, p: int, gen, shift=(0, 1), rows=None) -> np.ndarray:
+    """Coordinates nu_m(n(x) q_j(x) / p(x)) (+ Delta, mod 1)."""
+    r = gf2_residues(m, p, gen, rows)
+    Q = gf2_value_of_residue(m, p, r).astype(np.int64)
+    return _shifted_fraction(Q, 1 << m, shift)
+
+
+def gf2_digits_coords(m: int, p: int, gen, rows=None) -> np.ndarray:
+    """Second route to the GF(2) coordinates (no shift): the digits u_l of the
+    Laurent expansion r/p are read off one at a time by long division of the
+    remainder (u_l = 1 when x * remainder reaches degree m)."""
+    r = gf2_residues(m, p, gen, rows)
+    rem = r.copy()
+    val = np.zeros(r.shape, dtype=np.float64)
+    scale = 0.5
+    pp = np.uint64(p)
+    for _ in range(m):
+        rem = rem << np.uint64(1)
+        u = (rem >> np.uint64(m)) & np.uint64(1)
+        rem ^= np.where(u == 1, pp, np.uint64(0))
+        val += u.astype(np.float64) * scale
+        scale *= 0.5
+    return val
+
+
+def coords(rule: int, N: int, gen, modulus: int = 0, shift=(0, 1), rows=None) -> np.ndarray:
+    if rule == RULE_LATTICE:
+        return lattice_coords(N, gen, shift, rows)
+    if rule == RULE_POLY_GF2:
+        m = int(N).bit_length() - 1
+        assert 1 << m == N, "polynomial lattice rules need N = 2^m"
+        return gf2_coords(m, modulus, gen, shift, rows)
+    raise ValueError(f"unknown rule {rule}")
+
+
+def explicit_Y(rule: int, N: int, gen, phi: int, modulus: int = 0, shift=(0, 1),
+               rows=None) -> np.ndarray:
+    """Y[n, j] = phi(x_{n,j}) in conventional row order, FP64."""
+    return phi_apply(phi, coords(rule, N, gen, modulus, shift, rows))
+
+
+def phi_residue_values(rule: int, N: int, phi: int, modulus: int = 0,
+                       shift=(0, 1)) -> np.ndarray:
+    """The value of phi for every one-dimensional point: entry r is phi of the
+    coordinate of residue r (lattice: {r/N + Delta}; GF(2): nu_m(r/p) + Delta).
+    Obtained as the column of Y for the generator component 1."""
+    return explicit_Y(rule, N, np.array([1], dtype=np.uint64), phi, modulus, shift)[:, 0]

@@ -1,0 +1,316 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+No GPU.  Each check is chosen so that a plausible slip in the oracle (a
+dropped shift, a wrong index, a transposed operand, a wrong digit order)
+fails at least one of them; ``test_planted_mistakes_are_caught`` plants such
+slips in copies of the oracle and checks that the pins notice.
+"""
+import dataclasses
+import json
+import math
+import os
+import statistics
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import literal, exact
+import qmc_inputs as qi
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _inst(rule, N, gen, phi, A=None, modulus=0, shift=(0, 1), t=2, seed=0):
+    gen = np.asarray(gen, dtype=np.uint64)
+    if A is None:
+        A = np.random.default_rng(seed).standard_normal((len(gen), t))
+    return qi.Instance("pin", rule, N, len(gen), A.shape[1], gen, modulus, phi,
+                       shift, "f64", np.asarray(A, dtype=np.float64))
+
+
+# ---------------------------------------------------------------------------
+# Example 1 (Section 2.1): printed values
+# ---------------------------------------------------------------------------
+
+def _example():
+    with open(os.path.join(GOLDEN, "example_n7.json")) as f:
+        return json.load(f)
+
+
+def test_example1_conventional_points():
+    ex = _example()
+    x = oracle.lattice_coords(ex["N"], ex["gen"])
+    assert np.array_equal(np.rint(x * ex["N"]).astype(int), np.array(ex["conventional_numerators_over_N"]))
+    # the coordinates are exactly k/7 rounded once
+    assert np.array_equal(x, np.array(ex["conventional_numerators_over_N"]) / 7.0)
+
+
+def test_example1_paper_construction():
+    ex = _example()
+    inst = _inst(qi.RULE_LATTICE, ex["N"], ex["gen"], qi.PHI_IDENTITY)
+    con = literal.Construction(inst)
+    assert con.beta == ex["beta"]
+    assert con.c == ex["c"]
+    assert con.pow[(con.L - 1) % con.L] == ex["beta_inverse"]
+    assert np.array_equal(np.rint(con.Z * 7).astype(int), np.array(ex["Z_numerators_over_N"]))
+    assert np.array_equal(con.P.astype(int), np.array(ex["P"]))
+    # Y' = Z P reproduces the paper's reordered points x_1..x_6
+    yp = np.rint(con.Yprime() * 7).astype(int)
+    assert np.array_equal(yp, np.array(ex["paper_order_numerators_over_N"])[1:])
+    # and the row map sends paper row n to the conventional point beta^-(n-1)
+    conv = np.array(ex["conventional_numerators_over_N"])
+    for n in range(1, 7):
+        assert list(conv[con.conv_index[n]]) == ex["paper_order_numerators_over_N"][n]
+
+
+def test_example1_product_matches_dense():
+    ex = _example()
+    A = np.random.default_rng(3).standard_normal((3, 4))
+    for phi in (qi.PHI_IDENTITY, qi.PHI_CENTERED, qi.PHI_TENT):
+        inst = _inst(qi.RULE_LATTICE, 7, ex["gen"], phi, A)
+        np.testing.assert_allclose(literal.Construction(inst).product(), oracle.matmul(inst),
+                                   rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# brute force over exact rationals (tiny N)
+# ---------------------------------------------------------------------------
+
+SMALL_PRIMES = [2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31]
+
+
+@pytest.mark.parametrize("N", SMALL_PRIMES)
+@pytest.mark.parametrize("phi", [qi.PHI_IDENTITY, qi.PHI_CENTERED])
+def test_lattice_exact_bruteforce(N, phi):
+    rg = np.random.default_rng(N * 10 + phi)
+    for s in (1, 2, 3, 6):
+        gen = rg.integers(1, N, size=s) if N > 2 else np.ones(s, dtype=np.int64)
+        A = rg.standard_normal((s, 3))
+        inst = _inst(qi.RULE_LATTICE, N, gen, phi, A)
+        ex = exact.product(inst)
+        X = oracle.matmul(inst)
+        for n in range(N):
+            for c in range(3):
+                assert abs(X[n, c] - float(ex[n][c])) <= 4e-16 * (1 + sum(abs(A[:, c])))
+
+
+def test_lattice_identity_integer_A_is_exact():
+    """phi = identity and integer A: N X is an integer combination of A."""
+    N, s = 31, 6
+    rg = np.random.default_rng(5)
+    gen = rg.integers(1, N, size=s)
+    A = rg.integers(-50, 50, size=(s, 4)).astype(np.float64)
+    inst = _inst(qi.RULE_LATTICE, N, gen, qi.PHI_IDENTITY, A)
+    X = oracle.matmul(inst)
+    NX = np.rint(X * N)
+    assert np.max(np.abs(X * N - NX)) < 1e-9
+    # exact integer reference: sum_j ((n g_j) mod N) A_jc
+    n = np.arange(N)[:, None]
+    ref = ((n * gen[None, :]) % N) @ A.astype(np.int64)
+    assert np.array_equal(NX.astype(np.int64), ref)
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 4, 5])
+def test_gf2_exact_bruteforce(m):
+    rg = np.random.default_rng(100 + m)
+    p = qi.draw_primitive_poly(m, rg)
+    N = 1 << m
+    for s in (1, 3):
+        q = rg.integers(1, N, size=s)
+        A = rg.standard_normal((s, 2))
+        inst = _inst(qi.RULE_POLY_GF2, N, q, qi.PHI_CENTERED, A, modulus=p)
+        ex = exact.product(inst)
+        X = oracle.matmul(inst)
+        for n in range(N):
+            for c in range(2):
+                assert abs(X[n, c] - float(ex[n][c])) <= 4e-16 * (1 + sum(abs(A[:, c])))
+
+
+def test_gf2_known_small_field():
+    """GF(4) = GF(2)[x]/(x^2+x+1), q = x: n(x) x mod p and its digit value.
+
+    n = 1 -> r = x      -> x/(x^2+x+1) = x^-1 + x^-2 + ...   -> 0.11b = 3/4
+    n = 2 -> r = x^2 = x+1 -> (x+1)/(x^2+x+1) = x^-1 + 0 x^-2 ... -> 0.10b = 1/2
+    n = 3 -> r = x^2+x = 1 -> 1/(x^2+x+1) = 0 x^-1 + x^-2 ...  -> 0.01b = 1/4
+    """
+    x = oracle.gf2_coords(2, 0b111, [0b10])
+    assert list(x[:, 0]) == [0.0, 0.75, 0.5, 0.25]
+    assert list(oracle.gf2_digits_coords(2, 0b111, [0b10])[:, 0]) == [0.0, 0.75, 0.5, 0.25]
+
+
+@pytest.mark.parametrize("m", [6, 8, 10])
+def test_gf2_columns_are_permutations(m):
+    """For q_j != 0, n -> n q_j mod p is a bijection and so is the digit map:
+    every column of the (unshifted, identity) point matrix is {k / 2^m}."""
+    rg = np.random.default_rng(m)
+    p = qi.draw_primitive_poly(m, rg)
+    q = rg.integers(1, 1 << m, size=5)
+    x = oracle.gf2_coords(m, p, q)
+    for j in range(5):
+        assert np.array_equal(np.sort(np.rint(x[:, j] * (1 << m)).astype(int)), np.arange(1 << m))
+    np.testing.assert_array_equal(x, oracle.gf2_digits_coords(m, p, q))
+
+
+# ---------------------------------------------------------------------------
+# closed forms: column sums
+# ---------------------------------------------------------------------------
+
+def test_column_sum_identity_lattice():
+    """sum_n {n g / N} = (N-1)/2 for g coprime to N, so 1^T X = (N-1)/2 1^T A."""
+    inst = qi.small_lattice(1009, 37, 3)
+    X = oracle.matmul(inst)
+    np.testing.assert_allclose(X.sum(axis=0), (1009 - 1) / 2 * inst.A.sum(axis=0), rtol=1e-12)
+
+
+def test_column_sum_invnorm_shifted_is_zero():
+    """Phi^-1((2r+1)/(2N)) is odd about the middle residue: columns sum to 0."""
+    N = 2003
+    inst = qi.small_lattice(N, 64, 2, phi=qi.PHI_INVNORM, shift=(1, 2 * N))
+    Y = oracle.Y_rows(inst)
+    assert np.max(np.abs(Y.sum(axis=0))) < 1e-10
+    # and every column is a permutation of the one-dimensional value table
+    T = oracle.phi_residue_values(qi.RULE_LATTICE, N, qi.PHI_INVNORM, shift=(1, 2 * N))
+    for j in range(4):
+        np.testing.assert_array_equal(np.sort(Y[:, j]), np.sort(T))
+
+
+def test_column_sum_gf2_centered():
+    """sum over the 2^m points of (k/2^m - 1/2) = -1/2 in every column."""
+    inst = qi.small_gf2(10, 40, 2, phi=qi.PHI_CENTERED)
+    Y = oracle.Y_rows(inst)
+    np.testing.assert_allclose(Y.sum(axis=0), -0.5, atol=1e-12)
+
+
+def test_row_zero_is_phi_of_shift():
+    inst = qi.small_lattice(101, 9, 2, phi=qi.PHI_INVNORM, shift=(1, 202))
+    Y = oracle.Y_rows(inst)
+    assert np.all(Y[0] == Y[0, 0])
+    assert abs(Y[0, 0] - statistics.NormalDist().inv_cdf(1 / 202)) < 1e-14
+
+
+# ---------------------------------------------------------------------------
+# the paper's literal construction against the dense product (medium N)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("N,s,t", [(101, 20, 3), (257, 300, 2), (1009, 64, 2)])
+@pytest.mark.parametrize("phi,shift", [(qi.PHI_IDENTITY, None), (qi.PHI_CENTERED, None),
+                                       (qi.PHI_INVNORM, "half"), (qi.PHI_TENT, None)])
+def test_literal_construction_matches_dense(N, s, t, phi, shift):
+    sh = (1, 2 * N) if shift == "half" else (0, 1)
+    inst = qi.small_lattice(N, s, t, phi=phi, shift=sh)
+    con = literal.Construction(inst)
+    Xl = con.product()
+    Xd = oracle.matmul(inst)
+    scale = np.max(np.abs(oracle.Y_rows(inst))) * np.abs(inst.A).sum(axis=0)
+    assert np.max(np.abs(Xl - Xd) / scale) < 1e-13
+
+
+@pytest.mark.parametrize("m,s", [(6, 10), (8, 300)])
+def test_literal_construction_matches_dense_gf2(m, s):
+    inst = qi.small_gf2(m, s, 2, phi=qi.PHI_CENTERED)
+    con = literal.Construction(inst)
+    assert con.beta == 2  # x generates the group when p is primitive
+    np.testing.assert_allclose(con.product(), oracle.matmul(inst), rtol=0, atol=1e-12)
+
+
+def test_output_independent_of_primitive_root():
+    """Conventional-order output does not depend on which beta is used."""
+    N = 101
+    inst = qi.small_lattice(N, 30, 2, phi=qi.PHI_INVNORM, shift=(1, 2 * N))
+    grp = literal._Lattice(N)
+    roots = [b for b in range(2, N) if len(set(literal.powers(grp, b))) == N - 1][:4]
+    outs = [literal.Construction(inst, beta=b).product() for b in roots]
+    for o in outs[1:]:
+        np.testing.assert_allclose(o, outs[0], rtol=0, atol=1e-12)
+
+
+def test_identity_A_regenerates_points():
+    """A = I_s gives X = Y (the point set itself, Section 2.1 remark)."""
+    inst = qi.small_lattice(211, 15, 15)
+    I = np.eye(15)
+    np.testing.assert_allclose(literal.Construction(inst).product(I), oracle.Y_rows(inst), atol=1e-15)
+
+
+# ---------------------------------------------------------------------------
+# inverse normal CDF and the adjoint
+# ---------------------------------------------------------------------------
+
+def test_invnorm_against_stdlib_and_erfc():
+    nd = statistics.NormalDist()
+    ps = np.concatenate([np.linspace(1e-12, 1 - 1e-12, 2001), [1e-300, 1e-100, 1e-20, 0.5, 0.975, 0.999999]])
+    ys = oracle.phi_apply(qi.PHI_INVNORM, ps)
+    for p, y in zip(ps, ys):
+        ref = nd.inv_cdf(float(p))
+        assert abs(y - ref) <= 8e-16 * max(1.0, abs(ref)), (p, y, ref)
+        if 1e-300 < p < 1:
+            back = 0.5 * math.erfc(-y / math.sqrt(2.0))
+            # one ulp of y moves Phi(y) by about |y| ulp(y) relative: allow that
+            assert abs(back - p) <= 4e-15 * max(1.0, y * y) * p + 1e-300, (p, back)
+
+
+def test_adjoint_is_transpose():
+    inst = qi.small_lattice(257, 40, 3, phi=qi.PHI_INVNORM, shift=(1, 514))
+    G = np.random.default_rng(1).standard_normal((257, 3))
+    dA = oracle.adjoint(inst, G)
+    X = oracle.matmul(inst)
+    # <Y A, G> = <A, Y^T G>
+    assert abs(np.sum(X * G) - np.sum(inst.A * dA)) < 1e-10 * np.sum(np.abs(X * G))
+    # entry-sampled adjoint agrees with the full one
+    ent = [(0, 0), (5, 2), (39, 1), (17, 0)]
+    got = oracle.adjoint_entries(dataclasses.replace(inst, G=G), ent, chunk=50)
+    np.testing.assert_allclose(got, [dA[j, k] for j, k in ent], rtol=1e-12, atol=1e-12)
+
+
+def test_row_sampled_matmul_agrees():
+    inst = qi.small_gf2(9, 50, 3)
+    X = oracle.matmul(inst)
+    rows = np.array([0, 1, 7, 511, 300])
+    np.testing.assert_allclose(oracle.matmul_rows(inst, rows, chunk=2), X[rows], rtol=0, atol=1e-13)
+
+
+def test_cholesky_closed_form():
+    """The C2 matrix A is the upper Cholesky factor of exp(-|i-j|/410)."""
+    s = 300
+    A = qi.cholesky_exp_upper(s)
+    i = np.arange(s)
+    Sigma = np.exp(-np.abs(i[:, None] - i[None, :]) / 410.0)
+    np.testing.assert_allclose(A.T @ A, Sigma, atol=1e-13)
+    np.testing.assert_allclose(A, np.linalg.cholesky(Sigma).T, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# planted mistakes: mutated copies of oracle routines must fail the pins
+# ---------------------------------------------------------------------------
+
+def _pins_pass(coord_fn) -> bool:
+    """Run the coordinate-level pins against a candidate coordinate routine."""
+    ex = _example()
+    x = coord_fn(7, np.array(ex["gen"]), (0, 1))
+    if not np.array_equal(np.rint(x * 7).astype(int), np.array(ex["conventional_numerators_over_N"])):
+        return False
+    N = 101
+    x = coord_fn(N, np.arange(1, 6), (1, 2 * N))
+    ref = [[float((Fraction(n * g % N, N) + Fraction(1, 2 * N)) % 1) for g in range(1, 6)] for n in range(N)]
+    return bool(np.array_equal(x, np.array(ref)))
+
+
+def test_planted_mistakes_are_caught():
+    good = lambda N, g, sh: oracle.lattice_coords(N, g, sh)
+    assert _pins_pass(good)
+    dropped_shift = lambda N, g, sh: oracle.lattice_coords(N, g, (0, 1))
+    off_by_one_row = lambda N, g, sh: oracle.lattice_coords(N, g, sh, rows=np.arange(1, N + 1))
+    swapped = lambda N, g, sh: oracle.lattice_coords(N, (np.asarray(g) * 2) % N, sh)
+    for bad in (dropped_shift, off_by_one_row, swapped):
+        assert not _pins_pass(bad)
+
+
+def test_planted_gf2_digit_order_is_caught():
+    """Reading the quotient bits least-significant-first breaks the GF(4) pin."""
+    def reversed_digits(m, p, q):
+        x = oracle.gf2_coords(m, p, q)
+        k = np.rint(x * (1 << m)).astype(int)
+        rev = np.array([[int(format(v, f"0{m}b")[::-1], 2) for v in row] for row in k])
+        return rev / float(1 << m)
+    assert list(reversed_digits(2, 0b111, [0b10])[:, 0]) != [0.0, 0.75, 0.5, 0.25]
