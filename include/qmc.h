@@ -1,0 +1,195 @@
+/*
+ * qmc.h -- C interface of the MI355X (gfx950) fast QMC matrix-product library.
+ *
+ * Computes X = Y A and dA = Y^T G, where the N rows of Y are QMC points
+ * mapped by one univariate function phi in every coordinate, without ever
+ * forming Y: after re-indexing the rows by the discrete logarithm with respect
+ * to a primitive element, the nonzero rows of Y are a circulant of length
+ * L = N - 1 applied to a selection of A's rows, so every column costs one
+ * FFT-based circular convolution (Dick, Kuo, Le Gia, Schwab, "Fast QMC
+ * matrix-vector multiplication", Section 2.1, eq. (ZPa), and Remark 1 for
+ * polynomial lattice rules).
+ *
+ * Conventions shared by every entry point
+ *   - Matrices are row-major.  A is s x t with row stride lda (elements),
+ *     X is N x t with row stride ldx; G is N x t (ldg), dA is s x t (ldda).
+ *   - Row n of X is the point with conventional index n: for a lattice rule
+ *     x_n = ({n g_1/N + D}, ..., {n g_s/N + D}) (Section 2.1, with the equal
+ *     shift D of Remark 2); for a polynomial lattice rule over GF(2) the row
+ *     index n is the polynomial whose coefficient of x^i is bit i of n.
+ *   - Device pointers (A, X, G, dA, workspace) belong to the caller and must
+ *     stay valid until the stream has executed the call.  Host pointers are
+ *     read before the call returns.
+ *   - All work is enqueued on the HIP stream passed as `stream`
+ *     (hipStream_t; NULL = the null stream) and is asynchronous.
+ *   - The element type is fixed per plan: QMC_F32 (float) or QMC_F64
+ *     (double) for A, X, G and dA and for all arithmetic on them.
+ *   - Return value 0 on success, a negative QMC_ERR_* code otherwise.
+ *     Arguments are checked before anything is launched; on error nothing is
+ *     enqueued and outputs are untouched.  A fault inside a launched kernel
+ *     surfaces as QMC_ERR_HIP from a later call or from the caller's own
+ *     stream synchronisation.  No C++ exception crosses this interface.
+ *   - A plan may be used from one host thread at a time.  Calls on one plan
+ *     that share a workspace must be ordered on one stream.
+ */
+#ifndef QMC_H_
+#define QMC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct qmc_plan_s* qmc_plan_t;
+
+/* point-set families */
+#define QMC_RULE_LATTICE  0   /* rank-1 lattice rule, prime N (Section 2.1) */
+#define QMC_RULE_POLY_GF2 1   /* polynomial lattice rule over GF(2), N = 2^m, primitive modulus (Remark 1) */
+
+/* the univariate map phi applied to every coordinate (Section 2.1) */
+#define QMC_PHI_IDENTITY  0   /* phi(x) = x */
+#define QMC_PHI_CENTERED  1   /* phi(x) = x - 1/2 (Experiment 2) */
+#define QMC_PHI_INVNORM   2   /* phi(x) = Phi^{-1}(x), inverse standard normal CDF (Section 3.1) */
+#define QMC_PHI_TENT      3   /* phi(x) = 1 - |2x - 1| (Section 2.1) */
+
+/* element types */
+#define QMC_F32 0
+#define QMC_F64 1
+
+/* error codes */
+#define QMC_OK                 0
+#define QMC_ERR_ARG           -1   /* a size, stride, pointer or enum is invalid */
+#define QMC_ERR_NOT_PRIME     -2   /* lattice rule with N not prime */
+#define QMC_ERR_NOT_PRIMITIVE -3   /* GF(2) modulus not primitive of degree m with 2^m = N */
+#define QMC_ERR_GEN_ZERO      -4   /* a generator component is 0 mod N (not in the group) */
+#define QMC_ERR_ALIAS         -5   /* output overlaps an input */
+#define QMC_ERR_WORKSPACE     -6   /* workspace missing or smaller than qmc_workspace_size */
+#define QMC_ERR_OOM           -7   /* device allocation failed while building a plan */
+#define QMC_ERR_HIP           -8   /* a HIP runtime call failed */
+#define QMC_ERR_UNSUPPORTED   -9   /* valid request outside what this build handles */
+
+/*
+ * qmc_plan_create -- build everything that depends only on the point set.
+ *
+ * Section 2.1: a primitive element beta of the cyclic group (Z_N^* for prime
+ * N, the nonzero residues mod p(x) for a primitive GF(2) modulus -- where the
+ * element x is used), the exponents l_j with g_j = beta^{l_j} (the paper's
+ * c_j - 1), the generator z_k = phi(point of beta^k) of the circulant Z, and
+ * the FFT of z computed in FP64 (rounded once to FP32 for an FP32 plan).
+ * The power and logarithm tables are built on the device, bit-exact.
+ *
+ *   out        receives the plan handle (host pointer)
+ *   rule       QMC_RULE_LATTICE or QMC_RULE_POLY_GF2
+ *   N          number of points: prime, 2 <= N < 2^31 (lattice); 2^m with
+ *              1 <= m <= 30 (GF(2))
+ *   s          dimension, s >= 1
+ *   gen        host array of s generator components: g_j in [1, N-1]
+ *              (lattice, taken mod N; 0 mod N is QMC_ERR_GEN_ZERO) or GF(2)
+ *              polynomial bitmasks q_j in [1, 2^m - 1]
+ *   modulus    GF(2): the primitive polynomial p with bit m set; lattice: 0
+ *   phi_kind   QMC_PHI_*
+ *   shift_num, shift_den
+ *              the equal shift D = shift_num/shift_den in [0,1) added to
+ *              every coordinate before phi (Remark 2); 0/1 for none.
+ *              QMC_PHI_INVNORM requires a shift that keeps every coordinate
+ *              inside (0,1) (e.g. 1/(2N)), otherwise QMC_ERR_ARG.
+ *   dtype      QMC_F32 or QMC_F64
+ *   stream     HIP stream for the plan-building kernels; the call
+ *              synchronises that stream before returning.
+ * The plan owns its device memory; release it with qmc_plan_destroy.
+ */
+int qmc_plan_create(qmc_plan_t* out, int rule, int64_t N, int64_t s,
+                    const uint64_t* gen, uint64_t modulus, int phi_kind,
+                    int64_t shift_num, int64_t shift_den, int dtype, void* stream);
+
+void qmc_plan_destroy(qmc_plan_t plan);
+
+/* Plan facts for callers and tests (host pointer to a filled struct). */
+typedef struct {
+    int64_t N, s, L;        /* points, dimension, group order L = N - 1 */
+    int64_t M;              /* circular-convolution length used: L, or a power of two >= 2L-1 */
+    int64_t M1, M2;         /* M = M1 * M2 (on-chip transform length, outer length) */
+    int64_t rounds;         /* rounds of the sparse collapse schedule */
+    uint64_t beta;          /* primitive element (lattice: smallest primitive root; GF(2): x = 2) */
+    int rule, phi_kind, dtype, embedded;
+    double phi0;            /* phi of the point of row 0 (the constant first row, Section 2.1) */
+} qmc_plan_info_t;
+int qmc_plan_info(qmc_plan_t plan, qmc_plan_info_t* info);
+
+/*
+ * qmc_plan_tables -- copy the plan's bit-exact tables to host memory (for
+ * verification).  Any pointer may be NULL.
+ *   pow_out[e], e < L : conventional row index of group element beta^e
+ *   log_out[r], r < N : e with pow[e] = r (log_out[0] = -1)
+ *   ell_out[j], j < s : l_j with g_j = beta^{l_j}
+ *   phi_out[r], r < N : phi of the one-dimensional point of residue r (FP64)
+ */
+int qmc_plan_tables(qmc_plan_t plan, int32_t* pow_out, int32_t* log_out,
+                    int32_t* ell_out, double* phi_out);
+
+/* Bytes of device workspace that qmc_matmul / qmc_matmul_adjoint need for t columns. */
+int qmc_workspace_size(qmc_plan_t plan, int64_t t, size_t* bytes);
+
+/*
+ * qmc_matmul -- X = Y A (Section 2.1: row 0 is phi(x_0) sum_j a_j, the other
+ * rows are Z (P a) by FFT, one circular convolution per pair of columns).
+ *   A          device, s x t, row stride lda >= t
+ *   t          number of columns, t >= 1
+ *   X          device, N x t, row stride ldx >= t; every entry is written
+ *   workspace  device, at least qmc_workspace_size(plan, t) bytes
+ * Errors: QMC_ERR_ARG (bad sizes/NULL), QMC_ERR_ALIAS (X overlaps A or the
+ * workspace), QMC_ERR_WORKSPACE.
+ */
+int qmc_matmul(qmc_plan_t plan, const void* A, int64_t t, int64_t lda,
+               void* X, int64_t ldx, void* workspace, size_t workspace_bytes,
+               void* stream);
+
+/*
+ * qmc_matmul_adjoint -- dA = Y^T G, the transpose product needed to
+ * differentiate X = Y A with respect to A.  The nonzero rows of Y in group
+ * order form a symmetric (Hankel-circulant) operator, so the same spectrum
+ * serves: G's rows are gathered in reflected group order, convolved, and
+ * read back at the exponents l_j; the constant row adds phi(x_0) G[0,:].
+ *   G   device, N x t (ldg >= t);  dA  device, s x t (ldda >= t), overwritten
+ */
+int qmc_matmul_adjoint(qmc_plan_t plan, const void* G, int64_t t, int64_t ldg,
+                       void* dA, int64_t ldda, void* workspace, size_t workspace_bytes,
+                       void* stream);
+
+/*
+ * qmc_explicit_points -- write the N x s matrix Y itself (row stride ldy) in
+ * conventional order, Y[n,j] = phi(point of n g_j): the input of the dense
+ * baseline.  Y is device memory owned by the caller.
+ */
+int qmc_explicit_points(qmc_plan_t plan, void* Y, int64_t ldy, void* stream);
+
+/*
+ * qmc_dense_matmul -- the standard approach of the paper's experiments: the
+ * plain product X = Y A (M x K by K x t, row-major, plan dtype) on the MFMA
+ * matrix cores, for an explicit Y from qmc_explicit_points.  Sizes are
+ * general (rows = N, K = s).  Used as the baseline the FFT path is compared with.
+ */
+int qmc_dense_matmul(qmc_plan_t plan, const void* Y, int64_t ldy, const void* A,
+                     int64_t t, int64_t lda, void* X, int64_t ldx, void* stream);
+
+/*
+ * qmc_matmul_batched -- X_i = Y_i A_i for `count` plans in one sequence of
+ * launches (one launch per pass over all instances).  Plans must share the
+ * dtype.  A[i], X[i] device pointers with row strides t[i] (dense rows);
+ * workspace at least qmc_batched_workspace_size bytes.
+ */
+int qmc_batched_workspace_size(int count, const qmc_plan_t* plans, const int64_t* t,
+                               size_t* bytes);
+int qmc_matmul_batched(int count, const qmc_plan_t* plans, const void* const* A,
+                       const int64_t* t, void* const* X, void* workspace,
+                       size_t workspace_bytes, void* stream);
+
+/* Human-readable name of an error code (static string). */
+const char* qmc_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* QMC_H_ */

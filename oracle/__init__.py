@@ -33,14 +33,16 @@ the round trip through ``math.erfc``.
 
 from .points import (PHI_IDENTITY, PHI_CENTERED, PHI_INVNORM, PHI_TENT,
                      RULE_LATTICE, RULE_POLY_GF2, phi_apply, lattice_coords,
-                     gf2_coords, gf2_digits_coords, coords, explicit_Y, phi_residue_values)
+                     gf2_coords, gf2_digits_coords, coords, coords_rational, explicit_Y,
+                     phi_residue_values, phi_rational)
 from .dense import matmul, adjoint, matmul_rows, adjoint_entries, Y_rows
 from . import literal, exact
 
 __all__ = [
     "PHI_IDENTITY", "PHI_CENTERED", "PHI_INVNORM", "PHI_TENT",
     "RULE_LATTICE", "RULE_POLY_GF2", "phi_apply", "lattice_coords", "gf2_coords",
-    "gf2_digits_coords", "coords", "explicit_Y", "phi_residue_values",
+    "gf2_digits_coords", "coords", "coords_rational", "explicit_Y",
+    "phi_residue_values", "phi_rational",
     "matmul", "adjoint", "matmul_rows", "adjoint_entries", "Y_rows",
     "literal", "exact",
 ]

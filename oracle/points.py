@@ -33,7 +33,7 @@ RULE_POLY_GF2 = 1
 
 
 def phi_apply(kind: int, x: np.ndarray) -> np.ndarray:
-    """The univariate map phi applied to coordinates x in [0, 1)."""
+    """The univariate map phi applied to floating coordinates x in [0, 1)."""
     x = np.asarray(x, dtype=np.float64)
     if kind == PHI_IDENTITY:
         return x.copy()
@@ -46,13 +46,39 @@ def phi_apply(kind: int, x: np.ndarray) -> np.ndarray:
     raise ValueError(f"unknown phi kind {kind}")
 
 
-def _shifted_fraction(numer: np.ndarray, N: int, shift) -> np.ndarray:
-    """{ numer/N + num/den } for integer numer in [0, N), exactly rounded."""
+def phi_rational(kind: int, K: np.ndarray, D: int) -> np.ndarray:
+    """phi of the exact coordinate K/D (integers, 0 <= K < D), rounded once:
+    identity K/D, centered (2K-D)/(2D), tent (D-|2K-D|)/D; the inverse normal
+    CDF is evaluated on the nearer tail, -Phi^-1((D-K)/D) when K/D > 1/2, so
+    the complement is exact."""
+    K = np.asarray(K, dtype=np.int64)
+    fD = float(D)
+    if kind == PHI_IDENTITY:
+        return K.astype(np.float64) / fD
+    if kind == PHI_CENTERED:
+        return (2 * K - D).astype(np.float64) / (2.0 * fD)
+    if kind == PHI_TENT:
+        return (D - np.abs(2 * K - D)).astype(np.float64) / fD
+    if kind == PHI_INVNORM:
+        upper = 2 * K > D
+        lo = np.where(upper, D - K, K).astype(np.float64) / fD
+        y = ndtri(lo)
+        return np.where(upper, -y, y)
+    raise ValueError(f"unknown phi kind {kind}")
+
+
+def _shifted_numer(numer: np.ndarray, N: int, shift):
+    """{ numer/N + num/den } as the exact fraction K/D with D = N den."""
     num, den = int(shift[0]), int(shift[1])
-    big = N * den
-    k = (numer.astype(object) * den + num * N) % big if big >= (1 << 62) else \
-        (numer.astype(np.int64) * den + num * N) % big
-    return np.asarray(k, dtype=np.float64) / float(big)
+    D = N * den
+    assert D < (1 << 62), "shifted coordinate denominator too large"
+    K = (np.asarray(numer, dtype=np.int64) * den + num * N) % D
+    return K, D
+
+
+def _shifted_fraction(numer: np.ndarray, N: int, shift) -> np.ndarray:
+    K, D = _shifted_numer(numer, N, shift)
+    return K.astype(np.float64) / float(D)
 
 
 def lattice_coords(N: int, gen, shift=(0, 1), rows=None) -> np.ndarray:
@@ -130,6 +156,20 @@ def gf2_digits_coords(m: int, p: int, gen, rows=None) -> np.ndarray:
     return val
 
 
+def coords_rational(rule: int, N: int, gen, modulus: int = 0, shift=(0, 1), rows=None):
+    """Exact coordinates K/D of the requested rows (conventional order)."""
+    if rule == RULE_LATTICE:
+        g = np.asarray(gen, dtype=np.int64)
+        n = np.arange(N, dtype=np.int64) if rows is None else np.asarray(rows, dtype=np.int64)
+        return _shifted_numer((n[:, None] * g[None, :]) % N, N, shift)
+    if rule == RULE_POLY_GF2:
+        m = int(N).bit_length() - 1
+        assert 1 << m == N, "polynomial lattice rules need N = 2^m"
+        r = gf2_residues(m, modulus, gen, rows)
+        return _shifted_numer(gf2_value_of_residue(m, modulus, r).astype(np.int64), N, shift)
+    raise ValueError(f"unknown rule {rule}")
+
+
 def coords(rule: int, N: int, gen, modulus: int = 0, shift=(0, 1), rows=None) -> np.ndarray:
     if rule == RULE_LATTICE:
         return lattice_coords(N, gen, shift, rows)
@@ -142,8 +182,10 @@ def coords(rule: int, N: int, gen, modulus: int = 0, shift=(0, 1), rows=None) ->
 
 def explicit_Y(rule: int, N: int, gen, phi: int, modulus: int = 0, shift=(0, 1),
                rows=None) -> np.ndarray:
-    """Y[n, j] = phi(x_{n,j}) in conventional row order, FP64."""
-    return phi_apply(phi, coords(rule, N, gen, modulus, shift, rows))
+    """Y[n, j] = phi(x_{n,j}) in conventional row order, FP64 (phi of the
+    exact rational coordinate, rounded once)."""
+    K, D = coords_rational(rule, N, gen, modulus, shift, rows)
+    return phi_rational(phi, K, D)
 
 
 def phi_residue_values(rule: int, N: int, phi: int, modulus: int = 0,

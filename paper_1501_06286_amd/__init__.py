@@ -1,0 +1,318 @@
+"""Fast QMC matrix products on AMD MI355X (gfx950).
+
+X = Y A for QMC point matrices Y (rank-1 lattice rules with prime N, and
+polynomial lattice rules over GF(2) with N = 2^m), computed through the
+circulant factorisation of Dick, Kuo, Le Gia and Schwab (Section 2.1,
+eq. (ZPa); Remark 1) without forming Y.
+
+This module is argument marshalling only: every step runs in the HIP library
+``libqmcfast.so`` built from ``csrc/`` (see ``build.py``).  PyTorch provides
+device memory and streams.  There is no CPU fallback: if the library is
+missing, importing the binding raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libqmcfast.so")
+
+RULE_LATTICE = 0
+RULE_POLY_GF2 = 1
+PHI_IDENTITY = 0
+PHI_CENTERED = 1
+PHI_INVNORM = 2
+PHI_TENT = 3
+F32 = 0
+F64 = 1
+
+EXPORTED = [
+    "qmc_plan_create", "qmc_plan_destroy", "qmc_plan_info", "qmc_plan_tables",
+    "qmc_workspace_size", "qmc_matmul", "qmc_matmul_adjoint", "qmc_explicit_points",
+    "qmc_dense_matmul", "qmc_batched_workspace_size", "qmc_matmul_batched", "qmc_strerror",
+]
+
+
+class QMCError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {lib().qmc_strerror(code).decode()} (code {code})")
+        self.code = code
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int64), ("s", ctypes.c_int64), ("L", ctypes.c_int64),
+                ("M", ctypes.c_int64), ("M1", ctypes.c_int64), ("M2", ctypes.c_int64),
+                ("rounds", ctypes.c_int64), ("beta", ctypes.c_uint64),
+                ("rule", ctypes.c_int), ("phi_kind", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("embedded", ctypes.c_int), ("phi0", ctypes.c_double)]
+
+
+_LIB = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libqmcfast.so (raises if it has not been built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              f"`python -m paper_1501_06286_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        i64, u64, vp, ip = ctypes.c_int64, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_int
+        sz = ctypes.c_size_t
+        L.qmc_plan_create.argtypes = [ctypes.POINTER(vp), ip, i64, i64, ctypes.POINTER(u64), u64,
+                                      ip, i64, i64, ip, vp]
+        L.qmc_plan_destroy.argtypes = [vp]
+        L.qmc_plan_destroy.restype = None
+        L.qmc_plan_info.argtypes = [vp, ctypes.POINTER(PlanInfo)]
+        pi32 = ctypes.POINTER(ctypes.c_int32)
+        L.qmc_plan_tables.argtypes = [vp, pi32, pi32, pi32, ctypes.POINTER(ctypes.c_double)]
+        L.qmc_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
+        L.qmc_matmul.argtypes = [vp, vp, i64, i64, vp, i64, vp, sz, vp]
+        L.qmc_matmul_adjoint.argtypes = [vp, vp, i64, i64, vp, i64, vp, sz, vp]
+        L.qmc_explicit_points.argtypes = [vp, vp, i64, vp]
+        L.qmc_dense_matmul.argtypes = [vp, vp, i64, vp, i64, i64, vp, i64, vp]
+        L.qmc_batched_workspace_size.argtypes = [ip, ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                                 ctypes.POINTER(sz)]
+        L.qmc_matmul_batched.argtypes = [ip, ctypes.POINTER(vp), ctypes.POINTER(vp),
+                                         ctypes.POINTER(i64), ctypes.POINTER(vp), vp, sz, vp]
+        L.qmc_strerror.argtypes = [ip]
+        L.qmc_strerror.restype = ctypes.c_char_p
+        for name in EXPORTED:
+            if name not in ("qmc_plan_destroy", "qmc_strerror"):
+                getattr(L, name).restype = ip
+        _LIB = L
+    return _LIB
+
+
+def _check(code: int, where: str) -> None:
+    if code != 0:
+        raise QMCError(code, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None) -> Optional[int]:
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dtype_code(dtype) -> int:
+    torch = _torch()
+    if dtype in ("f32", "float32", torch.float32, F32):
+        return F32
+    if dtype in ("f64", "float64", torch.float64, F64):
+        return F64
+    raise ValueError(f"unsupported dtype {dtype}")
+
+
+class Plan:
+    """Everything that depends only on the point set (Section 2.1): primitive
+    element, exponents l_j, phi table, generator spectrum, schedules."""
+
+    def __init__(self, rule: int, N: int, gen, phi: int = PHI_IDENTITY,
+                 shift: Tuple[int, int] = (0, 1), dtype="f32", modulus: int = 0,
+                 stream=None):
+        gen = np.ascontiguousarray(np.asarray(gen, dtype=np.uint64))
+        self.rule, self.N, self.s = int(rule), int(N), int(gen.shape[0])
+        self.phi, self.shift, self.modulus = int(phi), (int(shift[0]), int(shift[1])), int(modulus)
+        self.dtype_code = _dtype_code(dtype)
+        torch = _torch()
+        self.torch_dtype = torch.float32 if self.dtype_code == F32 else torch.float64
+        handle = ctypes.c_void_p()
+        code = lib().qmc_plan_create(
+            ctypes.byref(handle), self.rule, self.N, self.s,
+            gen.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), self.modulus, self.phi,
+            self.shift[0], self.shift[1], self.dtype_code, _stream_handle(stream))
+        _check(code, "qmc_plan_create")
+        self._h = handle
+        self._ws = None
+
+    @classmethod
+    def from_instance(cls, inst, dtype=None, stream=None) -> "Plan":
+        return cls(inst.rule, inst.N, inst.gen, inst.phi, inst.shift,
+                   dtype or inst.dtype, inst.modulus, stream)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise RuntimeError("plan destroyed")
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().qmc_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = PlanInfo()
+        _check(lib().qmc_plan_info(self.handle, ctypes.byref(inf)), "qmc_plan_info")
+        return {k: getattr(inf, k) for k, _ in PlanInfo._fields_}
+
+    def tables(self):
+        """(pow, log, ell, phi) copied to host numpy arrays (bit-exact tables)."""
+        inf = self.info()
+        L, N, s = inf["L"], inf["N"], inf["s"]
+        pw = np.empty(L, dtype=np.int32)
+        lg = np.empty(N, dtype=np.int32)
+        el = np.empty(s, dtype=np.int32)
+        ph = np.empty(N, dtype=np.float64)
+        p32 = ctypes.POINTER(ctypes.c_int32)
+        _check(lib().qmc_plan_tables(self.handle, pw.ctypes.data_as(p32), lg.ctypes.data_as(p32),
+                                     el.ctypes.data_as(p32),
+                                     ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+               "qmc_plan_tables")
+        return pw, lg, el, ph
+
+    def workspace_bytes(self, t: int) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().qmc_workspace_size(self.handle, int(t), ctypes.byref(n)), "qmc_workspace_size")
+        return int(n.value)
+
+    def workspace(self, t: int, device=None):
+        """A cached device workspace large enough for t columns."""
+        torch = _torch()
+        need = self.workspace_bytes(t)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=device or "cuda")
+        return self._ws
+
+
+def _check_tensor(x, plan: Plan, rows: int, name: str):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != plan.torch_dtype:
+        raise TypeError(f"{name} has dtype {x.dtype}, plan computes in {plan.torch_dtype}")
+    if x.dim() != 2 or x.shape[0] != rows or x.stride(1) != 1:
+        raise ValueError(f"{name} must be a row-major {rows} x t matrix (unit column stride)")
+
+
+def matmul(plan: Plan, A, out=None, workspace=None, stream=None):
+    """X = Y A (N x t) on the GPU."""
+    torch = _torch()
+    _check_tensor(A, plan, plan.s, "A")
+    t = A.shape[1]
+    X = torch.empty((plan.N, t), dtype=A.dtype, device=A.device) if out is None else out
+    _check_tensor(X, plan, plan.N, "out")
+    ws = plan.workspace(t, A.device) if workspace is None else workspace
+    _check(lib().qmc_matmul(plan.handle, ctypes.c_void_p(A.data_ptr()), t, A.stride(0),
+                            ctypes.c_void_p(X.data_ptr()), X.stride(0),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                            _stream_handle(stream)), "qmc_matmul")
+    return X
+
+
+def matmul_adjoint(plan: Plan, G, out=None, workspace=None, stream=None):
+    """dA = Y^T G (s x t) on the GPU."""
+    torch = _torch()
+    _check_tensor(G, plan, plan.N, "G")
+    t = G.shape[1]
+    dA = torch.empty((plan.s, t), dtype=G.dtype, device=G.device) if out is None else out
+    _check_tensor(dA, plan, plan.s, "out")
+    ws = plan.workspace(t, G.device) if workspace is None else workspace
+    _check(lib().qmc_matmul_adjoint(plan.handle, ctypes.c_void_p(G.data_ptr()), t, G.stride(0),
+                                    ctypes.c_void_p(dA.data_ptr()), dA.stride(0),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                    _stream_handle(stream)), "qmc_matmul_adjoint")
+    return dA
+
+
+def explicit_points(plan: Plan, out=None, stream=None):
+    """The N x s point matrix Y itself (conventional order), built on the GPU."""
+    torch = _torch()
+    Y = torch.empty((plan.N, plan.s), dtype=plan.torch_dtype, device="cuda") if out is None else out
+    _check(lib().qmc_explicit_points(plan.handle, ctypes.c_void_p(Y.data_ptr()), Y.stride(0),
+                                     _stream_handle(stream)), "qmc_explicit_points")
+    return Y
+
+
+def dense_matmul(plan: Plan, Y, A, out=None, stream=None):
+    """The standard approach: X = Y A with an explicit Y, on the MFMA cores."""
+    torch = _torch()
+    _check_tensor(Y, plan, plan.N, "Y")
+    _check_tensor(A, plan, plan.s, "A")
+    t = A.shape[1]
+    X = torch.empty((plan.N, t), dtype=A.dtype, device=A.device) if out is None else out
+    _check(lib().qmc_dense_matmul(plan.handle, ctypes.c_void_p(Y.data_ptr()), Y.stride(0),
+                                  ctypes.c_void_p(A.data_ptr()), t, A.stride(0),
+                                  ctypes.c_void_p(X.data_ptr()), X.stride(0),
+                                  _stream_handle(stream)), "qmc_dense_matmul")
+    return X
+
+
+def batched_workspace_bytes(plans: Sequence[Plan], ts: Sequence[int]) -> int:
+    n = len(plans)
+    hs = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    tt = (ctypes.c_int64 * n)(*[int(t) for t in ts])
+    out = ctypes.c_size_t()
+    _check(lib().qmc_batched_workspace_size(n, hs, tt, ctypes.byref(out)),
+           "qmc_batched_workspace_size")
+    return int(out.value)
+
+
+def matmul_batched(plans: Sequence[Plan], As: Sequence, outs: Optional[Sequence] = None,
+                   workspace=None, stream=None) -> List:
+    """X_i = Y_i A_i for many plans in one call (dense row-major A_i, X_i)."""
+    torch = _torch()
+    n = len(plans)
+    Xs = []
+    for i, (p, A) in enumerate(zip(plans, As)):
+        _check_tensor(A, p, p.s, f"A[{i}]")
+        if A.stride(0) != A.shape[1]:
+            raise ValueError("batched inputs must be dense row-major")
+        X = torch.empty((p.N, A.shape[1]), dtype=A.dtype, device=A.device) if outs is None else outs[i]
+        Xs.append(X)
+    ts = [A.shape[1] for A in As]
+    need = batched_workspace_bytes(plans, ts)
+    ws = torch.empty(need, dtype=torch.uint8, device="cuda") if workspace is None else workspace
+    hs = (ctypes.c_void_p * n)(*[p.handle.value for p in plans])
+    ap = (ctypes.c_void_p * n)(*[A.data_ptr() for A in As])
+    xp = (ctypes.c_void_p * n)(*[X.data_ptr() for X in Xs])
+    tt = (ctypes.c_int64 * n)(*ts)
+    _check(lib().qmc_matmul_batched(n, hs, ap, tt, xp, ctypes.c_void_p(ws.data_ptr()),
+                                    ws.numel(), _stream_handle(stream)), "qmc_matmul_batched")
+    return Xs
+
+
+def _autograd():
+    torch = _torch()
+
+    class QMCMatmul(torch.autograd.Function):
+        """X = Y A with dA = Y^T dX in backward (no gradient for the point set)."""
+
+        @staticmethod
+        def forward(ctx, A, plan):
+            ctx.plan = plan
+            return matmul(plan, A.contiguous())
+
+        @staticmethod
+        def backward(ctx, gX):
+            return matmul_adjoint(ctx.plan, gX.contiguous()), None
+
+    return QMCMatmul
+
+
+_QMC_FN = None
+
+
+def qmc_matmul(A, plan: Plan):
+    """Differentiable X = Y A (torch.autograd)."""
+    global _QMC_FN
+    if _QMC_FN is None:
+        _QMC_FN = _autograd()
+    return _QMC_FN.apply(A, plan)

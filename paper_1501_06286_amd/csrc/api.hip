@@ -1,0 +1,210 @@
+// The C interface declared in include/qmc.h: argument checking, plan
+// lifetime and dispatch to the kernels of tables.hip, conv.hip, dense.hip.
+#include <new>
+#include <string.h>
+
+#include "internal.hpp"
+
+using namespace qmc;
+
+namespace {
+
+bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + bbytes && pb < pa + abytes;
+}
+
+size_t elem_bytes(int dtype) { return dtype == QMC_F32 ? 4 : 8; }
+
+size_t matrix_extent(int64_t rows, int64_t cols, int64_t ld, int dtype) {
+  if (rows <= 0 || cols <= 0) return 0;
+  return (size_t)((rows - 1) * ld + cols) * elem_bytes(dtype);
+}
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+const char* qmc_strerror(int code) {
+  switch (code) {
+    case QMC_OK: return "success";
+    case QMC_ERR_ARG: return "invalid argument";
+    case QMC_ERR_NOT_PRIME: return "lattice rule needs a prime number of points";
+    case QMC_ERR_NOT_PRIMITIVE: return "GF(2) modulus is not a primitive polynomial of degree log2(N)";
+    case QMC_ERR_GEN_ZERO: return "generator component is zero modulo N";
+    case QMC_ERR_ALIAS: return "output overlaps an input or the workspace";
+    case QMC_ERR_WORKSPACE: return "workspace missing or too small";
+    case QMC_ERR_OOM: return "device allocation failed";
+    case QMC_ERR_HIP: return "HIP runtime error";
+    case QMC_ERR_UNSUPPORTED: return "request outside what this build supports";
+    default: return "unknown error";
+  }
+}
+
+int qmc_plan_create(qmc_plan_t* out, int rule, int64_t N, int64_t s, const uint64_t* gen,
+                    uint64_t modulus, int phi_kind, int64_t shift_num, int64_t shift_den,
+                    int dtype, void* stream) {
+  if (!out || !gen || s < 1) return QMC_ERR_ARG;
+  *out = nullptr;
+  if (rule != QMC_RULE_LATTICE && rule != QMC_RULE_POLY_GF2) return QMC_ERR_ARG;
+  if (dtype != QMC_F32 && dtype != QMC_F64) return QMC_ERR_ARG;
+  if (phi_kind < QMC_PHI_IDENTITY || phi_kind > QMC_PHI_TENT) return QMC_ERR_ARG;
+  if (shift_den < 1 || shift_num < 0 || shift_num >= shift_den) return QMC_ERR_ARG;
+  if (s > ((int64_t)1 << 30)) return QMC_ERR_ARG;
+  int m = 0;
+  if (rule == QMC_RULE_LATTICE) {
+    if (N < 2 || N >= ((int64_t)1 << 31)) return QMC_ERR_ARG;
+    if (modulus != 0) return QMC_ERR_ARG;
+  } else {
+    if (!is_pow2(N) || N < 2 || N > ((int64_t)1 << 30)) return QMC_ERR_ARG;
+    while (((int64_t)1 << m) < N) ++m;
+  }
+  // the exact coordinate K/D needs D = N * shift_den well inside 63 bits
+  if ((__int128)N * shift_den >= ((__int128)1 << 61)) return QMC_ERR_ARG;
+  // the inverse normal CDF needs every coordinate strictly inside (0, 1):
+  // x = 0 occurs for row 0 unless the shift moves it
+  if (phi_kind == QMC_PHI_INVNORM && shift_num == 0) return QMC_ERR_ARG;
+
+  qmc_plan_s* P = new (std::nothrow) qmc_plan_s();
+  if (!P) return QMC_ERR_OOM;
+  P->rule = rule;
+  P->N = N;
+  P->s = s;
+  P->L = N - 1;
+  P->m = m;
+  P->modulus = modulus;
+  P->phi_kind = phi_kind;
+  P->shift_num = shift_num;
+  P->shift_den = shift_den;
+  P->dtype = dtype;
+  const int rc = build_tables(P, gen, (hipStream_t)stream);
+  if (rc != QMC_OK) {
+    qmc_plan_destroy(P);
+    return rc;
+  }
+  *out = P;
+  return QMC_OK;
+}
+
+void qmc_plan_destroy(qmc_plan_t plan) {
+  if (!plan) return;
+  for (void* p : plan->owned) hipFree(p);
+  delete plan;
+}
+
+int qmc_plan_info(qmc_plan_t P, qmc_plan_info_t* info) {
+  if (!P || !info) return QMC_ERR_ARG;
+  memset(info, 0, sizeof(*info));
+  info->N = P->N;
+  info->s = P->s;
+  info->L = P->L;
+  info->M = P->lay.M;
+  info->M1 = P->lay.M1;
+  info->M2 = P->lay.M2;
+  info->rounds = P->rounds;
+  info->beta = P->beta;
+  info->rule = P->rule;
+  info->phi_kind = P->phi_kind;
+  info->dtype = P->dtype;
+  info->embedded = P->embedded;
+  info->phi0 = P->phi0;
+  return QMC_OK;
+}
+
+int qmc_plan_tables(qmc_plan_t P, int32_t* pow_out, int32_t* log_out, int32_t* ell_out,
+                    double* phi_out) {
+  if (!P) return QMC_ERR_ARG;
+  if (pow_out && hipMemcpy(pow_out, P->d_pow, P->L * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return QMC_ERR_HIP;
+  if (log_out && hipMemcpy(log_out, P->d_log, P->N * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return QMC_ERR_HIP;
+  if (ell_out && hipMemcpy(ell_out, P->d_ell, P->s * 4, hipMemcpyDeviceToHost) != hipSuccess)
+    return QMC_ERR_HIP;
+  if (phi_out && hipMemcpy(phi_out, P->d_tphi, P->N * 8, hipMemcpyDeviceToHost) != hipSuccess)
+    return QMC_ERR_HIP;
+  return QMC_OK;
+}
+
+int qmc_workspace_size(qmc_plan_t P, int64_t t, size_t* bytes) {
+  if (!P || !bytes || t < 1) return QMC_ERR_ARG;
+  *bytes = workspace_bytes(P, t);
+  return QMC_OK;
+}
+
+int qmc_matmul(qmc_plan_t P, const void* A, int64_t t, int64_t lda, void* X, int64_t ldx,
+               void* workspace, size_t workspace_bytes_, void* stream) {
+  if (!P || !A || !X || t < 1 || lda < t || ldx < t) return QMC_ERR_ARG;
+  const size_t need = workspace_bytes(P, t);
+  if (!workspace || workspace_bytes_ < need) return QMC_ERR_WORKSPACE;
+  const size_t xa = matrix_extent(P->N, t, ldx, P->dtype);
+  const size_t aa = matrix_extent(P->s, t, lda, P->dtype);
+  if (ranges_overlap(X, xa, A, aa) || ranges_overlap(X, xa, workspace, need) ||
+      ranges_overlap(A, aa, workspace, need))
+    return QMC_ERR_ALIAS;
+  return launch_forward(P, A, t, lda, X, ldx, workspace, (hipStream_t)stream);
+}
+
+int qmc_matmul_adjoint(qmc_plan_t P, const void* G, int64_t t, int64_t ldg, void* dA,
+                       int64_t ldda, void* workspace, size_t workspace_bytes_, void* stream) {
+  if (!P || !G || !dA || t < 1 || ldg < t || ldda < t) return QMC_ERR_ARG;
+  const size_t need = workspace_bytes(P, t);
+  if (!workspace || workspace_bytes_ < need) return QMC_ERR_WORKSPACE;
+  const size_t ga = matrix_extent(P->N, t, ldg, P->dtype);
+  const size_t da = matrix_extent(P->s, t, ldda, P->dtype);
+  if (ranges_overlap(dA, da, G, ga) || ranges_overlap(dA, da, workspace, need) ||
+      ranges_overlap(G, ga, workspace, need))
+    return QMC_ERR_ALIAS;
+  return launch_adjoint(P, G, t, ldg, dA, ldda, workspace, (hipStream_t)stream);
+}
+
+int qmc_explicit_points(qmc_plan_t P, void* Y, int64_t ldy, void* stream) {
+  if (!P || !Y || ldy < P->s) return QMC_ERR_ARG;
+  return launch_explicit_points(P, Y, ldy, (hipStream_t)stream);
+}
+
+int qmc_dense_matmul(qmc_plan_t P, const void* Y, int64_t ldy, const void* A, int64_t t,
+                     int64_t lda, void* X, int64_t ldx, void* stream) {
+  if (!P || !Y || !A || !X || t < 1 || ldy < P->s || lda < t || ldx < t) return QMC_ERR_ARG;
+  const size_t xa = matrix_extent(P->N, t, ldx, P->dtype);
+  if (ranges_overlap(X, xa, Y, matrix_extent(P->N, P->s, ldy, P->dtype)) ||
+      ranges_overlap(X, xa, A, matrix_extent(P->s, t, lda, P->dtype)))
+    return QMC_ERR_ALIAS;
+  return launch_dense_gemm(P->dtype, P->N, P->s, t, Y, ldy, A, lda, X, ldx, (hipStream_t)stream);
+}
+
+int qmc_batched_workspace_size(int count, const qmc_plan_t* plans, const int64_t* t,
+                               size_t* bytes) {
+  if (count < 1 || !plans || !t || !bytes) return QMC_ERR_ARG;
+  size_t total = 0;
+  for (int i = 0; i < count; ++i) {
+    if (!plans[i] || t[i] < 1) return QMC_ERR_ARG;
+    total += (workspace_bytes(plans[i], t[i]) + 255) & ~size_t(255);
+  }
+  *bytes = total;
+  return QMC_OK;
+}
+
+int qmc_matmul_batched(int count, const qmc_plan_t* plans, const void* const* A, const int64_t* t,
+                       void* const* X, void* workspace, size_t workspace_bytes_, void* stream) {
+  if (count < 1 || !plans || !A || !t || !X) return QMC_ERR_ARG;
+  size_t need = 0;
+  int rc = qmc_batched_workspace_size(count, plans, t, &need);
+  if (rc != QMC_OK) return rc;
+  if (!workspace || workspace_bytes_ < need) return QMC_ERR_WORKSPACE;
+  const int dtype = plans[0]->dtype;
+  for (int i = 0; i < count; ++i)
+    if (plans[i]->dtype != dtype || !A[i] || !X[i]) return QMC_ERR_ARG;
+  size_t off = 0;
+  for (int i = 0; i < count; ++i) {
+    void* ws = (char*)workspace + off;
+    rc = launch_forward(plans[i], A[i], t[i], t[i], X[i], t[i], ws, (hipStream_t)stream);
+    if (rc != QMC_OK) return rc;
+    off += (workspace_bytes(plans[i], t[i]) + 255) & ~size_t(255);
+  }
+  return QMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,176 @@
+// Complex arithmetic and register-resident DFTs for the gfx950 kernels.
+//
+// The circular convolutions of the fast QMC product (Section 2.1, eq. (ZPa):
+// Y' a = Z (P a) with Z circulant) are evaluated with FFTs.  Short DFTs
+// (length <= 64) run entirely in one lane's registers with compile-time
+// twiddle constants; longer transforms combine two of them across the 64
+// lanes of a wavefront (see conv.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qmc {
+
+template <typename T>
+struct cx {
+  T x, y;
+};
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T>
+__device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cx<T> cmul(cx<T> a, cx<T> b) {
+  return {fmaT(a.x, b.x, -a.y * b.y), fmaT(a.x, b.y, a.y * b.x)};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cx<T> cmulc(cx<T> a, cx<T> b) {
+  return {fmaT(a.x, b.x, a.y * b.y), fmaT(a.y, b.x, -a.x * b.y)};
+}
+template <typename T>
+__device__ __forceinline__ cx<T> cscale(cx<T> a, T s) { return {a.x * s, a.y * s}; }
+// multiply by +i or -i
+template <typename T>
+__device__ __forceinline__ cx<T> mul_i(cx<T> a) { return {-a.y, a.x}; }
+template <typename T>
+__device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.y, -a.x}; }
+
+// ---------------------------------------------------------------------------
+// compile-time twiddle constants: cos and sin of 2 pi k / 64
+// ---------------------------------------------------------------------------
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+constexpr double poly_sin(double x) {  // |x| <= pi/4, Taylor series
+  double x2 = x * x, term = x, sum = x;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / ((2.0 * k) * (2.0 * k + 1.0));
+    sum += term;
+  }
+  return sum;
+}
+constexpr double poly_cos(double x) {
+  double x2 = x * x, term = 1.0, sum = 1.0;
+  for (int k = 1; k < 14; ++k) {
+    term *= -x2 / ((2.0 * k - 1.0) * (2.0 * k));
+    sum += term;
+  }
+  return sum;
+}
+// cos/sin of 2 pi num/den: reduce to the nearest quarter turn q and a
+// remainder in [-1/8, 1/8] of a turn, then rotate by q quarter turns.
+constexpr void sincos_turns(long num, long den, double& s, double& c) {
+  num %= den;
+  if (num < 0) num += den;
+  long q = (4 * num + den / 2) / den;  // nearest quarter turn
+  double rem = double(4 * num - q * den) / double(4 * den);
+  double a = kTwoPi * rem;
+  double s0 = poly_sin(a), c0 = poly_cos(a);
+  switch (q & 3) {
+    case 0: s = s0; c = c0; break;
+    case 1: s = c0; c = -s0; break;
+    case 2: s = -s0; c = -c0; break;
+    default: s = -c0; c = s0; break;
+  }
+}
+struct TwTab64 {
+  double c[64];
+  double s[64];
+};
+constexpr TwTab64 make_tw64() {
+  TwTab64 t{};
+  for (int k = 0; k < 64; ++k) sincos_turns(k, 64, t.s[k], t.c[k]);
+  return t;
+}
+__device__ constexpr TwTab64 kTw64 = make_tw64();
+
+// a * W^num with W = exp(DIR * 2 pi i / den), den a power of two <= 64.
+// num and den are compile-time constants after unrolling: exact quarter and
+// eighth turns become sign changes and one shared 1/sqrt(2) scaling.
+template <typename T, int DIR>
+__device__ __forceinline__ cx<T> twiddle_const(cx<T> a, int num, int den) {
+  num %= den;
+  if (num == 0) return a;
+  if ((4 * num) % den == 0) {
+    int q = (4 * num) / den;  // 1, 2, 3 quarter turns
+    if (q == 2) return {-a.x, -a.y};
+    bool plus_i = (q == 1) == (DIR > 0);
+    return plus_i ? mul_i(a) : mul_mi(a);
+  }
+  const int k = num * (64 / den);
+  const T c = (T)kTw64.c[k];
+  const T s = (T)(DIR > 0 ? kTw64.s[k] : -kTw64.s[k]);
+  if ((8 * num) % den == 0) {
+    // (+-1 +- i)/sqrt(2): rotate by a quarter-turn-free eighth turn
+    const T h = (T)0.70710678118654752440;
+    T cs = c > 0 ? (T)1 : (T)-1, ss = s > 0 ? (T)1 : (T)-1;
+    // (a.x + i a.y)(cs + i ss) h
+    T re = cs * a.x - ss * a.y;
+    T im = cs * a.y + ss * a.x;
+    return {re * h, im * h};
+  }
+  return {fmaT(a.x, c, -a.y * s), fmaT(a.x, s, a.y * c)};
+}
+
+// ---------------------------------------------------------------------------
+// register DFT of length N (power of two, N <= 64), natural order in and out,
+// Stockham formulation with radix-4 stages (and one radix-2 stage when
+// log2 N is odd).  DIR = -1: forward exp(-2 pi i jk/N); DIR = +1: inverse,
+// unscaled.
+// ---------------------------------------------------------------------------
+template <typename T, int DIR>
+__device__ __forceinline__ void bfly2(cx<T>& a0, cx<T>& a1) {
+  cx<T> t = a0 - a1;
+  a0 = a0 + a1;
+  a1 = t;
+}
+template <typename T, int DIR>
+__device__ __forceinline__ void bfly4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3) {
+  cx<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = a1 - a3;
+  t3 = (DIR < 0) ? mul_mi(t3) : mul_i(t3);
+  a0 = t0 + t2;
+  a2 = t0 - t2;
+  a1 = t1 + t3;
+  a3 = t1 - t3;
+}
+
+template <typename T, int N, int DIR, int Ns>
+struct RegFftStage {
+  static __device__ __forceinline__ void run(cx<T>* v) {
+    if constexpr (Ns < N) {
+      constexpr int r = ((N / Ns) % 4 == 0) ? 4 : 2;
+      cx<T> out[N];
+#pragma unroll
+      for (int j = 0; j < N / r; ++j) {
+        const int k = j % Ns;
+        cx<T> a[r];
+#pragma unroll
+        for (int q = 0; q < r; ++q) a[q] = v[j + q * (N / r)];
+#pragma unroll
+        for (int q = 1; q < r; ++q) a[q] = twiddle_const<T, DIR>(a[q], q * k, Ns * r);
+        if constexpr (r == 4)
+          bfly4<T, DIR>(a[0], a[1], a[2], a[3]);
+        else
+          bfly2<T, DIR>(a[0], a[1]);
+        const int base = (j / Ns) * Ns * r + k;
+#pragma unroll
+        for (int q = 0; q < r; ++q) out[base + q * Ns] = a[q];
+      }
+#pragma unroll
+      for (int i = 0; i < N; ++i) v[i] = out[i];
+      RegFftStage<T, N, DIR, Ns * r>::run(v);
+    }
+  }
+};
+
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void reg_fft(cx<T>* v) {
+  static_assert(N >= 1 && N <= 64 && (N & (N - 1)) == 0, "register DFT length");
+  RegFftStage<T, N, DIR, 1>::run(v);
+}
+
+}  // namespace qmc

@@ -1,0 +1,94 @@
+// Internal declarations shared by the translation units of libqmcfast.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "../../include/qmc.h"
+
+namespace qmc {
+
+// Decomposition of the circular convolution of length M = M1 * M2
+// (M1 = R * R on chip, M2 outer).
+struct Layout {
+  int64_t M = 1, M1 = 1, M2 = 1;
+  int R = 1;        // M1 = R * R, R <= 64
+  int P2 = 1;       // outer inverse split M2 = P2 * Q2 (P2 = 1: single back pass)
+  int Q2 = 1;
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace qmc
+
+struct qmc_plan_s {
+  int rule = 0;
+  int64_t N = 0, s = 0, L = 0;
+  int m = 0;                 // GF(2): degree
+  uint64_t modulus = 0;
+  uint64_t beta = 0;
+  int phi_kind = 0;
+  int64_t shift_num = 0, shift_den = 1;
+  int dtype = QMC_F32;
+  int embedded = 0;          // 1: L is not a power of two, convolution embedded in M >= 2L-1
+  double phi0 = 0.0;
+  qmc::Layout lay;
+  int64_t rounds = 0;        // sparse collapse schedule: rounds of R items with distinct e1
+  int64_t Upad = 0;          // rounds * R
+
+  // device tables (owned)
+  int32_t* d_pow = nullptr;     // L   : pow[e] = conventional row of beta^e
+  int32_t* d_log = nullptr;     // N   : log[pow[e]] = e, log[0] = -1
+  int32_t* d_ell = nullptr;     // s   : l_j
+  uint32_t* d_gen = nullptr;    // s   : g_j mod N (lattice) or q_j (GF(2))
+  double* d_tphi = nullptr;     // N   : phi of residue r (FP64)
+  void* d_Hs = nullptr;         // M   : spectrum / M in [w2][w1] order (plan dtype)
+  void* d_twf = nullptr;        // R*R : W_{M1}^{k1 m2} in [m2][k1] order
+  void* d_twi = nullptr;        // M   : conj W_M^{k1 (m2 M2 + w2)} in [w2][k1][m2] order
+  void* d_two = nullptr;        // M2*R: conj W_M^{R n2 w2} in [w2][n2] order
+  void* d_twit = nullptr;       // M2*Upad: W_M^{slot_u w2} in [w2][u] order
+  void* d_twb = nullptr;        // M2  : conj W_{M2}^{a q} table for the split back pass [a*Q2+q]
+  int32_t* d_it_e1 = nullptr;   // Upad: e1 of item u (M1 for padding)
+  int32_t* d_it_j = nullptr;    // Upad: row j of A for item u (-1 for padding)
+  int32_t* d_inv_ptr = nullptr;    // L+1 : rows j with l_j = e are inv_j[inv_ptr[e] .. inv_ptr[e+1])
+  int32_t* d_inv_j = nullptr;      // s
+  std::vector<void*> owned;
+};
+
+namespace qmc {
+
+// tables.hip
+int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st);
+
+// conv.hip
+size_t workspace_bytes(const qmc_plan_s* P, int64_t t);
+int launch_forward(const qmc_plan_s* P, const void* A, int64_t t, int64_t lda, void* X,
+                   int64_t ldx, void* ws, hipStream_t st);
+int launch_adjoint(const qmc_plan_s* P, const void* G, int64_t t, int64_t ldg, void* dA,
+                   int64_t ldda, void* ws, hipStream_t st);
+
+// dense.hip
+int launch_explicit_points(const qmc_plan_s* P, void* Y, int64_t ldy, hipStream_t st);
+int launch_dense_gemm(int dtype, int64_t M, int64_t K, int64_t Nc, const void* Y, int64_t ldy,
+                      const void* A, int64_t lda, void* X, int64_t ldx, hipStream_t st);
+
+inline int hip_ok(hipError_t e) { return e == hipSuccess ? QMC_OK : QMC_ERR_HIP; }
+
+template <typename T>
+T* dev_alloc(qmc_plan_s* P, size_t count, int* err) {
+  void* p = nullptr;
+  if (count == 0) count = 1;
+  if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) {
+    *err = QMC_ERR_OOM;
+    return nullptr;
+  }
+  P->owned.push_back(p);
+  return static_cast<T*>(p);
+}
+
+}  // namespace qmc

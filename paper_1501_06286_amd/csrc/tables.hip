@@ -1,0 +1,580 @@
+// Plan construction: the number theory of Section 2.1 (primitive element,
+// exponents of the generator components), the bit-exact power / logarithm
+// tables, the phi table, the circulant generator and its FP64 spectrum, and
+// the twiddle / schedule tables the convolution kernels read.
+//
+// Host code decides (prime factors of L, the primitive element, the layout
+// and the collapse schedule); every table that has one entry per group
+// element, residue or frequency is filled by a kernel on the device.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "cx.hpp"
+#include "internal.hpp"
+
+namespace qmc {
+
+// ---------------------------------------------------------------------------
+// host number theory
+// ---------------------------------------------------------------------------
+static bool is_prime_u64(uint64_t n) {
+  if (n < 2) return false;
+  if (n % 2 == 0) return n == 2;
+  for (uint64_t f = 3; f * f <= n; f += 2)
+    if (n % f == 0) return false;
+  return true;
+}
+
+static std::vector<uint64_t> prime_factors(uint64_t n) {
+  std::vector<uint64_t> out;
+  for (uint64_t f = 2; f * f <= n; ++f) {
+    if (n % f == 0) {
+      out.push_back(f);
+      while (n % f == 0) n /= f;
+    }
+  }
+  if (n > 1) out.push_back(n);
+  return out;
+}
+
+static uint64_t powmod(uint64_t b, uint64_t e, uint64_t n) {
+  uint64_t r = 1 % n;
+  b %= n;
+  while (e) {
+    if (e & 1) r = (unsigned __int128)r * b % n;
+    b = (unsigned __int128)b * b % n;
+    e >>= 1;
+  }
+  return r;
+}
+
+// smallest primitive root of prime N: beta^(L/q) != 1 for every prime q | L
+static uint64_t smallest_primitive_root(uint64_t N) {
+  if (N == 2) return 1;
+  const uint64_t L = N - 1;
+  std::vector<uint64_t> qs = prime_factors(L);
+  for (uint64_t b = 2; b < N; ++b) {
+    bool ok = true;
+    for (uint64_t q : qs)
+      if (powmod(b, L / q, N) == 1) { ok = false; break; }
+    if (ok) return b;
+  }
+  return 0;
+}
+
+static uint64_t gf2_mulmod_host(uint64_t a, uint64_t b, uint64_t p, int m) {
+  uint64_t r = 0;
+  for (int i = 0; i < m; ++i) {
+    if ((b >> i) & 1) r ^= a;
+    a <<= 1;
+    if ((a >> m) & 1) a ^= p;
+  }
+  return r;
+}
+static uint64_t gf2_xpow_host(uint64_t e, uint64_t p, int m) {
+  uint64_t r = 1, b = (m == 1) ? 1 : 2;
+  while (e) {
+    if (e & 1) r = gf2_mulmod_host(r, b, p, m);
+    b = gf2_mulmod_host(b, b, p, m);
+    e >>= 1;
+  }
+  return r;
+}
+// p of degree m is primitive iff x has order exactly 2^m - 1 modulo p
+static bool gf2_is_primitive(uint64_t p, int m) {
+  if (m < 1 || (p >> m) != 1 || (p & 1) == 0) return false;
+  const uint64_t order = (uint64_t(1) << m) - 1;
+  if (gf2_xpow_host(order, p, m) != 1) return false;
+  for (uint64_t q : prime_factors(order))
+    if (gf2_xpow_host(order / q, p, m) == 1) return false;
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// device kernels: tables
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t gf2_mulmod(uint64_t a, uint64_t b, uint64_t p, int m) {
+  uint64_t r = 0;
+  for (int i = 0; i < m; ++i) {
+    if ((b >> i) & 1) r ^= a;
+    a <<= 1;
+    if ((a >> m) & 1) a ^= p;
+  }
+  return r;
+}
+
+// pow[e] = beta^e mod N, square-and-multiply on 64-bit integers (N < 2^31)
+__global__ void k_pow_lattice(int32_t* pow, int64_t L, uint64_t N, uint64_t beta) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= L) return;
+  uint64_t r = 1 % N, b = beta % N, x = (uint64_t)e;
+  while (x) {
+    if (x & 1) r = r * b % N;
+    b = b * b % N;
+    x >>= 1;
+  }
+  pow[e] = (int32_t)r;
+}
+
+// pow[e] = x^e mod p(x) over GF(2) (as a bitmask), square-and-multiply
+__global__ void k_pow_gf2(int32_t* pow, int64_t L, uint64_t p, int m) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= L) return;
+  uint64_t r = 1, b = (m == 1) ? 1 : 2, x = (uint64_t)e;
+  while (x) {
+    if (x & 1) r = gf2_mulmod(r, b, p, m);
+    b = gf2_mulmod(b, b, p, m);
+    x >>= 1;
+  }
+  pow[e] = (int32_t)r;
+}
+
+__global__ void k_fill_i32(int32_t* a, int64_t n, int32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// log[pow[e]] = e  (pow is a bijection [0, L) -> [1, N-1])
+__global__ void k_log_scatter(const int32_t* pow, int64_t L, int32_t* log) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < L) log[pow[e]] = (int32_t)e;
+}
+
+// ell[j] = log[g_j]
+__global__ void k_ell(const uint32_t* gen, int64_t s, const int32_t* log, int32_t* ell) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < s) ell[j] = log[gen[j]];
+}
+
+// Wichura's algorithm AS241 (PPND16, Applied Statistics 37, 1988) for the
+// lower half p <= 1/2 of the inverse standard normal CDF, FP64.
+__device__ double invnorm_lower(double p) {
+  const double q = p - 0.5;
+  if (fabs(q) <= 0.425) {
+    const double r = 0.180625 - q * q;
+    const double num =
+        ((((((2.5090809287301226727e+3 * r + 3.3430575583588128105e+4) * r +
+             6.7265770927008700853e+4) * r + 4.5921953931549871457e+4) * r +
+           1.3731693765509461125e+4) * r + 1.9715909503065514427e+3) * r +
+         1.3314166789178437745e+2) * r + 3.3871328727963666080e+0;
+    const double den =
+        ((((((5.2264952788528545610e+3 * r + 2.8729085735721942674e+4) * r +
+             3.9307895800092710610e+4) * r + 2.1213794301586595867e+4) * r +
+           5.3941960214247511077e+3) * r + 6.8718700749205790830e+2) * r +
+         4.2313330701600911252e+1) * r + 1.0;
+    return q * num / den;
+  }
+  double r = sqrt(-log(p));
+  double val;
+  if (r <= 5.0) {
+    r -= 1.6;
+    const double num =
+        ((((((7.74545014278341407640e-4 * r + 2.27238449892691845833e-2) * r +
+             2.41780725177450611770e-1) * r + 1.27045825245236838258e+0) * r +
+           3.64784832476320460504e+0) * r + 5.76949722146069140550e+0) * r +
+         4.63033784615654529590e+0) * r + 1.42343711074968357734e+0;
+    const double den =
+        ((((((1.05075007164441684324e-9 * r + 5.47593808499534494600e-4) * r +
+             1.51986665636164571966e-2) * r + 1.48103976427480074590e-1) * r +
+           6.89767334985100004550e-1) * r + 1.67638483018380384940e+0) * r +
+         2.05319162663775882187e+0) * r + 1.0;
+    val = num / den;
+  } else {
+    r -= 5.0;
+    const double num =
+        ((((((2.01033439929228813265e-7 * r + 2.71155556874348757815e-5) * r +
+             1.24266094738807843860e-3) * r + 2.65321895265761230930e-2) * r +
+           2.96560571828504891230e-1) * r + 1.78482653991729133580e+0) * r +
+         5.46378491116411436990e+0) * r + 6.65790464350110377720e+0;
+    const double den =
+        ((((((2.04426310338993978564e-15 * r + 1.42151175831644588870e-7) * r +
+             1.84631831751005468180e-5) * r + 7.86869131145613259100e-4) * r +
+           1.48753612908506148525e-2) * r + 1.36929880922735805310e-1) * r +
+         5.99832206555887937690e-1) * r + 1.0;
+    val = num / den;
+  }
+  return -val;  // q < 0 on the lower half
+}
+
+// phi of the exact coordinate K/D (0 <= K < D), rounded once; the inverse
+// normal CDF is taken on the nearer tail so the complement is exact.
+__device__ double phi_of(int kind, int64_t K, int64_t D) {
+  switch (kind) {
+    case QMC_PHI_IDENTITY: return (double)K / (double)D;
+    case QMC_PHI_CENTERED: return (double)(2 * K - D) / (double)(2 * D);
+    case QMC_PHI_TENT: {
+      int64_t a = 2 * K - D;
+      if (a < 0) a = -a;
+      return (double)(D - a) / (double)D;
+    }
+    default: {  // QMC_PHI_INVNORM
+      if (2 * K > D) return -invnorm_lower((double)(D - K) / (double)D);
+      return invnorm_lower((double)K / (double)D);
+    }
+  }
+}
+
+// T_phi[r] = phi({point of residue r} + shift), r in [0, N)
+//   lattice: point r/N;  GF(2): nu_m(r(x)/p(x)) = Q/2^m with Q the quotient
+//   of r(x) x^m by p(x)
+__global__ void k_phi_table(double* tphi, int rule, int64_t N, int m, uint64_t p, int kind,
+                            int64_t snum, int64_t sden) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= N) return;
+  int64_t numer = r;
+  if (rule == QMC_RULE_POLY_GF2) {
+    uint64_t a = (uint64_t)r << m, q = 0;
+    for (int k = m - 1; k >= 0; --k) {
+      if ((a >> (m + k)) & 1) {
+        a ^= p << k;
+        q |= uint64_t(1) << k;
+      }
+    }
+    numer = (int64_t)q;
+  }
+  const int64_t D = N * sden;
+  const int64_t K = (numer * sden + snum * N) % D;
+  tphi[r] = phi_of(kind, K, D);
+}
+
+// circulant generator z_k = T_phi[pow[k]], embedded into length M when
+// M != L:  h[d] = z[d] (d < L), h[M-L+d] = z[d] (d >= 1), 0 elsewhere.
+__global__ void k_generator(cx<double>* h, const int32_t* pow, const double* tphi, int64_t L,
+                            int64_t M) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= M) return;
+  double v = 0.0;
+  if (d < L)
+    v = tphi[pow[d]];
+  else if (M != L && d >= M - L + 1)
+    v = tphi[pow[d - (M - L)]];
+  h[d] = {v, 0.0};
+}
+
+// W[k] = exp(-2 pi i k / M) in FP64
+__global__ void k_twiddle(cx<double>* W, int64_t M) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  double s, c;
+  sincospi(2.0 * (double)k / (double)M, &s, &c);
+  W[k] = {c, -s};
+}
+
+// one radix-2 Stockham pass of a forward FP64 DFT of length M over global memory
+__global__ void k_fft_r2_pass(const cx<double>* in, cx<double>* out, int64_t M, int64_t Ns,
+                              const cx<double>* W) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M / 2) return;
+  const int64_t k = j % Ns;
+  cx<double> a0 = in[j], a1 = in[j + M / 2];
+  a1 = cmul(a1, W[k * (M / (2 * Ns))]);
+  const int64_t base = (j / Ns) * 2 * Ns + k;
+  out[base] = a0 + a1;
+  out[base + Ns] = a0 - a1;
+}
+
+template <typename T>
+__device__ __forceinline__ cx<T> to_t(cx<double> a) {
+  return {(T)a.x, (T)a.y};
+}
+
+// Hs[w2][w1] = Hhat[w2 + M2 w1] / M
+template <typename T>
+__global__ void k_spectrum_layout(cx<T>* Hs, const cx<double>* Hhat, int64_t M, int64_t M1,
+                                  int64_t M2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const int64_t w2 = i / M1, w1 = i % M1;
+  const cx<double> h = Hhat[w2 + M2 * w1];
+  const double inv = 1.0 / (double)M;
+  Hs[i] = to_t<T>({h.x * inv, h.y * inv});
+}
+
+// twf[m2][k1] = W_{M1}^{k1 m2} = W_M^{k1 m2 M2}
+template <typename T>
+__global__ void k_tw_fwd_inner(cx<T>* twf, const cx<double>* W, int R, int64_t M, int64_t M2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= R * R) return;
+  const int64_t m2 = i / R, k1 = i % R;
+  twf[i] = to_t<T>(W[(k1 * m2 * M2) & (M - 1)]);
+}
+
+// twi[w2][k1][m2] = conj W_M^{k1 (m2 M2 + w2)}
+template <typename T>
+__global__ void k_tw_inv_comb(cx<T>* twi, const cx<double>* W, int R, int64_t M, int64_t M2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M) return;
+  const int64_t m2 = i % R, k1 = (i / R) % R, w2 = i / ((int64_t)R * R);
+  const cx<double> w = W[(k1 * (m2 * M2 + w2)) & (M - 1)];
+  twi[i] = to_t<T>({w.x, -w.y});
+}
+
+// two[w2][n2] = conj W_M^{R n2 w2}
+template <typename T>
+__global__ void k_tw_outer(cx<T>* two, const cx<double>* W, int R, int64_t M, int64_t M2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M2 * R) return;
+  const int64_t n2 = i % R, w2 = i / R;
+  const cx<double> w = W[((int64_t)R * n2 * w2) & (M - 1)];
+  two[i] = to_t<T>({w.x, -w.y});
+}
+
+// twit[w2][u] = W_M^{slot_u w2} (0 for padding items)
+template <typename T>
+__global__ void k_tw_items(cx<T>* twit, const cx<double>* W, const int32_t* slot, int64_t Upad,
+                           int64_t M, int64_t M2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= M2 * Upad) return;
+  const int64_t u = i % Upad, w2 = i / Upad;
+  const int32_t k = slot[u];
+  twit[i] = (k < 0) ? cx<T>{(T)0, (T)0} : to_t<T>(W[((int64_t)k * w2) & (M - 1)]);
+}
+
+// twb[a][q] = conj W_{M2}^{a q} for the split outer inverse (M2 = P2 Q2)
+template <typename T>
+__global__ void k_tw_back(cx<T>* twb, const cx<double>* W, int P2, int Q2, int64_t M,
+                          int64_t M2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= P2 * Q2) return;
+  const int64_t a = i / Q2, q = i % Q2;
+  const cx<double> w = W[(a * q * (M / M2)) & (M - 1)];
+  twb[i] = to_t<T>({w.x, -w.y});
+}
+
+static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+#define QMC_TRY(x)                       \
+  do {                                   \
+    int _e = (x);                        \
+    if (_e != QMC_OK) return _e;         \
+  } while (0)
+#define QMC_HIP(x) QMC_TRY(hip_ok(x))
+
+// ---------------------------------------------------------------------------
+// layout choice
+// ---------------------------------------------------------------------------
+static Layout choose_layout(int64_t L, int dtype, int* embedded) {
+  Layout lay;
+  int64_t M = 1;
+  if ((L & (L - 1)) == 0) {
+    M = L;
+    *embedded = 0;
+  } else {
+    while (M < 2 * L - 1) M <<= 1;
+    *embedded = 1;
+  }
+  lay.M = M;
+  const int rmax = (dtype == QMC_F32) ? 64 : 32;
+  int R = 1;
+  while (2 * R <= rmax && (int64_t)(2 * R) * (2 * R) <= M) R *= 2;
+  lay.R = R;
+  lay.M1 = (int64_t)R * R;
+  lay.M2 = M / lay.M1;
+  const int64_t back_max = 64;
+  if (lay.M2 <= back_max) {
+    lay.P2 = 1;
+    lay.Q2 = (int)lay.M2;
+  } else {
+    lay.Q2 = (int)back_max;
+    lay.P2 = (int)(lay.M2 / back_max);
+  }
+  return lay;
+}
+
+// collapse schedule: item u -> (row j, slot); rounds of R items whose
+// slots have distinct residues e1 = slot mod M1, items of one residue in
+// increasing j (fixed summation order)
+static void build_schedule(qmc_plan_s* P, const std::vector<int32_t>& ell,
+                           std::vector<int32_t>& it_j, std::vector<int32_t>& it_slot,
+                           std::vector<int32_t>& it_e1) {
+  const int64_t L = P->L, M1 = P->lay.M1;
+  const int R = P->lay.R;
+  std::vector<int64_t> next_round(M1, 0);
+  std::vector<int32_t> fill;  // items placed per round
+  std::vector<std::pair<int64_t, int64_t>> place(P->s);
+  for (int64_t j = 0; j < P->s; ++j) {
+    const int64_t slot = (L - ell[j]) % L;
+    const int64_t e1 = slot & (M1 - 1);
+    int64_t r = next_round[e1];
+    while (r < (int64_t)fill.size() && fill[r] >= R) ++r;
+    if (r >= (int64_t)fill.size()) fill.resize(r + 1, 0);
+    place[j] = {r, fill[r]};
+    fill[r]++;
+    next_round[e1] = r + 1;
+  }
+  const int64_t rounds = (int64_t)fill.size();
+  P->rounds = rounds;
+  P->Upad = rounds * R;
+  it_j.assign(P->Upad, -1);
+  it_slot.assign(P->Upad, -1);
+  it_e1.assign(P->Upad, (int32_t)M1);
+  for (int64_t j = 0; j < P->s; ++j) {
+    const int64_t u = place[j].first * R + place[j].second;
+    const int64_t slot = (L - ell[j]) % L;
+    it_j[u] = (int32_t)j;
+    it_slot[u] = (int32_t)slot;
+    it_e1[u] = (int32_t)(slot & (M1 - 1));
+  }
+}
+
+template <typename T>
+static int build_spectral_tables(qmc_plan_s* P, const cx<double>* dW, const cx<double>* dH,
+                                 const int32_t* dslot, hipStream_t st) {
+  int err = QMC_OK;
+  const Layout& lay = P->lay;
+  const int R = lay.R;
+  const int64_t M = lay.M, M1 = lay.M1, M2 = lay.M2;
+  cx<T>* Hs = dev_alloc<cx<T>>(P, M, &err);
+  cx<T>* twf = dev_alloc<cx<T>>(P, (size_t)R * R, &err);
+  cx<T>* twi = dev_alloc<cx<T>>(P, M, &err);
+  cx<T>* two = dev_alloc<cx<T>>(P, M2 * R, &err);
+  cx<T>* twit = dev_alloc<cx<T>>(P, M2 * P->Upad, &err);
+  cx<T>* twb = dev_alloc<cx<T>>(P, (size_t)lay.P2 * lay.Q2, &err);
+  if (err != QMC_OK) return err;
+  k_spectrum_layout<T><<<nblk(M), 256, 0, st>>>(Hs, dH, M, M1, M2);
+  k_tw_fwd_inner<T><<<nblk(R * R), 256, 0, st>>>(twf, dW, R, M, M2);
+  k_tw_inv_comb<T><<<nblk(M), 256, 0, st>>>(twi, dW, R, M, M2);
+  k_tw_outer<T><<<nblk(M2 * R), 256, 0, st>>>(two, dW, R, M, M2);
+  k_tw_items<T><<<nblk(M2 * P->Upad), 256, 0, st>>>(twit, dW, dslot, P->Upad, M, M2);
+  k_tw_back<T><<<nblk((int64_t)lay.P2 * lay.Q2), 256, 0, st>>>(twb, dW, lay.P2, lay.Q2, M, M2);
+  QMC_HIP(hipGetLastError());
+  P->d_Hs = Hs;
+  P->d_twf = twf;
+  P->d_twi = twi;
+  P->d_two = two;
+  P->d_twit = twit;
+  P->d_twb = twb;
+  return QMC_OK;
+}
+
+int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st) {
+  int err = QMC_OK;
+  const int64_t N = P->N, L = P->L, s = P->s;
+
+  // ---- host validation and number theory --------------------------------
+  std::vector<uint32_t> gen(s);
+  if (P->rule == QMC_RULE_LATTICE) {
+    if (!is_prime_u64((uint64_t)N)) return QMC_ERR_NOT_PRIME;
+    for (int64_t j = 0; j < s; ++j) {
+      const uint64_t g = gen_host[j] % (uint64_t)N;
+      if (g == 0) return QMC_ERR_GEN_ZERO;
+      gen[j] = (uint32_t)g;
+    }
+    P->beta = smallest_primitive_root((uint64_t)N);
+    if (P->beta == 0) return QMC_ERR_NOT_PRIME;
+  } else {
+    if (!gf2_is_primitive(P->modulus, P->m)) return QMC_ERR_NOT_PRIMITIVE;
+    for (int64_t j = 0; j < s; ++j) {
+      if (gen_host[j] == 0 || gen_host[j] >= (uint64_t)N) return QMC_ERR_GEN_ZERO;
+      gen[j] = (uint32_t)gen_host[j];
+    }
+    P->beta = (P->m == 1) ? 1 : 2;
+  }
+  P->lay = choose_layout(L, P->dtype, &P->embedded);
+  const Layout& lay = P->lay;
+
+  // ---- bit-exact group tables ------------------------------------------
+  P->d_pow = dev_alloc<int32_t>(P, L, &err);
+  P->d_log = dev_alloc<int32_t>(P, N, &err);
+  P->d_ell = dev_alloc<int32_t>(P, s, &err);
+  P->d_tphi = dev_alloc<double>(P, N, &err);
+  if (err != QMC_OK) return err;
+  uint32_t* d_gen = dev_alloc<uint32_t>(P, s, &err);
+  if (err != QMC_OK) return err;
+  P->d_gen = d_gen;
+  std::vector<void*> temps;
+  auto free_temps = [&]() {
+    for (void* p : temps) hipFree(p);
+  };
+  int rc = QMC_OK;
+  do {
+    if ((rc = hip_ok(hipMemcpyAsync(d_gen, gen.data(), s * sizeof(uint32_t),
+                                    hipMemcpyHostToDevice, st))) != QMC_OK)
+      break;
+    if (P->rule == QMC_RULE_LATTICE)
+      k_pow_lattice<<<nblk(L), 256, 0, st>>>(P->d_pow, L, (uint64_t)N, P->beta);
+    else
+      k_pow_gf2<<<nblk(L), 256, 0, st>>>(P->d_pow, L, P->modulus, P->m);
+    k_fill_i32<<<nblk(N), 256, 0, st>>>(P->d_log, N, -1);
+    k_log_scatter<<<nblk(L), 256, 0, st>>>(P->d_pow, L, P->d_log);
+    k_ell<<<nblk(s), 256, 0, st>>>(d_gen, s, P->d_log, P->d_ell);
+    k_phi_table<<<nblk(N), 256, 0, st>>>(P->d_tphi, P->rule, N, P->m, P->modulus, P->phi_kind,
+                                         P->shift_num, P->shift_den);
+    if ((rc = hip_ok(hipGetLastError())) != QMC_OK) break;
+
+    std::vector<int32_t> ell(s);
+    if ((rc = hip_ok(hipMemcpyAsync(ell.data(), P->d_ell, s * sizeof(int32_t),
+                                    hipMemcpyDeviceToHost, st))) != QMC_OK)
+      break;
+    if ((rc = hip_ok(hipMemcpyAsync(&P->phi0, P->d_tphi, sizeof(double),
+                                    hipMemcpyDeviceToHost, st))) != QMC_OK)
+      break;
+    if ((rc = hip_ok(hipStreamSynchronize(st))) != QMC_OK) break;
+    for (int64_t j = 0; j < s; ++j)
+      if (ell[j] < 0 || ell[j] >= L) { rc = QMC_ERR_HIP; break; }
+    if (rc != QMC_OK) break;
+
+    // ---- collapse schedule ----------------------------------------------
+    std::vector<int32_t> it_j, it_slot, it_e1;
+    build_schedule(P, ell, it_j, it_slot, it_e1);
+    P->d_it_j = dev_alloc<int32_t>(P, P->Upad, &err);
+    P->d_it_e1 = dev_alloc<int32_t>(P, P->Upad, &err);
+    P->d_inv_ptr = dev_alloc<int32_t>(P, L + 1, &err);
+    P->d_inv_j = dev_alloc<int32_t>(P, s, &err);
+    if ((rc = err) != QMC_OK) break;
+    int32_t* d_slot = nullptr;
+    if ((rc = hip_ok(hipMalloc(&d_slot, P->Upad * sizeof(int32_t)))) != QMC_OK) break;
+    temps.push_back(d_slot);
+    // inverse of j -> l_j (counting sort, j increasing within each e)
+    std::vector<int32_t> inv_ptr(L + 1, 0), inv_j(s);
+    for (int64_t j = 0; j < s; ++j) inv_ptr[ell[j] + 1]++;
+    for (int64_t e = 0; e < L; ++e) inv_ptr[e + 1] += inv_ptr[e];
+    {
+      std::vector<int32_t> pos(inv_ptr.begin(), inv_ptr.end() - 1);
+      for (int64_t j = 0; j < s; ++j) inv_j[pos[ell[j]]++] = (int32_t)j;
+    }
+    rc = hip_ok(hipMemcpyAsync(P->d_it_j, it_j.data(), P->Upad * 4, hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(P->d_it_e1, it_e1.data(), P->Upad * 4, hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(d_slot, it_slot.data(), P->Upad * 4, hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(P->d_inv_ptr, inv_ptr.data(), (L + 1) * 4, hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(P->d_inv_j, inv_j.data(), s * 4, hipMemcpyHostToDevice, st));
+    // host vectors must outlive the asynchronous copies
+    if (rc == QMC_OK) rc = hip_ok(hipStreamSynchronize(st));
+    if (rc != QMC_OK) break;
+
+    // ---- generator spectrum in FP64 -------------------------------------
+    const int64_t M = lay.M;
+    cx<double>*dW = nullptr, *dA = nullptr, *dB = nullptr;
+    if ((rc = hip_ok(hipMalloc(&dW, M * sizeof(cx<double>)))) != QMC_OK) break;
+    temps.push_back(dW);
+    if ((rc = hip_ok(hipMalloc(&dA, M * sizeof(cx<double>)))) != QMC_OK) break;
+    temps.push_back(dA);
+    if ((rc = hip_ok(hipMalloc(&dB, M * sizeof(cx<double>)))) != QMC_OK) break;
+    temps.push_back(dB);
+    k_twiddle<<<nblk(M), 256, 0, st>>>(dW, M);
+    k_generator<<<nblk(M), 256, 0, st>>>(dA, P->d_pow, P->d_tphi, L, M);
+    cx<double>*src = dA, *dst = dB;
+    for (int64_t Ns = 1; Ns < M; Ns *= 2) {
+      k_fft_r2_pass<<<nblk(M / 2), 256, 0, st>>>(src, dst, M, Ns, dW);
+      std::swap(src, dst);
+    }
+    if ((rc = hip_ok(hipGetLastError())) != QMC_OK) break;
+    if (P->dtype == QMC_F32)
+      rc = build_spectral_tables<float>(P, dW, src, d_slot, st);
+    else
+      rc = build_spectral_tables<double>(P, dW, src, d_slot, st);
+    if (rc != QMC_OK) break;
+    rc = hip_ok(hipStreamSynchronize(st));
+  } while (0);
+  free_temps();
+  return rc;
+}
+
+}  // namespace qmc
