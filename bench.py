@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the fast QMC matrix product X = Y A on one MI355X.
+
+Workload (one GPU): Gaussian sampling with a general covariance, rank-1
+lattice rule with N = 65537 points (N - 1 = 2^16), s = t = 4096, phi = inverse
+normal CDF applied to {n z_j / N + 1/(2N)}, A = upper Cholesky factor of
+exp(-|i-j|/410), FP32 (and FP64 beside it).  One step = one full qmc_matmul:
+collapse-transpose, fused sparse-DFT / FFT / spectral product / inverse FFT,
+outer inverse DFT with the row un-permutation.  Plan construction (tables,
+spectrum) is excluded from the timed region, as in the paper's experiments.
+
+Prints ONE JSON line:  metric, value (entries/s = N t / time), roofline of the
+dominant kernel (per-kernel HIP-event times measured in the timed region),
+cpu_baseline (the FP64 CPU oracle on a bounded sample of rows), the dense MFMA
+GEMM on the same GPU, and the FP64 path.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Y*A entries/sec (N*t per s), FFT vs dense GEMM, N=65537 s=t=4096; HBM GB/s"
+HBM_PEAK_GBPS = 8000.0
+# FP32 vector FMA peak without packed FP32 instructions (which this build does
+# not use): 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s
+# (157.3 TFLOP/s is the published figure with packed FP32).  FP64 vector: 78.6.
+VALU_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_model(plan_info, pairs, t, w, N, s):
+    """Algorithmic bytes and flops per launch of each kernel of one step.
+
+    Bytes count each operand the kernel must read or write in HBM once
+    (plan tables that stay in cache are not counted); flops are the nominal
+    5 n log2 n per complex DFT of length n, 6 per complex product, 8 per
+    complex multiply-add of the sparse outer DFT."""
+    M, M1, M2 = plan_info["M"], plan_info["M1"], plan_info["M2"]
+    U = plan_info["rounds"] * int(round(math.sqrt(M1)))
+    el = 2 * w
+    lg = lambda n: math.log2(n) if n > 1 else 0.0
+    out = {
+        "collapse_T": {"bytes": s * t * w + pairs * U * el, "flops": 0.0},
+        "middle": {"bytes": pairs * U * el + pairs * M * el,
+                   "flops": pairs * M2 * (2 * 5 * M1 * lg(M1) + 6 * M1 + 8 * U)},
+        "outer_split": {"bytes": 2 * pairs * M * el, "flops": pairs * M1 * M2 * 5 * lg(M2)},
+        "back": {"bytes": pairs * M * el + N * t * w, "flops": pairs * M1 * M2 * 5 * lg(M2)},
+    }
+    return out
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1501_06286_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1501_06286_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_sha") != source_sha():
+        return None
+    return d.get("bytes_per_dispatch")
+
+
+def time_steps(fn, steps, torch):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(inst, budget_s=12.0):
+    """The FP64 oracle (explicit Y rows, dense product) on a bounded sample."""
+    import numpy as np
+    import oracle
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        bl = [p.get("num_threads") for p in threadpool_info() if p.get("user_api") == "blas"]
+        if bl:
+            threads = int(bl[0])
+    except Exception:
+        pass
+    rng = np.random.default_rng(150106286 + 2000 + 7)
+    probe = 256
+    rows = np.sort(rng.choice(inst.N, size=probe, replace=False))
+    t0 = time.perf_counter()
+    oracle.matmul_rows(inst, rows)
+    dt = time.perf_counter() - t0
+    n = int(min(inst.N, max(probe, probe * budget_s / max(dt, 1e-3))))
+    rows = np.sort(rng.choice(inst.N, size=n, replace=False))
+    t0 = time.perf_counter()
+    oracle.matmul_rows(inst, rows)
+    dt = time.perf_counter() - t0
+    return {"value": n * inst.t / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} seeded rows of {inst.N} (all s={inst.s}, t={inst.t}), FP64 explicit Y "
+                      f"+ numpy matmul, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--s", type=int, default=4096)
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--fft-only", action="store_true",
+                    help="time only the FFT path (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the columns of A "
+              f"shard across GPUs without communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    if args.fft_only:
+        args.no_dense = args.no_cpu = args.no_f64 = True
+
+    import numpy as np
+    import torch
+    import paper_1501_06286_amd as q
+    import qmc_inputs as qi
+
+    dev = torch.device("cuda:0")
+    inst = qi.make_c2(args.dtype, s=args.s)
+    N, s, t = inst.N, inst.s, inst.t
+    w = 4 if args.dtype == "f32" else 8
+    tdt = torch.float32 if args.dtype == "f32" else torch.float64
+    log(f"workload {inst.name} dtype={args.dtype}")
+    plan = q.Plan.from_instance(inst)
+    info = plan.info()
+    log(f"plan: L={info['L']} M={info['M']} M1={info['M1']} M2={info['M2']} rounds={info['rounds']}")
+    A = torch.from_numpy(inst.A).to(tdt).to(dev)
+    X = torch.empty((N, t), dtype=tdt, device=dev)
+    ws = plan.workspace(t, dev)
+    step = lambda: q.matmul(plan, A, out=X, workspace=ws)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    plan.profile(True)
+    elapsed = time_steps(step, args.steps, torch)
+    prof = plan.profile_collect()
+    plan.profile(False)
+    ms_step = 1e3 * elapsed / args.steps
+    value = N * t / (elapsed / args.steps)
+    alg_bytes = (s + N) * t * w
+    log(f"FFT path {ms_step:.3f} ms/step, {value:.4e} entries/s")
+
+    pairs = (t + 1) // 2
+    model = kernel_model(info, pairs, t, w, N, s)
+    kernels = {}
+    for name, (tot, n) in prof.items():
+        avg = tot / n
+        mdl = model.get(name, {"bytes": 0, "flops": 0})
+        kernels[name] = {"avg_ms": round(avg, 4), "launches": n,
+                         "alg_GBps": round(mdl["bytes"] / (avg * 1e-3) / 1e9, 1),
+                         "alg_TFLOPs": round(mdl["flops"] / (avg * 1e-3) / 1e12, 2)}
+    dom = max(prof, key=lambda k: prof[k][0])
+    dmdl = model[dom]
+    davg_s = prof[dom][0] / prof[dom][1] * 1e-3
+    ai = dmdl["flops"] / max(dmdl["bytes"], 1)
+    ridge = VALU_PEAK_TFLOPS[args.dtype] * 1e12 / (HBM_PEAK_GBPS * 1e9)
+    workload = f"c2_gauss_n{N}_s{s}_t{t}_{args.dtype}"
+    traffic = measured_traffic(dom, workload)
+    if ai > ridge:
+        ach = dmdl["flops"] / davg_s / 1e12
+        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_TFLOPS[args.dtype],
+                "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS[args.dtype], 4),
+                "traffic": traffic, "kernel": dom}
+    else:
+        ach = dmdl["bytes"] / davg_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": dom}
+
+    result = {
+        "metric": METRIC, "value": value, "unit": "entries/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.dtype, "data": "synthetic",
+        "config": {"workload": workload, "rule": "rank-1 lattice", "N": N, "s": s, "t": t,
+                   "phi": "inverse normal CDF, shift 1/(2N)",
+                   "A": "upper Cholesky of exp(-|i-j|/410)", "M": info["M"], "M1": info["M1"],
+                   "M2": info["M2"]},
+        "hbm_GBps_algorithmic": round(alg_bytes / (elapsed / args.steps) / 1e9, 1),
+        "roofline": roof,
+        "kernels": kernels,
+    }
+
+    if not args.no_f64 and args.dtype == "f32":
+        inst64 = qi.make_c2("f64", s=args.s)
+        p64 = q.Plan.from_instance(inst64)
+        A64 = torch.from_numpy(inst64.A).to(dev)
+        X64 = torch.empty((N, t), dtype=torch.float64, device=dev)
+        ws64 = p64.workspace(t, dev)
+        st64 = lambda: q.matmul(p64, A64, out=X64, workspace=ws64)
+        st64()
+        n64 = max(3, args.steps // 2)
+        e64 = time_steps(st64, n64, torch)
+        result["fp64"] = {"value": N * t / (e64 / n64), "ms_per_step": round(1e3 * e64 / n64, 4),
+                          "hbm_GBps_algorithmic": round((s + N) * t * 8 / (e64 / n64) / 1e9, 1)}
+        log(f"FP64 path {1e3 * e64 / n64:.3f} ms/step")
+        del A64, X64, ws64, p64
+
+    if not args.no_dense:
+        Y = q.explicit_points(plan)
+        Xd = torch.empty((N, t), dtype=tdt, device=dev)
+        dstep = lambda: q.dense_matmul(plan, Y, A, out=Xd)
+        dstep()
+        nd = 3
+        ed = time_steps(dstep, nd, torch)
+        flops = 2.0 * N * s * t
+        dval = N * t / (ed / nd)
+        err = float((Xd - X).abs().max()) / (float(A.abs().sum(0).max()) * float(Y.abs().max()))
+        result["dense_gemm"] = {"value": dval, "ms_per_step": round(1e3 * ed / nd, 3),
+                                "TFLOPs": round(flops / (ed / nd) / 1e12, 2),
+                                "mfma_frac": round(flops / (ed / nd) / 1e12 / MFMA_PEAK_TFLOPS[args.dtype], 4),
+                                "fft_speedup": round(value / dval, 2),
+                                "max_norm_diff_vs_fft": err}
+        log(f"dense MFMA GEMM {1e3 * ed / nd:.2f} ms/step; speed-up {value / dval:.1f}x")
+        del Y, Xd
+
+    if not args.no_cpu:
+        log("cpu baseline (oracle, bounded sample)")
+        result["cpu_baseline"] = cpu_baseline(inst)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -186,6 +186,19 @@ int qmc_matmul_batched(int count, const qmc_plan_t* plans, const void* const* A,
                        const int64_t* t, void* const* X, void* workspace,
                        size_t workspace_bytes, void* stream);
 
+/*
+ * Timing instrumentation for benchmarks.  When enabled, every kernel launch
+ * of qmc_matmul / qmc_matmul_adjoint on this plan is bracketed by two HIP
+ * events recorded on the launch stream.  qmc_profile_collect waits for the
+ * recorded events, writes per kernel slot the summed elapsed milliseconds and
+ * the number of launches (arrays of QMC_PROF_SLOTS entries, host memory) and
+ * forgets the events.  Slot names: qmc_profile_slot_name.
+ */
+#define QMC_PROF_SLOTS 8
+int qmc_profile_enable(qmc_plan_t plan, int on);
+int qmc_profile_collect(qmc_plan_t plan, double* total_ms, int64_t* launches);
+const char* qmc_profile_slot_name(int slot);
+
 /* Human-readable name of an error code (static string). */
 const char* qmc_strerror(int code);
 

@@ -34,7 +34,9 @@ EXPORTED = [
     "qmc_plan_create", "qmc_plan_destroy", "qmc_plan_info", "qmc_plan_tables",
     "qmc_workspace_size", "qmc_matmul", "qmc_matmul_adjoint", "qmc_explicit_points",
     "qmc_dense_matmul", "qmc_batched_workspace_size", "qmc_matmul_batched", "qmc_strerror",
+    "qmc_profile_enable", "qmc_profile_collect", "qmc_profile_slot_name",
 ]
+PROF_SLOTS = 8
 
 
 class QMCError(RuntimeError):
@@ -82,8 +84,12 @@ def lib() -> ctypes.CDLL:
                                          ctypes.POINTER(i64), ctypes.POINTER(vp), vp, sz, vp]
         L.qmc_strerror.argtypes = [ip]
         L.qmc_strerror.restype = ctypes.c_char_p
+        L.qmc_profile_enable.argtypes = [vp, ip]
+        L.qmc_profile_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+        L.qmc_profile_slot_name.argtypes = [ip]
+        L.qmc_profile_slot_name.restype = ctypes.c_char_p
         for name in EXPORTED:
-            if name not in ("qmc_plan_destroy", "qmc_strerror"):
+            if name not in ("qmc_plan_destroy", "qmc_strerror", "qmc_profile_slot_name"):
                 getattr(L, name).restype = ip
         _LIB = L
     return _LIB
@@ -177,6 +183,21 @@ class Plan:
                                      ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                "qmc_plan_tables")
         return pw, lg, el, ph
+
+    def profile(self, on: bool = True) -> None:
+        """Bracket every kernel launch of this plan with HIP events."""
+        _check(lib().qmc_profile_enable(self.handle, 1 if on else 0), "qmc_profile_enable")
+
+    def profile_collect(self) -> dict:
+        """{kernel: (total_ms, launches)} since the last collect (waits for the events)."""
+        ms = (ctypes.c_double * PROF_SLOTS)()
+        n = (ctypes.c_int64 * PROF_SLOTS)()
+        _check(lib().qmc_profile_collect(self.handle, ms, n), "qmc_profile_collect")
+        out = {}
+        for k in range(PROF_SLOTS):
+            if n[k]:
+                out[lib().qmc_profile_slot_name(k).decode()] = (float(ms[k]), int(n[k]))
+        return out
 
     def workspace_bytes(self, t: int) -> int:
         n = ctypes.c_size_t()

@@ -89,10 +89,53 @@ int qmc_plan_create(qmc_plan_t* out, int rule, int64_t N, int64_t s, const uint6
   return QMC_OK;
 }
 
+static void prof_clear(qmc_plan_t P) {
+  for (int k = 0; k < PROF_NSLOTS; ++k) {
+    for (hipEvent_t e : P->prof[k].start) hipEventDestroy(e);
+    for (hipEvent_t e : P->prof[k].stop) hipEventDestroy(e);
+    P->prof[k].start.clear();
+    P->prof[k].stop.clear();
+  }
+}
+
 void qmc_plan_destroy(qmc_plan_t plan) {
   if (!plan) return;
+  prof_clear(plan);
   for (void* p : plan->owned) hipFree(p);
   delete plan;
+}
+
+int qmc_profile_enable(qmc_plan_t P, int on) {
+  if (!P) return QMC_ERR_ARG;
+  if (!on) prof_clear(P);
+  P->prof_on = on != 0;
+  return QMC_OK;
+}
+
+int qmc_profile_collect(qmc_plan_t P, double* total_ms, int64_t* launches) {
+  if (!P || !total_ms || !launches) return QMC_ERR_ARG;
+  int rc = QMC_OK;
+  for (int k = 0; k < PROF_NSLOTS; ++k) {
+    double sum = 0.0;
+    const size_t n = P->prof[k].stop.size();
+    for (size_t i = 0; i < n && i < P->prof[k].start.size(); ++i) {
+      float ms = 0.f;
+      if (hipEventSynchronize(P->prof[k].stop[i]) != hipSuccess ||
+          hipEventElapsedTime(&ms, P->prof[k].start[i], P->prof[k].stop[i]) != hipSuccess)
+        rc = QMC_ERR_HIP;
+      sum += ms;
+    }
+    total_ms[k] = sum;
+    launches[k] = (int64_t)n;
+  }
+  prof_clear(P);
+  return rc;
+}
+
+const char* qmc_profile_slot_name(int slot) {
+  static const char* names[PROF_NSLOTS] = {"collapse_T", "middle", "outer_split", "back",
+                                           "adj_front", "adj_split", "adj_middle", "adj_back"};
+  return (slot >= 0 && slot < PROF_NSLOTS) ? names[slot] : "";
 }
 
 int qmc_plan_info(qmc_plan_t P, qmc_plan_info_t* info) {

@@ -180,12 +180,16 @@ __global__ __launch_bounds__(64) void k_middle(
 }
 
 // ---------------------------------------------------------------------------
-// B1 (only when M2 = P2 * Q2 > 64): inverse DFT over the P2 factor of w2,
-// in place:  w2 = q + Q2 p'  ->  index a, times conj W_{M2}^{a q}
+// outer split (only when M2 = P2 * Q2 > 64), in place on C[pair][w2][e1]:
+//   DIR = +1 (forward product, first half of the inverse over w2):
+//     w2 = q + Q2 p'  ->  index a, times conj W_{M2}^{a q}
+//   DIR = -1 (adjoint front, second half of the forward DFT over e2):
+//     the values at q + Q2 a (already twiddled by W_{M2}^{a q}) -> p',
+//     stored at w2 = q + Q2 p'
 // ---------------------------------------------------------------------------
-template <typename T, int P2>
-__global__ __launch_bounds__(64) void k_back_split(cx<T>* __restrict__ C, int64_t M1, int64_t M2,
-                                                   int Q2, const cx<T>* __restrict__ twb) {
+template <typename T, int P2, int DIR>
+__global__ __launch_bounds__(64) void k_outer_split(cx<T>* __restrict__ C, int64_t M1, int64_t M2,
+                                                    int Q2, const cx<T>* __restrict__ twb) {
   const int64_t e1 = (int64_t)blockIdx.x * 64 + threadIdx.x;
   const int64_t q = blockIdx.y;
   const int64_t pair = blockIdx.z;
@@ -194,9 +198,11 @@ __global__ __launch_bounds__(64) void k_back_split(cx<T>* __restrict__ C, int64_
   cx<T> v[P2];
 #pragma unroll
   for (int p = 0; p < P2; ++p) v[p] = base[(q + (int64_t)Q2 * p) * M1];
-  reg_fft<T, P2, +1>(v);
+  reg_fft<T, P2, DIR>(v);
+  if constexpr (DIR > 0) {
 #pragma unroll
-  for (int a = 1; a < P2; ++a) v[a] = cmul(v[a], twb[a * Q2 + q]);
+    for (int a = 1; a < P2; ++a) v[a] = cmul(v[a], twb[a * Q2 + q]);
+  }
 #pragma unroll
   for (int a = 0; a < P2; ++a) base[(q + (int64_t)Q2 * a) * M1] = v[a];
 }
@@ -268,18 +274,22 @@ __global__ __launch_bounds__(256) void k_back(const cx<T>* __restrict__ C, int64
 
 // ---------------------------------------------------------------------------
 // adjoint front: g~[m] = G[pow[(L - m) mod L]] (m < L; 0 for L <= m < M)
-// gathered with coalesced row reads, then the forward DFT over e2 (length
-// M2 <= 64) for each (pair, e1):  B[pair][w2][e1]
+// gathered with coalesced row reads, then the forward DFT over e2.  With
+// M2 = P2 * Q: thread (pair, e1, a) transforms e2 = a + P2 b over b (length
+// Q) and multiplies by W_{M2}^{a q}; k_outer_split<-1> finishes over a.
+// Output: B[pair][w2][e1] (natural w2 order once the split has run).
 // ---------------------------------------------------------------------------
 template <typename T, int Q>
 __global__ __launch_bounds__(256) void k_adj_front(const T* __restrict__ G, int64_t ldg, int64_t t,
-                                                   int64_t M1, int64_t L, int64_t P,
-                                                   const int32_t* __restrict__ pow,
+                                                   int64_t M1, int64_t M2, int64_t P2, int64_t L,
+                                                   int64_t P, const int32_t* __restrict__ pow,
+                                                   const cx<T>* __restrict__ twb,
                                                    cx<T>* __restrict__ B) {
   constexpr int PB = 16, EB = 16;
   constexpr int CH = Q < 16 ? Q : 16;
   __shared__ cx<T> sm[CH][EB][PB + 1];
   const int64_t e1_0 = (int64_t)blockIdx.x * EB, p0 = (int64_t)blockIdx.y * PB;
+  const int64_t a = blockIdx.z;
   const int tid = threadIdx.x;
   const int pw = tid % PB, ew = tid / PB;     // gather mapping (pair-fast)
   const int el = tid % EB, pl = tid / EB;     // transform mapping (e1-fast)
@@ -290,7 +300,7 @@ __global__ __launch_bounds__(256) void k_adj_front(const T* __restrict__ G, int6
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
-      const int64_t e = e1w + M1 * (c0 + c);
+      const int64_t e = e1w + M1 * (a + P2 * (c0 + c));
       cx<T> g = {(T)0, (T)0};
       if (pairw < P && e1w < M1 && e < L) {
         const int64_t src = (L - e) % L;
@@ -306,11 +316,15 @@ __global__ __launch_bounds__(256) void k_adj_front(const T* __restrict__ G, int6
     for (int c = 0; c < CH; ++c) v[c0 + c] = sm[c][el][pl];
   }
   reg_fft<T, Q, -1>(v);
+  if (P2 > 1) {
+#pragma unroll
+    for (int q = 1; q < Q; ++q) v[q] = cmulc(v[q], twb[a * Q + q]);
+  }
   const int64_t e1 = e1_0 + el, pair = p0 + pl;
   if (pair < P && e1 < M1) {
-    cx<T>* base = B + pair * Q * M1 + e1;
+    cx<T>* base = B + pair * M2 * M1 + e1;
 #pragma unroll
-    for (int w = 0; w < Q; ++w) base[(int64_t)w * M1] = v[w];
+    for (int q = 0; q < Q; ++q) base[(q + Q * a) * M1] = v[q];
   }
 }
 
@@ -333,6 +347,7 @@ static void launch_middle_r(const qmc_plan_s* P, const cx<T>* src, int64_t pairs
   constexpr int TPW = 64 / R;
   const int64_t groups = (pairs + TPW - 1) / TPW;
   const int64_t G = groups * lay.M2;
+  ProfScope ps(P, SPARSE ? PROF_MIDDLE : PROF_ADJ_MIDDLE, st);
   k_middle<T, R, SPARSE><<<dim3((unsigned)G), dim3(64), 0, st>>>(
       src, P->Upad, P->rounds, P->d_it_e1, (const cx<T>*)P->d_twit, (const cx<T>*)P->d_twf,
       (const cx<T>*)P->d_Hs, (const cx<T>*)P->d_twi, (const cx<T>*)P->d_two, lay.M1, lay.M2,
@@ -360,19 +375,20 @@ static int launch_middle(const qmc_plan_s* P, const cx<T>* src, int64_t pairs, c
   return hip_ok(hipGetLastError());
 }
 
-template <typename T>
+template <typename T, int DIR>
 static int launch_split(const qmc_plan_s* P, cx<T>* C, int64_t pairs, hipStream_t st) {
   const Layout& lay = P->lay;
   if (lay.P2 == 1) return QMC_OK;
   dim3 grid((unsigned)((lay.M1 + 63) / 64), (unsigned)lay.Q2, (unsigned)pairs);
   const cx<T>* twb = (const cx<T>*)P->d_twb;
+  ProfScope ps(P, DIR > 0 ? PROF_SPLIT : PROF_ADJ_SPLIT, st);
   switch (lay.P2) {
-    case 2: k_back_split<T, 2><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
-    case 4: k_back_split<T, 4><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
-    case 8: k_back_split<T, 8><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
-    case 16: k_back_split<T, 16><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
-    case 32: k_back_split<T, 32><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
-    case 64: k_back_split<T, 64><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
+    case 2: k_outer_split<T, 2, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
+    case 4: k_outer_split<T, 4, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
+    case 8: k_outer_split<T, 8, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
+    case 16: k_outer_split<T, 16, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
+    case 32: k_outer_split<T, 32, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
+    case 64: k_outer_split<T, 64, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
     default: return QMC_ERR_UNSUPPORTED;
   }
   return hip_ok(hipGetLastError());
@@ -384,6 +400,7 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
                        hipStream_t st) {
   const Layout& lay = P->lay;
   dim3 grid((unsigned)((lay.M1 + 15) / 16), (unsigned)((pairs + 15) / 16), (unsigned)lay.P2);
+  ProfScope ps(P, ADJ ? PROF_ADJ_BACK : PROF_BACK, st);
 #define QMC_BACK(QQ)                                                                          \
   k_back<T, QQ, ADJ><<<grid, 256, 0, st>>>(C, lay.M1, lay.M2, lay.P2, P->L, pairs, P->d_pow, \
                                            inv_ptr, inv_j, G0, (T)P->phi0, X, ldx, t)
@@ -409,12 +426,15 @@ static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T*
   cx<T>* aT = (cx<T>*)ws;
   cx<T>* C = (cx<T>*)((char*)ws + align256(pairs * P->Upad * el));
   dim3 gT((unsigned)((P->Upad + 63) / 64), (unsigned)((pairs + 15) / 16));
-  k_collapse_T<T><<<gT, 256, 0, st>>>(A, lda, t, pairs, P->d_it_j, P->Upad, aT);
+  {
+    ProfScope ps(P, PROF_COLLAPSE, st);
+    k_collapse_T<T><<<gT, 256, 0, st>>>(A, lda, t, pairs, P->d_it_j, P->Upad, aT);
+  }
   int rc = hip_ok(hipGetLastError());
   if (rc != QMC_OK) return rc;
   rc = launch_middle<T, true>(P, aT, pairs, C, X, ldx, t, st);
   if (rc != QMC_OK) return rc;
-  rc = launch_split<T>(P, C, pairs, st);
+  rc = launch_split<T, +1>(P, C, pairs, st);
   if (rc != QMC_OK) return rc;
   return launch_back<T, false>(P, C, pairs, nullptr, nullptr, nullptr, X, ldx, t, st);
 }
@@ -430,22 +450,28 @@ template <typename T>
 static int launch_adj_front(const qmc_plan_s* P, const T* G, int64_t ldg, int64_t t,
                             int64_t pairs, cx<T>* B, hipStream_t st) {
   const Layout& lay = P->lay;
-  if (lay.P2 != 1) return QMC_ERR_UNSUPPORTED;
-  dim3 grid((unsigned)((lay.M1 + 15) / 16), (unsigned)((pairs + 15) / 16));
-#define QMC_AFRONT(QQ) \
-  k_adj_front<T, QQ><<<grid, 256, 0, st>>>(G, ldg, t, lay.M1, P->L, pairs, P->d_pow, B)
-  switch (lay.M2) {
-    case 1: QMC_AFRONT(1); break;
-    case 2: QMC_AFRONT(2); break;
-    case 4: QMC_AFRONT(4); break;
-    case 8: QMC_AFRONT(8); break;
-    case 16: QMC_AFRONT(16); break;
-    case 32: QMC_AFRONT(32); break;
-    case 64: QMC_AFRONT(64); break;
-    default: return QMC_ERR_UNSUPPORTED;
-  }
+  dim3 grid((unsigned)((lay.M1 + 15) / 16), (unsigned)((pairs + 15) / 16), (unsigned)lay.P2);
+  const cx<T>* twb = (const cx<T>*)P->d_twb;
+  {
+    ProfScope ps(P, PROF_ADJ_FRONT, st);
+#define QMC_AFRONT(QQ)                                                                        \
+  k_adj_front<T, QQ><<<grid, 256, 0, st>>>(G, ldg, t, lay.M1, lay.M2, lay.P2, P->L, pairs, \
+                                           P->d_pow, twb, B)
+    switch (lay.Q2) {
+      case 1: QMC_AFRONT(1); break;
+      case 2: QMC_AFRONT(2); break;
+      case 4: QMC_AFRONT(4); break;
+      case 8: QMC_AFRONT(8); break;
+      case 16: QMC_AFRONT(16); break;
+      case 32: QMC_AFRONT(32); break;
+      case 64: QMC_AFRONT(64); break;
+      default: return QMC_ERR_UNSUPPORTED;
+    }
 #undef QMC_AFRONT
-  return hip_ok(hipGetLastError());
+  }
+  int rc = hip_ok(hipGetLastError());
+  if (rc != QMC_OK) return rc;
+  return launch_split<T, -1>(P, B, pairs, st);
 }
 
 template <typename T>
@@ -459,7 +485,7 @@ static int adjoint_t(const qmc_plan_s* P, const T* G, int64_t t, int64_t ldg, T*
   if (rc != QMC_OK) return rc;
   rc = launch_middle<T, false>(P, B, pairs, C, nullptr, 0, t, st);
   if (rc != QMC_OK) return rc;
-  rc = launch_split<T>(P, C, pairs, st);
+  rc = launch_split<T, +1>(P, C, pairs, st);
   if (rc != QMC_OK) return rc;
   return launch_back<T, true>(P, C, pairs, P->d_inv_ptr, P->d_inv_j, G, dA, ldda, t, st);
 }

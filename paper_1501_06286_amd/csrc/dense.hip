@@ -52,7 +52,8 @@ int launch_explicit_points(const qmc_plan_s* P, void* Y, int64_t ldy, hipStream_
 // 128 x 128 block tile, 4 wavefronts of 64 x 64, v_mfma 16x16x4 (FP32 or
 // FP64), K-tiles of 16 staged through LDS with a register prefetch of the
 // next tile.  Operand layout of the 16x16x4 MFMA: lane l supplies
-// A[l % 16][l / 16] and B[l / 16][l % 16] and receives D[4 (l / 16) + r][l % 16].
+// A[l % 16][l / 16] and B[l / 16][l % 16]; it receives D[4 (l / 16) + r][l % 16]
+// in FP32 and D[l / 16 + 4 r][l % 16] in FP64 (r = 0..3).
 // ---------------------------------------------------------------------------
 template <typename T>
 struct Mfma;
@@ -62,6 +63,7 @@ struct Mfma<float> {
   static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
 };
 template <>
 struct Mfma<double> {
@@ -69,6 +71,7 @@ struct Mfma<double> {
   static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
 };
 
 template <typename T>
@@ -139,7 +142,7 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t K, int64_t Nc,
     for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gi = bm0 + wm * 64 + i * 16 + 4 * lk + r;
+        const int64_t gi = bm0 + wm * 64 + i * 16 + Mfma<T>::row(lk, r);
         const int64_t gj = bn0 + wn * 64 + j * 16 + li;
         if (gi < M && gj < Nc) X[gi * ldx + gj] = acc[i][j][r];
       }
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t K, int64_t Nc,
 int launch_dense_gemm(int dtype, int64_t M, int64_t K, int64_t Nc, const void* Y, int64_t ldy,
                       const void* A, int64_t lda, void* X, int64_t ldx, hipStream_t st) {
   const int64_t gx = (Nc + 127) / 128, gy = (M + 127) / 128;
-  if (gy > 65535 * 16 || gx > 65535) return QMC_ERR_UNSUPPORTED;
+  if (gy > 65535 || gx > 65535) return QMC_ERR_UNSUPPORTED;
   dim3 grid((unsigned)gx, (unsigned)gy);
   if (dtype == QMC_F32)
     k_gemm<float><<<grid, 256, 0, st>>>(M, K, Nc, (const float*)Y, ldy, (const float*)A, lda,

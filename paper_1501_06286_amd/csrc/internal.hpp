@@ -19,9 +19,14 @@ struct Layout {
   int Q2 = 1;
 };
 
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
+// per-kernel timing slots (HIP events recorded around each launch when on)
+enum ProfSlotId {
+  PROF_COLLAPSE = 0, PROF_MIDDLE, PROF_SPLIT, PROF_BACK,
+  PROF_ADJ_FRONT, PROF_ADJ_SPLIT, PROF_ADJ_MIDDLE, PROF_ADJ_BACK, PROF_NSLOTS
+};
+
+struct ProfEvents {
+  std::vector<hipEvent_t> start, stop;
 };
 
 }  // namespace qmc
@@ -58,6 +63,9 @@ struct qmc_plan_s {
   int32_t* d_inv_ptr = nullptr;    // L+1 : rows j with l_j = e are inv_j[inv_ptr[e] .. inv_ptr[e+1])
   int32_t* d_inv_j = nullptr;      // s
   std::vector<void*> owned;
+  // timing instrumentation (off by default)
+  mutable bool prof_on = false;
+  mutable qmc::ProfEvents prof[qmc::PROF_NSLOTS];
 };
 
 namespace qmc {
@@ -78,6 +86,30 @@ int launch_dense_gemm(int dtype, int64_t M, int64_t K, int64_t Nc, const void* Y
                       const void* A, int64_t lda, void* X, int64_t ldx, hipStream_t st);
 
 inline int hip_ok(hipError_t e) { return e == hipSuccess ? QMC_OK : QMC_ERR_HIP; }
+
+// records a start event at construction and a stop event at destruction on
+// the launch stream when the plan's timing instrumentation is on
+struct ProfScope {
+  const qmc_plan_s* P;
+  int slot;
+  hipStream_t st;
+  ProfScope(const qmc_plan_s* P_, int slot_, hipStream_t st_) : P(P_), slot(slot_), st(st_) {
+    if (!P->prof_on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) == hipSuccess) {
+      hipEventRecord(e, st);
+      P->prof[slot].start.push_back(e);
+    }
+  }
+  ~ProfScope() {
+    if (!P->prof_on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) == hipSuccess) {
+      hipEventRecord(e, st);
+      P->prof[slot].stop.push_back(e);
+    }
+  }
+};
 
 template <typename T>
 T* dev_alloc(qmc_plan_s* P, size_t count, int* err) {
