@@ -16,10 +16,9 @@
 //      become per-pair contiguous vectors aT[pair][u];
 //   F  for one outer frequency w2 and one pair: the sparse outer DFT over e2
 //      (only the s nonzero slots, scheduled in conflict-free rounds), the
-//      length-M1 DFT (two register DFTs of length R = sqrt(M1) across the
-//      lanes of a wavefront with one LDS exchange), the spectral product,
-//      the inverse length-M1 DFT and the outer twiddle; the DC term gives
-//      row 0;
+//      length-M1 DFT (three register DFTs of length R = M1^(1/3) across a
+//      workgroup with LDS exchanges), the spectral product, the inverse
+//      length-M1 DFT and the outer twiddle; the DC term gives row 0;
 //   B  for a tile of (e1, pairs): the inverse DFT over w2 and the row
 //      un-permutation X[pow[e]] (or, for the adjoint, the read-back at the
 //      exponents l_j).
@@ -76,106 +75,173 @@ __global__ __launch_bounds__(256) void k_collapse_T(const T* __restrict__ A, int
 }
 
 // ---------------------------------------------------------------------------
-// F: one (outer frequency w2, pair) per R lanes, 64/R pairs per wavefront
+// F: one (outer frequency w2, pair) per R^2 threads.
+//
+// The on-chip transform has length M1 = R^3, index e1 = a + R b + R^2 c and
+// frequency w1 = f + R g + R^2 h (a..h in [0, R)); every thread keeps R
+// values in registers and the data moves through one LDS buffer between the
+// three register DFTs of each direction:
+//   forward  thread e1'=(a + R b): DFT over c -> f, * W_{M1}^{e1' f}
+//            thread (a, f):        DFT over b -> g, * W_{R^2}^{a g}
+//            thread (f, g):        DFT over a -> h      => X[f + R g + R^2 h]
+//   product  * Hs[w2][w1]  (the spectrum, with 1/M folded in)
+//   inverse  thread (f, g):        IDFT over h -> a, * conj W_{R^2}^{a g}
+//            thread (f, a):        IDFT over g -> b, * conj W_M^{e1' (f M2 + w2)}
+//            thread e1':           IDFT over f -> c, * conj W_M^{R^2 c w2}
+// The conj W_M^{e1' w2} factor is the outer-step twiddle of M = M1 * M2.
 // ---------------------------------------------------------------------------
+template <int R>
+struct MidShape {
+  static constexpr int Q = R * R;                  // threads per transform
+  static constexpr int TPB = Q >= 64 ? 1 : 64 / Q; // transforms per block
+  static constexpr int BLOCK = Q * TPB;
+  static constexpr int BUFN = Q * (R + 1);         // LDS complex per transform (>= R^3 + 1)
+  static constexpr int G = Q < 64 ? Q : 64;        // sparse-front round width
+  static constexpr int F = Q / G;                  // front slices per transform (owners of e1 mod F)
+};
+
 template <typename T, int R, bool SPARSE>
-__global__ __launch_bounds__(64) void k_middle(
+__global__ __launch_bounds__(MidShape<R>::BLOCK) void k_middle(
     const cx<T>* __restrict__ src,      // SPARSE: aT [pair][Upad]; dense: B [pair][M2][M1]
     int64_t Upad, int64_t rounds, const int32_t* __restrict__ it_e1,
-    const cx<T>* __restrict__ twit, const cx<T>* __restrict__ twf, const cx<T>* __restrict__ Hs,
-    const cx<T>* __restrict__ twi, const cx<T>* __restrict__ two, int64_t M1, int64_t M2,
-    int64_t P, cx<T>* __restrict__ C, T* __restrict__ X, int64_t ldx, int64_t t, T phi0) {
-  constexpr int TPW = 64 / R;
-  constexpr int PITCH = R + 1;
-  constexpr int BUF = R * PITCH;
-  __shared__ cx<T> lds[TPW * BUF];
+    const cx<T>* __restrict__ twit, const cx<T>* __restrict__ twf1,
+    const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs, const cx<T>* __restrict__ twi3,
+    const cx<T>* __restrict__ two, int64_t M2, int64_t P, cx<T>* __restrict__ C,
+    T* __restrict__ X, int64_t t, T phi0) {
+  typedef MidShape<R> S;
+  constexpr int Q = S::Q, M1 = R * R * R, PB = R * (R + 1);
+  __shared__ cx<T> lds[S::TPB * S::BUFN];
   const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t w2 = b % M2;
   const int64_t pg = b / M2;
-  const int lane = threadIdx.x;
-  const int tau = lane / R, k = lane % R;
-  const int64_t pair = pg * TPW + tau;
+  const int tid = threadIdx.x;
+  const int tr = tid / Q, q = tid % Q;
+  const int64_t pair = pg * S::TPB + tr;
   const bool active = pair < P;
-  cx<T>* buf = lds + tau * BUF;
+  cx<T>* buf = lds + tr * S::BUFN;
   const cx<T> zero = {(T)0, (T)0};
   cx<T> x[R];
 
+  // ---- front: B[e1] for this w2, in registers of thread e1' = q ----------
   if constexpr (SPARSE) {
-    // sparse outer DFT over e2 into buf[e1] (buf[M1] absorbs padding items)
-    for (int64_t i = k; i <= M1; i += R) buf[i] = zero;
+    for (int i = q; i <= M1; i += Q) buf[i] = zero;
     __syncthreads();
+    // slice f_own = q / G owns the residues e1 = f_own (mod F); its rounds
+    // carry G items with distinct e1, so each LDS address is updated by one
+    // wavefront only, in round order
+    const int fo = q / S::G, ln = q % S::G;
     const cx<T>* av = src + (active ? pair : 0) * Upad;
     const cx<T>* tw = twit + w2 * Upad;
-    for (int64_t r = 0; r < rounds; ++r) {
-      const int64_t u = r * R + k;
-      const int e1 = it_e1[u];
-      const cx<T> v = active ? av[u] : zero;
-      const cx<T> c = cmul(v, tw[u]);
-      const cx<T> acc = buf[e1];
-      buf[e1] = acc + c;
+    constexpr int RB = 4;
+    for (int64_t r0 = 0; r0 < rounds; r0 += RB) {
+      int e1[RB];
+      cx<T> v[RB], w[RB];
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const bool ok = r0 + i < rounds;
+        const int64_t u = (((ok ? r0 + i : 0) * S::F) + fo) * S::G + ln;
+        e1[i] = ok ? it_e1[u] : M1;
+        v[i] = (ok && active) ? av[u] : zero;
+        w[i] = tw[u];
+      }
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const cx<T> c = cmul(v[i], w[i]);
+        const cx<T> acc = buf[e1[i]];
+        buf[e1[i]] = acc + c;
+      }
     }
     __syncthreads();
 #pragma unroll
-    for (int n2 = 0; n2 < R; ++n2) x[n2] = buf[k + R * n2];
+    for (int c = 0; c < R; ++c) x[c] = buf[q + Q * c];
   } else {
-    // dense outer DFT already done: load B[pair][w2][e1] and apply the outer
-    // twiddle W_M^{e1 w2} = W_M^{k w2} W_M^{R n2 w2} (conjugates of the
-    // inverse tables)
+    // dense outer DFT already done: B[pair][w2][e1], times W_M^{e1 w2}
     const cx<T>* bv = src + ((active ? pair : 0) * M2 + w2) * M1;
-    const cx<T> tk = twi[(w2 * R + k) * R];
+    const cx<T> tq = twi3[w2 * M1 + (int64_t)q * R];  // conj W_M^{q w2} (f = 0 entry)
 #pragma unroll
-    for (int n2 = 0; n2 < R; ++n2) {
-      cx<T> v = active ? bv[k + R * n2] : zero;
-      v = cmulc(v, tk);
-      if (n2 > 0) v = cmulc(v, two[w2 * R + n2]);
-      x[n2] = v;
+    for (int c = 0; c < R; ++c) {
+      cx<T> v = active ? bv[q + Q * c] : zero;
+      v = cmulc(v, tq);
+      if (c > 0) v = cmulc(v, two[w2 * R + c]);
+      x[c] = v;
     }
   }
 
-  // length-M1 forward DFT: e1 = k1 + R n2 -> w1 = m2 + R m1
-  reg_fft<T, R, -1>(x);  // over n2 -> m2 (lane = k1)
+  // ---- forward step 1: thread e1' = q, DFT over c -> f --------------------
+  reg_fft<T, R, -1>(x);
 #pragma unroll
-  for (int m2 = 1; m2 < R; ++m2) x[m2] = cmul(x[m2], twf[m2 * R + k]);
+  for (int f = 1; f < R; ++f) x[f] = cmul(x[f], twf1[f * Q + q]);
   __syncthreads();
 #pragma unroll
-  for (int m2 = 0; m2 < R; ++m2) buf[m2 * PITCH + k] = x[m2];
+  for (int f = 0; f < R; ++f) buf[f * PB + q] = x[f];
   __syncthreads();
+  // ---- forward step 2: thread (a, f), q = a + R f: DFT over b -> g --------
+  {
+    const int a = q % R, f = q / R;
 #pragma unroll
-  for (int k1 = 0; k1 < R; ++k1) x[k1] = buf[k * PITCH + k1];
-  reg_fft<T, R, -1>(x);  // over k1 -> m1 (lane = m2)
+    for (int bb = 0; bb < R; ++bb) x[bb] = buf[f * PB + a + R * bb];
+    reg_fft<T, R, -1>(x);
+#pragma unroll
+    for (int g = 1; g < R; ++g) x[g] = cmul(x[g], twf2[g * R + a]);
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < R; ++g) buf[(f + R * g) * (R + 1) + a] = x[g];
+    __syncthreads();
+  }
+  // ---- forward step 3: thread (f, g), q = f + R g: DFT over a -> h --------
+#pragma unroll
+  for (int a = 0; a < R; ++a) x[a] = buf[q * (R + 1) + a];
+  reg_fft<T, R, -1>(x);  // x[h] = X[q + R^2 h]
 
   if constexpr (SPARSE) {
-    // DC term: sum of the collapsed column pair = sum_j A[j, :] -> row 0
-    if (w2 == 0 && k == 0 && active) {
+    if (w2 == 0 && q == 0 && active) {  // DC term -> row 0
       X[2 * pair] = phi0 * x[0].x;
       if (2 * pair + 1 < t) X[2 * pair + 1] = phi0 * x[0].y;
     }
   }
-
-  // spectral product (the spectrum carries the 1/M of the inverse)
   const cx<T>* hs = Hs + w2 * M1;
 #pragma unroll
-  for (int m1 = 0; m1 < R; ++m1) x[m1] = cmul(x[m1], hs[k + R * m1]);
+  for (int h = 0; h < R; ++h) x[h] = cmul(x[h], hs[q + Q * h]);
 
-  // inverse length-M1 DFT: w1 = m2 + R m1 -> e1 = k1 + R n2
-  reg_fft<T, R, +1>(x);  // over m1 -> k1 (lane = m2)
-  const cx<T>* ti = twi + w2 * R * R;
+  // ---- inverse step 1: thread (f, g), IDFT over h -> a --------------------
+  reg_fft<T, R, +1>(x);
+  {
+    const int f = q % R, g = q / R;
 #pragma unroll
-  for (int k1 = 1; k1 < R; ++k1) x[k1] = cmul(x[k1], ti[k1 * R + k]);
-  __syncthreads();
+    for (int a = 1; a < R; ++a) x[a] = cmulc(x[a], twf2[g * R + a]);
+    __syncthreads();
 #pragma unroll
-  for (int k1 = 0; k1 < R; ++k1) buf[k1 * PITCH + k] = x[k1];
-  __syncthreads();
+    for (int a = 0; a < R; ++a) buf[(f + R * a) * (R + 1) + g] = x[a];
+    __syncthreads();
+  }
+  // ---- inverse step 2: thread (f, a), q = f + R a: IDFT over g -> b -------
+  {
+    const int f = q % R, a = q / R;
 #pragma unroll
-  for (int m2 = 0; m2 < R; ++m2) x[m2] = buf[k * PITCH + m2];
-  reg_fft<T, R, +1>(x);  // over m2 -> n2 (lane = k1)
+    for (int g = 0; g < R; ++g) x[g] = buf[q * (R + 1) + g];
+    reg_fft<T, R, +1>(x);
+    const cx<T>* ti = twi3 + w2 * M1;
+#pragma unroll
+    for (int bb = 0; bb < R; ++bb) {
+      const int e1p = a + R * bb;
+      if (e1p > 0) x[bb] = cmul(x[bb], ti[e1p * R + f]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bb = 0; bb < R; ++bb) buf[(a + R * bb) * (R + 1) + f] = x[bb];
+    __syncthreads();
+  }
+  // ---- inverse step 3: thread e1' = q, IDFT over f -> c -------------------
+#pragma unroll
+  for (int f = 0; f < R; ++f) x[f] = buf[q * (R + 1) + f];
+  reg_fft<T, R, +1>(x);
   const cx<T>* to = two + w2 * R;
 #pragma unroll
-  for (int n2 = 1; n2 < R; ++n2) x[n2] = cmul(x[n2], to[n2]);
+  for (int c = 1; c < R; ++c) x[c] = cmul(x[c], to[c]);
   if (active) {
-    cx<T>* c = C + (pair * M2 + w2) * M1;
+    cx<T>* cp = C + (pair * M2 + w2) * M1;
 #pragma unroll
-    for (int n2 = 0; n2 < R; ++n2) c[k + R * n2] = x[n2];
+    for (int c = 0; c < R; ++c) cp[q + Q * c] = x[c];
   }
 }
 
@@ -342,34 +408,27 @@ size_t workspace_bytes(const qmc_plan_s* P, int64_t t) {
 
 template <typename T, int R, bool SPARSE>
 static void launch_middle_r(const qmc_plan_s* P, const cx<T>* src, int64_t pairs, cx<T>* C,
-                            T* X, int64_t ldx, int64_t t, hipStream_t st) {
+                            T* X, int64_t t, hipStream_t st) {
   const Layout& lay = P->lay;
-  constexpr int TPW = 64 / R;
-  const int64_t groups = (pairs + TPW - 1) / TPW;
+  typedef MidShape<R> S;
+  const int64_t groups = (pairs + S::TPB - 1) / S::TPB;
   const int64_t G = groups * lay.M2;
   ProfScope ps(P, SPARSE ? PROF_MIDDLE : PROF_ADJ_MIDDLE, st);
-  k_middle<T, R, SPARSE><<<dim3((unsigned)G), dim3(64), 0, st>>>(
-      src, P->Upad, P->rounds, P->d_it_e1, (const cx<T>*)P->d_twit, (const cx<T>*)P->d_twf,
-      (const cx<T>*)P->d_Hs, (const cx<T>*)P->d_twi, (const cx<T>*)P->d_two, lay.M1, lay.M2,
-      pairs, C, X, ldx, t, (T)P->phi0);
+  k_middle<T, R, SPARSE><<<dim3((unsigned)G), dim3(S::BLOCK), 0, st>>>(
+      src, P->Upad, P->rounds, P->d_it_e1, (const cx<T>*)P->d_twit, (const cx<T>*)P->d_twf1,
+      (const cx<T>*)P->d_twf2, (const cx<T>*)P->d_Hs, (const cx<T>*)P->d_twi3,
+      (const cx<T>*)P->d_two, lay.M2, pairs, C, X, t, (T)P->phi0);
 }
 
 template <typename T, bool SPARSE>
 static int launch_middle(const qmc_plan_s* P, const cx<T>* src, int64_t pairs, cx<T>* C, T* X,
-                         int64_t ldx, int64_t t, hipStream_t st) {
+                         int64_t t, hipStream_t st) {
   switch (P->lay.R) {
-    case 1: launch_middle_r<T, 1, SPARSE>(P, src, pairs, C, X, ldx, t, st); break;
-    case 2: launch_middle_r<T, 2, SPARSE>(P, src, pairs, C, X, ldx, t, st); break;
-    case 4: launch_middle_r<T, 4, SPARSE>(P, src, pairs, C, X, ldx, t, st); break;
-    case 8: launch_middle_r<T, 8, SPARSE>(P, src, pairs, C, X, ldx, t, st); break;
-    case 16: launch_middle_r<T, 16, SPARSE>(P, src, pairs, C, X, ldx, t, st); break;
-    case 32: launch_middle_r<T, 32, SPARSE>(P, src, pairs, C, X, ldx, t, st); break;
-    case 64:
-      if constexpr (sizeof(T) == 4) {
-        launch_middle_r<T, 64, SPARSE>(P, src, pairs, C, X, ldx, t, st);
-        break;
-      }
-      return QMC_ERR_UNSUPPORTED;
+    case 1: launch_middle_r<T, 1, SPARSE>(P, src, pairs, C, X, t, st); break;
+    case 2: launch_middle_r<T, 2, SPARSE>(P, src, pairs, C, X, t, st); break;
+    case 4: launch_middle_r<T, 4, SPARSE>(P, src, pairs, C, X, t, st); break;
+    case 8: launch_middle_r<T, 8, SPARSE>(P, src, pairs, C, X, t, st); break;
+    case 16: launch_middle_r<T, 16, SPARSE>(P, src, pairs, C, X, t, st); break;
     default: return QMC_ERR_UNSUPPORTED;
   }
   return hip_ok(hipGetLastError());
@@ -432,7 +491,7 @@ static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T*
   }
   int rc = hip_ok(hipGetLastError());
   if (rc != QMC_OK) return rc;
-  rc = launch_middle<T, true>(P, aT, pairs, C, X, ldx, t, st);
+  rc = launch_middle<T, true>(P, aT, pairs, C, X, t, st);
   if (rc != QMC_OK) return rc;
   rc = launch_split<T, +1>(P, C, pairs, st);
   if (rc != QMC_OK) return rc;
@@ -483,7 +542,7 @@ static int adjoint_t(const qmc_plan_s* P, const T* G, int64_t t, int64_t ldg, T*
   cx<T>* C = (cx<T>*)((char*)B + align256(pairs * P->lay.M * el));
   int rc = launch_adj_front<T>(P, G, ldg, t, pairs, B, st);
   if (rc != QMC_OK) return rc;
-  rc = launch_middle<T, false>(P, B, pairs, C, nullptr, 0, t, st);
+  rc = launch_middle<T, false>(P, B, pairs, C, nullptr, t, st);
   if (rc != QMC_OK) return rc;
   rc = launch_split<T, +1>(P, C, pairs, st);
   if (rc != QMC_OK) return rc;

@@ -14,7 +14,7 @@ namespace qmc {
 // (M1 = R * R on chip, M2 outer).
 struct Layout {
   int64_t M = 1, M1 = 1, M2 = 1;
-  int R = 1;        // M1 = R * R, R <= 64
+  int R = 1;        // M1 = R * R * R, R <= 16
   int P2 = 1;       // outer inverse split M2 = P2 * Q2 (P2 = 1: single back pass)
   int Q2 = 1;
 };
@@ -43,8 +43,8 @@ struct qmc_plan_s {
   int embedded = 0;          // 1: L is not a power of two, convolution embedded in M >= 2L-1
   double phi0 = 0.0;
   qmc::Layout lay;
-  int64_t rounds = 0;        // sparse collapse schedule: rounds of R items with distinct e1
-  int64_t Upad = 0;          // rounds * R
+  int64_t rounds = 0;        // sparse collapse schedule: rounds per front slice
+  int64_t Upad = 0;          // rounds * R^2 (slices x round width)
 
   // device tables (owned)
   int32_t* d_pow = nullptr;     // L   : pow[e] = conventional row of beta^e
@@ -53,9 +53,10 @@ struct qmc_plan_s {
   uint32_t* d_gen = nullptr;    // s   : g_j mod N (lattice) or q_j (GF(2))
   double* d_tphi = nullptr;     // N   : phi of residue r (FP64)
   void* d_Hs = nullptr;         // M   : spectrum / M in [w2][w1] order (plan dtype)
-  void* d_twf = nullptr;        // R*R : W_{M1}^{k1 m2} in [m2][k1] order
-  void* d_twi = nullptr;        // M   : conj W_M^{k1 (m2 M2 + w2)} in [w2][k1][m2] order
-  void* d_two = nullptr;        // M2*R: conj W_M^{R n2 w2} in [w2][n2] order
+  void* d_twf1 = nullptr;       // R*R^2: W_{M1}^{e1' f} in [f][e1'] order (e1' < R^2)
+  void* d_twf2 = nullptr;       // R*R : W_{R^2}^{a g} in [g][a] order
+  void* d_twi3 = nullptr;       // M   : conj W_M^{e1' (f M2 + w2)} in [w2][e1'][f] order
+  void* d_two = nullptr;        // M2*R: conj W_M^{R^2 c w2} in [w2][c] order
   void* d_twit = nullptr;       // M2*Upad: W_M^{slot_u w2} in [w2][u] order
   void* d_twb = nullptr;        // M2  : conj W_{M2}^{a q} table for the split back pass [a*Q2+q]
   int32_t* d_it_e1 = nullptr;   // Upad: e1 of item u (M1 for padding)

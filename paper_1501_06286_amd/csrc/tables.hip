@@ -293,32 +293,43 @@ __global__ void k_spectrum_layout(cx<T>* Hs, const cx<double>* Hhat, int64_t M, 
   Hs[i] = to_t<T>({h.x * inv, h.y * inv});
 }
 
-// twf[m2][k1] = W_{M1}^{k1 m2} = W_M^{k1 m2 M2}
+// twf1[f][e1'] = W_{M1}^{e1' f} = W_M^{e1' f M2}   (e1' < R^2, f < R)
 template <typename T>
-__global__ void k_tw_fwd_inner(cx<T>* twf, const cx<double>* W, int R, int64_t M, int64_t M2) {
+__global__ void k_tw_f1(cx<T>* twf1, const cx<double>* W, int R, int64_t M, int64_t M2) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int Q = R * R;
+  if (i >= R * Q) return;
+  const int64_t f = i / Q, e = i % Q;
+  twf1[i] = to_t<T>(W[(e * f * M2) & (M - 1)]);
+}
+
+// twf2[g][a] = W_{R^2}^{a g} = W_M^{a g M / R^2}
+template <typename T>
+__global__ void k_tw_f2(cx<T>* twf2, const cx<double>* W, int R, int64_t M) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= R * R) return;
-  const int64_t m2 = i / R, k1 = i % R;
-  twf[i] = to_t<T>(W[(k1 * m2 * M2) & (M - 1)]);
+  const int64_t g = i / R, a = i % R;
+  twf2[i] = to_t<T>(W[(a * g * (M / ((int64_t)R * R))) & (M - 1)]);
 }
 
-// twi[w2][k1][m2] = conj W_M^{k1 (m2 M2 + w2)}
+// twi3[w2][e1'][f] = conj W_M^{e1' (f M2 + w2)}
 template <typename T>
-__global__ void k_tw_inv_comb(cx<T>* twi, const cx<double>* W, int R, int64_t M, int64_t M2) {
+__global__ void k_tw_i3(cx<T>* twi3, const cx<double>* W, int R, int64_t M, int64_t M2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
-  const int64_t m2 = i % R, k1 = (i / R) % R, w2 = i / ((int64_t)R * R);
-  const cx<double> w = W[(k1 * (m2 * M2 + w2)) & (M - 1)];
-  twi[i] = to_t<T>({w.x, -w.y});
+  const int64_t M1 = M / M2;
+  const int64_t f = i % R, e = (i / R) % (M1 / R), w2 = i / M1;
+  const cx<double> w = W[(e * (f * M2 + w2)) & (M - 1)];
+  twi3[i] = to_t<T>({w.x, -w.y});
 }
 
-// two[w2][n2] = conj W_M^{R n2 w2}
+// two[w2][c] = conj W_M^{R^2 c w2}
 template <typename T>
 __global__ void k_tw_outer(cx<T>* two, const cx<double>* W, int R, int64_t M, int64_t M2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M2 * R) return;
-  const int64_t n2 = i % R, w2 = i / R;
-  const cx<double> w = W[((int64_t)R * n2 * w2) & (M - 1)];
+  const int64_t c = i % R, w2 = i / R;
+  const cx<double> w = W[((int64_t)R * R * c * w2) & (M - 1)];
   two[i] = to_t<T>({w.x, -w.y});
 }
 
@@ -367,11 +378,12 @@ static Layout choose_layout(int64_t L, int dtype, int* embedded) {
     *embedded = 1;
   }
   lay.M = M;
-  const int rmax = (dtype == QMC_F32) ? 64 : 32;
+  (void)dtype;
+  const int rmax = 16;
   int R = 1;
-  while (2 * R <= rmax && (int64_t)(2 * R) * (2 * R) <= M) R *= 2;
+  while (2 * R <= rmax && (int64_t)(2 * R) * (2 * R) * (2 * R) <= M) R *= 2;
   lay.R = R;
-  lay.M1 = (int64_t)R * R;
+  lay.M1 = (int64_t)R * R * R;
   lay.M2 = M / lay.M1;
   const int64_t back_max = 64;
   if (lay.M2 <= back_max) {
@@ -384,35 +396,43 @@ static Layout choose_layout(int64_t L, int dtype, int* embedded) {
   return lay;
 }
 
-// collapse schedule: item u -> (row j, slot); rounds of R items whose
-// slots have distinct residues e1 = slot mod M1, items of one residue in
-// increasing j (fixed summation order)
+// collapse schedule: item u -> (row j, slot).  The residues e1 = slot mod M1
+// are owned by F slices (e1 mod F); each slice runs rounds of G items whose
+// e1 are distinct, items of one residue in increasing j (fixed summation
+// order).  Item u = (round * F + slice) * G + lane.
 static void build_schedule(qmc_plan_s* P, const std::vector<int32_t>& ell,
                            std::vector<int32_t>& it_j, std::vector<int32_t>& it_slot,
                            std::vector<int32_t>& it_e1) {
   const int64_t L = P->L, M1 = P->lay.M1;
   const int R = P->lay.R;
+  const int Q = R * R;
+  const int G = Q < 64 ? Q : 64;
+  const int F = Q / G;
   std::vector<int64_t> next_round(M1, 0);
-  std::vector<int32_t> fill;  // items placed per round
+  std::vector<std::vector<int32_t>> fill(F);  // items placed per (slice, round)
   std::vector<std::pair<int64_t, int64_t>> place(P->s);
   for (int64_t j = 0; j < P->s; ++j) {
     const int64_t slot = (L - ell[j]) % L;
     const int64_t e1 = slot & (M1 - 1);
+    const int f = (int)(e1 % F);
+    std::vector<int32_t>& fl = fill[f];
     int64_t r = next_round[e1];
-    while (r < (int64_t)fill.size() && fill[r] >= R) ++r;
-    if (r >= (int64_t)fill.size()) fill.resize(r + 1, 0);
-    place[j] = {r, fill[r]};
-    fill[r]++;
+    while (r < (int64_t)fl.size() && fl[r] >= G) ++r;
+    if (r >= (int64_t)fl.size()) fl.resize(r + 1, 0);
+    place[j] = {r, (int64_t)f * G + fl[r]};
+    fl[r]++;
     next_round[e1] = r + 1;
   }
-  const int64_t rounds = (int64_t)fill.size();
+  int64_t rounds = 1;
+  for (int f = 0; f < F; ++f) rounds = std::max(rounds, (int64_t)fill[f].size());
   P->rounds = rounds;
-  P->Upad = rounds * R;
+  P->Upad = rounds * Q;
   it_j.assign(P->Upad, -1);
   it_slot.assign(P->Upad, -1);
   it_e1.assign(P->Upad, (int32_t)M1);
   for (int64_t j = 0; j < P->s; ++j) {
-    const int64_t u = place[j].first * R + place[j].second;
+    const int64_t f = place[j].second / G, lane = place[j].second % G;
+    const int64_t u = (place[j].first * F + f) * G + lane;
     const int64_t slot = (L - ell[j]) % L;
     it_j[u] = (int32_t)j;
     it_slot[u] = (int32_t)slot;
@@ -428,22 +448,25 @@ static int build_spectral_tables(qmc_plan_s* P, const cx<double>* dW, const cx<d
   const int R = lay.R;
   const int64_t M = lay.M, M1 = lay.M1, M2 = lay.M2;
   cx<T>* Hs = dev_alloc<cx<T>>(P, M, &err);
-  cx<T>* twf = dev_alloc<cx<T>>(P, (size_t)R * R, &err);
-  cx<T>* twi = dev_alloc<cx<T>>(P, M, &err);
+  cx<T>* twf1 = dev_alloc<cx<T>>(P, (size_t)R * R * R, &err);
+  cx<T>* twf2 = dev_alloc<cx<T>>(P, (size_t)R * R, &err);
+  cx<T>* twi3 = dev_alloc<cx<T>>(P, M, &err);
   cx<T>* two = dev_alloc<cx<T>>(P, M2 * R, &err);
   cx<T>* twit = dev_alloc<cx<T>>(P, M2 * P->Upad, &err);
   cx<T>* twb = dev_alloc<cx<T>>(P, (size_t)lay.P2 * lay.Q2, &err);
   if (err != QMC_OK) return err;
   k_spectrum_layout<T><<<nblk(M), 256, 0, st>>>(Hs, dH, M, M1, M2);
-  k_tw_fwd_inner<T><<<nblk(R * R), 256, 0, st>>>(twf, dW, R, M, M2);
-  k_tw_inv_comb<T><<<nblk(M), 256, 0, st>>>(twi, dW, R, M, M2);
+  k_tw_f1<T><<<nblk(R * R * R), 256, 0, st>>>(twf1, dW, R, M, M2);
+  k_tw_f2<T><<<nblk(R * R), 256, 0, st>>>(twf2, dW, R, M);
+  k_tw_i3<T><<<nblk(M), 256, 0, st>>>(twi3, dW, R, M, M2);
   k_tw_outer<T><<<nblk(M2 * R), 256, 0, st>>>(two, dW, R, M, M2);
   k_tw_items<T><<<nblk(M2 * P->Upad), 256, 0, st>>>(twit, dW, dslot, P->Upad, M, M2);
   k_tw_back<T><<<nblk((int64_t)lay.P2 * lay.Q2), 256, 0, st>>>(twb, dW, lay.P2, lay.Q2, M, M2);
   QMC_HIP(hipGetLastError());
   P->d_Hs = Hs;
-  P->d_twf = twf;
-  P->d_twi = twi;
+  P->d_twf1 = twf1;
+  P->d_twf2 = twf2;
+  P->d_twi3 = twi3;
   P->d_two = two;
   P->d_twit = twit;
   P->d_twb = twb;
