@@ -46,7 +46,8 @@ def kernel_model(plan_info, pairs, t, w, N, s):
     5 n log2 n per complex DFT of length n, 6 per complex product, 8 per
     complex multiply-add of the sparse outer DFT."""
     M, M1, M2 = plan_info["M"], plan_info["M1"], plan_info["M2"]
-    U = plan_info["rounds"] * int(round(math.sqrt(M1)))
+    R = int(round(M1 ** (1.0 / 3.0)))
+    U = plan_info["rounds"] * R * R  # scheduled items (s plus padding)
     el = 2 * w
     lg = lambda n: math.log2(n) if n > 1 else 0.0
     out = {
@@ -129,6 +130,9 @@ def main():
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--fft-only", action="store_true",
                     help="time only the FFT path (for profiler runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 3 times (reference "
+                         "for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the columns of A "
@@ -136,6 +140,16 @@ def main():
         sys.exit(2)
     if args.fft_only:
         args.no_dense = args.no_cpu = args.no_f64 = True
+    if args.copy_calibration:
+        import torch
+        n = 1 << 28  # 2^28 float32 = 1 GiB
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 3}))
+        return
 
     import numpy as np
     import torch

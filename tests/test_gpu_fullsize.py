@@ -1,0 +1,133 @@
+"""Parity at the full benchmark sizes, in the configuration bench.py times.
+
+The oracle cannot form these products whole, so it computes sampled rows of
+X (and sampled entries of dA) one by one; properties that hold at any size
+(column sums, the adjoint identity, finite differences of a linear map) are
+checked on the whole output.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import qmc_inputs as qi
+from gpu_helpers import TOL, announce, assert_close, plan_of, to_dev, torch_cuda, ymax
+
+pytestmark = pytest.mark.gpu
+
+
+def sample_rows(N, k, seed):
+    rg = np.random.default_rng(seed)
+    rows = set(rg.choice(N, size=k, replace=False).tolist())
+    rows |= {0, 1, N - 1}
+    return np.array(sorted(rows))
+
+
+def _forward_sampled(inst, dtype, nrows=48):
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    p = plan_of(inst)
+    A = to_dev(inst.A, dtype)
+    X = q.matmul(p, A)
+    rows = sample_rows(inst.N, nrows, inst.N + inst.s)
+    got = X[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+    ref = oracle.matmul_rows(inst, rows)
+    worst = assert_close(got, ref, inst.A, inst, dtype, inst.name)
+    # column sums: sum_n Y[n, j] = S_phi for every j (each column runs through
+    # all one-dimensional points once), so 1^T X = S_phi 1^T A
+    T = oracle.phi_residue_values(inst.rule, inst.N, inst.phi, inst.modulus, inst.shift)
+    S = float(np.sum(T))
+    colsum = X.double().sum(dim=0).cpu().numpy()
+    bound = S * inst.A.sum(axis=0)
+    scale = ymax(inst) * np.abs(inst.A).sum(axis=0) * math.sqrt(inst.N)
+    assert np.max(np.abs(colsum - bound) / scale) < (1e-10 if dtype == "f64" else 1e-5)
+    return p, A, X, worst
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_c2_gaussian_full(dtype):
+    inst = qi.make_c2(dtype)
+    announce(f"C2 full size {dtype}")
+    _forward_sampled(inst, dtype)
+
+
+def test_c2_matches_dense_baseline():
+    """FFT path and dense MFMA GEMM agree on the whole C2 output (FP32)."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    inst = qi.make_c2("f32")
+    announce("C2 FFT vs dense")
+    p = plan_of(inst)
+    A = to_dev(inst.A, "f32")
+    X = q.matmul(p, A)
+    Y = q.explicit_points(p)
+    Xd = q.dense_matmul(p, Y, A)
+    scale = float(Y.abs().max()) * A.abs().sum(dim=0)
+    err = float(((X - Xd).abs().max(dim=0).values / scale).max())
+    assert err < 2 * TOL["f32"]
+
+
+def test_c3_pde_gf2_full():
+    inst = qi.make_c3("f32")
+    announce("C3 full size (GF(2), m=16, s=16384, t=4096)")
+    _forward_sampled(inst, "f32", nrows=24)
+
+
+def test_c5_forward_adjoint_fd():
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    inst = qi.make_c5("f32")
+    announce("C5 full size forward")
+    p, A, X, _ = _forward_sampled(inst, "f32", nrows=16)
+    info = p.info()
+    assert info["M2"] > 64  # exercises the split outer pass
+    announce("C5 adjoint sampled entries")
+    G = to_dev(inst.G, "f32")
+    dA = q.matmul_adjoint(p, G)
+    ent = qi.fd_entries(inst.s, inst.t)
+    got = np.array([float(dA[j, k]) for j, k in ent])
+    ref = oracle.adjoint_entries(inst, ent)
+    scale = ymax(inst) * np.abs(inst.G).sum(axis=0)
+    err = np.abs(got - ref) / np.array([scale[k] for _, k in ent])
+    assert np.max(err) <= TOL["f32"], np.max(err)
+    announce("C5 finite differences")
+    # L(A) = <X(A), G> is linear in A: a central difference with the step that
+    # is actually representable recovers dA up to the FP32 rounding of X
+    Gd = G.double()
+    for (j, k) in ent[:8]:
+        a0 = float(A[j, k])
+        h = 16.0
+        up = np.float32(a0 + h)
+        dn = np.float32(a0 - h)
+        Ap = A.clone()
+        Ap[j, k] = float(up)
+        Lp = float((q.matmul(p, Ap).double() * Gd).sum())
+        Ap[j, k] = float(dn)
+        Lm = float((q.matmul(p, Ap).double() * Gd).sum())
+        fd = (Lp - Lm) / (float(up) - float(dn))
+        assert abs(fd - float(dA[j, k])) <= 2e-3 * (abs(float(dA[j, k])) + scale[k] * 1e-3), (j, k, fd)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_split_outer_pass_lattice(dtype):
+    """N = 139999 (L = 2 * 69999 not a power of two): M = 2^19, M2 = 128 > 64."""
+    N = 139999
+    assert qi.is_prime(N)
+    inst = qi.small_lattice(N, 300, 5, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype)
+    announce(f"split outer pass N={N} {dtype}")
+    p, A, X, _ = _forward_sampled(inst, dtype, nrows=32)
+    assert p.info()["M2"] == 128
+    import paper_1501_06286_amd as q
+    G = qi.randn((N, inst.t), seed=11, dtype=dtype)
+    dA = q.matmul_adjoint(p, to_dev(G, dtype)).double().cpu().numpy()
+    assert_close(dA, oracle.adjoint(inst, G), G, inst, dtype, "split adjoint")
+
+
+def test_split_outer_pass_gf2():
+    """m = 19: L = 2^19 - 1, embedded in M = 2^20, M2 = 256."""
+    torch_cuda()
+    inst = qi.small_gf2(19, 96, 3, dtype="f64")
+    announce("split outer pass GF(2) m=19")
+    p, A, X, _ = _forward_sampled(inst, "f64", nrows=24)
+    assert p.info()["M2"] == 256
