@@ -128,6 +128,7 @@ def main():
     ap.add_argument("--no-dense", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="use the default launch tuning")
     ap.add_argument("--fft-only", action="store_true",
                     help="time only the FFT path (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -167,6 +168,11 @@ def main():
     log(f"plan: L={info['L']} M={info['M']} M1={info['M1']} M2={info['M2']} rounds={info['rounds']}")
     A = torch.from_numpy(inst.A).to(tdt).to(dev)
     X = torch.empty((N, t), dtype=tdt, device=dev)
+    tuning = plan.get_tuning()
+    if not args.no_tune:
+        from paper_1501_06286_amd import autotune
+        tuning, _ = autotune.tune(plan, t, reps=3)
+        log(f"autotuned launch: {tuning}")
     ws = plan.workspace(t, dev)
     step = lambda: q.matmul(plan, A, out=X, workspace=ws)
     for _ in range(args.warmup):
@@ -217,7 +223,7 @@ def main():
         "config": {"workload": workload, "rule": "rank-1 lattice", "N": N, "s": s, "t": t,
                    "phi": "inverse normal CDF, shift 1/(2N)",
                    "A": "upper Cholesky of exp(-|i-j|/410)", "M": info["M"], "M1": info["M1"],
-                   "M2": info["M2"]},
+                   "M2": info["M2"], "tuning": tuning},
         "hbm_GBps_algorithmic": round(alg_bytes / (elapsed / args.steps) / 1e9, 1),
         "roofline": roof,
         "kernels": kernels,
@@ -226,6 +232,9 @@ def main():
     if not args.no_f64 and args.dtype == "f32":
         inst64 = qi.make_c2("f64", s=args.s)
         p64 = q.Plan.from_instance(inst64)
+        if not args.no_tune:
+            from paper_1501_06286_amd import autotune
+            autotune.tune(p64, t, reps=3)
         A64 = torch.from_numpy(inst64.A).to(dev)
         X64 = torch.empty((N, t), dtype=torch.float64, device=dev)
         ws64 = p64.workspace(t, dev)

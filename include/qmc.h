@@ -129,6 +129,25 @@ int qmc_plan_info(qmc_plan_t plan, qmc_plan_info_t* info);
 int qmc_plan_tables(qmc_plan_t plan, int32_t* pow_out, int32_t* log_out,
                     int32_t* ell_out, double* phi_out);
 
+/*
+ * Launch tuning of a plan (chosen by paper_1501_06286_amd/autotune.py):
+ *   chunk_pairs  column pairs per chunk of the fused and back passes; the
+ *                intermediate spectrum buffer then holds one or two chunks
+ *                instead of all pairs (0 = one chunk of all pairs)
+ *   streams      1, or 2 to run the back pass of chunk c on a second stream,
+ *                overlapping the fused pass of chunk c+1 (needs chunk_pairs > 0)
+ *   nt_store     1 = write X with non-temporal stores
+ * The workspace size depends on the tuning: query it after setting it.
+ * Returns QMC_ERR_ARG for negative chunks or streams outside {1, 2}.
+ */
+typedef struct {
+    int64_t chunk_pairs;
+    int streams;
+    int nt_store;
+} qmc_tuning_t;
+int qmc_plan_set_tuning(qmc_plan_t plan, const qmc_tuning_t* tuning);
+int qmc_plan_get_tuning(qmc_plan_t plan, qmc_tuning_t* tuning);
+
 /* Bytes of device workspace that qmc_matmul / qmc_matmul_adjoint need for t columns. */
 int qmc_workspace_size(qmc_plan_t plan, int64_t t, size_t* bytes);
 

@@ -35,6 +35,7 @@ EXPORTED = [
     "qmc_workspace_size", "qmc_matmul", "qmc_matmul_adjoint", "qmc_explicit_points",
     "qmc_dense_matmul", "qmc_batched_workspace_size", "qmc_matmul_batched", "qmc_strerror",
     "qmc_profile_enable", "qmc_profile_collect", "qmc_profile_slot_name",
+    "qmc_plan_set_tuning", "qmc_plan_get_tuning",
 ]
 PROF_SLOTS = 8
 
@@ -43,6 +44,10 @@ class QMCError(RuntimeError):
     def __init__(self, code: int, where: str):
         super().__init__(f"{where}: {lib().qmc_strerror(code).decode()} (code {code})")
         self.code = code
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("chunk_pairs", ctypes.c_int64), ("streams", ctypes.c_int), ("nt_store", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -84,6 +89,8 @@ def lib() -> ctypes.CDLL:
                                          ctypes.POINTER(i64), ctypes.POINTER(vp), vp, sz, vp]
         L.qmc_strerror.argtypes = [ip]
         L.qmc_strerror.restype = ctypes.c_char_p
+        L.qmc_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.qmc_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.qmc_profile_enable.argtypes = [vp, ip]
         L.qmc_profile_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.qmc_profile_slot_name.argtypes = [ip]
@@ -183,6 +190,16 @@ class Plan:
                                      ph.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
                "qmc_plan_tables")
         return pw, lg, el, ph
+
+    def set_tuning(self, chunk_pairs: int = 0, streams: int = 1, nt_store: int = 0) -> None:
+        """Launch tuning (see autotune.py); changes the workspace size."""
+        tu = Tuning(int(chunk_pairs), int(streams), int(nt_store))
+        _check(lib().qmc_plan_set_tuning(self.handle, ctypes.byref(tu)), "qmc_plan_set_tuning")
+
+    def get_tuning(self) -> dict:
+        tu = Tuning()
+        _check(lib().qmc_plan_get_tuning(self.handle, ctypes.byref(tu)), "qmc_plan_get_tuning")
+        return {"chunk_pairs": tu.chunk_pairs, "streams": tu.streams, "nt_store": tu.nt_store}
 
     def profile(self, on: bool = True) -> None:
         """Bracket every kernel launch of this plan with HIP events."""

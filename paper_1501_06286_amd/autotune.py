@@ -1,0 +1,99 @@
+"""Launch-configuration autotuner.
+
+For a plan and a column count t it times the candidate launch tunings of
+``qmc_plan_set_tuning`` (chunk of column pairs per fused/back pass, one or two
+streams, plain or non-temporal stores of X) on the GPU with HIP events, keeps
+the fastest, and caches the choice in a JSON file keyed by the GPU
+architecture and the plan's shape (rule, L, M, s, t, dtype).
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, List, Optional, Tuple
+
+CACHE = os.environ.get("QMC_AUTOTUNE_CACHE",
+                       os.path.join(os.path.expanduser("~"), ".cache", "qmcfast", "autotune.json"))
+
+
+def candidates(pairs: int) -> List[Dict[str, int]]:
+    chunks = [0] + [c for c in (64, 128, 256, 512, 1024) if c < pairs]
+    out = []
+    for c in chunks:
+        for streams in ((1, 2) if c else (1,)):
+            for nt in (0, 1):
+                out.append({"chunk_pairs": c, "streams": streams, "nt_store": nt})
+    return out
+
+
+def _arch() -> str:
+    import torch
+    try:
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return "unknown"
+
+
+def cache_key(plan, t: int) -> str:
+    i = plan.info()
+    return f"{_arch()}|rule{i['rule']}|L{i['L']}|M{i['M']}|s{i['s']}|t{t}|dtype{i['dtype']}"
+
+
+def _load() -> dict:
+    try:
+        with open(CACHE) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(d: dict) -> None:
+    try:
+        os.makedirs(os.path.dirname(CACHE), exist_ok=True)
+        tmp = CACHE + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(d, f, indent=1, sort_keys=True)
+        os.replace(tmp, CACHE)
+    except OSError:
+        pass
+
+
+def time_config(plan, A, X, cfg: Dict[str, int], reps: int = 3) -> float:
+    """Milliseconds per qmc_matmul with the given tuning (events on the caller's stream)."""
+    import torch
+    import paper_1501_06286_amd as q
+    plan.set_tuning(**cfg)
+    ws = plan.workspace(A.shape[1], A.device)
+    q.matmul(plan, A, out=X, workspace=ws)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        q.matmul(plan, A, out=X, workspace=ws)
+    e1.record()
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def tune(plan, t: int, reps: int = 3, use_cache: bool = True,
+         cands: Optional[List[Dict[str, int]]] = None) -> Tuple[Dict[str, int], List]:
+    """Pick and set the fastest tuning for (plan, t).  Returns (best, timings)."""
+    import torch
+    key = cache_key(plan, t)
+    cache = _load() if use_cache else {}
+    if use_cache and key in cache:
+        best = cache[key]["best"]
+        plan.set_tuning(**best)
+        return best, cache[key].get("timings", [])
+    A = torch.randn((plan.s, t), dtype=plan.torch_dtype, device="cuda")
+    X = torch.empty((plan.N, t), dtype=plan.torch_dtype, device="cuda")
+    results = []
+    for cfg in (cands or candidates((t + 1) // 2)):
+        results.append((cfg, time_config(plan, A, X, cfg, reps)))
+    best = min(results, key=lambda r: r[1])[0]
+    plan.set_tuning(**best)
+    if use_cache:
+        cache = _load()
+        cache[key] = {"best": best, "timings": [[c, round(ms, 4)] for c, ms in results]}
+        _store(cache)
+    return best, results

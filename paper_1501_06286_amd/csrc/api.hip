@@ -101,6 +101,12 @@ static void prof_clear(qmc_plan_t P) {
 void qmc_plan_destroy(qmc_plan_t plan) {
   if (!plan) return;
   prof_clear(plan);
+  if (plan->side) {
+    hipStreamSynchronize(plan->side);
+    hipStreamDestroy(plan->side);
+  }
+  for (hipEvent_t e : plan->ev)
+    if (e) hipEventDestroy(e);
   for (void* p : plan->owned) hipFree(p);
   delete plan;
 }
@@ -136,6 +142,21 @@ const char* qmc_profile_slot_name(int slot) {
   static const char* names[PROF_NSLOTS] = {"collapse_T", "middle", "outer_split", "back",
                                            "adj_front", "adj_split", "adj_middle", "adj_back"};
   return (slot >= 0 && slot < PROF_NSLOTS) ? names[slot] : "";
+}
+
+int qmc_plan_set_tuning(qmc_plan_t P, const qmc_tuning_t* tu) {
+  if (!P || !tu) return QMC_ERR_ARG;
+  if (tu->chunk_pairs < 0 || (tu->streams != 1 && tu->streams != 2) ||
+      (tu->nt_store != 0 && tu->nt_store != 1))
+    return QMC_ERR_ARG;
+  P->tune = *tu;
+  return QMC_OK;
+}
+
+int qmc_plan_get_tuning(qmc_plan_t P, qmc_tuning_t* tu) {
+  if (!P || !tu) return QMC_ERR_ARG;
+  *tu = P->tune;
+  return QMC_OK;
 }
 
 int qmc_plan_info(qmc_plan_t P, qmc_plan_info_t* info) {

@@ -22,6 +22,8 @@
 //   B  for a tile of (e1, pairs): the inverse DFT over w2 and the row
 //      un-permutation X[pow[e]] (or, for the adjoint, the read-back at the
 //      exponents l_j).
+#include <algorithm>
+
 #include "cx.hpp"
 #include "internal.hpp"
 
@@ -279,7 +281,7 @@ __global__ __launch_bounds__(64) void k_outer_split(cx<T>* __restrict__ C, int64
 //   forward: X[pow[e]][2 pair .. 2 pair + 1] = out[e] for e < L
 //   adjoint: dA[j][...] = out[e] + phi0 G[0][...] for every j with l_j = e
 // ---------------------------------------------------------------------------
-template <typename T, int Q, bool ADJ>
+template <typename T, int Q, bool ADJ, bool NT>
 __global__ __launch_bounds__(256) void k_back(const cx<T>* __restrict__ C, int64_t M1, int64_t M2,
                                               int64_t P2, int64_t L, int64_t P,
                                               const int32_t* __restrict__ rowmap,
@@ -320,8 +322,13 @@ __global__ __launch_bounds__(256) void k_back(const cx<T>* __restrict__ C, int64
             const int64_t col = 2 * pairw;
             if constexpr (!ADJ) {
               T* row = X + (int64_t)rowmap[e] * ldx;
-              row[col] = o.x;
-              if (col + 1 < t) row[col + 1] = o.y;
+              if constexpr (NT) {
+                __builtin_nontemporal_store(o.x, row + col);
+                if (col + 1 < t) __builtin_nontemporal_store(o.y, row + col + 1);
+              } else {
+                row[col] = o.x;
+                if (col + 1 < t) row[col + 1] = o.y;
+              }
             } else {
               const T g0 = phi0 * G0[col];
               const T g1 = (col + 1 < t) ? phi0 * G0[col + 1] : (T)0;
@@ -399,11 +406,21 @@ __global__ __launch_bounds__(256) void k_adj_front(const T* __restrict__ G, int6
 // ---------------------------------------------------------------------------
 static inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
+// pairs of the forward pass whose spectra are resident in the workspace at once
+static int64_t fwd_c_pairs(const qmc_plan_s* P, int64_t pairs) {
+  const int64_t ch = P->tune.chunk_pairs;
+  if (ch <= 0 || ch >= pairs) return pairs;
+  const int64_t slots = P->tune.streams == 2 ? 2 : 1;
+  return std::min(pairs, ch * slots);
+}
+
 size_t workspace_bytes(const qmc_plan_s* P, int64_t t) {
   const size_t el = (P->dtype == QMC_F32) ? sizeof(cx<float>) : sizeof(cx<double>);
   const int64_t pairs = (t + 1) / 2;
-  return align256(pairs * P->Upad * el) + align256(pairs * P->lay.M * el) +
-         align256(pairs * P->lay.M * el);
+  const size_t aT = align256(pairs * P->Upad * el);
+  const size_t fwd = aT + align256(fwd_c_pairs(P, pairs) * P->lay.M * el);
+  const size_t adj = aT + 2 * align256(pairs * P->lay.M * el);
+  return std::max(fwd, adj);
 }
 
 template <typename T, int R, bool SPARSE>
@@ -453,7 +470,7 @@ static int launch_split(const qmc_plan_s* P, cx<T>* C, int64_t pairs, hipStream_
   return hip_ok(hipGetLastError());
 }
 
-template <typename T, bool ADJ>
+template <typename T, bool ADJ, bool NT = false>
 static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const int32_t* inv_ptr,
                        const int32_t* inv_j, const T* G0, T* X, int64_t ldx, int64_t t,
                        hipStream_t st) {
@@ -461,7 +478,7 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
   dim3 grid((unsigned)((lay.M1 + 15) / 16), (unsigned)((pairs + 15) / 16), (unsigned)lay.P2);
   ProfScope ps(P, ADJ ? PROF_ADJ_BACK : PROF_BACK, st);
 #define QMC_BACK(QQ)                                                                          \
-  k_back<T, QQ, ADJ><<<grid, 256, 0, st>>>(C, lay.M1, lay.M2, lay.P2, P->L, pairs, P->d_pow, \
+  k_back<T, QQ, ADJ, NT><<<grid, 256, 0, st>>>(C, lay.M1, lay.M2, lay.P2, P->L, pairs, P->d_pow, \
                                            inv_ptr, inv_j, G0, (T)P->phi0, X, ldx, t)
   switch (lay.Q2) {
     case 1: QMC_BACK(1); break;
@@ -477,13 +494,33 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
   return hip_ok(hipGetLastError());
 }
 
+static int ensure_side_stream(const qmc_plan_s* P) {
+  if (!P->side && hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking) != hipSuccess)
+    return QMC_ERR_HIP;
+  for (hipEvent_t& e : P->ev)
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return QMC_ERR_HIP;
+  return QMC_OK;
+}
+
+template <typename T>
+static int back_dispatch(const qmc_plan_s* P, const cx<T>* C, int64_t np, T* X, int64_t ldx,
+                         int64_t t, hipStream_t st) {
+  if (P->tune.nt_store)
+    return launch_back<T, false, true>(P, C, np, nullptr, nullptr, nullptr, X, ldx, t, st);
+  return launch_back<T, false, false>(P, C, np, nullptr, nullptr, nullptr, X, ldx, t, st);
+}
+
+// X = Y A: collapse-transpose once, then the fused and back passes per chunk
+// of column pairs.  With two streams the back pass of chunk c runs on the
+// plan's side stream while the caller's stream starts chunk c+1; the two
+// spectrum slots alternate and are released by events.
 template <typename T>
 static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T* X, int64_t ldx,
                      void* ws, hipStream_t st) {
   const int64_t pairs = (t + 1) / 2;
   const size_t el = sizeof(cx<T>);
   cx<T>* aT = (cx<T>*)ws;
-  cx<T>* C = (cx<T>*)((char*)ws + align256(pairs * P->Upad * el));
+  cx<T>* Cbase = (cx<T>*)((char*)ws + align256(pairs * P->Upad * el));
   dim3 gT((unsigned)((P->Upad + 63) / 64), (unsigned)((pairs + 15) / 16));
   {
     ProfScope ps(P, PROF_COLLAPSE, st);
@@ -491,11 +528,44 @@ static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T*
   }
   int rc = hip_ok(hipGetLastError());
   if (rc != QMC_OK) return rc;
-  rc = launch_middle<T, true>(P, aT, pairs, C, X, t, st);
-  if (rc != QMC_OK) return rc;
-  rc = launch_split<T, +1>(P, C, pairs, st);
-  if (rc != QMC_OK) return rc;
-  return launch_back<T, false>(P, C, pairs, nullptr, nullptr, nullptr, X, ldx, t, st);
+  const int64_t chunk = (P->tune.chunk_pairs > 0 && P->tune.chunk_pairs < pairs)
+                            ? P->tune.chunk_pairs : pairs;
+  const bool two = P->tune.streams == 2 && chunk < pairs;
+  hipStream_t sb = st;
+  if (two) {
+    if ((rc = ensure_side_stream(P)) != QMC_OK) return rc;
+    sb = P->side;
+    // fork: the side stream starts after everything already on st
+    if ((rc = hip_ok(hipEventRecord(P->ev[4], st))) != QMC_OK) return rc;
+    if ((rc = hip_ok(hipStreamWaitEvent(sb, P->ev[4], 0))) != QMC_OK) return rc;
+  }
+  int64_t c = 0;
+  for (int64_t p0 = 0; p0 < pairs; p0 += chunk, ++c) {
+    const int64_t np = std::min(chunk, pairs - p0);
+    const int slot = two ? (int)(c & 1) : 0;
+    cx<T>* C = Cbase + (int64_t)slot * chunk * P->lay.M;
+    if (two && c >= 2) {  // the back pass of chunk c-2 has released this slot
+      if ((rc = hip_ok(hipStreamWaitEvent(st, P->ev[2 + slot], 0))) != QMC_OK) return rc;
+    }
+    rc = launch_middle<T, true>(P, aT + p0 * P->Upad, np, C, X + 2 * p0, t - 2 * p0, st);
+    if (rc != QMC_OK) return rc;
+    rc = launch_split<T, +1>(P, C, np, st);
+    if (rc != QMC_OK) return rc;
+    if (two) {
+      if ((rc = hip_ok(hipEventRecord(P->ev[slot], st))) != QMC_OK) return rc;
+      if ((rc = hip_ok(hipStreamWaitEvent(sb, P->ev[slot], 0))) != QMC_OK) return rc;
+    }
+    rc = back_dispatch<T>(P, C, np, X + 2 * p0, ldx, t - 2 * p0, sb);
+    if (rc != QMC_OK) return rc;
+    if (two) {
+      if ((rc = hip_ok(hipEventRecord(P->ev[2 + slot], sb))) != QMC_OK) return rc;
+    }
+  }
+  if (two) {  // join
+    if ((rc = hip_ok(hipEventRecord(P->ev[5], sb))) != QMC_OK) return rc;
+    if ((rc = hip_ok(hipStreamWaitEvent(st, P->ev[5], 0))) != QMC_OK) return rc;
+  }
+  return QMC_OK;
 }
 
 int launch_forward(const qmc_plan_s* P, const void* A, int64_t t, int64_t lda, void* X,

@@ -1,0 +1,52 @@
+"""Every launch tuning (chunks of column pairs, one or two streams, plain or
+non-temporal stores) gives the same X, to the parity bar, as the oracle."""
+import numpy as np
+import pytest
+
+import oracle
+import qmc_inputs as qi
+from gpu_helpers import announce, assert_close, plan_of, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("chunk,streams,nt", [(0, 1, 1), (5, 1, 0), (5, 2, 0), (7, 2, 1), (16, 2, 0),
+                                              (1, 2, 1)])
+def test_tuned_forward(chunk, streams, nt, dtype):
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    N, s, t = 8209, 400, 33  # 17 column pairs: ragged chunks
+    inst = qi.small_lattice(N, s, t, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype)
+    announce(f"tuning chunk={chunk} streams={streams} nt={nt} {dtype}")
+    p = plan_of(inst)
+    p.set_tuning(chunk_pairs=chunk, streams=streams, nt_store=nt)
+    assert p.get_tuning() == {"chunk_pairs": chunk, "streams": streams, "nt_store": nt}
+    A = to_dev(inst.A, dtype)
+    X1 = q.matmul(p, A)
+    X2 = q.matmul(p, A)  # back-to-back calls reuse the slots and events
+    torch.cuda.synchronize()
+    assert torch.equal(X1, X2)
+    assert_close(X1.double().cpu().numpy(), oracle.matmul(inst), inst.A, inst, dtype, "tuned")
+
+
+def test_tuning_rejects_bad_values():
+    torch_cuda()
+    import paper_1501_06286_amd as q
+    p = plan_of(qi.small_lattice(101, 5, 2))
+    for bad in ({"chunk_pairs": -1}, {"streams": 3}, {"nt_store": 2}):
+        with pytest.raises(q.QMCError):
+            p.set_tuning(**bad)
+
+
+def test_autotune_picks_a_candidate(tmp_path, monkeypatch):
+    torch_cuda()
+    from paper_1501_06286_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "cache.json"))
+    inst = qi.small_lattice(8209, 300, 64, phi=qi.PHI_INVNORM, shift=(1, 2 * 8209), dtype="f32")
+    p = plan_of(inst)
+    best, res = autotune.tune(p, 64, reps=2)
+    assert best in [c for c, _ in res]
+    assert p.get_tuning() == best
+    best2, _ = autotune.tune(p, 64)  # from the cache
+    assert best2 == best
