@@ -194,10 +194,30 @@ int qmc_dense_matmul(qmc_plan_t plan, const void* Y, int64_t ldy, const void* A,
                      int64_t t, int64_t lda, void* X, int64_t ldx, void* stream);
 
 /*
- * qmc_matmul_batched -- X_i = Y_i A_i for `count` plans in one sequence of
- * launches (one launch per pass over all instances).  Plans must share the
- * dtype.  A[i], X[i] device pointers with row strides t[i] (dense rows);
- * workspace at least qmc_batched_workspace_size bytes.
+ * Batched products X_i = Y_i A_i for many plans of uneven size.
+ *
+ * qmc_batch_create binds `count` plans (same dtype) to their device
+ * matrices A[i] (s_i x t[i], row stride lda[i], or t[i] if lda is NULL) and
+ * X[i] (N_i x t[i], ldx[i] or t[i]); it uploads one descriptor per product
+ * and synchronises `stream`.  The plans and buffers must outlive the batch.
+ * qmc_batch_run enqueues one persistent launch per pass over all products
+ * (products with different on-chip transform sizes form separate groups)
+ * and makes no host-to-device copies, so it can be captured in a HIP graph
+ * and replayed.  Workspace: qmc_batch_workspace_size bytes, caller-owned.
+ * Errors: QMC_ERR_ARG (bad arguments or mixed dtypes), QMC_ERR_WORKSPACE.
+ */
+typedef struct qmc_batch_s* qmc_batch_t;
+int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const int64_t* t,
+                     const void* const* A, const int64_t* lda, void* const* X,
+                     const int64_t* ldx, void* stream);
+int qmc_batch_workspace_size(qmc_batch_t batch, size_t* bytes);
+int qmc_batch_run(qmc_batch_t batch, void* workspace, size_t workspace_bytes, void* stream);
+void qmc_batch_destroy(qmc_batch_t batch);
+
+/*
+ * qmc_matmul_batched -- one-shot form: create a batch over dense row-major
+ * A[i], X[i] (row stride t[i]), run it, synchronise `stream` and release the
+ * batch.  Workspace: qmc_batched_workspace_size bytes.
  */
 int qmc_batched_workspace_size(int count, const qmc_plan_t* plans, const int64_t* t,
                                size_t* bytes);

@@ -36,6 +36,7 @@ EXPORTED = [
     "qmc_dense_matmul", "qmc_batched_workspace_size", "qmc_matmul_batched", "qmc_strerror",
     "qmc_profile_enable", "qmc_profile_collect", "qmc_profile_slot_name",
     "qmc_plan_set_tuning", "qmc_plan_get_tuning",
+    "qmc_batch_create", "qmc_batch_workspace_size", "qmc_batch_run", "qmc_batch_destroy",
 ]
 PROF_SLOTS = 8
 
@@ -89,6 +90,14 @@ def lib() -> ctypes.CDLL:
                                          ctypes.POINTER(i64), ctypes.POINTER(vp), vp, sz, vp]
         L.qmc_strerror.argtypes = [ip]
         L.qmc_strerror.restype = ctypes.c_char_p
+        L.qmc_batch_create.argtypes = [ctypes.POINTER(vp), ip, ctypes.POINTER(vp),
+                                       ctypes.POINTER(i64), ctypes.POINTER(vp),
+                                       ctypes.POINTER(i64), ctypes.POINTER(vp),
+                                       ctypes.POINTER(i64), vp]
+        L.qmc_batch_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
+        L.qmc_batch_run.argtypes = [vp, vp, sz, vp]
+        L.qmc_batch_destroy.argtypes = [vp]
+        L.qmc_batch_destroy.restype = None
         L.qmc_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.qmc_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.qmc_profile_enable.argtypes = [vp, ip]
@@ -96,7 +105,8 @@ def lib() -> ctypes.CDLL:
         L.qmc_profile_slot_name.argtypes = [ip]
         L.qmc_profile_slot_name.restype = ctypes.c_char_p
         for name in EXPORTED:
-            if name not in ("qmc_plan_destroy", "qmc_strerror", "qmc_profile_slot_name"):
+            if name not in ("qmc_plan_destroy", "qmc_strerror", "qmc_profile_slot_name",
+                            "qmc_batch_destroy"):
                 getattr(L, name).restype = ip
         _LIB = L
     return _LIB
@@ -325,6 +335,57 @@ def matmul_batched(plans: Sequence[Plan], As: Sequence, outs: Optional[Sequence]
     _check(lib().qmc_matmul_batched(n, hs, ap, tt, xp, ctypes.c_void_p(ws.data_ptr()),
                                     ws.numel(), _stream_handle(stream)), "qmc_matmul_batched")
     return Xs
+
+
+class Batch:
+    """Many products X_i = Y_i A_i bound once; run() is one persistent launch
+    per pass over all of them and can be captured in a graph
+    (torch.cuda.graph) and replayed.  The plans and tensors must stay alive."""
+
+    def __init__(self, plans: Sequence[Plan], As: Sequence, Xs: Optional[Sequence] = None,
+                 stream=None):
+        torch = _torch()
+        self.plans = list(plans)
+        self.As = list(As)
+        if Xs is None:
+            Xs = [torch.empty((p.N, A.shape[1]), dtype=A.dtype, device=A.device)
+                  for p, A in zip(self.plans, self.As)]
+        self.Xs = list(Xs)
+        n = len(self.plans)
+        for i, (p, A, X) in enumerate(zip(self.plans, self.As, self.Xs)):
+            _check_tensor(A, p, p.s, f"A[{i}]")
+            _check_tensor(X, p, p.N, f"X[{i}]")
+            if X.shape[1] != A.shape[1]:
+                raise ValueError(f"X[{i}] and A[{i}] column counts differ")
+        hs = (ctypes.c_void_p * n)(*[p.handle.value for p in self.plans])
+        tt = (ctypes.c_int64 * n)(*[A.shape[1] for A in self.As])
+        ap = (ctypes.c_void_p * n)(*[A.data_ptr() for A in self.As])
+        la = (ctypes.c_int64 * n)(*[A.stride(0) for A in self.As])
+        xp = (ctypes.c_void_p * n)(*[X.data_ptr() for X in self.Xs])
+        lx = (ctypes.c_int64 * n)(*[X.stride(0) for X in self.Xs])
+        h = ctypes.c_void_p()
+        _check(lib().qmc_batch_create(ctypes.byref(h), n, hs, tt, ap, la, xp, lx,
+                                      _stream_handle(stream)), "qmc_batch_create")
+        self._h = h
+        nb = ctypes.c_size_t()
+        _check(lib().qmc_batch_workspace_size(h, ctypes.byref(nb)), "qmc_batch_workspace_size")
+        self.workspace = torch.empty(max(1, nb.value), dtype=torch.uint8, device="cuda")
+
+    def run(self, stream=None) -> List:
+        _check(lib().qmc_batch_run(self._h, ctypes.c_void_p(self.workspace.data_ptr()),
+                                   self.workspace.numel(), _stream_handle(stream)), "qmc_batch_run")
+        return self.Xs
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            lib().qmc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _autograd():

@@ -8,7 +8,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["tables.hip", "conv.hip", "dense.hip", "api.hip"]
+SOURCES = ["tables.hip", "conv.hip", "batch.hip", "dense.hip", "api.hip"]
 LIB = os.path.join(HERE, "libqmcfast.so")
 ARCH = "gfx950"
 
@@ -27,7 +27,7 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False) -> str:
     """Compile every source to an object in parallel, then link the shared library."""
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
@@ -41,12 +41,6 @@ def build(verbose: bool = False, jobs: int = 4) -> str:
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
-        while len([p for _, p in procs if p.poll() is None]) >= jobs:
-            procs[0][1].wait() if procs[0][1].poll() is None else None
-            for _, p in procs:
-                if p.poll() is None:
-                    p.wait()
-                    break
     failed = []
     for src, p in procs:
         out, _ = p.communicate()

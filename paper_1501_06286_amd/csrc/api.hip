@@ -245,7 +245,10 @@ int qmc_batched_workspace_size(int count, const qmc_plan_t* plans, const int64_t
   size_t total = 0;
   for (int i = 0; i < count; ++i) {
     if (!plans[i] || t[i] < 1) return QMC_ERR_ARG;
-    total += (workspace_bytes(plans[i], t[i]) + 255) & ~size_t(255);
+    const size_t el = plans[i]->dtype == QMC_F32 ? 8 : 16;
+    const int64_t pairs = (t[i] + 1) / 2;
+    total += ((pairs * plans[i]->Upad * el + 255) & ~size_t(255)) +
+             ((pairs * plans[i]->lay.M * el + 255) & ~size_t(255));
   }
   *bytes = total;
   return QMC_OK;
@@ -253,22 +256,13 @@ int qmc_batched_workspace_size(int count, const qmc_plan_t* plans, const int64_t
 
 int qmc_matmul_batched(int count, const qmc_plan_t* plans, const void* const* A, const int64_t* t,
                        void* const* X, void* workspace, size_t workspace_bytes_, void* stream) {
-  if (count < 1 || !plans || !A || !t || !X) return QMC_ERR_ARG;
-  size_t need = 0;
-  int rc = qmc_batched_workspace_size(count, plans, t, &need);
+  qmc_batch_t B = nullptr;
+  int rc = qmc_batch_create(&B, count, plans, t, A, nullptr, X, nullptr, stream);
   if (rc != QMC_OK) return rc;
-  if (!workspace || workspace_bytes_ < need) return QMC_ERR_WORKSPACE;
-  const int dtype = plans[0]->dtype;
-  for (int i = 0; i < count; ++i)
-    if (plans[i]->dtype != dtype || !A[i] || !X[i]) return QMC_ERR_ARG;
-  size_t off = 0;
-  for (int i = 0; i < count; ++i) {
-    void* ws = (char*)workspace + off;
-    rc = launch_forward(plans[i], A[i], t[i], t[i], X[i], t[i], ws, (hipStream_t)stream);
-    if (rc != QMC_OK) return rc;
-    off += (workspace_bytes(plans[i], t[i]) + 255) & ~size_t(255);
-  }
-  return QMC_OK;
+  rc = qmc_batch_run(B, workspace, workspace_bytes_, stream);
+  if (rc == QMC_OK) rc = hip_ok(hipStreamSynchronize((hipStream_t)stream));
+  qmc_batch_destroy(B);
+  return rc;
 }
 
 }  // extern "C"

@@ -1,0 +1,320 @@
+// Batched products X_i = Y_i A_i for many plans of uneven size.
+//
+// A batch binds the plans and their A_i, X_i once and uploads one descriptor
+// per product.  A run is one persistent launch per pass over all products
+// (collapse-transpose, fused middle, outer split where needed, back); every
+// workgroup loops over logical blocks, finds its product by binary search in
+// the descriptors' block offsets, and runs the same device bodies as a single
+// product.  A run makes no host-to-device copies, so it can be captured in a
+// HIP graph and replayed.  Products are grouped by the on-chip transform size
+// R (one set of launches per group).
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "kernels.hpp"
+
+namespace qmc {
+
+enum { PASS_COLLAPSE = 0, PASS_MIDDLE = 1, PASS_SPLIT = 2, PASS_BACK = 3, NPASS = 4 };
+
+struct BatchInst {
+  const void* A;
+  void* X;
+  int64_t lda, ldx, t, pairs;
+  int64_t aT_off, C_off;  // byte offsets into the run's workspace
+  const int32_t* it_j;
+  const int32_t* it_e1;
+  const int32_t* pow;
+  const void* twit;
+  const void* twf1;
+  const void* twf2;
+  const void* Hs;
+  const void* twi3;
+  const void* two;
+  const void* twb;
+  int64_t Upad, rounds, M1, M2, P2, Q2, L;
+  double phi0;
+  int64_t off[NPASS];  // first logical block of this product in each pass
+  int64_t nb[NPASS];   // logical blocks of this product in each pass
+  int64_t gx_collapse, gx_split, gx_back, gy_back;
+};
+
+// largest i with D[i].off[pass] <= b (the product owning logical block b)
+__device__ __forceinline__ int find_inst(const BatchInst* __restrict__ D, int n, int pass,
+                                         int64_t b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (D[mid].off[pass] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);  // uniform: descriptor loads stay scalar
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_collapse(const BatchInst* __restrict__ D, int n,
+                                                   int64_t total, char* __restrict__ ws) {
+  __shared__ CollapseSmem<T> S;
+  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    const BatchInst I = D[find_inst(D, n, PASS_COLLAPSE, b)];
+    const int64_t lb = b - I.off[PASS_COLLAPSE];
+    collapse_body<T>((const T*)I.A, I.lda, I.t, I.pairs, I.it_j, I.Upad,
+                     (cx<T>*)(ws + I.aT_off), lb % I.gx_collapse, lb / I.gx_collapse, S,
+                     opaque_tid());
+    __syncthreads();
+  }
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(MidShape<R>::BLOCK) void kb_middle(const BatchInst* __restrict__ D,
+                                                                int n, int64_t total,
+                                                                char* __restrict__ ws) {
+  __shared__ MidSmem<T, R> S;
+  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    const BatchInst I = D[find_inst(D, n, PASS_MIDDLE, b)];
+    const int64_t lb = b - I.off[PASS_MIDDLE];
+    middle_body<T, R, true>((const cx<T>*)(ws + I.aT_off), I.Upad, I.rounds, I.it_e1,
+                            (const cx<T>*)I.twit, (const cx<T>*)I.twf1, (const cx<T>*)I.twf2,
+                            (const cx<T>*)I.Hs, (const cx<T>*)I.twi3, (const cx<T>*)I.two, I.M2,
+                            I.pairs, (cx<T>*)(ws + I.C_off), (T*)I.X, I.t, (T)I.phi0, lb, S,
+                            opaque_tid());
+    __syncthreads();
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(64) void kb_split(const BatchInst* __restrict__ D, int n,
+                                               int64_t total, char* __restrict__ ws) {
+  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    const BatchInst I = D[find_inst(D, n, PASS_SPLIT, b)];
+    const int64_t lb = b - I.off[PASS_SPLIT];
+    const int64_t bx = lb % I.gx_split, rest = lb / I.gx_split;
+    const int64_t q = rest % I.Q2, pair = rest / I.Q2;
+    cx<T>* C = (cx<T>*)(ws + I.C_off);
+    const cx<T>* twb = (const cx<T>*)I.twb;
+    const int tid = opaque_tid();
+    switch (I.P2) {
+      case 2: split_body<T, 2, +1>(C, I.M1, I.M2, (int)I.Q2, twb, bx, q, pair, tid); break;
+      case 4: split_body<T, 4, +1>(C, I.M1, I.M2, (int)I.Q2, twb, bx, q, pair, tid); break;
+      case 8: split_body<T, 8, +1>(C, I.M1, I.M2, (int)I.Q2, twb, bx, q, pair, tid); break;
+      case 16: split_body<T, 16, +1>(C, I.M1, I.M2, (int)I.Q2, twb, bx, q, pair, tid); break;
+      case 32: split_body<T, 32, +1>(C, I.M1, I.M2, (int)I.Q2, twb, bx, q, pair, tid); break;
+      case 64: split_body<T, 64, +1>(C, I.M1, I.M2, (int)I.Q2, twb, bx, q, pair, tid); break;
+      default: break;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void kb_back(const BatchInst* __restrict__ D, int n,
+                                               int64_t total, char* __restrict__ ws) {
+  __shared__ BackSmem<T> S;
+  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    const BatchInst I = D[find_inst(D, n, PASS_BACK, b)];
+    const int64_t lb = b - I.off[PASS_BACK];
+    const int64_t bx = lb % I.gx_back, rest = lb / I.gx_back;
+    const int64_t by = rest % I.gy_back, a = rest / I.gy_back;
+    const cx<T>* C = (const cx<T>*)(ws + I.C_off);
+    const int tid = opaque_tid();
+#define QMC_BB(QQ)                                                                              \
+  back_body<T, QQ, false, false>(C, I.M1, I.M2, I.P2, I.L, I.pairs, I.pow, nullptr, nullptr,   \
+                                 nullptr, (T)I.phi0, (T*)I.X, I.ldx, I.t, bx, by, a, S, tid)
+    switch (I.Q2) {
+      case 1: QMC_BB(1); break;
+      case 2: QMC_BB(2); break;
+      case 4: QMC_BB(4); break;
+      case 8: QMC_BB(8); break;
+      case 16: QMC_BB(16); break;
+      case 32: QMC_BB(32); break;
+      case 64: QMC_BB(64); break;
+      default: break;
+    }
+#undef QMC_BB
+    __syncthreads();
+  }
+}
+
+}  // namespace qmc
+
+using namespace qmc;
+
+struct qmc_batch_s {
+  int dtype = QMC_F32;
+  size_t ws_bytes = 0;
+  struct Group {
+    int R = 0;
+    int n = 0;
+    BatchInst* d_desc = nullptr;
+    int64_t total[NPASS] = {0, 0, 0, 0};
+  };
+  std::vector<Group> groups;
+};
+
+static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+extern "C" {
+
+int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const int64_t* t,
+                     const void* const* A, const int64_t* lda, void* const* X,
+                     const int64_t* ldx, void* stream) {
+  if (!out || count < 1 || !plans || !t || !A || !X) return QMC_ERR_ARG;
+  *out = nullptr;
+  const int dtype = plans[0] ? plans[0]->dtype : -1;
+  for (int i = 0; i < count; ++i) {
+    const qmc_plan_s* P = plans[i];
+    if (!P || P->dtype != dtype || t[i] < 1 || !A[i] || !X[i]) return QMC_ERR_ARG;
+    const int64_t la = lda ? lda[i] : t[i], lx = ldx ? ldx[i] : t[i];
+    if (la < t[i] || lx < t[i]) return QMC_ERR_ARG;
+  }
+  qmc_batch_s* B = new (std::nothrow) qmc_batch_s();
+  if (!B) return QMC_ERR_OOM;
+  B->dtype = dtype;
+  const size_t el = dtype == QMC_F32 ? sizeof(cx<float>) : sizeof(cx<double>);
+  std::vector<std::vector<BatchInst>> byR(17);
+  size_t ws = 0;
+  for (int i = 0; i < count; ++i) {
+    const qmc_plan_s* P = plans[i];
+    const Layout& lay = P->lay;
+    BatchInst I{};
+    I.A = A[i];
+    I.X = X[i];
+    I.lda = lda ? lda[i] : t[i];
+    I.ldx = ldx ? ldx[i] : t[i];
+    I.t = t[i];
+    I.pairs = (t[i] + 1) / 2;
+    I.aT_off = (int64_t)ws;
+    ws += al256(I.pairs * P->Upad * el);
+    I.C_off = (int64_t)ws;
+    ws += al256(I.pairs * lay.M * el);
+    I.it_j = P->d_it_j;
+    I.it_e1 = P->d_it_e1;
+    I.pow = P->d_pow;
+    I.twit = P->d_twit;
+    I.twf1 = P->d_twf1;
+    I.twf2 = P->d_twf2;
+    I.Hs = P->d_Hs;
+    I.twi3 = P->d_twi3;
+    I.two = P->d_two;
+    I.twb = P->d_twb;
+    I.Upad = P->Upad;
+    I.rounds = P->rounds;
+    I.M1 = lay.M1;
+    I.M2 = lay.M2;
+    I.P2 = lay.P2;
+    I.Q2 = lay.Q2;
+    I.L = P->L;
+    I.phi0 = P->phi0;
+    const int64_t tpb = (int64_t)(lay.R * lay.R >= 64 ? 1 : 64 / (lay.R * lay.R));
+    I.gx_collapse = (P->Upad + 63) / 64;
+    I.nb[PASS_COLLAPSE] = I.gx_collapse * ((I.pairs + 15) / 16);
+    I.nb[PASS_MIDDLE] = ((I.pairs + tpb - 1) / tpb) * lay.M2;
+    I.gx_split = (lay.M1 + 63) / 64;
+    I.nb[PASS_SPLIT] = lay.P2 > 1 ? I.gx_split * lay.Q2 * I.pairs : 0;
+    I.gx_back = (lay.M1 + 15) / 16;
+    I.gy_back = (I.pairs + 15) / 16;
+    I.nb[PASS_BACK] = I.gx_back * I.gy_back * lay.P2;
+    byR[lay.R].push_back(I);
+  }
+  B->ws_bytes = ws;
+  hipStream_t st = (hipStream_t)stream;
+  int rc = QMC_OK;
+  for (int R = 1; R <= 16 && rc == QMC_OK; R *= 2) {
+    std::vector<BatchInst>& v = byR[R];
+    if (v.empty()) continue;
+    qmc_batch_s::Group g;
+    g.R = R;
+    g.n = (int)v.size();
+    for (int p = 0; p < NPASS; ++p) {
+      int64_t off = 0;
+      for (BatchInst& I : v) {
+        I.off[p] = off;
+        off += I.nb[p];
+      }
+      g.total[p] = off;
+    }
+    if (hipMalloc(&g.d_desc, v.size() * sizeof(BatchInst)) != hipSuccess) {
+      rc = QMC_ERR_OOM;
+      break;
+    }
+    B->groups.push_back(g);
+    rc = hip_ok(hipMemcpyAsync(g.d_desc, v.data(), v.size() * sizeof(BatchInst),
+                               hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK) rc = hip_ok(hipStreamSynchronize(st));  // v is freed on return
+  }
+  if (rc != QMC_OK) {
+    qmc_batch_destroy(B);
+    return rc;
+  }
+  *out = B;
+  return QMC_OK;
+}
+
+void qmc_batch_destroy(qmc_batch_t B) {
+  if (!B) return;
+  for (auto& g : B->groups)
+    if (g.d_desc) hipFree(g.d_desc);
+  delete B;
+}
+
+int qmc_batch_workspace_size(qmc_batch_t B, size_t* bytes) {
+  if (!B || !bytes) return QMC_ERR_ARG;
+  *bytes = B->ws_bytes;
+  return QMC_OK;
+}
+
+}  // extern "C"
+
+namespace qmc {
+
+static inline unsigned grid_for(int64_t total, int64_t cap) {
+  return (unsigned)std::max<int64_t>(1, std::min(total, cap));
+}
+
+template <typename T, int R>
+static void run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
+  // persistent grids: a few resident workgroups per CU (256 CUs)
+  if (g.total[PASS_COLLAPSE])
+    kb_collapse<T><<<grid_for(g.total[PASS_COLLAPSE], 2048), 256, 0, st>>>(
+        g.d_desc, g.n, g.total[PASS_COLLAPSE], ws);
+  if (g.total[PASS_MIDDLE])
+    kb_middle<T, R><<<grid_for(g.total[PASS_MIDDLE], 1024), MidShape<R>::BLOCK, 0, st>>>(
+        g.d_desc, g.n, g.total[PASS_MIDDLE], ws);
+  if (g.total[PASS_SPLIT])
+    kb_split<T><<<grid_for(g.total[PASS_SPLIT], 4096), 64, 0, st>>>(g.d_desc, g.n,
+                                                                     g.total[PASS_SPLIT], ws);
+  if (g.total[PASS_BACK])
+    kb_back<T><<<grid_for(g.total[PASS_BACK], 1024), 256, 0, st>>>(g.d_desc, g.n,
+                                                                   g.total[PASS_BACK], ws);
+}
+
+template <typename T>
+static int run_group(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
+  switch (g.R) {
+    case 1: run_group_r<T, 1>(g, ws, st); break;
+    case 2: run_group_r<T, 2>(g, ws, st); break;
+    case 4: run_group_r<T, 4>(g, ws, st); break;
+    case 8: run_group_r<T, 8>(g, ws, st); break;
+    case 16: run_group_r<T, 16>(g, ws, st); break;
+    default: return QMC_ERR_UNSUPPORTED;
+  }
+  return hip_ok(hipGetLastError());
+}
+
+}  // namespace qmc
+
+extern "C" {
+
+int qmc_batch_run(qmc_batch_t B, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!B) return QMC_ERR_ARG;
+  if (!workspace || workspace_bytes < B->ws_bytes) return QMC_ERR_WORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  for (const auto& g : B->groups) {
+    const int rc = B->dtype == QMC_F32 ? run_group<float>(g, (char*)workspace, st)
+                                       : run_group<double>(g, (char*)workspace, st);
+    if (rc != QMC_OK) return rc;
+  }
+  return QMC_OK;
+}
+
+}  // extern "C"
