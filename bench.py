@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch tuning")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--fft-only", action="store_true",
                     help="time only the FFT path (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -140,7 +142,7 @@ def main():
               f"shard across GPUs without communication, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
     if args.fft_only:
-        args.no_dense = args.no_cpu = args.no_f64 = True
+        args.no_dense = args.no_cpu = args.no_f64 = args.no_batched = args.no_adjoint = True
     if args.copy_calibration:
         import torch
         n = 1 << 28  # 2^28 float32 = 1 GiB
@@ -180,31 +182,40 @@ def main():
     torch.cuda.synchronize()
     log("warmup done")
 
-    plan.profile(True)
     elapsed = time_steps(step, args.steps, torch)
-    prof = plan.profile_collect()
-    plan.profile(False)
     ms_step = 1e3 * elapsed / args.steps
     value = N * t / (elapsed / args.steps)
     alg_bytes = (s + N) * t * w
     log(f"FFT path {ms_step:.3f} ms/step, {value:.4e} entries/s")
+    # the same timed steps again with HIP events around every kernel launch
+    # (on the stream each kernel is launched on) for the per-kernel roofline
+    plan.profile(True)
+    elapsed_p = time_steps(step, args.steps, torch)
+    prof = plan.profile_collect()
+    plan.profile(False)
+    log(f"instrumented pass {1e3 * elapsed_p / args.steps:.3f} ms/step")
 
     pairs = (t + 1) // 2
-    model = kernel_model(info, pairs, t, w, N, s)
+    model = kernel_model(info, pairs, t, w, N, s)  # per step (all column pairs)
     kernels = {}
     for name, (tot, n) in prof.items():
+        per_step = n / args.steps  # launches of this kernel per step (chunks)
         avg = tot / n
         mdl = model.get(name, {"bytes": 0, "flops": 0})
-        kernels[name] = {"avg_ms": round(avg, 4), "launches": n,
-                         "alg_GBps": round(mdl["bytes"] / (avg * 1e-3) / 1e9, 1),
-                         "alg_TFLOPs": round(mdl["flops"] / (avg * 1e-3) / 1e12, 2)}
+        kernels[name] = {"avg_ms": round(avg, 4), "launches_per_step": per_step,
+                         "ms_per_step": round(tot / args.steps, 4),
+                         "alg_GBps": round(mdl["bytes"] / per_step / (avg * 1e-3) / 1e9, 1),
+                         "alg_TFLOPs": round(mdl["flops"] / per_step / (avg * 1e-3) / 1e12, 2)}
     dom = max(prof, key=lambda k: prof[k][0])
-    dmdl = model[dom]
+    per_launch = prof[dom][1] / args.steps
+    dmdl = {k: v / per_launch for k, v in model[dom].items()}  # one launch = one chunk
     davg_s = prof[dom][0] / prof[dom][1] * 1e-3
     ai = dmdl["flops"] / max(dmdl["bytes"], 1)
     ridge = VALU_PEAK_TFLOPS[args.dtype] * 1e12 / (HBM_PEAK_GBPS * 1e9)
     workload = f"c2_gauss_n{N}_s{s}_t{t}_{args.dtype}"
     traffic = measured_traffic(dom, workload)
+    if traffic is not None:
+        traffic = traffic  # bytes per launch of the same chunking (see profiles/)
     if ai > ridge:
         ach = dmdl["flops"] / davg_s / 1e12
         roof = {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_TFLOPS[args.dtype],
@@ -246,6 +257,45 @@ def main():
                           "hbm_GBps_algorithmic": round((s + N) * t * 8 / (e64 / n64) / 1e9, 1)}
         log(f"FP64 path {1e3 * e64 / n64:.3f} ms/step")
         del A64, X64, ws64, p64
+
+    if not args.no_adjoint:
+        G = torch.randn((N, t), dtype=tdt, device=dev)
+        dA = torch.empty((s, t), dtype=tdt, device=dev)
+        astep = lambda: q.matmul_adjoint(plan, G, out=dA, workspace=ws)
+        astep()
+        na = max(3, args.steps // 2)
+        ea = time_steps(astep, na, torch)
+        result["adjoint"] = {"value": N * t / (ea / na), "unit": "entries/s (N*t per s)",
+                             "ms_per_step": round(1e3 * ea / na, 4)}
+        log(f"adjoint dA = Y^T G {1e3 * ea / na:.3f} ms/step")
+        del G, dA
+
+    if not args.no_batched:
+        insts = qi.make_c4(dtype=args.dtype)
+        bplans = [q.Plan.from_instance(i) for i in insts]
+        bA = [torch.from_numpy(i.A).to(tdt).to(dev) for i in insts]
+        batch = q.Batch(bplans, bA)
+        batch.run()
+        nb = 5
+        eb = time_steps(batch.run, nb, torch)
+        g = torch.cuda.CUDAGraph()
+        sg = torch.cuda.Stream()
+        sg.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(sg):
+            batch.run()
+        torch.cuda.current_stream().wait_stream(sg)
+        with torch.cuda.graph(g):
+            batch.run()
+        eg = time_steps(g.replay, nb, torch)
+        ent = sum(i.N * i.t for i in insts)
+        result["batched"] = {"workload": "256 lattice instances, N primes in [1000, 200000], "
+                                         "s in [256, 8192], t in [1, 64], Phi^-1 1/(2N)",
+                             "entries": ent, "value": ent / (eb / nb),
+                             "ms_per_batch": round(1e3 * eb / nb, 4),
+                             "graph_value": ent / (eg / nb),
+                             "graph_ms_per_batch": round(1e3 * eg / nb, 4)}
+        log(f"batched 256 products: {1e3 * eb / nb:.3f} ms eager, {1e3 * eg / nb:.3f} ms graph")
+        del batch, bA, bplans, g
 
     if not args.no_dense:
         Y = q.explicit_points(plan)

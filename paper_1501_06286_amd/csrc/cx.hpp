@@ -11,8 +11,10 @@
 
 namespace qmc {
 
+// aligned to its full size so loads, stores and LDS accesses move both
+// parts in one instruction
 template <typename T>
-struct cx {
+struct alignas(2 * sizeof(T)) cx {
   T x, y;
 };
 

@@ -6,7 +6,7 @@
 
 #include <vector>
 
-#include "../../include/qmc.h"
+#include "qmc.h"
 
 namespace qmc {
 

@@ -83,6 +83,10 @@ __device__ __forceinline__ void collapse_body(const T* __restrict__ A, int64_t l
 //            thread e1':           IDFT over f -> c, * conj W_M^{R^2 c w2}
 // The conj W_M^{e1' w2} factor is the outer-step twiddle of M = M1 * M2.
 // ---------------------------------------------------------------------------
+// rounds of the sparse front whose loads are issued together; the
+// schedule's round count is a multiple of it
+constexpr int MID_RB = 4;
+
 template <int R>
 struct MidShape {
   static constexpr int Q = R * R;                  // threads per transform
@@ -127,22 +131,23 @@ __device__ __forceinline__ void middle_body(
     // carry G items with distinct e1, so each LDS address is updated by one
     // wavefront only, in round order
     const int fo = q / S::G, ln = q % S::G;
+    // rounds is a multiple of MID_RB (the schedule pads with items that
+    // point at the spare slot buf[M1]); inactive transforms read pair 0
     const cx<T>* av = src + (active ? pair : 0) * Upad;
     const cx<T>* tw = twit + w2 * Upad;
-    constexpr int RB = 4;
-    for (int64_t r0 = 0; r0 < rounds; r0 += RB) {
-      int e1[RB];
-      cx<T> v[RB], w[RB];
+    const int nr = (int)rounds;
+    for (int r0 = 0; r0 < nr; r0 += MID_RB) {
+      int e1[MID_RB];
+      cx<T> v[MID_RB], w[MID_RB];
 #pragma unroll
-      for (int i = 0; i < RB; ++i) {
-        const bool ok = r0 + i < rounds;
-        const int64_t u = (((ok ? r0 + i : 0) * S::F) + fo) * S::G + ln;
-        e1[i] = ok ? it_e1[u] : M1;
-        v[i] = (ok && active) ? av[u] : zero;
+      for (int i = 0; i < MID_RB; ++i) {
+        const int u = ((r0 + i) * S::F + fo) * S::G + ln;
+        e1[i] = it_e1[u];
+        v[i] = av[u];
         w[i] = tw[u];
       }
 #pragma unroll
-      for (int i = 0; i < RB; ++i) {
+      for (int i = 0; i < MID_RB; ++i) {
         const cx<T> c = cmul(v[i], w[i]);
         const cx<T> acc = buf[e1[i]];
         buf[e1[i]] = acc + c;

@@ -12,8 +12,7 @@
 #include <algorithm>
 #include <vector>
 
-#include "cx.hpp"
-#include "internal.hpp"
+#include "kernels.hpp"
 
 namespace qmc {
 
@@ -425,6 +424,7 @@ static void build_schedule(qmc_plan_s* P, const std::vector<int32_t>& ell,
   }
   int64_t rounds = 1;
   for (int f = 0; f < F; ++f) rounds = std::max(rounds, (int64_t)fill[f].size());
+  rounds = (rounds + MID_RB - 1) / MID_RB * MID_RB;  // whole batches of the fused kernel
   P->rounds = rounds;
   P->Upad = rounds * Q;
   it_j.assign(P->Upad, -1);
