@@ -43,12 +43,12 @@ template <typename T, int R, bool SPARSE>
 __global__ __launch_bounds__(MidShape<R>::BLOCK) void k_middle(
     const cx<T>* __restrict__ src, int64_t Upad, int64_t rounds, const int32_t* __restrict__ it_e1,
     const cx<T>* __restrict__ twit, const cx<T>* __restrict__ twf1,
-    const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs, const cx<T>* __restrict__ twi3,
-    const cx<T>* __restrict__ two, int64_t M2, int64_t P, cx<T>* __restrict__ C,
-    T* __restrict__ X, int64_t t, T phi0) {
+    const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ twf2t, const cx<T>* __restrict__ Hs,
+    const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M2, int64_t P,
+    cx<T>* __restrict__ C, T* __restrict__ X, int64_t t, T phi0) {
   __shared__ MidSmem<T, R> S;
-  middle_body<T, R, SPARSE>(src, Upad, rounds, it_e1, twit, twf1, twf2, Hs, twi3, two, M2, P, C,
-                            X, t, phi0, xcd_remap(blockIdx.x, gridDim.x), S, threadIdx.x);
+  middle_body<T, R, SPARSE>(src, Upad, rounds, it_e1, twit, twf1, twf2, twf2t, Hs, twi3, two, M2,
+                            P, C, X, t, phi0, xcd_remap(blockIdx.x, gridDim.x), S, threadIdx.x);
 }
 
 template <typename T, int P2, int DIR>
@@ -113,7 +113,8 @@ static void launch_middle_r(const qmc_plan_s* P, const cx<T>* src, int64_t pairs
   ProfScope ps(P, SPARSE ? PROF_MIDDLE : PROF_ADJ_MIDDLE, st);
   k_middle<T, R, SPARSE><<<dim3((unsigned)G), dim3(S::BLOCK), 0, st>>>(
       src, P->Upad, P->rounds, P->d_it_e1, (const cx<T>*)P->d_twit, (const cx<T>*)P->d_twf1,
-      (const cx<T>*)P->d_twf2, (const cx<T>*)P->d_Hs, (const cx<T>*)P->d_twi3,
+      (const cx<T>*)P->d_twf2, (const cx<T>*)P->d_twf2t, (const cx<T>*)P->d_Hs,
+      (const cx<T>*)P->d_twi3,
       (const cx<T>*)P->d_two, lay.M2, pairs, C, X, t, (T)P->phi0);
 }
 

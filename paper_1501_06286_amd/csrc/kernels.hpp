@@ -87,6 +87,36 @@ __device__ __forceinline__ void collapse_body(const T* __restrict__ A, int64_t l
 // schedule's round count is a multiple of it
 constexpr int MID_RB = 4;
 
+// Per-thread tables keep each thread's consecutive values in adjacent
+// pairs, so one 16-byte load (FP32) brings two complex values: value h of
+// thread q in a table of Q threads is stored at
+//   (h / PP) * PP * Q + PP * q + h % PP,   PP = 2 (1 when a thread has one value).
+__host__ __device__ constexpr int pair_pp(int R) { return R >= 2 ? 2 : 1; }
+__host__ __device__ constexpr int64_t paired_index(int64_t h, int64_t q, int64_t Q, int PP) {
+  return (h / PP) * PP * Q + PP * q + h % PP;
+}
+
+template <typename T>
+struct alignas(4 * sizeof(T)) cx2 {
+  cx<T> a, b;
+};
+
+// v[h] = table value h of thread q, h = 0..R-1
+template <typename T, int R>
+__device__ __forceinline__ void load_paired(cx<T> (&v)[R], const cx<T>* __restrict__ base, int q,
+                                            int Q) {
+  if constexpr (R >= 2) {
+#pragma unroll
+    for (int h = 0; h < R; h += 2) {
+      const cx2<T> p = *reinterpret_cast<const cx2<T>*>(base + (int64_t)h * Q + 2 * q);
+      v[h] = p.a;
+      v[h + 1] = p.b;
+    }
+  } else {
+    v[0] = base[q];
+  }
+}
+
 template <int R>
 struct MidShape {
   static constexpr int Q = R * R;                  // threads per transform
@@ -108,9 +138,10 @@ __device__ __forceinline__ void middle_body(
     const cx<T>* __restrict__ src,      // SPARSE: aT [pair][Upad]; dense: B [pair][M2][M1]
     int64_t Upad, int64_t rounds, const int32_t* __restrict__ it_e1,
     const cx<T>* __restrict__ twit, const cx<T>* __restrict__ twf1,
-    const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs, const cx<T>* __restrict__ twi3,
-    const cx<T>* __restrict__ two, int64_t M2, int64_t P, cx<T>* __restrict__ C,
-    T* __restrict__ X, int64_t t, T phi0, int64_t b, MidSmem<T, R>& SM, int tid) {
+    const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ twf2t, const cx<T>* __restrict__ Hs,
+    const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M2, int64_t P,
+    cx<T>* __restrict__ C, T* __restrict__ X, int64_t t, T phi0, int64_t b, MidSmem<T, R>& SM,
+    int tid) {
   typedef MidShape<R> S;
   constexpr int Q = S::Q, M1 = R * R * R, PB = R * (R + 1);
   cx<T>* lds = SM.lds;
@@ -127,39 +158,61 @@ __device__ __forceinline__ void middle_body(
   if constexpr (SPARSE) {
     for (int i = q; i <= M1; i += Q) buf[i] = zero;
     __syncthreads();
-    // slice f_own = q / G owns the residues e1 = f_own (mod F); its rounds
-    // carry G items with distinct e1, so each LDS address is updated by one
-    // wavefront only, in round order
     const int fo = q / S::G, ln = q % S::G;
-    // rounds is a multiple of MID_RB (the schedule pads with items that
-    // point at the spare slot buf[M1]); inactive transforms read pair 0
+    // every lane owns whole buckets (all items of a residue e1, in a fixed
+    // order): it sums a bucket in registers and stores it once when the
+    // next item belongs to another bucket.  The item count per lane is a
+    // multiple of MID_RB; padding items carry e1 = M1 (the spare slot).
+    // Inactive transforms read pair 0 and store nothing that is used.
     const cx<T>* av = src + (active ? pair : 0) * Upad;
     const cx<T>* tw = twit + w2 * Upad;
     const int nr = (int)rounds;
+    int cur = M1;
+    cx<T> acc = zero;
+    constexpr int PP = pair_pp(R);
     for (int r0 = 0; r0 < nr; r0 += MID_RB) {
       int e1[MID_RB];
       cx<T> v[MID_RB], w[MID_RB];
 #pragma unroll
-      for (int i = 0; i < MID_RB; ++i) {
-        const int u = ((r0 + i) * S::F + fo) * S::G + ln;
-        e1[i] = it_e1[u];
-        v[i] = av[u];
-        w[i] = tw[u];
+      for (int i = 0; i < MID_RB; i += PP) {
+        const int u = (((r0 + i) / PP * S::F + fo) * S::G + ln) * PP;  // items k, k+1 adjacent
+        if constexpr (PP == 2) {
+          const int2 ee = *reinterpret_cast<const int2*>(it_e1 + u);
+          const cx2<T> vv = *reinterpret_cast<const cx2<T>*>(av + u);
+          const cx2<T> ww = *reinterpret_cast<const cx2<T>*>(tw + u);
+          e1[i] = ee.x;
+          e1[i + 1] = ee.y;
+          v[i] = vv.a;
+          v[i + 1] = vv.b;
+          w[i] = ww.a;
+          w[i + 1] = ww.b;
+        } else {
+          e1[i] = it_e1[u];
+          v[i] = av[u];
+          w[i] = tw[u];
+        }
       }
 #pragma unroll
       for (int i = 0; i < MID_RB; ++i) {
         const cx<T> c = cmul(v[i], w[i]);
-        const cx<T> acc = buf[e1[i]];
-        buf[e1[i]] = acc + c;
+        if (e1[i] != cur) {
+          buf[cur] = acc;
+          cur = e1[i];
+          acc = c;
+        } else {
+          acc = acc + c;
+        }
       }
     }
+    buf[cur] = acc;
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < R; ++c) x[c] = buf[q + Q * c];
   } else {
     // dense outer DFT already done: B[pair][w2][e1], times W_M^{e1 w2}
     const cx<T>* bv = src + ((active ? pair : 0) * M2 + w2) * M1;
-    const cx<T> tq = twi3[w2 * M1 + (int64_t)q * R];  // conj W_M^{q w2} (f = 0 entry)
+    // conj W_M^{q w2}: the twi3 entry of e1' = q, f = 0 (thread R (q mod R), value q / R)
+    const cx<T> tq = twi3[w2 * M1 + paired_index(q / R, R * (q % R), Q, pair_pp(R))];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
       cx<T> v = active ? bv[q + Q * c] : zero;
@@ -171,8 +224,12 @@ __device__ __forceinline__ void middle_body(
 
   // ---- forward step 1: thread e1' = q, DFT over c -> f --------------------
   reg_fft<T, R, -1>(x);
+  {
+    cx<T> tw[R];
+    load_paired<T, R>(tw, twf1, q, Q);
 #pragma unroll
-  for (int f = 1; f < R; ++f) x[f] = cmul(x[f], twf1[f * Q + q]);
+    for (int f = 1; f < R; ++f) x[f] = cmul(x[f], tw[f]);
+  }
   __syncthreads();
 #pragma unroll
   for (int f = 0; f < R; ++f) buf[f * PB + q] = x[f];
@@ -183,8 +240,12 @@ __device__ __forceinline__ void middle_body(
 #pragma unroll
     for (int bb = 0; bb < R; ++bb) x[bb] = buf[f * PB + a + R * bb];
     reg_fft<T, R, -1>(x);
+    {
+      cx<T> tw[R];
+      load_paired<T, R>(tw, twf2, a, R);
 #pragma unroll
-    for (int g = 1; g < R; ++g) x[g] = cmul(x[g], twf2[g * R + a]);
+      for (int g = 1; g < R; ++g) x[g] = cmul(x[g], tw[g]);
+    }
     __syncthreads();
 #pragma unroll
     for (int g = 0; g < R; ++g) buf[(f + R * g) * (R + 1) + a] = x[g];
@@ -201,16 +262,23 @@ __device__ __forceinline__ void middle_body(
       if (2 * pair + 1 < t) X[2 * pair + 1] = phi0 * x[0].y;
     }
   }
-  const cx<T>* hs = Hs + w2 * M1;
+  {
+    cx<T> hv[R];
+    load_paired<T, R>(hv, Hs + w2 * M1, q, Q);
 #pragma unroll
-  for (int h = 0; h < R; ++h) x[h] = cmul(x[h], hs[q + Q * h]);
+    for (int h = 0; h < R; ++h) x[h] = cmul(x[h], hv[h]);
+  }
 
   // ---- inverse step 1: thread (f, g), IDFT over h -> a --------------------
   reg_fft<T, R, +1>(x);
   {
     const int f = q % R, g = q / R;
+    {
+      cx<T> tw[R];
+      load_paired<T, R>(tw, twf2t, g, R);
 #pragma unroll
-    for (int a = 1; a < R; ++a) x[a] = cmulc(x[a], twf2[g * R + a]);
+      for (int a = 1; a < R; ++a) x[a] = cmulc(x[a], tw[a]);
+    }
     __syncthreads();
 #pragma unroll
     for (int a = 0; a < R; ++a) buf[(f + R * a) * (R + 1) + g] = x[a];
@@ -222,11 +290,11 @@ __device__ __forceinline__ void middle_body(
 #pragma unroll
     for (int g = 0; g < R; ++g) x[g] = buf[q * (R + 1) + g];
     reg_fft<T, R, +1>(x);
-    const cx<T>* ti = twi3 + w2 * M1;
+    {
+      cx<T> tw[R];
+      load_paired<T, R>(tw, twi3 + w2 * M1, q, Q);  // value bb: conj W_M^{(a + R bb)(f M2 + w2)}
 #pragma unroll
-    for (int bb = 0; bb < R; ++bb) {
-      const int e1p = a + R * bb;
-      if (e1p > 0) x[bb] = cmul(x[bb], ti[e1p * R + f]);
+      for (int bb = 0; bb < R; ++bb) x[bb] = cmul(x[bb], tw[bb]);
     }
     __syncthreads();
 #pragma unroll

@@ -280,46 +280,57 @@ __device__ __forceinline__ cx<T> to_t(cx<double> a) {
   return {(T)a.x, (T)a.y};
 }
 
-// Hs[w2][w1] = Hhat[w2 + M2 w1] / M
+// Per-thread tables of the fused kernel use the paired order of
+// paired_index(value, thread, threads, PP): a thread's values 2k and 2k+1
+// are adjacent.
+
+// spectrum / M: block w2, thread q < R^2, value h for w1 = q + R^2 h,
+// holding Hhat[w2 + M2 w1] / M
 template <typename T>
-__global__ void k_spectrum_layout(cx<T>* Hs, const cx<double>* Hhat, int64_t M, int64_t M1,
+__global__ void k_spectrum_layout(cx<T>* Hs, const cx<double>* Hhat, int R, int64_t M,
                                   int64_t M2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
+  const int64_t M1 = M / M2, Q = (int64_t)R * R;
   const int64_t w2 = i / M1, w1 = i % M1;
   const cx<double> h = Hhat[w2 + M2 * w1];
   const double inv = 1.0 / (double)M;
-  Hs[i] = to_t<T>({h.x * inv, h.y * inv});
+  Hs[w2 * M1 + paired_index(w1 / Q, w1 % Q, Q, pair_pp(R))] = to_t<T>({h.x * inv, h.y * inv});
 }
 
-// twf1[f][e1'] = W_{M1}^{e1' f} = W_M^{e1' f M2}   (e1' < R^2, f < R)
+// twf1: thread e1' < R^2, value f < R: W_{M1}^{e1' f} = W_M^{e1' f M2}
 template <typename T>
 __global__ void k_tw_f1(cx<T>* twf1, const cx<double>* W, int R, int64_t M, int64_t M2) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int Q = R * R;
   if (i >= R * Q) return;
   const int64_t f = i / Q, e = i % Q;
-  twf1[i] = to_t<T>(W[(e * f * M2) & (M - 1)]);
+  twf1[paired_index(f, e, Q, pair_pp(R))] = to_t<T>(W[(e * f * M2) & (M - 1)]);
 }
 
-// twf2[g][a] = W_{R^2}^{a g} = W_M^{a g M / R^2}
+// W_{R^2}^{a g} = W_M^{a g M / R^2}, twice: twf2 with thread a and value g,
+// twf2t with thread g and value a
 template <typename T>
-__global__ void k_tw_f2(cx<T>* twf2, const cx<double>* W, int R, int64_t M) {
+__global__ void k_tw_f2(cx<T>* twf2, cx<T>* twf2t, const cx<double>* W, int R, int64_t M) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= R * R) return;
   const int64_t g = i / R, a = i % R;
-  twf2[i] = to_t<T>(W[(a * g * (M / ((int64_t)R * R))) & (M - 1)]);
+  const cx<T> w = to_t<T>(W[(a * g * (M / ((int64_t)R * R))) & (M - 1)]);
+  twf2[paired_index(g, a, R, pair_pp(R))] = w;
+  twf2t[paired_index(a, g, R, pair_pp(R))] = w;
 }
 
-// twi3[w2][e1'][f] = conj W_M^{e1' (f M2 + w2)}
+// twi3: block w2, thread f + R a, value bb: conj W_M^{e1' (f M2 + w2)} with
+// e1' = a + R bb
 template <typename T>
 __global__ void k_tw_i3(cx<T>* twi3, const cx<double>* W, int R, int64_t M, int64_t M2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M) return;
-  const int64_t M1 = M / M2;
-  const int64_t f = i % R, e = (i / R) % (M1 / R), w2 = i / M1;
+  const int64_t M1 = M / M2, Q = (int64_t)R * R;
+  const int64_t f = i % R, e = (i / R) % Q, w2 = i / M1;
   const cx<double> w = W[(e * (f * M2 + w2)) & (M - 1)];
-  twi3[i] = to_t<T>({w.x, -w.y});
+  const int64_t a = e % R, bb = e / R;
+  twi3[w2 * M1 + paired_index(bb, f + R * a, Q, pair_pp(R))] = to_t<T>({w.x, -w.y});
 }
 
 // two[w2][c] = conj W_M^{R^2 c w2}
@@ -396,9 +407,13 @@ static Layout choose_layout(int64_t L, int dtype, int* embedded) {
 }
 
 // collapse schedule: item u -> (row j, slot).  The residues e1 = slot mod M1
-// are owned by F slices (e1 mod F); each slice runs rounds of G items whose
-// e1 are distinct, items of one residue in increasing j (fixed summation
-// order).  Item u = (round * F + slice) * G + lane.
+// are owned by F slices (e1 mod F, one wavefront each); inside a slice every
+// residue's items (its "bucket", in increasing j: a fixed summation order)
+// go to one lane, buckets assigned longest-first to the least-loaded lane.
+// A lane accumulates one bucket in registers and writes it once.  The lane's
+// k-th item is u = ((k / PP * F + slice) * G + lane) * PP + k % PP, so its
+// items come in adjacent pairs; the item count per lane is padded to a
+// common multiple of the fused kernel's batch.
 static void build_schedule(qmc_plan_s* P, const std::vector<int32_t>& ell,
                            std::vector<int32_t>& it_j, std::vector<int32_t>& it_slot,
                            std::vector<int32_t>& it_e1) {
@@ -407,37 +422,55 @@ static void build_schedule(qmc_plan_s* P, const std::vector<int32_t>& ell,
   const int Q = R * R;
   const int G = Q < 64 ? Q : 64;
   const int F = Q / G;
-  std::vector<int64_t> next_round(M1, 0);
-  std::vector<std::vector<int32_t>> fill(F);  // items placed per (slice, round)
-  std::vector<std::pair<int64_t, int64_t>> place(P->s);
-  for (int64_t j = 0; j < P->s; ++j) {
-    const int64_t slot = (L - ell[j]) % L;
-    const int64_t e1 = slot & (M1 - 1);
-    const int f = (int)(e1 % F);
-    std::vector<int32_t>& fl = fill[f];
-    int64_t r = next_round[e1];
-    while (r < (int64_t)fl.size() && fl[r] >= G) ++r;
-    if (r >= (int64_t)fl.size()) fl.resize(r + 1, 0);
-    place[j] = {r, (int64_t)f * G + fl[r]};
-    fl[r]++;
-    next_round[e1] = r + 1;
+  const int PP = pair_pp(R);
+  // buckets: items of each residue e1, in increasing j
+  std::vector<int64_t> start(M1 + 1, 0);
+  for (int64_t j = 0; j < P->s; ++j) start[((L - ell[j]) % L & (M1 - 1)) + 1]++;
+  for (int64_t e = 0; e < M1; ++e) start[e + 1] += start[e];
+  std::vector<int32_t> members(P->s);
+  {
+    std::vector<int64_t> pos(start.begin(), start.end() - 1);
+    for (int64_t j = 0; j < P->s; ++j) members[pos[((L - ell[j]) % L) & (M1 - 1)]++] = (int32_t)j;
+  }
+  // per slice: longest-first assignment of buckets to lanes
+  std::vector<std::vector<int32_t>> lane_items((size_t)F * G);  // j's in order
+  std::vector<int64_t> load(G);
+  std::vector<int64_t> order;
+  for (int f = 0; f < F; ++f) {
+    order.clear();
+    for (int64_t e = f; e < M1; e += F)
+      if (start[e + 1] > start[e]) order.push_back(e);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+      return start[a + 1] - start[a] > start[b + 1] - start[b];
+    });
+    std::fill(load.begin(), load.end(), 0);
+    for (int64_t e : order) {
+      const int ln = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[ln] += start[e + 1] - start[e];
+      std::vector<int32_t>& li = lane_items[(size_t)f * G + ln];
+      for (int64_t k = start[e]; k < start[e + 1]; ++k) li.push_back(members[k]);
+    }
   }
   int64_t rounds = 1;
-  for (int f = 0; f < F; ++f) rounds = std::max(rounds, (int64_t)fill[f].size());
+  for (const auto& li : lane_items) rounds = std::max(rounds, (int64_t)li.size());
   rounds = (rounds + MID_RB - 1) / MID_RB * MID_RB;  // whole batches of the fused kernel
   P->rounds = rounds;
   P->Upad = rounds * Q;
   it_j.assign(P->Upad, -1);
   it_slot.assign(P->Upad, -1);
   it_e1.assign(P->Upad, (int32_t)M1);
-  for (int64_t j = 0; j < P->s; ++j) {
-    const int64_t f = place[j].second / G, lane = place[j].second % G;
-    const int64_t u = (place[j].first * F + f) * G + lane;
-    const int64_t slot = (L - ell[j]) % L;
-    it_j[u] = (int32_t)j;
-    it_slot[u] = (int32_t)slot;
-    it_e1[u] = (int32_t)(slot & (M1 - 1));
-  }
+  for (int f = 0; f < F; ++f)
+    for (int ln = 0; ln < G; ++ln) {
+      const std::vector<int32_t>& li = lane_items[(size_t)f * G + ln];
+      for (size_t k = 0; k < li.size(); ++k) {
+        const int64_t u = (((int64_t)k / PP * F + f) * G + ln) * PP + (int64_t)k % PP;
+        const int64_t j = li[k];
+        const int64_t slot = (L - ell[j]) % L;
+        it_j[u] = (int32_t)j;
+        it_slot[u] = (int32_t)slot;
+        it_e1[u] = (int32_t)(slot & (M1 - 1));
+      }
+    }
 }
 
 template <typename T>
@@ -450,14 +483,15 @@ static int build_spectral_tables(qmc_plan_s* P, const cx<double>* dW, const cx<d
   cx<T>* Hs = dev_alloc<cx<T>>(P, M, &err);
   cx<T>* twf1 = dev_alloc<cx<T>>(P, (size_t)R * R * R, &err);
   cx<T>* twf2 = dev_alloc<cx<T>>(P, (size_t)R * R, &err);
+  cx<T>* twf2t = dev_alloc<cx<T>>(P, (size_t)R * R, &err);
   cx<T>* twi3 = dev_alloc<cx<T>>(P, M, &err);
   cx<T>* two = dev_alloc<cx<T>>(P, M2 * R, &err);
   cx<T>* twit = dev_alloc<cx<T>>(P, M2 * P->Upad, &err);
   cx<T>* twb = dev_alloc<cx<T>>(P, (size_t)lay.P2 * lay.Q2, &err);
   if (err != QMC_OK) return err;
-  k_spectrum_layout<T><<<nblk(M), 256, 0, st>>>(Hs, dH, M, M1, M2);
+  k_spectrum_layout<T><<<nblk(M), 256, 0, st>>>(Hs, dH, R, M, M2);
   k_tw_f1<T><<<nblk(R * R * R), 256, 0, st>>>(twf1, dW, R, M, M2);
-  k_tw_f2<T><<<nblk(R * R), 256, 0, st>>>(twf2, dW, R, M);
+  k_tw_f2<T><<<nblk(R * R), 256, 0, st>>>(twf2, twf2t, dW, R, M);
   k_tw_i3<T><<<nblk(M), 256, 0, st>>>(twi3, dW, R, M, M2);
   k_tw_outer<T><<<nblk(M2 * R), 256, 0, st>>>(two, dW, R, M, M2);
   k_tw_items<T><<<nblk(M2 * P->Upad), 256, 0, st>>>(twit, dW, dslot, P->Upad, M, M2);
@@ -466,6 +500,7 @@ static int build_spectral_tables(qmc_plan_s* P, const cx<double>* dW, const cx<d
   P->d_Hs = Hs;
   P->d_twf1 = twf1;
   P->d_twf2 = twf2;
+  P->d_twf2t = twf2t;
   P->d_twi3 = twi3;
   P->d_two = two;
   P->d_twit = twit;
