@@ -68,7 +68,8 @@ __global__ __launch_bounds__(256) void kb_collapse(const BatchInst* __restrict__
 }
 
 template <typename T, int R>
-__global__ __launch_bounds__(MidShape<R>::BLOCK) void kb_middle(const BatchInst* __restrict__ D,
+__global__ __launch_bounds__(MidShape<R>::BLOCK)
+__attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void kb_middle(const BatchInst* __restrict__ D,
                                                                 int n, int64_t total,
                                                                 char* __restrict__ ws) {
   __shared__ MidSmem<T, R> S;

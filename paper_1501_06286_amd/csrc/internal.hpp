@@ -52,11 +52,11 @@ struct qmc_plan_s {
   int32_t* d_ell = nullptr;     // s   : l_j
   uint32_t* d_gen = nullptr;    // s   : g_j mod N (lattice) or q_j (GF(2))
   double* d_tphi = nullptr;     // N   : phi of residue r (FP64)
-  void* d_Hs = nullptr;         // M   : spectrum / M, [w2] then thread q value h for w1 = q + R^2 h (paired)
+  void* d_Hs = nullptr;         // M   : spectrum / M, [w2] then thread g + R f value h for w1 = f + R g + R^2 h (paired)
   void* d_twf1 = nullptr;       // R*R^2: W_{M1}^{e1' f}, thread e1' (< R^2), value f (paired)
   void* d_twf2 = nullptr;       // R*R : W_{R^2}^{a g}, thread a, value g (paired layout)
   void* d_twf2t = nullptr;      // R*R : W_{R^2}^{a g}, thread g, value a (paired layout)
-  void* d_twi3 = nullptr;       // M   : conj W_M^{e1' (f M2 + w2)}, [w2] then thread f + R a value bb, e1' = a + R bb (paired)
+  void* d_twi3 = nullptr;       // M   : conj W_M^{e1' (f M2 + w2)}, [w2] then thread a + R f value bb, e1' = a + R bb (paired)
   void* d_two = nullptr;        // M2*R: conj W_M^{R^2 c w2} in [w2][c] order
   void* d_twit = nullptr;       // M2*Upad: W_M^{slot_u w2} in [w2][u] order
   void* d_twb = nullptr;        // M2  : conj W_{M2}^{a q} table for the split back pass [a*Q2+q]

@@ -75,14 +75,24 @@ __device__ __forceinline__ void collapse_body(const T* __restrict__ A, int64_t l
 // values in registers and the data moves through one LDS buffer between the
 // three register DFTs of each direction:
 //   forward  thread e1'=(a + R b): DFT over c -> f, * W_{M1}^{e1' f}
-//            thread (a, f):        DFT over b -> g, * W_{R^2}^{a g}
-//            thread (f, g):        DFT over a -> h      => X[f + R g + R^2 h]
+//            thread a + R f:       DFT over b -> g, * W_{R^2}^{a g}
+//            thread g + R f:       DFT over a -> h      => X[f + R g + R^2 h]
 //   product  * Hs[w2][w1]  (the spectrum, with 1/M folded in)
-//   inverse  thread (f, g):        IDFT over h -> a, * conj W_{R^2}^{a g}
-//            thread (f, a):        IDFT over g -> b, * conj W_M^{e1' (f M2 + w2)}
+//   inverse  thread g + R f:       IDFT over h -> a, * conj W_{R^2}^{a g}
+//            thread a + R f:       IDFT over g -> b, * conj W_M^{e1' (f M2 + w2)}
 //            thread e1':           IDFT over f -> c, * conj W_M^{R^2 c w2}
+// The middle four steps keep f fixed, so their exchanges stay inside a
+// group of R lanes of one wavefront.
 // The conj W_M^{e1' w2} factor is the outer-step twiddle of M = M1 * M2.
 // ---------------------------------------------------------------------------
+// orders this wavefront's LDS accesses before and after the call (LDS
+// operations of one wavefront complete in issue order)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // rounds of the sparse front whose loads are issued together; the
 // schedule's round count is a multiple of it
 constexpr int MID_RB = 4;
@@ -127,6 +137,14 @@ struct MidShape {
   static constexpr int F = Q / G;                  // front slices per transform (owners of e1 mod F)
 };
 
+// waves per SIMD the fused kernel is compiled for: the LDS of R = 16
+// admits four FP32 or two FP64 workgroups per CU and the register budget
+// follows (128 or 256 per lane); FP64 at R = 8 needs more than 128
+template <typename T, int R>
+constexpr int mid_waves() {
+  return sizeof(T) == 8 ? (R == 16 ? 2 : R == 8 ? 3 : 4) : 4;
+}
+
 template <typename T, int R>
 struct MidSmem {
   cx<T> lds[MidShape<R>::TPB * MidShape<R>::BUFN];
@@ -153,6 +171,11 @@ __device__ __forceinline__ void middle_body(
   cx<T>* buf = lds + tr * S::BUFN;
   const cx<T> zero = {(T)0, (T)0};
   cx<T> x[R];
+
+  // The first twiddles and the spectrum are loaded ahead of use, so their
+  // latency hides behind the front and the steps in between.
+  cx<T> tw_a[R], tw_b[R], hv[R];
+  load_paired<T, R>(tw_a, twf1, q, Q);
 
   // ---- front: B[e1] for this w2, in registers of thread e1' = q ----------
   if constexpr (SPARSE) {
@@ -211,8 +234,8 @@ __device__ __forceinline__ void middle_body(
   } else {
     // dense outer DFT already done: B[pair][w2][e1], times W_M^{e1 w2}
     const cx<T>* bv = src + ((active ? pair : 0) * M2 + w2) * M1;
-    // conj W_M^{q w2}: the twi3 entry of e1' = q, f = 0 (thread R (q mod R), value q / R)
-    const cx<T> tq = twi3[w2 * M1 + paired_index(q / R, R * (q % R), Q, pair_pp(R))];
+    // conj W_M^{q w2}: the twi3 entry of e1' = q, f = 0 (thread q mod R, value q / R)
+    const cx<T> tq = twi3[w2 * M1 + paired_index(q / R, q % R, Q, pair_pp(R))];
 #pragma unroll
     for (int c = 0; c < R; ++c) {
       cx<T> v = active ? bv[q + Q * c] : zero;
@@ -224,37 +247,33 @@ __device__ __forceinline__ void middle_body(
 
   // ---- forward step 1: thread e1' = q, DFT over c -> f --------------------
   reg_fft<T, R, -1>(x);
-  {
-    cx<T> tw[R];
-    load_paired<T, R>(tw, twf1, q, Q);
 #pragma unroll
-    for (int f = 1; f < R; ++f) x[f] = cmul(x[f], tw[f]);
-  }
+  for (int f = 1; f < R; ++f) x[f] = cmul(x[f], tw_a[f]);
+  const int gl = q % R;
+  load_paired<T, R>(hv, Hs + w2 * M1, q, Q);  // two steps early
   __syncthreads();
 #pragma unroll
   for (int f = 0; f < R; ++f) buf[f * PB + q] = x[f];
   __syncthreads();
-  // ---- forward step 2: thread (a, f), q = a + R f: DFT over b -> g --------
-  {
-    const int a = q % R, f = q / R;
+  // The next four steps stay inside one group of R lanes (fixed f, lane
+  // index gl), which only touches its own LDS tile grp = buf + f * PB, an
+  // R x (R + 1) array; the exchanges need no workgroup barrier.
+  cx<T>* grp = buf + (q / R) * PB;
+  // ---- forward step 2: thread (a = gl, f): DFT over b -> g ----------------
 #pragma unroll
-    for (int bb = 0; bb < R; ++bb) x[bb] = buf[f * PB + a + R * bb];
-    reg_fft<T, R, -1>(x);
-    {
-      cx<T> tw[R];
-      load_paired<T, R>(tw, twf2, a, R);
+  for (int bb = 0; bb < R; ++bb) x[bb] = grp[gl + R * bb];
+  reg_fft<T, R, -1>(x);
+  load_paired<T, R>(tw_b, twf2, gl, R);
 #pragma unroll
-      for (int g = 1; g < R; ++g) x[g] = cmul(x[g], tw[g]);
-    }
-    __syncthreads();
+  for (int g = 1; g < R; ++g) x[g] = cmul(x[g], tw_b[g]);
+  wave_lds_sync();
 #pragma unroll
-    for (int g = 0; g < R; ++g) buf[(f + R * g) * (R + 1) + a] = x[g];
-    __syncthreads();
-  }
-  // ---- forward step 3: thread (f, g), q = f + R g: DFT over a -> h --------
+  for (int g = 0; g < R; ++g) grp[g * (R + 1) + gl] = x[g];
+  wave_lds_sync();
+  // ---- forward step 3: thread (g = gl, f): DFT over a -> h ----------------
 #pragma unroll
-  for (int a = 0; a < R; ++a) x[a] = buf[q * (R + 1) + a];
-  reg_fft<T, R, -1>(x);  // x[h] = X[q + R^2 h]
+  for (int a = 0; a < R; ++a) x[a] = grp[gl * (R + 1) + a];
+  reg_fft<T, R, -1>(x);  // x[h] = X[f + R g + R^2 h]
 
   if constexpr (SPARSE) {
     if (w2 == 0 && q == 0 && active) {  // DC term -> row 0
@@ -262,52 +281,38 @@ __device__ __forceinline__ void middle_body(
       if (2 * pair + 1 < t) X[2 * pair + 1] = phi0 * x[0].y;
     }
   }
-  {
-    cx<T> hv[R];
-    load_paired<T, R>(hv, Hs + w2 * M1, q, Q);
 #pragma unroll
-    for (int h = 0; h < R; ++h) x[h] = cmul(x[h], hv[h]);
-  }
+  for (int h = 0; h < R; ++h) x[h] = cmul(x[h], hv[h]);
 
-  // ---- inverse step 1: thread (f, g), IDFT over h -> a --------------------
+  // ---- inverse step 1: thread (g = gl, f): IDFT over h -> a ---------------
   reg_fft<T, R, +1>(x);
-  {
-    const int f = q % R, g = q / R;
-    {
-      cx<T> tw[R];
-      load_paired<T, R>(tw, twf2t, g, R);
+  load_paired<T, R>(tw_a, twf2t, gl, R);
 #pragma unroll
-      for (int a = 1; a < R; ++a) x[a] = cmulc(x[a], tw[a]);
-    }
-    __syncthreads();
+  for (int a = 1; a < R; ++a) x[a] = cmulc(x[a], tw_a[a]);
+  wave_lds_sync();
 #pragma unroll
-    for (int a = 0; a < R; ++a) buf[(f + R * a) * (R + 1) + g] = x[a];
-    __syncthreads();
-  }
-  // ---- inverse step 2: thread (f, a), q = f + R a: IDFT over g -> b -------
-  {
-    const int f = q % R, a = q / R;
+  for (int a = 0; a < R; ++a) grp[a * (R + 1) + gl] = x[a];
+  wave_lds_sync();
+  // ---- inverse step 2: thread (a = gl, f): IDFT over g -> b ---------------
 #pragma unroll
-    for (int g = 0; g < R; ++g) x[g] = buf[q * (R + 1) + g];
-    reg_fft<T, R, +1>(x);
-    {
-      cx<T> tw[R];
-      load_paired<T, R>(tw, twi3 + w2 * M1, q, Q);  // value bb: conj W_M^{(a + R bb)(f M2 + w2)}
+  for (int g = 0; g < R; ++g) x[g] = grp[gl * (R + 1) + g];
+  reg_fft<T, R, +1>(x);
+  // value bb: conj W_M^{(a + R bb)(f M2 + w2)}
+  load_paired<T, R>(tw_b, twi3 + w2 * M1, q, Q);
 #pragma unroll
-      for (int bb = 0; bb < R; ++bb) x[bb] = cmul(x[bb], tw[bb]);
-    }
-    __syncthreads();
+  for (int bb = 0; bb < R; ++bb) x[bb] = cmul(x[bb], tw_b[bb]);
 #pragma unroll
-    for (int bb = 0; bb < R; ++bb) buf[(a + R * bb) * (R + 1) + f] = x[bb];
-    __syncthreads();
-  }
+  for (int c = 1; c < R; ++c) tw_a[c] = two[w2 * R + c];
+  __syncthreads();
+#pragma unroll
+  for (int bb = 0; bb < R; ++bb) buf[(gl + R * bb) * (R + 1) + q / R] = x[bb];
+  __syncthreads();
   // ---- inverse step 3: thread e1' = q, IDFT over f -> c -------------------
 #pragma unroll
   for (int f = 0; f < R; ++f) x[f] = buf[q * (R + 1) + f];
   reg_fft<T, R, +1>(x);
-  const cx<T>* to = two + w2 * R;
 #pragma unroll
-  for (int c = 1; c < R; ++c) x[c] = cmul(x[c], to[c]);
+  for (int c = 1; c < R; ++c) x[c] = cmul(x[c], tw_a[c]);
   if (active) {
     cx<T>* cp = C + (pair * M2 + w2) * M1;
 #pragma unroll
@@ -348,10 +353,31 @@ __device__ __forceinline__ void split_body(cx<T>* __restrict__ C, int64_t M1, in
 //   forward: X[pow[e]][2 pair .. 2 pair + 1] = out[e] for e < L
 //   adjoint: dA[j][...] = out[e] + phi0 G[0][...] for every j with l_j = e
 // ---------------------------------------------------------------------------
+// values per thread exchanged per round through LDS in the back and
+// adjoint-front passes; small enough that a back workgroup fits beside
+// four fused-kernel workgroups on one CU
+constexpr int BACK_CH = 8;
 template <typename T>
-struct BackSmem {  // sized for the largest chunk (16 values per thread)
-  cx<T> sm[16][16][17];
+struct BackSmem {
+  cx<T> sm[BACK_CH][16][17];
 };
+
+// whether element pairs (2k, 2k+1) of every row of a row-major matrix are
+// aligned for one vector access
+template <typename T>
+__device__ __forceinline__ bool pairs_aligned(const T* p, int64_t ld) {
+  return (ld % 2 == 0) && (reinterpret_cast<uintptr_t>(p) % (2 * sizeof(T)) == 0);
+}
+template <typename T>
+using vec2_t = T __attribute__((ext_vector_type(2)));
+template <typename T, bool NT>
+__device__ __forceinline__ void store_pair(T* p, T x, T y) {
+  const vec2_t<T> v = {x, y};
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, reinterpret_cast<vec2_t<T>*>(p));
+  else
+    *reinterpret_cast<vec2_t<T>*>(p) = v;
+}
 
 template <typename T, int Q, bool ADJ, bool NT>
 __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M1, int64_t M2,
@@ -363,10 +389,11 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
                                           T* __restrict__ X, int64_t ldx, int64_t t, int64_t bx,
                                           int64_t by, int64_t a, BackSmem<T>& S, int tid) {
   constexpr int PB = 16, EB = 16;
-  constexpr int CH = Q < 16 ? Q : 16;
+  constexpr int CH = Q < BACK_CH ? Q : BACK_CH;
   auto& sm = S.sm;
   const int64_t e1_0 = bx * EB, p0 = by * PB;
   const int el = tid % EB, pl = tid / EB;
+  const bool v2 = pairs_aligned(X, ldx);
   {
     const int64_t e1 = e1_0 + el, pair = p0 + pl;
     cx<T> v[Q];
@@ -391,22 +418,29 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
           if (e < L) {
             const cx<T> o = sm[c][ew][pw];
             const int64_t col = 2 * pairw;
+            const bool both = col + 1 < t;
             if constexpr (!ADJ) {
               T* row = X + (int64_t)rowmap[e] * ldx;
-              if constexpr (NT) {
+              if (v2 && both) {
+                store_pair<T, NT>(row + col, o.x, o.y);
+              } else if constexpr (NT) {
                 __builtin_nontemporal_store(o.x, row + col);
-                if (col + 1 < t) __builtin_nontemporal_store(o.y, row + col + 1);
+                if (both) __builtin_nontemporal_store(o.y, row + col + 1);
               } else {
                 row[col] = o.x;
-                if (col + 1 < t) row[col + 1] = o.y;
+                if (both) row[col + 1] = o.y;
               }
             } else {
               const T g0 = phi0 * G0[col];
-              const T g1 = (col + 1 < t) ? phi0 * G0[col + 1] : (T)0;
+              const T g1 = both ? phi0 * G0[col + 1] : (T)0;
               for (int32_t jj = inv_ptr[e]; jj < inv_ptr[e + 1]; ++jj) {
                 T* row = X + (int64_t)inv_j[jj] * ldx;
-                row[col] = o.x + g0;
-                if (col + 1 < t) row[col + 1] = o.y + g1;
+                if (v2 && both) {
+                  store_pair<T, false>(row + col, o.x + g0, o.y + g1);
+                } else {
+                  row[col] = o.x + g0;
+                  if (both) row[col + 1] = o.y + g1;
+                }
               }
             }
           }
@@ -431,9 +465,10 @@ __device__ __forceinline__ void adj_front_body(const T* __restrict__ G, int64_t 
                                                cx<T>* __restrict__ B, int64_t bx, int64_t by,
                                                int64_t a, BackSmem<T>& S, int tid) {
   constexpr int PB = 16, EB = 16;
-  constexpr int CH = Q < 16 ? Q : 16;
+  constexpr int CH = Q < BACK_CH ? Q : BACK_CH;
   auto& sm = S.sm;
   const int64_t e1_0 = bx * EB, p0 = by * PB;
+  const bool v2 = pairs_aligned(G, ldg);
   const int pw = tid % PB, ew = tid / PB;     // gather mapping (pair-fast)
   const int el = tid % EB, pl = tid / EB;     // transform mapping (e1-fast)
   const int64_t pairw = p0 + pw, e1w = e1_0 + ew;
@@ -449,8 +484,14 @@ __device__ __forceinline__ void adj_front_body(const T* __restrict__ G, int64_t 
         const int64_t src = (L - e) % L;
         const T* row = G + (int64_t)pow[src] * ldg;
         const int64_t col = 2 * pairw;
-        g.x = row[col];
-        if (col + 1 < t) g.y = row[col + 1];
+        if (v2 && col + 1 < t) {
+          const vec2_t<T> gg = *reinterpret_cast<const vec2_t<T>*>(row + col);
+          g.x = gg.x;
+          g.y = gg.y;
+        } else {
+          g.x = row[col];
+          if (col + 1 < t) g.y = row[col + 1];
+        }
       }
       sm[c][ew][pw] = g;
     }

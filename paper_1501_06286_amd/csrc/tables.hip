@@ -284,7 +284,7 @@ __device__ __forceinline__ cx<T> to_t(cx<double> a) {
 // paired_index(value, thread, threads, PP): a thread's values 2k and 2k+1
 // are adjacent.
 
-// spectrum / M: block w2, thread q < R^2, value h for w1 = q + R^2 h,
+// spectrum / M: block w2, thread g + R f, value h for w1 = f + R g + R^2 h,
 // holding Hhat[w2 + M2 w1] / M
 template <typename T>
 __global__ void k_spectrum_layout(cx<T>* Hs, const cx<double>* Hhat, int R, int64_t M,
@@ -293,9 +293,10 @@ __global__ void k_spectrum_layout(cx<T>* Hs, const cx<double>* Hhat, int R, int6
   if (i >= M) return;
   const int64_t M1 = M / M2, Q = (int64_t)R * R;
   const int64_t w2 = i / M1, w1 = i % M1;
-  const cx<double> h = Hhat[w2 + M2 * w1];
+  const int64_t f = w1 % R, g = (w1 / R) % R, h = w1 / Q;
+  const cx<double> v = Hhat[w2 + M2 * w1];
   const double inv = 1.0 / (double)M;
-  Hs[w2 * M1 + paired_index(w1 / Q, w1 % Q, Q, pair_pp(R))] = to_t<T>({h.x * inv, h.y * inv});
+  Hs[w2 * M1 + paired_index(h, g + R * f, Q, pair_pp(R))] = to_t<T>({v.x * inv, v.y * inv});
 }
 
 // twf1: thread e1' < R^2, value f < R: W_{M1}^{e1' f} = W_M^{e1' f M2}
@@ -320,7 +321,7 @@ __global__ void k_tw_f2(cx<T>* twf2, cx<T>* twf2t, const cx<double>* W, int R, i
   twf2t[paired_index(a, g, R, pair_pp(R))] = w;
 }
 
-// twi3: block w2, thread f + R a, value bb: conj W_M^{e1' (f M2 + w2)} with
+// twi3: block w2, thread a + R f, value bb: conj W_M^{e1' (f M2 + w2)} with
 // e1' = a + R bb
 template <typename T>
 __global__ void k_tw_i3(cx<T>* twi3, const cx<double>* W, int R, int64_t M, int64_t M2) {
@@ -330,7 +331,7 @@ __global__ void k_tw_i3(cx<T>* twi3, const cx<double>* W, int R, int64_t M, int6
   const int64_t f = i % R, e = (i / R) % Q, w2 = i / M1;
   const cx<double> w = W[(e * (f * M2 + w2)) & (M - 1)];
   const int64_t a = e % R, bb = e / R;
-  twi3[w2 * M1 + paired_index(bb, f + R * a, Q, pair_pp(R))] = to_t<T>({w.x, -w.y});
+  twi3[w2 * M1 + paired_index(bb, a + R * f, Q, pair_pp(R))] = to_t<T>({w.x, -w.y});
 }
 
 // two[w2][c] = conj W_M^{R^2 c w2}
