@@ -2,6 +2,7 @@
 // launches (conv.hip) and the batched persistent launches (batch.hip).
 // Each body takes its block coordinates and its LDS storage as arguments.
 #pragma once
+#include <type_traits>
 #include "cx.hpp"
 #include "internal.hpp"
 
@@ -93,8 +94,8 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// rounds of the sparse front whose loads are issued together; the
-// schedule's round count is a multiple of it
+// rounds of the sparse front whose loads are issued together (a shorter
+// tail batch covers the rest)
 constexpr int MID_RB = 4;
 
 // Per-thread tables keep each thread's consecutive values in adjacent
@@ -185,7 +186,8 @@ __device__ __forceinline__ void middle_body(
     // every lane owns whole buckets (all items of a residue e1, in a fixed
     // order): it sums a bucket in registers and stores it once when the
     // next item belongs to another bucket.  The item count per lane is a
-    // multiple of MID_RB; padding items carry e1 = M1 (the spare slot).
+    // multiple of the pairing PP; padding items carry e1 = M1 (the spare
+    // slot).
     // Inactive transforms read pair 0 and store nothing that is used.
     const cx<T>* av = src + (active ? pair : 0) * Upad;
     const cx<T>* tw = twit + w2 * Upad;
@@ -193,11 +195,13 @@ __device__ __forceinline__ void middle_body(
     int cur = M1;
     cx<T> acc = zero;
     constexpr int PP = pair_pp(R);
-    for (int r0 = 0; r0 < nr; r0 += MID_RB) {
-      int e1[MID_RB];
-      cx<T> v[MID_RB], w[MID_RB];
+    // NB rounds from r0: all loads first, then the bucket sums
+    auto rounds_from = [&](int r0, auto nb) {
+      constexpr int NB = decltype(nb)::value;
+      int e1[NB];
+      cx<T> v[NB], w[NB];
 #pragma unroll
-      for (int i = 0; i < MID_RB; i += PP) {
+      for (int i = 0; i < NB; i += PP) {
         const int u = (((r0 + i) / PP * S::F + fo) * S::G + ln) * PP;  // items k, k+1 adjacent
         if constexpr (PP == 2) {
           const int2 ee = *reinterpret_cast<const int2*>(it_e1 + u);
@@ -216,7 +220,7 @@ __device__ __forceinline__ void middle_body(
         }
       }
 #pragma unroll
-      for (int i = 0; i < MID_RB; ++i) {
+      for (int i = 0; i < NB; ++i) {
         const cx<T> c = cmul(v[i], w[i]);
         if (e1[i] != cur) {
           buf[cur] = acc;
@@ -226,7 +230,10 @@ __device__ __forceinline__ void middle_body(
           acc = acc + c;
         }
       }
-    }
+    };
+    int r0 = 0;
+    for (; r0 + MID_RB <= nr; r0 += MID_RB) rounds_from(r0, std::integral_constant<int, MID_RB>{});
+    for (; r0 < nr; r0 += PP) rounds_from(r0, std::integral_constant<int, PP>{});
     buf[cur] = acc;
     __syncthreads();
 #pragma unroll

@@ -414,7 +414,7 @@ static Layout choose_layout(int64_t L, int dtype, int* embedded) {
 // A lane accumulates one bucket in registers and writes it once.  The lane's
 // k-th item is u = ((k / PP * F + slice) * G + lane) * PP + k % PP, so its
 // items come in adjacent pairs; the item count per lane is padded to a
-// common multiple of the fused kernel's batch.
+// multiple of PP.
 static void build_schedule(qmc_plan_s* P, const std::vector<int32_t>& ell,
                            std::vector<int32_t>& it_j, std::vector<int32_t>& it_slot,
                            std::vector<int32_t>& it_e1) {
@@ -454,7 +454,7 @@ static void build_schedule(qmc_plan_s* P, const std::vector<int32_t>& ell,
   }
   int64_t rounds = 1;
   for (const auto& li : lane_items) rounds = std::max(rounds, (int64_t)li.size());
-  rounds = (rounds + MID_RB - 1) / MID_RB * MID_RB;  // whole batches of the fused kernel
+  rounds = (rounds + PP - 1) / PP * PP;  // whole item pairs
   P->rounds = rounds;
   P->Upad = rounds * Q;
   it_j.assign(P->Upad, -1);
