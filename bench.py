@@ -68,9 +68,10 @@ def source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, tuning):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
-    was taken on the current kernel sources (else None)."""
+    was taken on the current kernel sources with the same launch tuning (else
+    None)."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -78,7 +79,10 @@ def measured_traffic(kernel, workload):
         d = json.load(f)
     if d.get("source_sha") != source_sha():
         return None
-    return d.get("bytes_per_dispatch")
+    for rec in d.get("by_tuning", []):
+        if rec.get("tuning") == dict(tuning):
+            return rec.get("bytes_per_dispatch")
+    return None
 
 
 def time_steps(fn, steps, torch):
@@ -129,6 +133,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch tuning")
+    ap.add_argument("--tuning", default=None,
+                    help="fixed launch tuning chunk_pairs,streams,nt_store,front instead of autotuning")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--fft-only", action="store_true",
@@ -171,7 +177,12 @@ def main():
     A = torch.from_numpy(inst.A).to(tdt).to(dev)
     X = torch.empty((N, t), dtype=tdt, device=dev)
     tuning = plan.get_tuning()
-    if not args.no_tune:
+    if args.tuning:
+        c, st, nt, fr = (int(v) for v in args.tuning.split(","))
+        plan.set_tuning(chunk_pairs=c, streams=st, nt_store=nt, front=fr)
+        tuning = plan.get_tuning()
+        log(f"fixed launch tuning: {tuning}")
+    elif not args.no_tune:
         from paper_1501_06286_amd import autotune
         tuning, _ = autotune.tune(plan, t, reps=3)
         log(f"autotuned launch: {tuning}")
@@ -213,9 +224,7 @@ def main():
     ai = dmdl["flops"] / max(dmdl["bytes"], 1)
     ridge = VALU_PEAK_TFLOPS[args.dtype] * 1e12 / (HBM_PEAK_GBPS * 1e9)
     workload = f"c2_gauss_n{N}_s{s}_t{t}_{args.dtype}"
-    traffic = measured_traffic(dom, workload)
-    if traffic is not None:
-        traffic = traffic  # bytes per launch of the same chunking (see profiles/)
+    traffic = measured_traffic(dom, workload, tuning)  # bytes per launch, same chunking
     if ai > ridge:
         ach = dmdl["flops"] / davg_s / 1e12
         roof = {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_TFLOPS[args.dtype],

@@ -137,13 +137,21 @@ int qmc_plan_tables(qmc_plan_t plan, int32_t* pow_out, int32_t* log_out,
  *   streams      1, or 2 to run the back pass of chunk c on a second stream,
  *                overlapping the fused pass of chunk c+1 (needs chunk_pairs > 0)
  *   nt_store     1 = write X with non-temporal stores
+ *   front        how qmc_matmul forms the outer DFT of the collapsed columns:
+ *                1 = sparse: the fused pass sums the s rows of A directly for
+ *                every outer frequency (cost grows with s times M2);
+ *                2 = dense: a gather pass collapses A into length-M columns and
+ *                transforms the outer index (extra passes over M per pair,
+ *                one stream); 0 = dense when s > 8 M1, else sparse
  * The workspace size depends on the tuning: query it after setting it.
- * Returns QMC_ERR_ARG for negative chunks or streams outside {1, 2}.
+ * Returns QMC_ERR_ARG for negative chunks, streams outside {1, 2}, nt_store
+ * outside {0, 1} or front outside {0, 1, 2}.
  */
 typedef struct {
     int64_t chunk_pairs;
     int streams;
     int nt_store;
+    int front;
 } qmc_tuning_t;
 int qmc_plan_set_tuning(qmc_plan_t plan, const qmc_tuning_t* tuning);
 int qmc_plan_get_tuning(qmc_plan_t plan, qmc_tuning_t* tuning);
@@ -233,7 +241,7 @@ int qmc_matmul_batched(int count, const qmc_plan_t* plans, const void* const* A,
  * the number of launches (arrays of QMC_PROF_SLOTS entries, host memory) and
  * forgets the events.  Slot names: qmc_profile_slot_name.
  */
-#define QMC_PROF_SLOTS 8
+#define QMC_PROF_SLOTS 10
 int qmc_profile_enable(qmc_plan_t plan, int on);
 int qmc_profile_collect(qmc_plan_t plan, double* total_ms, int64_t* launches);
 const char* qmc_profile_slot_name(int slot);

@@ -38,7 +38,7 @@ EXPORTED = [
     "qmc_plan_set_tuning", "qmc_plan_get_tuning",
     "qmc_batch_create", "qmc_batch_workspace_size", "qmc_batch_run", "qmc_batch_destroy",
 ]
-PROF_SLOTS = 8
+PROF_SLOTS = 10
 
 
 class QMCError(RuntimeError):
@@ -48,7 +48,8 @@ class QMCError(RuntimeError):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("chunk_pairs", ctypes.c_int64), ("streams", ctypes.c_int), ("nt_store", ctypes.c_int)]
+    _fields_ = [("chunk_pairs", ctypes.c_int64), ("streams", ctypes.c_int), ("nt_store", ctypes.c_int),
+                ("front", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -201,15 +202,17 @@ class Plan:
                "qmc_plan_tables")
         return pw, lg, el, ph
 
-    def set_tuning(self, chunk_pairs: int = 0, streams: int = 1, nt_store: int = 0) -> None:
+    def set_tuning(self, chunk_pairs: int = 0, streams: int = 1, nt_store: int = 0,
+                   front: int = 0) -> None:
         """Launch tuning (see autotune.py); changes the workspace size."""
-        tu = Tuning(int(chunk_pairs), int(streams), int(nt_store))
+        tu = Tuning(int(chunk_pairs), int(streams), int(nt_store), int(front))
         _check(lib().qmc_plan_set_tuning(self.handle, ctypes.byref(tu)), "qmc_plan_set_tuning")
 
     def get_tuning(self) -> dict:
         tu = Tuning()
         _check(lib().qmc_plan_get_tuning(self.handle, ctypes.byref(tu)), "qmc_plan_get_tuning")
-        return {"chunk_pairs": tu.chunk_pairs, "streams": tu.streams, "nt_store": tu.nt_store}
+        return {"chunk_pairs": tu.chunk_pairs, "streams": tu.streams, "nt_store": tu.nt_store,
+                "front": tu.front}
 
     def profile(self, on: bool = True) -> None:
         """Bracket every kernel launch of this plan with HIP events."""

@@ -1,10 +1,10 @@
 """Launch-configuration autotuner.
 
 For a plan and a column count t it times the candidate launch tunings of
-``qmc_plan_set_tuning`` (chunk of column pairs per fused/back pass, one or two
-streams, plain or non-temporal stores of X) on the GPU with HIP events, keeps
-the fastest, and caches the choice in a JSON file keyed by the GPU
-architecture and the plan's shape (rule, L, M, s, t, dtype).
+``qmc_plan_set_tuning`` (sparse or dense outer front, chunk of column pairs
+per pass, one or two streams, plain or non-temporal stores of X) on the GPU
+with HIP events, keeps the fastest, and caches the choice in a JSON file keyed
+by the GPU architecture and the plan's shape (rule, L, M, s, t, dtype).
 """
 from __future__ import annotations
 
@@ -17,12 +17,17 @@ CACHE = os.environ.get("QMC_AUTOTUNE_CACHE",
 
 
 def candidates(pairs: int) -> List[Dict[str, int]]:
-    chunks = [0] + [c for c in (64, 128, 256, 512, 1024) if c < pairs]
+    """Sparse front: every chunk, one or two streams, plain or non-temporal
+    stores.  Dense front (one stream): every chunk, both store kinds."""
+    chunks = [0] + [c for c in (8, 16, 32, 64, 128, 256, 512, 1024) if c < pairs]
     out = []
     for c in chunks:
         for streams in ((1, 2) if c else (1,)):
             for nt in (0, 1):
-                out.append({"chunk_pairs": c, "streams": streams, "nt_store": nt})
+                out.append({"chunk_pairs": c, "streams": streams, "nt_store": nt, "front": 1})
+    for c in chunks:
+        for nt in (0, 1):
+            out.append({"chunk_pairs": c, "streams": 1, "nt_store": nt, "front": 2})
     return out
 
 

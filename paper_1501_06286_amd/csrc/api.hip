@@ -138,16 +138,20 @@ int qmc_profile_collect(qmc_plan_t P, double* total_ms, int64_t* launches) {
   return rc;
 }
 
+static_assert(PROF_NSLOTS == QMC_PROF_SLOTS, "profiling slots of the header");
+
 const char* qmc_profile_slot_name(int slot) {
-  static const char* names[PROF_NSLOTS] = {"collapse_T", "middle", "outer_split", "back",
-                                           "adj_front", "adj_split", "adj_middle", "adj_back"};
+  static const char* names[PROF_NSLOTS] = {"collapse_T", "middle",    "outer_split",
+                                           "back",       "adj_front", "adj_split",
+                                           "adj_middle", "adj_back",  "dense_front",
+                                           "dense_front_split"};
   return (slot >= 0 && slot < PROF_NSLOTS) ? names[slot] : "";
 }
 
 int qmc_plan_set_tuning(qmc_plan_t P, const qmc_tuning_t* tu) {
   if (!P || !tu) return QMC_ERR_ARG;
   if (tu->chunk_pairs < 0 || (tu->streams != 1 && tu->streams != 2) ||
-      (tu->nt_store != 0 && tu->nt_store != 1))
+      (tu->nt_store != 0 && tu->nt_store != 1) || tu->front < 0 || tu->front > 2)
     return QMC_ERR_ARG;
   P->tune = *tu;
   return QMC_OK;

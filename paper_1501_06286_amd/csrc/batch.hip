@@ -29,7 +29,6 @@ struct BatchInst {
   const void* twit;
   const void* twf1;
   const void* twf2;
-  const void* twf2t;
   const void* Hs;
   const void* twi3;
   const void* two;
@@ -78,7 +77,7 @@ __attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void kb_middle(const Bat
     const int64_t lb = b - I.off[PASS_MIDDLE];
     middle_body<T, R, true>((const cx<T>*)(ws + I.aT_off), I.Upad, I.rounds, I.it_e1,
                             (const cx<T>*)I.twit, (const cx<T>*)I.twf1, (const cx<T>*)I.twf2,
-                            (const cx<T>*)I.twf2t, (const cx<T>*)I.Hs, (const cx<T>*)I.twi3, (const cx<T>*)I.two, I.M2,
+                            (const cx<T>*)I.Hs, (const cx<T>*)I.twi3, (const cx<T>*)I.two, I.M2,
                             I.pairs, (cx<T>*)(ws + I.C_off), (T*)I.X, I.t, (T)I.phi0, lb, S,
                             opaque_tid());
     __syncthreads();
@@ -195,7 +194,6 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
     I.twit = P->d_twit;
     I.twf1 = P->d_twf1;
     I.twf2 = P->d_twf2;
-    I.twf2t = P->d_twf2t;
     I.Hs = P->d_Hs;
     I.twi3 = P->d_twi3;
     I.two = P->d_two;

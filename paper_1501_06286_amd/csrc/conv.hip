@@ -44,11 +44,11 @@ __global__ __launch_bounds__(MidShape<R>::BLOCK)
 __attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void k_middle(
     const cx<T>* __restrict__ src, int64_t Upad, int64_t rounds, const int32_t* __restrict__ it_e1,
     const cx<T>* __restrict__ twit, const cx<T>* __restrict__ twf1,
-    const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ twf2t, const cx<T>* __restrict__ Hs,
+    const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs,
     const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M2, int64_t P,
     cx<T>* __restrict__ C, T* __restrict__ X, int64_t t, T phi0) {
   __shared__ MidSmem<T, R> S;
-  middle_body<T, R, SPARSE>(src, Upad, rounds, it_e1, twit, twf1, twf2, twf2t, Hs, twi3, two, M2,
+  middle_body<T, R, SPARSE>(src, Upad, rounds, it_e1, twit, twf1, twf2, Hs, twi3, two, M2,
                             P, C, X, t, phi0, xcd_remap(blockIdx.x, gridDim.x), S, threadIdx.x);
 }
 
@@ -78,8 +78,22 @@ __global__ __launch_bounds__(256) void k_adj_front(const T* __restrict__ G, int6
                                                    const cx<T>* __restrict__ twb,
                                                    cx<T>* __restrict__ B) {
   __shared__ BackSmem<T> S;
-  adj_front_body<T, Q>(G, ldg, t, M1, M2, P2, L, P, pow, twb, B, blockIdx.x, blockIdx.y,
-                       blockIdx.z, S, threadIdx.x);
+  const AdjGather<T> g{{G, ldg, t, pairs_aligned(G, ldg)}, pow, L};
+  outer_front_body<T, Q>(g, M1, M2, P2, L, P, twb, B, blockIdx.x, blockIdx.y, blockIdx.z, S,
+                         threadIdx.x);
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(256) void k_fwd_front(const T* __restrict__ A, int64_t lda, int64_t t,
+                                                   int64_t M1, int64_t M2, int64_t P2, int64_t L,
+                                                   int64_t P, const int32_t* __restrict__ inv_ptr,
+                                                   const int32_t* __restrict__ inv_j,
+                                                   const cx<T>* __restrict__ twb,
+                                                   cx<T>* __restrict__ B) {
+  __shared__ BackSmem<T> S;
+  const FwdGather<T> g{{A, lda, t, pairs_aligned(A, lda)}, inv_ptr, inv_j, L};
+  outer_front_body<T, Q>(g, M1, M2, P2, L, P, twb, B, blockIdx.x, blockIdx.y, blockIdx.z, S,
+                         threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -95,51 +109,64 @@ static int64_t fwd_c_pairs(const qmc_plan_s* P, int64_t pairs) {
   return std::min(pairs, ch * slots);
 }
 
+// whether qmc_matmul uses the dense outer front (tuning field front; 0 picks
+// it when the sparse front's per-frequency sums over all s rows cost more
+// than the extra passes over the length-M columns: measured on MI355X, the
+// two break even near s = 4 M1, so the switch is at s > 8 M1)
+bool dense_front(const qmc_plan_s* P) {
+  if (P->tune.front != 0) return P->tune.front == 2;
+  return P->s > 8 * P->lay.M1;
+}
+
 size_t workspace_bytes(const qmc_plan_s* P, int64_t t) {
   const size_t el = (P->dtype == QMC_F32) ? sizeof(cx<float>) : sizeof(cx<double>);
   const int64_t pairs = (t + 1) / 2;
   const size_t aT = align256(pairs * P->Upad * el);
-  const size_t fwd = aT + align256(fwd_c_pairs(P, pairs) * P->lay.M * el);
+  const int64_t chunk = (P->tune.chunk_pairs > 0 && P->tune.chunk_pairs < pairs)
+                            ? P->tune.chunk_pairs : pairs;
+  const size_t fwd = dense_front(P) ? 2 * align256(chunk * P->lay.M * el)
+                                    : aT + align256(fwd_c_pairs(P, pairs) * P->lay.M * el);
   const size_t adj = aT + 2 * align256(pairs * P->lay.M * el);
   return std::max(fwd, adj);
 }
 
 template <typename T, int R, bool SPARSE>
 static void launch_middle_r(const qmc_plan_s* P, const cx<T>* src, int64_t pairs, cx<T>* C,
-                            T* X, int64_t t, hipStream_t st) {
+                            T* X, int64_t t, int slot, hipStream_t st) {
   const Layout& lay = P->lay;
   typedef MidShape<R> S;
   const int64_t groups = (pairs + S::TPB - 1) / S::TPB;
   const int64_t G = groups * lay.M2;
-  ProfScope ps(P, SPARSE ? PROF_MIDDLE : PROF_ADJ_MIDDLE, st);
+  ProfScope ps(P, slot, st);
   k_middle<T, R, SPARSE><<<dim3((unsigned)G), dim3(S::BLOCK), 0, st>>>(
       src, P->Upad, P->rounds, P->d_it_e1, (const cx<T>*)P->d_twit, (const cx<T>*)P->d_twf1,
-      (const cx<T>*)P->d_twf2, (const cx<T>*)P->d_twf2t, (const cx<T>*)P->d_Hs,
+      (const cx<T>*)P->d_twf2, (const cx<T>*)P->d_Hs,
       (const cx<T>*)P->d_twi3,
       (const cx<T>*)P->d_two, lay.M2, pairs, C, X, t, (T)P->phi0);
 }
 
+// X != nullptr: forward product, the DC term of each pair goes to row 0
 template <typename T, bool SPARSE>
 static int launch_middle(const qmc_plan_s* P, const cx<T>* src, int64_t pairs, cx<T>* C, T* X,
-                         int64_t t, hipStream_t st) {
+                         int64_t t, int slot, hipStream_t st) {
   switch (P->lay.R) {
-    case 1: launch_middle_r<T, 1, SPARSE>(P, src, pairs, C, X, t, st); break;
-    case 2: launch_middle_r<T, 2, SPARSE>(P, src, pairs, C, X, t, st); break;
-    case 4: launch_middle_r<T, 4, SPARSE>(P, src, pairs, C, X, t, st); break;
-    case 8: launch_middle_r<T, 8, SPARSE>(P, src, pairs, C, X, t, st); break;
-    case 16: launch_middle_r<T, 16, SPARSE>(P, src, pairs, C, X, t, st); break;
+    case 1: launch_middle_r<T, 1, SPARSE>(P, src, pairs, C, X, t, slot, st); break;
+    case 2: launch_middle_r<T, 2, SPARSE>(P, src, pairs, C, X, t, slot, st); break;
+    case 4: launch_middle_r<T, 4, SPARSE>(P, src, pairs, C, X, t, slot, st); break;
+    case 8: launch_middle_r<T, 8, SPARSE>(P, src, pairs, C, X, t, slot, st); break;
+    case 16: launch_middle_r<T, 16, SPARSE>(P, src, pairs, C, X, t, slot, st); break;
     default: return QMC_ERR_UNSUPPORTED;
   }
   return hip_ok(hipGetLastError());
 }
 
 template <typename T, int DIR>
-static int launch_split(const qmc_plan_s* P, cx<T>* C, int64_t pairs, hipStream_t st) {
+static int launch_split(const qmc_plan_s* P, cx<T>* C, int64_t pairs, int slot, hipStream_t st) {
   const Layout& lay = P->lay;
   if (lay.P2 == 1) return QMC_OK;
   dim3 grid((unsigned)((lay.M1 + 63) / 64), (unsigned)lay.Q2, (unsigned)pairs);
   const cx<T>* twb = (const cx<T>*)P->d_twb;
-  ProfScope ps(P, DIR > 0 ? PROF_SPLIT : PROF_ADJ_SPLIT, st);
+  ProfScope ps(P, slot, st);
   switch (lay.P2) {
     case 2: k_outer_split<T, 2, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
     case 4: k_outer_split<T, 4, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
@@ -196,9 +223,35 @@ static int back_dispatch(const qmc_plan_s* P, const cx<T>* C, int64_t np, T* X, 
 // of column pairs.  With two streams the back pass of chunk c runs on the
 // plan's side stream while the caller's stream starts chunk c+1; the two
 // spectrum slots alternate and are released by events.
+// X = Y A with the dense outer front, per chunk of column pairs: gather and
+// transform the outer index into B, the fused pass (dense front) into C, the
+// outer split and the back pass.  One stream.
+template <typename T>
+static int forward_dense_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T* X,
+                           int64_t ldx, void* ws, hipStream_t st) {
+  const int64_t pairs = (t + 1) / 2;
+  const int64_t chunk = (P->tune.chunk_pairs > 0 && P->tune.chunk_pairs < pairs)
+                            ? P->tune.chunk_pairs : pairs;
+  cx<T>* B = (cx<T>*)ws;
+  cx<T>* C = (cx<T>*)((char*)ws + align256(chunk * P->lay.M * sizeof(cx<T>)));
+  for (int64_t p0 = 0; p0 < pairs; p0 += chunk) {
+    const int64_t np = std::min(chunk, pairs - p0), tc = t - 2 * p0;
+    int rc = launch_outer_front<T>(P, A + 2 * p0, nullptr, lda, tc, np, B, st);
+    if (rc != QMC_OK) return rc;
+    rc = launch_middle<T, false>(P, B, np, C, X + 2 * p0, tc, PROF_MIDDLE, st);
+    if (rc != QMC_OK) return rc;
+    rc = launch_split<T, +1>(P, C, np, PROF_SPLIT, st);
+    if (rc != QMC_OK) return rc;
+    rc = back_dispatch<T>(P, C, np, X + 2 * p0, ldx, tc, st);
+    if (rc != QMC_OK) return rc;
+  }
+  return QMC_OK;
+}
+
 template <typename T>
 static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T* X, int64_t ldx,
                      void* ws, hipStream_t st) {
+  if (dense_front(P)) return forward_dense_t<T>(P, A, t, lda, X, ldx, ws, st);
   const int64_t pairs = (t + 1) / 2;
   const size_t el = sizeof(cx<T>);
   cx<T>* aT = (cx<T>*)ws;
@@ -229,9 +282,10 @@ static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T*
     if (two && c >= 2) {  // the back pass of chunk c-2 has released this slot
       if ((rc = hip_ok(hipStreamWaitEvent(st, P->ev[2 + slot], 0))) != QMC_OK) return rc;
     }
-    rc = launch_middle<T, true>(P, aT + p0 * P->Upad, np, C, X + 2 * p0, t - 2 * p0, st);
+    rc = launch_middle<T, true>(P, aT + p0 * P->Upad, np, C, X + 2 * p0, t - 2 * p0,
+                                PROF_MIDDLE, st);
     if (rc != QMC_OK) return rc;
-    rc = launch_split<T, +1>(P, C, np, st);
+    rc = launch_split<T, +1>(P, C, np, PROF_SPLIT, st);
     if (rc != QMC_OK) return rc;
     if (two) {
       if ((rc = hip_ok(hipEventRecord(P->ev[slot], st))) != QMC_OK) return rc;
@@ -257,32 +311,39 @@ int launch_forward(const qmc_plan_s* P, const void* A, int64_t t, int64_t lda, v
   return forward_t<double>(P, (const double*)A, t, lda, (double*)X, ldx, ws, st);
 }
 
+// dense outer front into B[pair][w2][e1]: the adjoint's gather of G
+// (A == nullptr) or the forward's collapse of A, then the outer split
 template <typename T>
-static int launch_adj_front(const qmc_plan_s* P, const T* G, int64_t ldg, int64_t t,
-                            int64_t pairs, cx<T>* B, hipStream_t st) {
+static int launch_outer_front(const qmc_plan_s* P, const T* A, const T* G, int64_t ld,
+                              int64_t t, int64_t pairs, cx<T>* B, hipStream_t st) {
   const Layout& lay = P->lay;
   dim3 grid((unsigned)((lay.M1 + 15) / 16), (unsigned)((pairs + 15) / 16), (unsigned)lay.P2);
   const cx<T>* twb = (const cx<T>*)P->d_twb;
+  const bool fwd = A != nullptr;
   {
-    ProfScope ps(P, PROF_ADJ_FRONT, st);
-#define QMC_AFRONT(QQ)                                                                        \
-  k_adj_front<T, QQ><<<grid, 256, 0, st>>>(G, ldg, t, lay.M1, lay.M2, lay.P2, P->L, pairs, \
-                                           P->d_pow, twb, B)
+    ProfScope ps(P, fwd ? PROF_DFRONT : PROF_ADJ_FRONT, st);
+#define QMC_OFRONT(QQ)                                                                         \
+  if (fwd)                                                                                     \
+    k_fwd_front<T, QQ><<<grid, 256, 0, st>>>(A, ld, t, lay.M1, lay.M2, lay.P2, P->L, pairs,   \
+                                             P->d_inv_ptr, P->d_inv_j, twb, B);               \
+  else                                                                                         \
+    k_adj_front<T, QQ><<<grid, 256, 0, st>>>(G, ld, t, lay.M1, lay.M2, lay.P2, P->L, pairs,   \
+                                             P->d_pow, twb, B)
     switch (lay.Q2) {
-      case 1: QMC_AFRONT(1); break;
-      case 2: QMC_AFRONT(2); break;
-      case 4: QMC_AFRONT(4); break;
-      case 8: QMC_AFRONT(8); break;
-      case 16: QMC_AFRONT(16); break;
-      case 32: QMC_AFRONT(32); break;
-      case 64: QMC_AFRONT(64); break;
+      case 1: QMC_OFRONT(1); break;
+      case 2: QMC_OFRONT(2); break;
+      case 4: QMC_OFRONT(4); break;
+      case 8: QMC_OFRONT(8); break;
+      case 16: QMC_OFRONT(16); break;
+      case 32: QMC_OFRONT(32); break;
+      case 64: QMC_OFRONT(64); break;
       default: return QMC_ERR_UNSUPPORTED;
     }
-#undef QMC_AFRONT
+#undef QMC_OFRONT
   }
   int rc = hip_ok(hipGetLastError());
   if (rc != QMC_OK) return rc;
-  return launch_split<T, -1>(P, B, pairs, st);
+  return launch_split<T, -1>(P, B, pairs, fwd ? PROF_DFRONT_SPLIT : PROF_ADJ_SPLIT, st);
 }
 
 template <typename T>
@@ -292,11 +353,11 @@ static int adjoint_t(const qmc_plan_s* P, const T* G, int64_t t, int64_t ldg, T*
   const size_t el = sizeof(cx<T>);
   cx<T>* B = (cx<T>*)((char*)ws + align256(pairs * P->Upad * el));
   cx<T>* C = (cx<T>*)((char*)B + align256(pairs * P->lay.M * el));
-  int rc = launch_adj_front<T>(P, G, ldg, t, pairs, B, st);
+  int rc = launch_outer_front<T>(P, nullptr, G, ldg, t, pairs, B, st);
   if (rc != QMC_OK) return rc;
-  rc = launch_middle<T, false>(P, B, pairs, C, nullptr, t, st);
+  rc = launch_middle<T, false>(P, B, pairs, C, nullptr, t, PROF_ADJ_MIDDLE, st);
   if (rc != QMC_OK) return rc;
-  rc = launch_split<T, +1>(P, C, pairs, st);
+  rc = launch_split<T, +1>(P, C, pairs, PROF_SPLIT, st);
   if (rc != QMC_OK) return rc;
   return launch_back<T, true>(P, C, pairs, P->d_inv_ptr, P->d_inv_j, G, dA, ldda, t, st);
 }

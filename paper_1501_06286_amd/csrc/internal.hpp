@@ -22,7 +22,8 @@ struct Layout {
 // per-kernel timing slots (HIP events recorded around each launch when on)
 enum ProfSlotId {
   PROF_COLLAPSE = 0, PROF_MIDDLE, PROF_SPLIT, PROF_BACK,
-  PROF_ADJ_FRONT, PROF_ADJ_SPLIT, PROF_ADJ_MIDDLE, PROF_ADJ_BACK, PROF_NSLOTS
+  PROF_ADJ_FRONT, PROF_ADJ_SPLIT, PROF_ADJ_MIDDLE, PROF_ADJ_BACK, PROF_DFRONT, PROF_DFRONT_SPLIT,
+  PROF_NSLOTS
 };
 
 struct ProfEvents {
@@ -55,7 +56,6 @@ struct qmc_plan_s {
   void* d_Hs = nullptr;         // M   : spectrum / M, [w2] then thread g + R f value h for w1 = f + R g + R^2 h (paired)
   void* d_twf1 = nullptr;       // R*R^2: W_{M1}^{e1' f}, thread e1' (< R^2), value f (paired)
   void* d_twf2 = nullptr;       // R*R : W_{R^2}^{a g}, thread a, value g (paired layout)
-  void* d_twf2t = nullptr;      // R*R : W_{R^2}^{a g}, thread g, value a (paired layout)
   void* d_twi3 = nullptr;       // M   : conj W_M^{e1' (f M2 + w2)}, [w2] then thread a + R f value bb, e1' = a + R bb (paired)
   void* d_two = nullptr;        // M2*R: conj W_M^{R^2 c w2} in [w2][c] order
   void* d_twit = nullptr;       // M2*Upad: W_M^{slot_u w2} in [w2][u] order
@@ -65,7 +65,7 @@ struct qmc_plan_s {
   int32_t* d_inv_ptr = nullptr;    // L+1 : rows j with l_j = e are inv_j[inv_ptr[e] .. inv_ptr[e+1])
   int32_t* d_inv_j = nullptr;      // s
   std::vector<void*> owned;
-  qmc_tuning_t tune = {0, 1, 0};
+  qmc_tuning_t tune = {0, 1, 0, 0};
   // second stream and events for the two-stream chunk pipeline (created lazily)
   mutable hipStream_t side = nullptr;
   mutable hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -80,6 +80,7 @@ namespace qmc {
 int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st);
 
 // conv.hip
+bool dense_front(const qmc_plan_s* P);
 size_t workspace_bytes(const qmc_plan_s* P, int64_t t);
 int launch_forward(const qmc_plan_s* P, const void* A, int64_t t, int64_t lda, void* X,
                    int64_t ldx, void* ws, hipStream_t st);

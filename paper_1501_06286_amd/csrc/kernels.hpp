@@ -149,6 +149,7 @@ constexpr int mid_waves() {
 template <typename T, int R>
 struct MidSmem {
   cx<T> lds[MidShape<R>::TPB * MidShape<R>::BUFN];
+  cx<T> wr2[R * (R + 1)];  // W_{R^2}^{i j} at [i][j], rows padded to R + 1
 };
 
 // b: logical block of this product (w2 = b mod M2, pair group = b / M2)
@@ -157,7 +158,7 @@ __device__ __forceinline__ void middle_body(
     const cx<T>* __restrict__ src,      // SPARSE: aT [pair][Upad]; dense: B [pair][M2][M1]
     int64_t Upad, int64_t rounds, const int32_t* __restrict__ it_e1,
     const cx<T>* __restrict__ twit, const cx<T>* __restrict__ twf1,
-    const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ twf2t, const cx<T>* __restrict__ Hs,
+    const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs,
     const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M2, int64_t P,
     cx<T>* __restrict__ C, T* __restrict__ X, int64_t t, T phi0, int64_t b, MidSmem<T, R>& SM,
     int tid) {
@@ -177,6 +178,10 @@ __device__ __forceinline__ void middle_body(
   // latency hides behind the front and the steps in between.
   cx<T> tw_a[R], tw_b[R], hv[R];
   load_paired<T, R>(tw_a, twf1, q, Q);
+  // the R x R roots W_{R^2}^{a g} of the middle steps live in LDS (first
+  // read after the barriers of step 1); twf2 holds value g of thread a
+  for (int i = tid; i < R * R; i += S::BLOCK)
+    SM.wr2[(i % R) * (R + 1) + i / R] = twf2[paired_index(i / R, i % R, R, pair_pp(R))];
 
   // ---- front: B[e1] for this w2, in registers of thread e1' = q ----------
   if constexpr (SPARSE) {
@@ -270,9 +275,9 @@ __device__ __forceinline__ void middle_body(
 #pragma unroll
   for (int bb = 0; bb < R; ++bb) x[bb] = grp[gl + R * bb];
   reg_fft<T, R, -1>(x);
-  load_paired<T, R>(tw_b, twf2, gl, R);
+  const cx<T>* wrow = SM.wr2 + gl * (R + 1);  // W_{R^2}^{gl j}, j < R
 #pragma unroll
-  for (int g = 1; g < R; ++g) x[g] = cmul(x[g], tw_b[g]);
+  for (int g = 1; g < R; ++g) x[g] = cmul(x[g], wrow[g]);
   wave_lds_sync();
 #pragma unroll
   for (int g = 0; g < R; ++g) grp[g * (R + 1) + gl] = x[g];
@@ -282,20 +287,17 @@ __device__ __forceinline__ void middle_body(
   for (int a = 0; a < R; ++a) x[a] = grp[gl * (R + 1) + a];
   reg_fft<T, R, -1>(x);  // x[h] = X[f + R g + R^2 h]
 
-  if constexpr (SPARSE) {
-    if (w2 == 0 && q == 0 && active) {  // DC term -> row 0
-      X[2 * pair] = phi0 * x[0].x;
-      if (2 * pair + 1 < t) X[2 * pair + 1] = phi0 * x[0].y;
-    }
+  if (X != nullptr && w2 == 0 && q == 0 && active) {  // forward: DC term -> row 0
+    X[2 * pair] = phi0 * x[0].x;
+    if (2 * pair + 1 < t) X[2 * pair + 1] = phi0 * x[0].y;
   }
 #pragma unroll
   for (int h = 0; h < R; ++h) x[h] = cmul(x[h], hv[h]);
 
   // ---- inverse step 1: thread (g = gl, f): IDFT over h -> a ---------------
   reg_fft<T, R, +1>(x);
-  load_paired<T, R>(tw_a, twf2t, gl, R);
 #pragma unroll
-  for (int a = 1; a < R; ++a) x[a] = cmulc(x[a], tw_a[a]);
+  for (int a = 1; a < R; ++a) x[a] = cmulc(x[a], wrow[a]);
   wave_lds_sync();
 #pragma unroll
   for (int a = 0; a < R; ++a) grp[a * (R + 1) + gl] = x[a];
@@ -458,24 +460,72 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
 }
 
 // ---------------------------------------------------------------------------
-// adjoint front: g~[m] = G[pow[(L - m) mod L]] (m < L; 0 for L <= m < M)
-// gathered with coalesced row reads, then the forward DFT over e2.  With
-// M2 = P2 * Q: thread (pair, e1, a) transforms e2 = a + P2 b over b (length
-// Q) and multiplies by W_{M2}^{a q}; k_outer_split<-1> finishes over a.
+// dense outer front: the length-M input column pair v[m] (m < L; 0 for
+// L <= m < M) is gathered with coalesced row reads, then transformed over
+// e2 (the forward DFT of the outer index).  With M2 = P2 * Q: thread
+// (pair, e1, a) transforms e2 = a + P2 b over b (length Q) and multiplies by
+// W_{M2}^{a q}; k_outer_split<-1> finishes over a.
 // Output: B[pair][w2][e1] (natural w2 order once the split has run).
+//   adjoint:  v[m] = G[pow[(L - m) mod L]]                      (gather)
+//   forward:  v[m] = sum of A[j] over j with l_j = (L - m) mod L (the
+//             reflected collapse, Section 2.1, as a gather through the
+//             CSR lists of equal l_j, in increasing j)
 // ---------------------------------------------------------------------------
-template <typename T, int Q>
-__device__ __forceinline__ void adj_front_body(const T* __restrict__ G, int64_t ldg, int64_t t,
-                                               int64_t M1, int64_t M2, int64_t P2, int64_t L,
-                                               int64_t P, const int32_t* __restrict__ pow,
-                                               const cx<T>* __restrict__ twb,
-                                               cx<T>* __restrict__ B, int64_t bx, int64_t by,
-                                               int64_t a, BackSmem<T>& S, int tid) {
+template <typename T>
+struct RowPairReader {  // columns 2 pair, 2 pair + 1 of a row-major matrix
+  const T* __restrict__ M;
+  int64_t ld, t;
+  bool v2;
+  __device__ __forceinline__ cx<T> operator()(int64_t row, int64_t pair) const {
+    const T* r = M + row * ld;
+    const int64_t col = 2 * pair;
+    cx<T> g = {(T)0, (T)0};
+    if (v2 && col + 1 < t) {
+      const vec2_t<T> gg = *reinterpret_cast<const vec2_t<T>*>(r + col);
+      g.x = gg.x;
+      g.y = gg.y;
+    } else {
+      g.x = r[col];
+      if (col + 1 < t) g.y = r[col + 1];
+    }
+    return g;
+  }
+};
+
+template <typename T>
+struct AdjGather {
+  RowPairReader<T> G;
+  const int32_t* __restrict__ pow;
+  int64_t L;
+  __device__ __forceinline__ cx<T> operator()(int64_t m, int64_t pair) const {
+    return G((int64_t)pow[(L - m) % L], pair);
+  }
+};
+
+template <typename T>
+struct FwdGather {
+  RowPairReader<T> A;
+  const int32_t* __restrict__ inv_ptr;
+  const int32_t* __restrict__ inv_j;
+  int64_t L;
+  __device__ __forceinline__ cx<T> operator()(int64_t m, int64_t pair) const {
+    const int64_t e = (L - m) % L;
+    cx<T> acc = {(T)0, (T)0};
+    for (int32_t jj = inv_ptr[e]; jj < inv_ptr[e + 1]; ++jj) acc = acc + A(inv_j[jj], pair);
+    return acc;
+  }
+};
+
+template <typename T, int Q, typename Gather>
+__device__ __forceinline__ void outer_front_body(const Gather& gather, int64_t M1, int64_t M2,
+                                                 int64_t P2, int64_t L, int64_t P,
+                                                 const cx<T>* __restrict__ twb,
+                                                 cx<T>* __restrict__ B, int64_t bx, int64_t by,
+                                                 int64_t a, BackSmem<T>& S, int tid) {
   constexpr int PB = 16, EB = 16;
   constexpr int CH = Q < BACK_CH ? Q : BACK_CH;
   auto& sm = S.sm;
   const int64_t e1_0 = bx * EB, p0 = by * PB;
-  const bool v2 = pairs_aligned(G, ldg);
   const int pw = tid % PB, ew = tid / PB;     // gather mapping (pair-fast)
   const int el = tid % EB, pl = tid / EB;     // transform mapping (e1-fast)
   const int64_t pairw = p0 + pw, e1w = e1_0 + ew;
@@ -487,19 +537,7 @@ __device__ __forceinline__ void adj_front_body(const T* __restrict__ G, int64_t 
     for (int c = 0; c < CH; ++c) {
       const int64_t e = e1w + M1 * (a + P2 * (c0 + c));
       cx<T> g = {(T)0, (T)0};
-      if (pairw < P && e1w < M1 && e < L) {
-        const int64_t src = (L - e) % L;
-        const T* row = G + (int64_t)pow[src] * ldg;
-        const int64_t col = 2 * pairw;
-        if (v2 && col + 1 < t) {
-          const vec2_t<T> gg = *reinterpret_cast<const vec2_t<T>*>(row + col);
-          g.x = gg.x;
-          g.y = gg.y;
-        } else {
-          g.x = row[col];
-          if (col + 1 < t) g.y = row[col + 1];
-        }
-      }
+      if (pairw < P && e1w < M1 && e < L) g = gather(e, pairw);
       sm[c][ew][pw] = g;
     }
     __syncthreads();

@@ -309,16 +309,13 @@ __global__ void k_tw_f1(cx<T>* twf1, const cx<double>* W, int R, int64_t M, int6
   twf1[paired_index(f, e, Q, pair_pp(R))] = to_t<T>(W[(e * f * M2) & (M - 1)]);
 }
 
-// W_{R^2}^{a g} = W_M^{a g M / R^2}, twice: twf2 with thread a and value g,
-// twf2t with thread g and value a
+// twf2: thread a, value g: W_{R^2}^{a g} = W_M^{a g M / R^2}
 template <typename T>
-__global__ void k_tw_f2(cx<T>* twf2, cx<T>* twf2t, const cx<double>* W, int R, int64_t M) {
+__global__ void k_tw_f2(cx<T>* twf2, const cx<double>* W, int R, int64_t M) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= R * R) return;
   const int64_t g = i / R, a = i % R;
-  const cx<T> w = to_t<T>(W[(a * g * (M / ((int64_t)R * R))) & (M - 1)]);
-  twf2[paired_index(g, a, R, pair_pp(R))] = w;
-  twf2t[paired_index(a, g, R, pair_pp(R))] = w;
+  twf2[paired_index(g, a, R, pair_pp(R))] = to_t<T>(W[(a * g * (M / ((int64_t)R * R))) & (M - 1)]);
 }
 
 // twi3: block w2, thread a + R f, value bb: conj W_M^{e1' (f M2 + w2)} with
@@ -484,7 +481,6 @@ static int build_spectral_tables(qmc_plan_s* P, const cx<double>* dW, const cx<d
   cx<T>* Hs = dev_alloc<cx<T>>(P, M, &err);
   cx<T>* twf1 = dev_alloc<cx<T>>(P, (size_t)R * R * R, &err);
   cx<T>* twf2 = dev_alloc<cx<T>>(P, (size_t)R * R, &err);
-  cx<T>* twf2t = dev_alloc<cx<T>>(P, (size_t)R * R, &err);
   cx<T>* twi3 = dev_alloc<cx<T>>(P, M, &err);
   cx<T>* two = dev_alloc<cx<T>>(P, M2 * R, &err);
   cx<T>* twit = dev_alloc<cx<T>>(P, M2 * P->Upad, &err);
@@ -492,7 +488,7 @@ static int build_spectral_tables(qmc_plan_s* P, const cx<double>* dW, const cx<d
   if (err != QMC_OK) return err;
   k_spectrum_layout<T><<<nblk(M), 256, 0, st>>>(Hs, dH, R, M, M2);
   k_tw_f1<T><<<nblk(R * R * R), 256, 0, st>>>(twf1, dW, R, M, M2);
-  k_tw_f2<T><<<nblk(R * R), 256, 0, st>>>(twf2, twf2t, dW, R, M);
+  k_tw_f2<T><<<nblk(R * R), 256, 0, st>>>(twf2, dW, R, M);
   k_tw_i3<T><<<nblk(M), 256, 0, st>>>(twi3, dW, R, M, M2);
   k_tw_outer<T><<<nblk(M2 * R), 256, 0, st>>>(two, dW, R, M, M2);
   k_tw_items<T><<<nblk(M2 * P->Upad), 256, 0, st>>>(twit, dW, dslot, P->Upad, M, M2);
@@ -501,7 +497,6 @@ static int build_spectral_tables(qmc_plan_s* P, const cx<double>* dW, const cx<d
   P->d_Hs = Hs;
   P->d_twf1 = twf1;
   P->d_twf2 = twf2;
-  P->d_twf2t = twf2t;
   P->d_twi3 = twi3;
   P->d_two = two;
   P->d_twit = twit;

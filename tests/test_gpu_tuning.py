@@ -1,5 +1,6 @@
-"""Every launch tuning (chunks of column pairs, one or two streams, plain or
-non-temporal stores) gives the same X, to the parity bar, as the oracle."""
+"""Every launch tuning (sparse or dense outer front, chunks of column pairs,
+one or two streams, plain or non-temporal stores) gives the same X, to the
+parity bar, as the oracle."""
 import numpy as np
 import pytest
 
@@ -11,17 +12,19 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("chunk,streams,nt", [(0, 1, 1), (5, 1, 0), (5, 2, 0), (7, 2, 1), (16, 2, 0),
-                                              (1, 2, 1)])
-def test_tuned_forward(chunk, streams, nt, dtype):
+@pytest.mark.parametrize("chunk,streams,nt,front", [
+    (0, 1, 1, 1), (5, 1, 0, 1), (5, 2, 0, 1), (7, 2, 1, 1), (16, 2, 0, 1), (1, 2, 1, 1),
+    (0, 1, 0, 2), (5, 1, 1, 2), (16, 1, 0, 2), (1, 1, 0, 2), (3, 2, 0, 2)])
+def test_tuned_forward(chunk, streams, nt, front, dtype):
     torch = torch_cuda()
     import paper_1501_06286_amd as q
     N, s, t = 8209, 400, 33  # 17 column pairs: ragged chunks
     inst = qi.small_lattice(N, s, t, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype)
-    announce(f"tuning chunk={chunk} streams={streams} nt={nt} {dtype}")
+    announce(f"tuning chunk={chunk} streams={streams} nt={nt} front={front} {dtype}")
     p = plan_of(inst)
-    p.set_tuning(chunk_pairs=chunk, streams=streams, nt_store=nt)
-    assert p.get_tuning() == {"chunk_pairs": chunk, "streams": streams, "nt_store": nt}
+    p.set_tuning(chunk_pairs=chunk, streams=streams, nt_store=nt, front=front)
+    assert p.get_tuning() == {"chunk_pairs": chunk, "streams": streams, "nt_store": nt,
+                              "front": front}
     A = to_dev(inst.A, dtype)
     X1 = q.matmul(p, A)
     X2 = q.matmul(p, A)  # back-to-back calls reuse the slots and events
@@ -34,7 +37,8 @@ def test_tuning_rejects_bad_values():
     torch_cuda()
     import paper_1501_06286_amd as q
     p = plan_of(qi.small_lattice(101, 5, 2))
-    for bad in ({"chunk_pairs": -1}, {"streams": 3}, {"nt_store": 2}):
+    for bad in ({"chunk_pairs": -1}, {"streams": 3}, {"nt_store": 2}, {"front": 3},
+                {"front": -1}):
         with pytest.raises(q.QMCError):
             p.set_tuning(**bad)
 
@@ -50,3 +54,33 @@ def test_autotune_picks_a_candidate(tmp_path, monkeypatch):
     assert p.get_tuning() == best
     best2, _ = autotune.tune(p, 64)  # from the cache
     assert best2 == best
+
+
+# dense outer front on every layout kind: direct and embedded lengths, the
+# split outer pass (M2 > 64), GF(2), repeated generators, odd t, one column
+DENSE_CASES = [
+    ("lattice", 2003, 500, 7), ("lattice", 65537, 300, 4), ("lattice", 139999, 100, 3),
+    ("lattice", 557057, 64, 2), ("lattice", 101, 300, 1), ("gf2", 12, 900, 5), ("gf2", 18, 50, 2),
+]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("kind,n,s,t", DENSE_CASES)
+def test_dense_front_matches_oracle_and_sparse(kind, n, s, t, dtype):
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    if kind == "lattice":
+        inst = qi.small_lattice(n, s, t, phi=qi.PHI_INVNORM, shift=(1, 2 * n), dtype=dtype, seed=11)
+    else:
+        inst = qi.small_gf2(n, s, t, dtype=dtype, seed=11)
+    announce(f"dense front {inst.name} {dtype}")
+    p = plan_of(inst)
+    A = to_dev(inst.A, dtype)
+    p.set_tuning(front=2)
+    Xd = q.matmul(p, A)
+    p.set_tuning(front=1)
+    Xs = q.matmul(p, A)
+    torch.cuda.synchronize()
+    ref = oracle.matmul(inst)
+    assert_close(Xd.double().cpu().numpy(), ref, inst.A, inst, dtype, "dense front")
+    assert_close(Xs.double().cpu().numpy(), ref, inst.A, inst, dtype, "sparse front")
