@@ -234,6 +234,55 @@ int qmc_matmul_batched(int count, const qmc_plan_t* plans, const void* const* A,
                        size_t workspace_bytes, void* stream);
 
 /*
+ * Union of all Korobov lattice point sets (Section 2.2, after Hua and Wang):
+ * for a prime K the N = (K-1)^2 points
+ *     x_{b,n} = ({n b^0 / K + D}, {n b^1 / K + D}, ..., {n b^{s-1} / K + D}),
+ *     b, n = 1..K-1,
+ * in conventional order: row (b-1)(K-1) + (n-1) holds x_{b,n} (block b is
+ * the Korobov lattice rule of base b without its point n = 0).  Every block
+ * is one rank-1 lattice product sharing the spectrum of z (Section 2.2:
+ * Y'_g = Z P_g); block b collapses A through the exponents
+ * l_{b,j} = j log_beta(b) mod (K-1), which are c_{g,j} - 1 of the paper's
+ * ordering for b = beta^(g-1), taken in [0, K-2].
+ *
+ * qmc_korobov_create -- tables for K, s, phi (as qmc_plan_create; the shift
+ *   D = shift_num / shift_den may be 0 for every phi since no coordinate is 0),
+ *   dtype.  Synchronous on `stream`.  Device memory grows as (K-1) times the
+ *   collapse schedule of s rows.
+ *   Errors: QMC_ERR_ARG (K < 3, s < 1, bad phi/dtype/shift), QMC_ERR_NOT_PRIME,
+ *   QMC_ERR_OOM, QMC_ERR_HIP.
+ * qmc_korobov_info -- N, s, K, L = K-1, the convolution layout and beta.
+ * qmc_korobov_set_chunk -- blocks per run of the passes (0: all blocks);
+ *   the workspace holds one run.
+ * qmc_korobov_workspace_size -- device bytes qmc_korobov_matmul needs for t.
+ * qmc_korobov_plan -- the lattice plan of K points whose spectrum and tables
+ *   every block shares (owned by the union: valid until qmc_korobov_destroy;
+ *   for qmc_plan_tables and the timing instrumentation, which also covers
+ *   qmc_korobov_matmul; its own generating vector is all ones).
+ * qmc_korobov_matmul -- X = Y A: A device s x t (row stride lda >= t), X
+ *   device N x t (ldx >= t), every entry written; asynchronous on `stream`.
+ *   Errors: QMC_ERR_ARG, QMC_ERR_ALIAS (X overlaps A), QMC_ERR_WORKSPACE.
+ */
+typedef struct qmc_korobov_s* qmc_korobov_t;
+typedef struct {
+    int64_t K, s, N, L, M, M1, M2;
+    int64_t blocks;          /* K - 1 */
+    int64_t rounds;          /* collapse rounds per block (common to all blocks) */
+    uint64_t beta;           /* primitive root used */
+    int phi_kind, dtype;
+    int64_t chunk_blocks;
+} qmc_korobov_info_t;
+int qmc_korobov_create(qmc_korobov_t* out, int64_t K, int64_t s, int phi_kind,
+                       int64_t shift_num, int64_t shift_den, int dtype, void* stream);
+int qmc_korobov_info(qmc_korobov_t U, qmc_korobov_info_t* info);
+int qmc_korobov_set_chunk(qmc_korobov_t U, int64_t chunk_blocks);
+int qmc_korobov_workspace_size(qmc_korobov_t U, int64_t t, size_t* bytes);
+qmc_plan_t qmc_korobov_plan(qmc_korobov_t U);
+int qmc_korobov_matmul(qmc_korobov_t U, const void* A, int64_t t, int64_t lda, void* X,
+                       int64_t ldx, void* workspace, size_t workspace_bytes, void* stream);
+void qmc_korobov_destroy(qmc_korobov_t U);
+
+/*
  * Timing instrumentation for benchmarks.  When enabled, every kernel launch
  * of qmc_matmul / qmc_matmul_adjoint on this plan is bracketed by two HIP
  * events recorded on the launch stream.  qmc_profile_collect waits for the

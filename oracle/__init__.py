@@ -10,8 +10,9 @@ multiplication"):
 
 * ``points``  -- the point set in conventional order, written out from its
   definition: rank-1 lattice points {n g_j / N} (Section 2.1), optionally with
-  an equal shift Delta in every coordinate (Remark 2), and polynomial lattice
-  points over GF(2) (Remark 1, Niederreiter's construction), each mapped by
+  an equal shift Delta in every coordinate (Remark 2), polynomial lattice
+  points over GF(2) (Remark 1, Niederreiter's construction) and the union of
+  all Korobov lattice point sets {n b^j / K} (Section 2.2), each mapped by
   one univariate phi (Section 2.1: identity, the tent map, the inverse normal
   CDF; x - 1/2 as in Experiment 2).
 * ``dense``   -- X = Y A and dA = Y^T G by forming Y explicitly and multiplying
@@ -32,7 +33,7 @@ the round trip through ``math.erfc``.
 """
 
 from .points import (PHI_IDENTITY, PHI_CENTERED, PHI_INVNORM, PHI_TENT,
-                     RULE_LATTICE, RULE_POLY_GF2, phi_apply, lattice_coords,
+                     RULE_LATTICE, RULE_POLY_GF2, RULE_KOROBOV_UNION, phi_apply, lattice_coords,
                      gf2_coords, gf2_digits_coords, coords, coords_rational, explicit_Y,
                      phi_residue_values, phi_rational)
 from .dense import matmul, adjoint, matmul_rows, adjoint_entries, Y_rows
@@ -40,7 +41,7 @@ from . import literal, exact
 
 __all__ = [
     "PHI_IDENTITY", "PHI_CENTERED", "PHI_INVNORM", "PHI_TENT",
-    "RULE_LATTICE", "RULE_POLY_GF2", "phi_apply", "lattice_coords", "gf2_coords",
+    "RULE_LATTICE", "RULE_POLY_GF2", "RULE_KOROBOV_UNION", "phi_apply", "lattice_coords", "gf2_coords",
     "gf2_digits_coords", "coords", "coords_rational", "explicit_Y",
     "phi_residue_values", "phi_rational",
     "matmul", "adjoint", "matmul_rows", "adjoint_entries", "Y_rows",

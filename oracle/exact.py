@@ -7,7 +7,9 @@ formed exactly with ``fractions.Fraction`` (A's binary floats are exact
 rationals).  Lattice coordinates are {n g_j / N} (Section 2.1); GF(2)
 coordinates are the first m digits of the Laurent expansion of
 n(x) q_j(x) / p(x) (Remark 1), found here with plain Python integers by
-repeated doubling of n(x) (n(x) q(x) = sum over set bits i of q of x^i n(x)).
+repeated doubling of n(x) (n(x) q(x) = sum over set bits i of q of x^i n(x));
+the union of Korobov rules has {n b^e_j / K} in row (b-1)(K-1) + (n-1)
+(Section 2.2), with Python's built-in modular power.
 """
 from __future__ import annotations
 
@@ -16,7 +18,7 @@ from typing import List
 
 import numpy as np
 
-from .points import PHI_CENTERED, PHI_IDENTITY, RULE_LATTICE
+from .points import PHI_CENTERED, PHI_IDENTITY, RULE_KOROBOV_UNION, RULE_LATTICE
 
 
 def _gf2_point(m: int, p: int, n: int, q: int) -> Fraction:
@@ -49,6 +51,10 @@ def point_matrix(inst) -> List[List[Fraction]]:
         for gj in g:
             if inst.rule == RULE_LATTICE:
                 x = Fraction((n * gj) % inst.N, inst.N)
+            elif inst.rule == RULE_KOROBOV_UNION:
+                K = int(inst.modulus)
+                b, k = n // (K - 1) + 1, n % (K - 1) + 1
+                x = Fraction(k * pow(b, gj, K) % K, K)
             else:
                 x = _gf2_point(inst.N.bit_length() - 1, inst.modulus, n, gj)
             x = x + shift

@@ -15,6 +15,13 @@ product path.
   nu_m(r/p) = sum_{l=1}^m u_l 2^-l where r(x)/p(x) = sum_{l>=1} u_l x^-l.
   Equivalently u_1..u_m are the bits (most significant first) of the
   quotient floor(r(x) x^m / p(x)).  An equal shift is applied as for lattices.
+* Union of all Korobov lattice point sets with a prime K (Section 2.2, the
+  point set of Hua and Wang): for b, n = 1..K-1 the point
+  x_{b,n} = ({n b^0 / K}, {n b^1 / K}, ..., {n b^{s-1} / K}); conventional
+  order is b-major, row (b-1)(K-1) + (n-1), N = (K-1)^2.  The coordinate of
+  column j is taken for the exponent e_j given in ``gen`` (e_j = j for the
+  point set itself; a subset of exponents selects columns).  The equal shift
+  is applied as for lattices.
 * phi (Section 2.1): identity, the tent transform 1 - |2x - 1|, the inverse
   normal CDF; and x - 1/2 (Experiment 2).
 """
@@ -30,6 +37,7 @@ PHI_TENT = 3
 
 RULE_LATTICE = 0
 RULE_POLY_GF2 = 1
+RULE_KOROBOV_UNION = 2
 
 
 def phi_apply(kind: int, x: np.ndarray) -> np.ndarray:
@@ -156,6 +164,31 @@ def gf2_digits_coords(m: int, p: int, gen, rows=None) -> np.ndarray:
     return val
 
 
+def _powmod(base: np.ndarray, exp: np.ndarray, K: int) -> np.ndarray:
+    """base^exp mod K elementwise (square and multiply; K < 2^31)."""
+    base = np.asarray(base, dtype=np.int64) % K
+    exp = np.asarray(exp, dtype=np.int64).copy()
+    base, exp = np.broadcast_arrays(base, exp)
+    base, exp = base.copy(), exp.copy()
+    out = np.ones(base.shape, dtype=np.int64)
+    while np.any(exp > 0):
+        odd = (exp & 1) == 1
+        out = np.where(odd, out * base % K, out)
+        base = base * base % K
+        exp >>= 1
+    return out
+
+
+def korobov_union_numerators(K: int, exps, rows=None) -> np.ndarray:
+    """(n b^{e_j}) mod K for the requested rows (b, n) of the union."""
+    N = (K - 1) ** 2
+    rho = np.arange(N, dtype=np.int64) if rows is None else np.asarray(rows, dtype=np.int64)
+    b = rho // (K - 1) + 1
+    n = rho % (K - 1) + 1
+    e = np.asarray(exps, dtype=np.int64)
+    return n[:, None] * _powmod(b[:, None], e[None, :], K) % K
+
+
 def coords_rational(rule: int, N: int, gen, modulus: int = 0, shift=(0, 1), rows=None):
     """Exact coordinates K/D of the requested rows (conventional order)."""
     if rule == RULE_LATTICE:
@@ -167,6 +200,10 @@ def coords_rational(rule: int, N: int, gen, modulus: int = 0, shift=(0, 1), rows
         assert 1 << m == N, "polynomial lattice rules need N = 2^m"
         r = gf2_residues(m, modulus, gen, rows)
         return _shifted_numer(gf2_value_of_residue(m, modulus, r).astype(np.int64), N, shift)
+    if rule == RULE_KOROBOV_UNION:
+        K = int(modulus)
+        assert N == (K - 1) ** 2, "the union of Korobov rules has (K-1)^2 points"
+        return _shifted_numer(korobov_union_numerators(K, gen, rows), K, shift)
     raise ValueError(f"unknown rule {rule}")
 
 
@@ -177,6 +214,9 @@ def coords(rule: int, N: int, gen, modulus: int = 0, shift=(0, 1), rows=None) ->
         m = int(N).bit_length() - 1
         assert 1 << m == N, "polynomial lattice rules need N = 2^m"
         return gf2_coords(m, modulus, gen, shift, rows)
+    if rule == RULE_KOROBOV_UNION:
+        K, D = coords_rational(rule, N, gen, modulus, shift, rows)
+        return K.astype(np.float64) / float(D)
     raise ValueError(f"unknown rule {rule}")
 
 

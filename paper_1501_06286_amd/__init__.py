@@ -37,6 +37,8 @@ EXPORTED = [
     "qmc_profile_enable", "qmc_profile_collect", "qmc_profile_slot_name",
     "qmc_plan_set_tuning", "qmc_plan_get_tuning",
     "qmc_batch_create", "qmc_batch_workspace_size", "qmc_batch_run", "qmc_batch_destroy",
+    "qmc_korobov_create", "qmc_korobov_destroy", "qmc_korobov_info", "qmc_korobov_set_chunk",
+    "qmc_korobov_workspace_size", "qmc_korobov_plan", "qmc_korobov_matmul",
 ]
 PROF_SLOTS = 10
 
@@ -58,6 +60,14 @@ class PlanInfo(ctypes.Structure):
                 ("rounds", ctypes.c_int64), ("beta", ctypes.c_uint64),
                 ("rule", ctypes.c_int), ("phi_kind", ctypes.c_int), ("dtype", ctypes.c_int),
                 ("embedded", ctypes.c_int), ("phi0", ctypes.c_double)]
+
+
+class KorobovInfo(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int64), ("s", ctypes.c_int64), ("N", ctypes.c_int64),
+                ("L", ctypes.c_int64), ("M", ctypes.c_int64), ("M1", ctypes.c_int64),
+                ("M2", ctypes.c_int64), ("blocks", ctypes.c_int64), ("rounds", ctypes.c_int64),
+                ("beta", ctypes.c_uint64), ("phi_kind", ctypes.c_int), ("dtype", ctypes.c_int),
+                ("chunk_blocks", ctypes.c_int64)]
 
 
 _LIB = None
@@ -105,9 +115,18 @@ def lib() -> ctypes.CDLL:
         L.qmc_profile_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
         L.qmc_profile_slot_name.argtypes = [ip]
         L.qmc_profile_slot_name.restype = ctypes.c_char_p
+        L.qmc_korobov_create.argtypes = [ctypes.POINTER(vp), i64, i64, ip, i64, i64, ip, vp]
+        L.qmc_korobov_destroy.argtypes = [vp]
+        L.qmc_korobov_destroy.restype = None
+        L.qmc_korobov_info.argtypes = [vp, ctypes.POINTER(KorobovInfo)]
+        L.qmc_korobov_set_chunk.argtypes = [vp, i64]
+        L.qmc_korobov_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
+        L.qmc_korobov_plan.argtypes = [vp]
+        L.qmc_korobov_plan.restype = vp
+        L.qmc_korobov_matmul.argtypes = [vp, vp, i64, i64, vp, i64, vp, sz, vp]
         for name in EXPORTED:
             if name not in ("qmc_plan_destroy", "qmc_strerror", "qmc_profile_slot_name",
-                            "qmc_batch_destroy"):
+                            "qmc_batch_destroy", "qmc_korobov_destroy", "qmc_korobov_plan"):
                 getattr(L, name).restype = ip
         _LIB = L
     return _LIB
@@ -158,6 +177,7 @@ class Plan:
             self.shift[0], self.shift[1], self.dtype_code, _stream_handle(stream))
         _check(code, "qmc_plan_create")
         self._h = handle
+        self._owned = True
         self._ws = None
 
     @classmethod
@@ -173,7 +193,8 @@ class Plan:
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
-            lib().qmc_plan_destroy(self._h)
+            if getattr(self, "_owned", True):
+                lib().qmc_plan_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -389,6 +410,95 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+class KorobovUnion:
+    """The union of all Korobov lattice point sets with a prime K (Section 2.2):
+    N = (K-1)^2 points x_{b,n} = ({n b^j / K + Delta})_{j < s}, b, n = 1..K-1,
+    row (b-1)(K-1) + (n-1).  The K-1 blocks share one generator spectrum."""
+
+    def __init__(self, K: int, s: int, phi: int = PHI_INVNORM,
+                 shift: Tuple[int, int] = (0, 1), dtype="f32", stream=None):
+        self.K, self.s = int(K), int(s)
+        self.N = (self.K - 1) ** 2
+        self.phi, self.shift = int(phi), (int(shift[0]), int(shift[1]))
+        self.dtype_code = _dtype_code(dtype)
+        torch = _torch()
+        self.torch_dtype = torch.float32 if self.dtype_code == F32 else torch.float64
+        h = ctypes.c_void_p()
+        _check(lib().qmc_korobov_create(ctypes.byref(h), self.K, self.s, self.phi, self.shift[0],
+                                        self.shift[1], self.dtype_code, _stream_handle(stream)),
+               "qmc_korobov_create")
+        self._h = h
+        self._ws = None
+        # the shared lattice plan of K points (owned by the union)
+        base = Plan.__new__(Plan)
+        base.rule, base.N, base.s = RULE_LATTICE, self.K, self.s
+        base.phi, base.shift, base.modulus = self.phi, self.shift, 0
+        base.dtype_code, base.torch_dtype = self.dtype_code, self.torch_dtype
+        base._h = ctypes.c_void_p(lib().qmc_korobov_plan(h))
+        base._owned = False
+        base._ws = None
+        self.plan = base
+
+    @classmethod
+    def from_instance(cls, inst, dtype=None, stream=None) -> "KorobovUnion":
+        return cls(inst.modulus, inst.s, inst.phi, inst.shift, dtype or inst.dtype, stream)
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if self._h is None:
+            raise RuntimeError("union plan destroyed")
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            self.plan._h = None
+            lib().qmc_korobov_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = KorobovInfo()
+        _check(lib().qmc_korobov_info(self.handle, ctypes.byref(inf)), "qmc_korobov_info")
+        return {k: getattr(inf, k) for k, _ in KorobovInfo._fields_}
+
+    def set_chunk(self, blocks: int) -> None:
+        """Blocks per run of the passes (0: all); changes the workspace size."""
+        _check(lib().qmc_korobov_set_chunk(self.handle, int(blocks)), "qmc_korobov_set_chunk")
+
+    def workspace_bytes(self, t: int) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().qmc_korobov_workspace_size(self.handle, int(t), ctypes.byref(n)),
+               "qmc_korobov_workspace_size")
+        return int(n.value)
+
+    def workspace(self, t: int, device=None):
+        torch = _torch()
+        need = self.workspace_bytes(t)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = torch.empty(need, dtype=torch.uint8, device=device or "cuda")
+        return self._ws
+
+
+def korobov_matmul(U: KorobovUnion, A, out=None, workspace=None, stream=None):
+    """X = Y A for the union of Korobov lattice point sets ((K-1)^2 x t)."""
+    torch = _torch()
+    _check_tensor(A, U, U.s, "A")
+    t = A.shape[1]
+    X = torch.empty((U.N, t), dtype=A.dtype, device=A.device) if out is None else out
+    _check_tensor(X, U, U.N, "out")
+    ws = U.workspace(t, A.device) if workspace is None else workspace
+    _check(lib().qmc_korobov_matmul(U.handle, ctypes.c_void_p(A.data_ptr()), t, A.stride(0),
+                                    ctypes.c_void_p(X.data_ptr()), X.stride(0),
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                    _stream_handle(stream)), "qmc_korobov_matmul")
+    return X
 
 
 def _autograd():

@@ -102,3 +102,29 @@ def tune(plan, t: int, reps: int = 3, use_cache: bool = True,
         cache[key] = {"best": best, "timings": [[c, round(ms, 4)] for c, ms in results]}
         _store(cache)
     return best, results
+
+
+def tune_korobov(U, t: int, reps: int = 3, chunks=(0, 16, 32, 64, 128, 256)) -> Tuple[int, List]:
+    """Pick and set the fastest blocks-per-run for a union of Korobov rules."""
+    import torch
+    import paper_1501_06286_amd as q
+    A = torch.randn((U.s, t), dtype=U.torch_dtype, device="cuda")
+    X = torch.empty((U.N, t), dtype=U.torch_dtype, device="cuda")
+    results = []
+    for c in chunks:
+        if c >= U.K - 1:
+            continue
+        U.set_chunk(c)
+        ws = U.workspace(t, "cuda")
+        q.korobov_matmul(U, A, out=X, workspace=ws)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            q.korobov_matmul(U, A, out=X, workspace=ws)
+        e1.record()
+        e1.synchronize()
+        results.append((c, e0.elapsed_time(e1) / reps))
+    best = min(results, key=lambda r: r[1])[0]
+    U.set_chunk(best)
+    return best, results

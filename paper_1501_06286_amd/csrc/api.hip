@@ -7,7 +7,7 @@
 
 using namespace qmc;
 
-namespace {
+namespace qmc {
 
 bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) {
   const char* pa = (const char*)a;
@@ -15,16 +15,59 @@ bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes) 
   return pa < pb + bbytes && pb < pa + abytes;
 }
 
-size_t elem_bytes(int dtype) { return dtype == QMC_F32 ? 4 : 8; }
-
 size_t matrix_extent(int64_t rows, int64_t cols, int64_t ld, int dtype) {
   if (rows <= 0 || cols <= 0) return 0;
-  return (size_t)((rows - 1) * ld + cols) * elem_bytes(dtype);
+  return (size_t)((rows - 1) * ld + cols) * (dtype == QMC_F32 ? 4 : 8);
 }
 
-bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
-}  // namespace
+int plan_create(qmc_plan_s** out, int rule, int64_t N, int64_t s, const uint64_t* gen,
+                uint64_t modulus, int phi_kind, int64_t shift_num, int64_t shift_den, int dtype,
+                bool row0_used, hipStream_t stream) {
+  if (!out || !gen || s < 1) return QMC_ERR_ARG;
+  *out = nullptr;
+  if (rule != QMC_RULE_LATTICE && rule != QMC_RULE_POLY_GF2) return QMC_ERR_ARG;
+  if (dtype != QMC_F32 && dtype != QMC_F64) return QMC_ERR_ARG;
+  if (phi_kind < QMC_PHI_IDENTITY || phi_kind > QMC_PHI_TENT) return QMC_ERR_ARG;
+  if (shift_den < 1 || shift_num < 0 || shift_num >= shift_den) return QMC_ERR_ARG;
+  if (s > ((int64_t)1 << 30)) return QMC_ERR_ARG;
+  int m = 0;
+  if (rule == QMC_RULE_LATTICE) {
+    if (N < 2 || N >= ((int64_t)1 << 31)) return QMC_ERR_ARG;
+    if (modulus != 0) return QMC_ERR_ARG;
+  } else {
+    if (!is_pow2(N) || N < 2 || N > ((int64_t)1 << 30)) return QMC_ERR_ARG;
+    while (((int64_t)1 << m) < N) ++m;
+  }
+  // the exact coordinate K/D needs D = N * shift_den well inside 63 bits
+  if ((__int128)N * shift_den >= ((__int128)1 << 61)) return QMC_ERR_ARG;
+  // the inverse normal CDF needs every coordinate strictly inside (0, 1):
+  // x = 0 occurs for row 0 unless the shift moves it
+  if (row0_used && phi_kind == QMC_PHI_INVNORM && shift_num == 0) return QMC_ERR_ARG;
+
+  qmc_plan_s* P = new (std::nothrow) qmc_plan_s();
+  if (!P) return QMC_ERR_OOM;
+  P->rule = rule;
+  P->N = N;
+  P->s = s;
+  P->L = N - 1;
+  P->m = m;
+  P->modulus = modulus;
+  P->phi_kind = phi_kind;
+  P->shift_num = shift_num;
+  P->shift_den = shift_den;
+  P->dtype = dtype;
+  const int rc = build_tables(P, gen, stream);
+  if (rc != QMC_OK) {
+    qmc_plan_destroy(P);
+    return rc;
+  }
+  *out = P;
+  return QMC_OK;
+}
+
+}  // namespace qmc
 
 extern "C" {
 
@@ -47,46 +90,8 @@ const char* qmc_strerror(int code) {
 int qmc_plan_create(qmc_plan_t* out, int rule, int64_t N, int64_t s, const uint64_t* gen,
                     uint64_t modulus, int phi_kind, int64_t shift_num, int64_t shift_den,
                     int dtype, void* stream) {
-  if (!out || !gen || s < 1) return QMC_ERR_ARG;
-  *out = nullptr;
-  if (rule != QMC_RULE_LATTICE && rule != QMC_RULE_POLY_GF2) return QMC_ERR_ARG;
-  if (dtype != QMC_F32 && dtype != QMC_F64) return QMC_ERR_ARG;
-  if (phi_kind < QMC_PHI_IDENTITY || phi_kind > QMC_PHI_TENT) return QMC_ERR_ARG;
-  if (shift_den < 1 || shift_num < 0 || shift_num >= shift_den) return QMC_ERR_ARG;
-  if (s > ((int64_t)1 << 30)) return QMC_ERR_ARG;
-  int m = 0;
-  if (rule == QMC_RULE_LATTICE) {
-    if (N < 2 || N >= ((int64_t)1 << 31)) return QMC_ERR_ARG;
-    if (modulus != 0) return QMC_ERR_ARG;
-  } else {
-    if (!is_pow2(N) || N < 2 || N > ((int64_t)1 << 30)) return QMC_ERR_ARG;
-    while (((int64_t)1 << m) < N) ++m;
-  }
-  // the exact coordinate K/D needs D = N * shift_den well inside 63 bits
-  if ((__int128)N * shift_den >= ((__int128)1 << 61)) return QMC_ERR_ARG;
-  // the inverse normal CDF needs every coordinate strictly inside (0, 1):
-  // x = 0 occurs for row 0 unless the shift moves it
-  if (phi_kind == QMC_PHI_INVNORM && shift_num == 0) return QMC_ERR_ARG;
-
-  qmc_plan_s* P = new (std::nothrow) qmc_plan_s();
-  if (!P) return QMC_ERR_OOM;
-  P->rule = rule;
-  P->N = N;
-  P->s = s;
-  P->L = N - 1;
-  P->m = m;
-  P->modulus = modulus;
-  P->phi_kind = phi_kind;
-  P->shift_num = shift_num;
-  P->shift_den = shift_den;
-  P->dtype = dtype;
-  const int rc = build_tables(P, gen, (hipStream_t)stream);
-  if (rc != QMC_OK) {
-    qmc_plan_destroy(P);
-    return rc;
-  }
-  *out = P;
-  return QMC_OK;
+  return plan_create(out, rule, N, s, gen, modulus, phi_kind, shift_num, shift_den, dtype, true,
+                     (hipStream_t)stream);
 }
 
 static void prof_clear(qmc_plan_t P) {

@@ -74,10 +74,44 @@ struct qmc_plan_s {
   mutable qmc::ProfEvents prof[qmc::PROF_NSLOTS];
 };
 
+// union of all Korobov lattice point sets with a prime K: K - 1 blocks (one
+// per Korobov base b) of the rank-1 lattice rule of K points, rows n >= 1
+struct qmc_korobov_s {
+  qmc_plan_s* base = nullptr;   // lattice plan of N = K: pow, spectrum, twiddles (owns the
+                                // memory below); its own collapse schedule is unused
+  int64_t K = 0, s = 0, blocks = 0;
+  int64_t rounds = 0, Upad = 0;  // common collapse schedule size of every block
+  int32_t* d_it_j = nullptr;     // blocks*Upad
+  int32_t* d_it_e1 = nullptr;    // blocks*Upad
+  void* d_twit = nullptr;        // blocks*M2*Upad: W_M^{slot w2} per block
+  int32_t* d_rowmap = nullptr;   // L: pow[e] - 1 (row n - 1 of a block)
+  int64_t chunk_blocks = 0;      // blocks per run (0: chosen from the shape)
+};
+
 namespace qmc {
 
 // tables.hip
 int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st);
+int build_korobov_tables(qmc_korobov_s* U, hipStream_t st);
+
+// sparse collapse schedule for exponents l_j (j < s) on a layout: item u
+// carries row it_j[u] (-1: padding), reflected slot it_slot[u] = (L - l_j)
+// mod L and its residue it_e1[u] = slot mod M1 (M1 for padding)
+struct Schedule {
+  int64_t rounds = 0, Upad = 0;
+  std::vector<int32_t> it_j, it_slot, it_e1;
+};
+Schedule make_schedule(const Layout& lay, int64_t L, int64_t s, const int32_t* ell);
+void pad_schedule(Schedule& sc, int64_t rounds, int64_t M1, int R);
+
+// api.hip
+bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes);
+size_t matrix_extent(int64_t rows, int64_t cols, int64_t ld, int dtype);
+// row0_used = false: the point of row 0 never enters a product (the union of
+// Korobov rules), so phi may be unbounded there
+int plan_create(qmc_plan_s** out, int rule, int64_t N, int64_t s, const uint64_t* gen,
+                uint64_t modulus, int phi_kind, int64_t shift_num, int64_t shift_den, int dtype,
+                bool row0_used, hipStream_t stream);
 
 // conv.hip
 bool dense_front(const qmc_plan_s* P);

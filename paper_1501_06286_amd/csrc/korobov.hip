@@ -1,0 +1,257 @@
+// X = Y A for the union of all Korobov lattice point sets (Section 2.2).
+//
+// The K - 1 blocks are rank-1 lattice products of K points that share one
+// spectrum: block b (Korobov base b) differs from the others only in its
+// collapse, through the exponents l_{b,j} = j log_beta(b) mod (K - 1).  A run
+// covers a chunk of blocks with one launch per pass -- collapse-transpose,
+// fused middle (sparse front, no constant row since the union has no point
+// n = 0), outer split where needed, back -- indexing the block from the
+// workgroup id, so every block's tables sit at a fixed stride.
+#include <algorithm>
+#include <new>
+
+#include "kernels.hpp"
+
+namespace qmc {
+
+template <typename T>
+__global__ __launch_bounds__(256) void ku_collapse(const T* __restrict__ A, int64_t lda, int64_t t,
+                                                   int64_t P, const int32_t* __restrict__ it_j,
+                                                   int64_t Upad, cx<T>* __restrict__ aT,
+                                                   int64_t gx, int64_t per_block) {
+  __shared__ CollapseSmem<T> S;
+  const int64_t b = blockIdx.x / per_block, lb = blockIdx.x % per_block;
+  collapse_body<T>(A, lda, t, P, it_j + b * Upad, Upad, aT + b * P * Upad, lb % gx, lb / gx, S,
+                   threadIdx.x);
+}
+
+template <typename T, int R>
+__global__ __launch_bounds__(MidShape<R>::BLOCK)
+__attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void ku_middle(
+    const cx<T>* __restrict__ aT, int64_t Upad, int64_t rounds, const int32_t* __restrict__ it_e1,
+    const cx<T>* __restrict__ twit, const cx<T>* __restrict__ twf1,
+    const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs,
+    const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M1, int64_t M2,
+    int64_t P, cx<T>* __restrict__ C, int64_t per_block) {
+  __shared__ MidSmem<T, R> S;
+  const int64_t id = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t b = id / per_block, lb = id % per_block;
+  middle_body<T, R, true>(aT + b * P * Upad, Upad, rounds, it_e1 + b * Upad,
+                          twit + b * M2 * Upad, twf1, twf2, Hs, twi3, two, M2, P,
+                          C + b * P * M1 * M2, (T*)nullptr, 0, (T)0, lb, S, threadIdx.x);
+}
+
+template <typename T, int P2>
+__global__ __launch_bounds__(64) void ku_split(cx<T>* __restrict__ C, int64_t M1, int64_t M2,
+                                               int Q2, const cx<T>* __restrict__ twb,
+                                               int64_t gx, int64_t pairs_total) {
+  // blockIdx.x = (bx, q) and blockIdx.y + gridDim.y * blockIdx.z = pair of the run
+  const int64_t pair = (int64_t)blockIdx.y + (int64_t)gridDim.y * blockIdx.z;
+  if (pair >= pairs_total) return;
+  split_body<T, P2, +1>(C, M1, M2, Q2, twb, blockIdx.x % gx, blockIdx.x / gx, pair, threadIdx.x);
+}
+
+template <typename T, int Q>
+__global__ __launch_bounds__(256) void ku_back(const cx<T>* __restrict__ C, int64_t M1, int64_t M2,
+                                               int64_t P2, int64_t L, int64_t P,
+                                               const int32_t* __restrict__ rowmap,
+                                               T* __restrict__ X, int64_t ldx, int64_t t,
+                                               int64_t block_rows, int64_t gx, int64_t gy,
+                                               int64_t per_block) {
+  __shared__ BackSmem<T> S;
+  const int64_t b = blockIdx.x / per_block, lb = blockIdx.x % per_block;
+  const int64_t bx = lb % gx, rest = lb / gx;
+  back_body<T, Q, false, false>(C + b * P * M1 * M2, M1, M2, P2, L, P, rowmap, nullptr, nullptr,
+                                nullptr, (T)0, X + b * block_rows * ldx, ldx, t, bx, rest % gy,
+                                rest / gy, S, threadIdx.x);
+}
+
+static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+static int64_t chunk_of(const qmc_korobov_s* U) {
+  return (U->chunk_blocks > 0 && U->chunk_blocks < U->blocks) ? U->chunk_blocks : U->blocks;
+}
+
+static size_t korobov_ws(const qmc_korobov_s* U, int64_t t) {
+  const qmc_plan_s* P = U->base;
+  const size_t el = P->dtype == QMC_F32 ? sizeof(cx<float>) : sizeof(cx<double>);
+  const int64_t pairs = (t + 1) / 2, nb = chunk_of(U);
+  return al256(nb * pairs * U->Upad * el) + al256(nb * pairs * P->lay.M * el);
+}
+
+template <typename T, int R>
+static void ku_middle_launch(const qmc_korobov_s* U, const cx<T>* aT, int64_t b0, int64_t nb,
+                             int64_t pairs, cx<T>* C, hipStream_t st) {
+  const qmc_plan_s* P = U->base;
+  const Layout& lay = P->lay;
+  typedef MidShape<R> S;
+  const int64_t per_block = ((pairs + S::TPB - 1) / S::TPB) * lay.M2;
+  ProfScope ps(P, PROF_MIDDLE, st);
+  ku_middle<T, R><<<dim3((unsigned)(nb * per_block)), dim3(S::BLOCK), 0, st>>>(
+      aT, U->Upad, U->rounds, U->d_it_e1 + b0 * U->Upad,
+      (const cx<T>*)U->d_twit + b0 * lay.M2 * U->Upad, (const cx<T>*)P->d_twf1,
+      (const cx<T>*)P->d_twf2, (const cx<T>*)P->d_Hs, (const cx<T>*)P->d_twi3,
+      (const cx<T>*)P->d_two, lay.M1, lay.M2, pairs, C, per_block);
+}
+
+template <typename T>
+static int korobov_forward(const qmc_korobov_s* U, const T* A, int64_t t, int64_t lda, T* X,
+                           int64_t ldx, void* ws, hipStream_t st) {
+  const qmc_plan_s* P = U->base;
+  const Layout& lay = P->lay;
+  const int64_t pairs = (t + 1) / 2, chunk = chunk_of(U), K = U->K;
+  const size_t el = sizeof(cx<T>);
+  cx<T>* aT = (cx<T>*)ws;
+  cx<T>* C = (cx<T>*)((char*)ws + al256(chunk * pairs * U->Upad * el));
+  for (int64_t b0 = 0; b0 < U->blocks; b0 += chunk) {
+    const int64_t nb = std::min(chunk, U->blocks - b0);
+    {
+      const int64_t gx = (U->Upad + 63) / 64, per_block = gx * ((pairs + 15) / 16);
+      ProfScope ps(P, PROF_COLLAPSE, st);
+      ku_collapse<T><<<dim3((unsigned)(nb * per_block)), 256, 0, st>>>(
+          A, lda, t, pairs, U->d_it_j + b0 * U->Upad, U->Upad, aT, gx, per_block);
+    }
+    switch (lay.R) {
+      case 1: ku_middle_launch<T, 1>(U, aT, b0, nb, pairs, C, st); break;
+      case 2: ku_middle_launch<T, 2>(U, aT, b0, nb, pairs, C, st); break;
+      case 4: ku_middle_launch<T, 4>(U, aT, b0, nb, pairs, C, st); break;
+      case 8: ku_middle_launch<T, 8>(U, aT, b0, nb, pairs, C, st); break;
+      case 16: ku_middle_launch<T, 16>(U, aT, b0, nb, pairs, C, st); break;
+      default: return QMC_ERR_UNSUPPORTED;
+    }
+    if (lay.P2 > 1) {
+      const int64_t gx = (lay.M1 + 63) / 64, tot = nb * pairs;
+      const int64_t gy = std::min<int64_t>(tot, 65535), gz = (tot + gy - 1) / gy;
+      dim3 grid((unsigned)(gx * lay.Q2), (unsigned)gy, (unsigned)gz);
+      const cx<T>* twb = (const cx<T>*)P->d_twb;
+      ProfScope ps(P, PROF_SPLIT, st);
+#define QMC_KSPLIT(PP) \
+  ku_split<T, PP><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb, gx, tot)
+      switch (lay.P2) {
+        case 2: QMC_KSPLIT(2); break;
+        case 4: QMC_KSPLIT(4); break;
+        case 8: QMC_KSPLIT(8); break;
+        case 16: QMC_KSPLIT(16); break;
+        case 32: QMC_KSPLIT(32); break;
+        case 64: QMC_KSPLIT(64); break;
+        default: return QMC_ERR_UNSUPPORTED;
+      }
+#undef QMC_KSPLIT
+    }
+    {
+      const int64_t gx = (lay.M1 + 15) / 16, gy = (pairs + 15) / 16;
+      const int64_t per_block = gx * gy * lay.P2;
+      T* Xb = X + b0 * (K - 1) * ldx;
+      ProfScope ps(P, PROF_BACK, st);
+#define QMC_KBACK(QQ)                                                                             \
+  ku_back<T, QQ><<<dim3((unsigned)(nb * per_block)), 256, 0, st>>>(                               \
+      C, lay.M1, lay.M2, lay.P2, P->L, pairs, U->d_rowmap, Xb, ldx, t, K - 1, gx, gy, per_block)
+      switch (lay.Q2) {
+        case 1: QMC_KBACK(1); break;
+        case 2: QMC_KBACK(2); break;
+        case 4: QMC_KBACK(4); break;
+        case 8: QMC_KBACK(8); break;
+        case 16: QMC_KBACK(16); break;
+        case 32: QMC_KBACK(32); break;
+        case 64: QMC_KBACK(64); break;
+        default: return QMC_ERR_UNSUPPORTED;
+      }
+#undef QMC_KBACK
+    }
+    const int rc = hip_ok(hipGetLastError());
+    if (rc != QMC_OK) return rc;
+  }
+  return QMC_OK;
+}
+
+}  // namespace qmc
+
+using namespace qmc;
+
+extern "C" {
+
+int qmc_korobov_create(qmc_korobov_t* out, int64_t K, int64_t s, int phi_kind,
+                       int64_t shift_num, int64_t shift_den, int dtype, void* stream) {
+  if (!out || K < 3 || s < 1 || K >= ((int64_t)1 << 31) || s > ((int64_t)1 << 30))
+    return QMC_ERR_ARG;
+  *out = nullptr;
+  std::vector<uint64_t> ones(s, 1);  // the base plan's own generating vector (block b = 1)
+  qmc_plan_s* base = nullptr;
+  int rc = plan_create(&base, QMC_RULE_LATTICE, K, s, ones.data(), 0, phi_kind, shift_num,
+                       shift_den, dtype, false, (hipStream_t)stream);
+  if (rc != QMC_OK) return rc;
+  qmc_korobov_s* U = new (std::nothrow) qmc_korobov_s();
+  if (!U) {
+    qmc_plan_destroy(base);
+    return QMC_ERR_OOM;
+  }
+  U->base = base;
+  U->K = K;
+  U->s = s;
+  U->blocks = K - 1;
+  rc = build_korobov_tables(U, (hipStream_t)stream);
+  if (rc != QMC_OK) {
+    qmc_korobov_destroy(U);
+    return rc;
+  }
+  *out = U;
+  return QMC_OK;
+}
+
+void qmc_korobov_destroy(qmc_korobov_t U) {
+  if (!U) return;
+  qmc_plan_destroy(U->base);  // owns the union's device tables too
+  delete U;
+}
+
+int qmc_korobov_info(qmc_korobov_t U, qmc_korobov_info_t* info) {
+  if (!U || !info) return QMC_ERR_ARG;
+  const qmc_plan_s* P = U->base;
+  info->K = U->K;
+  info->s = U->s;
+  info->N = (U->K - 1) * (U->K - 1);
+  info->L = P->L;
+  info->M = P->lay.M;
+  info->M1 = P->lay.M1;
+  info->M2 = P->lay.M2;
+  info->blocks = U->blocks;
+  info->rounds = U->rounds;
+  info->beta = P->beta;
+  info->phi_kind = P->phi_kind;
+  info->dtype = P->dtype;
+  info->chunk_blocks = U->chunk_blocks;
+  return QMC_OK;
+}
+
+int qmc_korobov_set_chunk(qmc_korobov_t U, int64_t chunk_blocks) {
+  if (!U || chunk_blocks < 0) return QMC_ERR_ARG;
+  U->chunk_blocks = chunk_blocks;
+  return QMC_OK;
+}
+
+int qmc_korobov_workspace_size(qmc_korobov_t U, int64_t t, size_t* bytes) {
+  if (!U || !bytes || t < 1) return QMC_ERR_ARG;
+  *bytes = korobov_ws(U, t);
+  return QMC_OK;
+}
+
+qmc_plan_t qmc_korobov_plan(qmc_korobov_t U) { return U ? U->base : nullptr; }
+
+int qmc_korobov_matmul(qmc_korobov_t U, const void* A, int64_t t, int64_t lda, void* X,
+                       int64_t ldx, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!U || !A || !X || t < 1 || lda < t || ldx < t) return QMC_ERR_ARG;
+  const size_t need = korobov_ws(U, t);
+  if (!workspace || workspace_bytes < need) return QMC_ERR_WORKSPACE;
+  const int dt = U->base->dtype;
+  const int64_t N = (U->K - 1) * (U->K - 1);
+  const size_t xa = matrix_extent(N, t, ldx, dt), aa = matrix_extent(U->s, t, lda, dt);
+  if (ranges_overlap(X, xa, A, aa) || ranges_overlap(X, xa, workspace, need) ||
+      ranges_overlap(A, aa, workspace, need))
+    return QMC_ERR_ALIAS;
+  hipStream_t st = (hipStream_t)stream;
+  if (dt == QMC_F32)
+    return korobov_forward<float>(U, (const float*)A, t, lda, (float*)X, ldx, workspace, st);
+  return korobov_forward<double>(U, (const double*)A, t, lda, (double*)X, ldx, workspace, st);
+}
+
+}  // extern "C"

@@ -341,15 +341,22 @@ __global__ void k_tw_outer(cx<T>* two, const cx<double>* W, int R, int64_t M, in
   two[i] = to_t<T>({w.x, -w.y});
 }
 
-// twit[w2][u] = W_M^{slot_u w2} (0 for padding items)
+// twit[b][w2][u] = W_M^{slot_{b,u} w2} for nb schedules b of Upad items
+// each (0 for padding items)
 template <typename T>
 __global__ void k_tw_items(cx<T>* twit, const cx<double>* W, const int32_t* slot, int64_t Upad,
-                           int64_t M, int64_t M2) {
+                           int64_t M, int64_t M2, int64_t nb) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M2 * Upad) return;
-  const int64_t u = i % Upad, w2 = i / Upad;
-  const int32_t k = slot[u];
+  if (i >= nb * M2 * Upad) return;
+  const int64_t u = i % Upad, w2 = (i / Upad) % M2, b = i / (Upad * M2);
+  const int32_t k = slot[b * Upad + u];
   twit[i] = (k < 0) ? cx<T>{(T)0, (T)0} : to_t<T>(W[((int64_t)k * w2) & (M - 1)]);
+}
+
+// rowmap[e] = pow[e] - 1
+__global__ void k_minus1(int32_t* out, const int32_t* in, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[i] - 1;
 }
 
 // twb[a][q] = conj W_{M2}^{a q} for the split outer inverse (M2 = P2 Q2)
@@ -412,23 +419,21 @@ static Layout choose_layout(int64_t L, int dtype, int* embedded) {
 // k-th item is u = ((k / PP * F + slice) * G + lane) * PP + k % PP, so its
 // items come in adjacent pairs; the item count per lane is padded to a
 // multiple of PP.
-static void build_schedule(qmc_plan_s* P, const std::vector<int32_t>& ell,
-                           std::vector<int32_t>& it_j, std::vector<int32_t>& it_slot,
-                           std::vector<int32_t>& it_e1) {
-  const int64_t L = P->L, M1 = P->lay.M1;
-  const int R = P->lay.R;
+Schedule make_schedule(const Layout& lay, int64_t L, int64_t s, const int32_t* ell) {
+  const int64_t M1 = lay.M1;
+  const int R = lay.R;
   const int Q = R * R;
   const int G = Q < 64 ? Q : 64;
   const int F = Q / G;
   const int PP = pair_pp(R);
   // buckets: items of each residue e1, in increasing j
   std::vector<int64_t> start(M1 + 1, 0);
-  for (int64_t j = 0; j < P->s; ++j) start[((L - ell[j]) % L & (M1 - 1)) + 1]++;
+  for (int64_t j = 0; j < s; ++j) start[((L - ell[j]) % L & (M1 - 1)) + 1]++;
   for (int64_t e = 0; e < M1; ++e) start[e + 1] += start[e];
-  std::vector<int32_t> members(P->s);
+  std::vector<int32_t> members(s);
   {
     std::vector<int64_t> pos(start.begin(), start.end() - 1);
-    for (int64_t j = 0; j < P->s; ++j) members[pos[((L - ell[j]) % L) & (M1 - 1)]++] = (int32_t)j;
+    for (int64_t j = 0; j < s; ++j) members[pos[((L - ell[j]) % L) & (M1 - 1)]++] = (int32_t)j;
   }
   // per slice: longest-first assignment of buckets to lanes
   std::vector<std::vector<int32_t>> lane_items((size_t)F * G);  // j's in order
@@ -449,14 +454,15 @@ static void build_schedule(qmc_plan_s* P, const std::vector<int32_t>& ell,
       for (int64_t k = start[e]; k < start[e + 1]; ++k) li.push_back(members[k]);
     }
   }
+  Schedule sc;
   int64_t rounds = 1;
   for (const auto& li : lane_items) rounds = std::max(rounds, (int64_t)li.size());
   rounds = (rounds + PP - 1) / PP * PP;  // whole item pairs
-  P->rounds = rounds;
-  P->Upad = rounds * Q;
-  it_j.assign(P->Upad, -1);
-  it_slot.assign(P->Upad, -1);
-  it_e1.assign(P->Upad, (int32_t)M1);
+  sc.rounds = rounds;
+  sc.Upad = rounds * Q;
+  sc.it_j.assign(sc.Upad, -1);
+  sc.it_slot.assign(sc.Upad, -1);
+  sc.it_e1.assign(sc.Upad, (int32_t)M1);
   for (int f = 0; f < F; ++f)
     for (int ln = 0; ln < G; ++ln) {
       const std::vector<int32_t>& li = lane_items[(size_t)f * G + ln];
@@ -464,11 +470,23 @@ static void build_schedule(qmc_plan_s* P, const std::vector<int32_t>& ell,
         const int64_t u = (((int64_t)k / PP * F + f) * G + ln) * PP + (int64_t)k % PP;
         const int64_t j = li[k];
         const int64_t slot = (L - ell[j]) % L;
-        it_j[u] = (int32_t)j;
-        it_slot[u] = (int32_t)slot;
-        it_e1[u] = (int32_t)(slot & (M1 - 1));
+        sc.it_j[u] = (int32_t)j;
+        sc.it_slot[u] = (int32_t)slot;
+        sc.it_e1[u] = (int32_t)(slot & (M1 - 1));
       }
     }
+  return sc;
+}
+
+void pad_schedule(Schedule& sc, int64_t rounds, int64_t M1, int R) {
+  if (rounds <= sc.rounds) return;
+  // the item index of a lane's k-th item does not depend on the round
+  // count: extra rounds are padding items appended at the end
+  sc.rounds = rounds;
+  sc.Upad = rounds * R * R;
+  sc.it_j.resize(sc.Upad, -1);
+  sc.it_slot.resize(sc.Upad, -1);
+  sc.it_e1.resize(sc.Upad, (int32_t)M1);
 }
 
 template <typename T>
@@ -491,7 +509,7 @@ static int build_spectral_tables(qmc_plan_s* P, const cx<double>* dW, const cx<d
   k_tw_f2<T><<<nblk(R * R), 256, 0, st>>>(twf2, dW, R, M);
   k_tw_i3<T><<<nblk(M), 256, 0, st>>>(twi3, dW, R, M, M2);
   k_tw_outer<T><<<nblk(M2 * R), 256, 0, st>>>(two, dW, R, M, M2);
-  k_tw_items<T><<<nblk(M2 * P->Upad), 256, 0, st>>>(twit, dW, dslot, P->Upad, M, M2);
+  k_tw_items<T><<<nblk(M2 * P->Upad), 256, 0, st>>>(twit, dW, dslot, P->Upad, M, M2, 1);
   k_tw_back<T><<<nblk((int64_t)lay.P2 * lay.Q2), 256, 0, st>>>(twb, dW, lay.P2, lay.Q2, M, M2);
   QMC_HIP(hipGetLastError());
   P->d_Hs = Hs;
@@ -572,8 +590,10 @@ int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st) {
     if (rc != QMC_OK) break;
 
     // ---- collapse schedule ----------------------------------------------
-    std::vector<int32_t> it_j, it_slot, it_e1;
-    build_schedule(P, ell, it_j, it_slot, it_e1);
+    Schedule sc = make_schedule(lay, L, s, ell.data());
+    P->rounds = sc.rounds;
+    P->Upad = sc.Upad;
+    const std::vector<int32_t>&it_j = sc.it_j, &it_slot = sc.it_slot, &it_e1 = sc.it_e1;
     P->d_it_j = dev_alloc<int32_t>(P, P->Upad, &err);
     P->d_it_e1 = dev_alloc<int32_t>(P, P->Upad, &err);
     P->d_inv_ptr = dev_alloc<int32_t>(P, L + 1, &err);
@@ -628,6 +648,78 @@ int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st) {
     rc = hip_ok(hipStreamSynchronize(st));
   } while (0);
   free_temps();
+  return rc;
+}
+
+// ---------------------------------------------------------------------------
+// union of Korobov lattice point sets: per block b (Korobov base b = 1..K-1,
+// generating vector b^j mod K) the exponents l_{b,j} = j log(b) mod (K-1),
+// i.e. c_{g,j} - 1 of the paper's ordering with b = beta^(g-1); every block
+// shares the base plan's spectrum and twiddles and has its own collapse
+// schedule, padded to a common size
+// ---------------------------------------------------------------------------
+int build_korobov_tables(qmc_korobov_s* U, hipStream_t st) {
+  qmc_plan_s* P = U->base;
+  const Layout& lay = P->lay;
+  const int64_t K = P->N, L = P->L, s = U->s, nb = K - 1, M = lay.M, M2 = lay.M2;
+  std::vector<int32_t> logt(K);
+  int rc = hip_ok(hipMemcpyAsync(logt.data(), P->d_log, K * sizeof(int32_t),
+                                 hipMemcpyDeviceToHost, st));
+  if (rc == QMC_OK) rc = hip_ok(hipStreamSynchronize(st));
+  if (rc != QMC_OK) return rc;
+  std::vector<Schedule> scs(nb);
+  std::vector<int32_t> ell(s);
+  int64_t rounds = 0;
+  for (int64_t b = 1; b <= nb; ++b) {
+    const int64_t lam = logt[b];
+    if (lam < 0 || lam >= L) return QMC_ERR_HIP;
+    for (int64_t j = 0; j < s; ++j) ell[j] = (int32_t)((j % L) * lam % L);
+    scs[b - 1] = make_schedule(lay, L, s, ell.data());
+    rounds = std::max(rounds, scs[b - 1].rounds);
+  }
+  for (Schedule& sc : scs) pad_schedule(sc, rounds, lay.M1, lay.R);
+  U->rounds = rounds;
+  U->Upad = scs[0].Upad;
+  const int64_t Upad = U->Upad;
+  std::vector<int32_t> it_j(nb * Upad), it_e1(nb * Upad), slot(nb * Upad);
+  for (int64_t b = 0; b < nb; ++b) {
+    std::copy(scs[b].it_j.begin(), scs[b].it_j.end(), it_j.begin() + b * Upad);
+    std::copy(scs[b].it_e1.begin(), scs[b].it_e1.end(), it_e1.begin() + b * Upad);
+    std::copy(scs[b].it_slot.begin(), scs[b].it_slot.end(), slot.begin() + b * Upad);
+  }
+  scs.clear();
+  int err = QMC_OK;
+  const size_t el = P->dtype == QMC_F32 ? sizeof(cx<float>) : sizeof(cx<double>);
+  U->d_it_j = dev_alloc<int32_t>(P, nb * Upad, &err);
+  U->d_it_e1 = dev_alloc<int32_t>(P, nb * Upad, &err);
+  U->d_rowmap = dev_alloc<int32_t>(P, L, &err);
+  U->d_twit = dev_alloc<char>(P, nb * M2 * Upad * el, &err);
+  if (err != QMC_OK) return err;
+  int32_t* d_slot = nullptr;
+  cx<double>* dW = nullptr;
+  do {
+    if ((rc = hip_ok(hipMalloc(&d_slot, nb * Upad * sizeof(int32_t)))) != QMC_OK) break;
+    if ((rc = hip_ok(hipMalloc(&dW, M * sizeof(cx<double>)))) != QMC_OK) break;
+    rc = hip_ok(hipMemcpyAsync(U->d_it_j, it_j.data(), nb * Upad * 4, hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(U->d_it_e1, it_e1.data(), nb * Upad * 4, hipMemcpyHostToDevice,
+                                 st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(d_slot, slot.data(), nb * Upad * 4, hipMemcpyHostToDevice, st));
+    if (rc != QMC_OK) break;
+    k_twiddle<<<nblk(M), 256, 0, st>>>(dW, M);
+    if (P->dtype == QMC_F32)
+      k_tw_items<float><<<nblk(nb * M2 * Upad), 256, 0, st>>>((cx<float>*)U->d_twit, dW, d_slot,
+                                                             Upad, M, M2, nb);
+    else
+      k_tw_items<double><<<nblk(nb * M2 * Upad), 256, 0, st>>>((cx<double>*)U->d_twit, dW,
+                                                              d_slot, Upad, M, M2, nb);
+    k_minus1<<<nblk(L), 256, 0, st>>>(U->d_rowmap, P->d_pow, L);
+    if ((rc = hip_ok(hipGetLastError())) != QMC_OK) break;
+    rc = hip_ok(hipStreamSynchronize(st));  // the host vectors outlive the copies
+  } while (0);
+  if (d_slot) hipFree(d_slot);
+  if (dW) hipFree(dW);
   return rc;
 }
 

@@ -20,7 +20,12 @@ applications (Section 3 and the three experiments of Section 4):
           t = 4096, phi(y) = y - 1/2, A_jk = j^-2 sin(j pi x_k);
 * ``c4``  256 heterogeneous lattice instances for one batched launch;
 * ``c5``  a large lattice rule (N = 1048573, s = 65536, t = 256) with the
-          adjoint product.
+          adjoint product;
+* ``korobov``  the union of all Korobov lattice point sets (Section 2.2) for
+          K = 1021 (N = 1020^2 = 1040400 points), s = 512, t = 256,
+          phi = inverse normal CDF with the equal shift 1/(2K), A i.i.d.
+          N(0,1)/sqrt(s) (Gaussian-sampling shapes as in ``c2``; the paper
+          runs no experiment on this point set).
 
 Every draw uses ``numpy.random.default_rng(150106286 + 1000*config + stream)``
 with streams 0 = generating vector, 1 = A, 2 = G, 3 = finite-difference
@@ -44,6 +49,7 @@ PHI_TENT = 3
 
 RULE_LATTICE = 0
 RULE_POLY_GF2 = 1
+RULE_KOROBOV_UNION = 2   # union of Korobov rules: N = (K-1)^2, modulus = K, gen = exponents j
 
 
 def rng(config: int, stream: int) -> np.random.Generator:
@@ -167,8 +173,9 @@ class Instance:
     N: int
     s: int
     t: int
-    gen: np.ndarray              # uint64, g_j (lattice) or q_j bitmask (GF(2))
-    modulus: int                 # GF(2) primitive polynomial, 0 for lattice
+    gen: np.ndarray              # uint64, g_j (lattice), q_j bitmask (GF(2)) or the
+                                 # exponent j of coordinate j (Korobov union)
+    modulus: int                 # GF(2) primitive polynomial, K (Korobov union), 0 for lattice
     phi: int
     shift: Tuple[int, int]       # equal shift Delta = num/den
     dtype: str                   # "f32" or "f64"
@@ -278,3 +285,21 @@ def small_gf2(m: int, s: int, t: int, phi: int = PHI_CENTERED,
 def randn(shape, seed, dtype="f64") -> np.ndarray:
     g = np.random.default_rng([SEED_BASE, 9] + list(np.atleast_1d(seed)))
     return _round_to(g.standard_normal(shape), dtype)
+
+
+def make_korobov(dtype: str = "f32", K: int = 1021, s: int = 512, t: int = 256) -> Instance:
+    """Union of all Korobov lattice point sets, Gaussian sampling shapes."""
+    A = rng(6, 1).standard_normal((s, t)) / math.sqrt(s)
+    return Instance(f"korobov_k{K}_s{s}_t{t}", RULE_KOROBOV_UNION, (K - 1) ** 2, s, t,
+                    np.arange(s, dtype=np.uint64), K, PHI_INVNORM, (1, 2 * K), dtype,
+                    _round_to(A, dtype))
+
+
+def small_korobov(K: int, s: int, t: int, phi: int = PHI_IDENTITY,
+                  shift: Tuple[int, int] = (0, 1), dtype: str = "f64",
+                  seed: int = 0) -> Instance:
+    """A small seeded union-of-Korobov instance for parity tests."""
+    gen = np.random.default_rng([SEED_BASE, 9, K, s, t, seed])
+    A = gen.standard_normal((s, t))
+    return Instance(f"small_kor_k{K}_s{s}_t{t}", RULE_KOROBOV_UNION, (K - 1) ** 2, s, t,
+                    np.arange(s, dtype=np.uint64), K, phi, shift, dtype, _round_to(A, dtype))

@@ -79,3 +79,19 @@ def test_null_arguments_rejected():
     assert L.qmc_workspace_size(None, 1, None) == -1
     assert L.qmc_plan_info(None, None) == -1
     L.qmc_plan_destroy(None)
+
+
+@pytest.mark.parametrize("K,s,phi,snum,sden,dtype,code", [
+    (9, 3, 0, 0, 1, 0, -2),      # K not prime
+    (2, 3, 0, 0, 1, 0, -1),      # K < 3
+    (7, 0, 0, 0, 1, 0, -1),      # s < 1
+    (7, 3, 9, 0, 1, 0, -1),      # unknown phi
+    (7, 3, 0, 3, 2, 0, -1),      # shift outside [0, 1)
+    (7, 3, 0, 0, 1, 5, -1),      # unknown dtype
+])
+def test_korobov_create_rejects_before_gpu_work(K, s, phi, snum, sden, dtype, code):
+    L = q.lib()
+    h = ctypes.c_void_p()
+    assert L.qmc_korobov_create(ctypes.byref(h), K, s, phi, snum, sden, dtype, None) == code
+    assert not h.value
+    assert L.qmc_korobov_plan(None) is None

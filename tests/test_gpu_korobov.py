@@ -1,0 +1,109 @@
+"""Union of all Korobov lattice point sets (Section 2.2): the HIP path
+against the oracle's explicit product, element by element."""
+import numpy as np
+import pytest
+
+import oracle
+import qmc_inputs as qi
+from gpu_helpers import announce, assert_close, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+# K: direct (L a power of two) and embedded lengths, one and several on-chip
+# sizes; s from one column of Y to more than K - 1; t odd, even, one
+CASES = [
+    (3, 1, 1, qi.PHI_IDENTITY, (0, 1)),
+    (5, 3, 2, qi.PHI_CENTERED, (0, 1)),
+    (7, 9, 3, qi.PHI_IDENTITY, (1, 3)),
+    (17, 40, 5, qi.PHI_INVNORM, (0, 1)),       # no point is 0: Phi^-1 needs no shift
+    (101, 64, 7, qi.PHI_INVNORM, (1, 202)),
+    (257, 300, 4, qi.PHI_TENT, (0, 1)),
+    (1021, 33, 2, qi.PHI_INVNORM, (1, 2042)),
+    (1031, 48, 1, qi.PHI_CENTERED, (0, 1)),
+]
+
+
+def _union(inst, dtype):
+    import paper_1501_06286_amd as q
+    return q.KorobovUnion.from_instance(inst, dtype=dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("K,s,t,phi,shift", CASES)
+def test_korobov_union_matches_oracle(K, s, t, phi, shift, dtype):
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    inst = qi.small_korobov(K, s, t, phi=phi, shift=shift, dtype=dtype, seed=K)
+    announce(f"korobov union {inst.name} phi={phi} {dtype}")
+    U = _union(inst, dtype)
+    info = U.info()
+    assert info["N"] == (K - 1) ** 2 and info["blocks"] == K - 1 and info["L"] == K - 1
+    X = q.korobov_matmul(U, to_dev(inst.A, dtype))
+    torch.cuda.synchronize()
+    assert_close(X.double().cpu().numpy(), oracle.matmul(inst), inst.A, inst, dtype, inst.name)
+
+
+@pytest.mark.parametrize("chunk", [1, 7, 100, 0])
+def test_korobov_chunks_give_the_same_bits(chunk):
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    inst = qi.small_korobov(101, 50, 9, phi=qi.PHI_INVNORM, shift=(1, 202), dtype="f32", seed=1)
+    announce(f"korobov chunk={chunk}")
+    U = _union(inst, "f32")
+    A = to_dev(inst.A, "f32")
+    X0 = q.korobov_matmul(U, A)
+    U.set_chunk(chunk)
+    assert U.info()["chunk_blocks"] == chunk
+    X1 = q.korobov_matmul(U, A, workspace=U.workspace(9))
+    torch.cuda.synchronize()
+    assert torch.equal(X0, X1)
+
+
+def test_korobov_strided_operands():
+    """Row strides beyond t on both A and X."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    inst = qi.small_korobov(61, 20, 5, phi=qi.PHI_CENTERED, dtype="f64", seed=2)
+    announce("korobov strided")
+    U = _union(inst, "f64")
+    Abig = torch.zeros((inst.s, 8), dtype=torch.float64, device="cuda")
+    Abig[:, :5] = to_dev(inst.A, "f64")
+    Xbig = torch.full((inst.N, 11), 7.0, dtype=torch.float64, device="cuda")
+    q.korobov_matmul(U, Abig[:, :5], out=Xbig[:, :5])
+    torch.cuda.synchronize()
+    assert_close(Xbig[:, :5].cpu().numpy(), oracle.matmul(inst), inst.A, inst, "f64", "strided")
+    assert bool((Xbig[:, 5:] == 7.0).all())
+
+
+def test_korobov_errors():
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    inst = qi.small_korobov(13, 4, 2, dtype="f32")
+    U = _union(inst, "f32")
+    A = to_dev(inst.A, "f32")
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(q.QMCError) as e:
+        q.korobov_matmul(U, A, workspace=small)
+    assert e.value.code == -6
+    X = torch.empty((inst.N, 2), dtype=torch.float32, device="cuda")
+    with pytest.raises(q.QMCError) as e:
+        q.korobov_matmul(U, X[:inst.s], out=X)  # output overlaps the input
+    assert e.value.code == -5
+
+
+def test_korobov_full_size_sampled_rows():
+    """The benchmark workload (K = 1021, s = 512, t = 256): every block's first
+    and last row plus seeded random rows, against the oracle."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    inst = qi.make_korobov("f32")
+    announce(f"korobov full size {inst.name}")
+    U = _union(inst, "f32")
+    X = q.korobov_matmul(U, to_dev(inst.A, "f32"))
+    torch.cuda.synchronize()
+    K = inst.modulus
+    rg = np.random.default_rng(6)
+    rows = np.unique(np.concatenate([np.arange(0, inst.N, K - 1), np.arange(K - 2, inst.N, K - 1),
+                                     rg.integers(0, inst.N, size=512)]))
+    got = X[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+    assert_close(got, oracle.matmul_rows(inst, rows), inst.A, inst, "f32", "korobov full")

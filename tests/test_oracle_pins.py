@@ -314,3 +314,122 @@ def test_planted_gf2_digit_order_is_caught():
         rev = np.array([[int(format(v, f"0{m}b")[::-1], 2) for v in row] for row in k])
         return rev / float(1 << m)
     assert list(reversed_digits(2, 0b111, [0b10])[:, 0]) != [0.0, 0.75, 0.5, 0.25]
+
+
+# ---------------------------------------------------------------------------
+# union of all Korobov lattice point sets (Section 2.2)
+# ---------------------------------------------------------------------------
+
+def _kor(K, s, phi, shift=(0, 1), t=3, seed=0):
+    return qi.small_korobov(K, s, t, phi=phi, shift=shift, dtype="f64", seed=seed)
+
+
+@pytest.mark.parametrize("K", [3, 5, 7, 11, 13])
+@pytest.mark.parametrize("phi,shift", [(qi.PHI_IDENTITY, (0, 1)), (qi.PHI_CENTERED, (0, 1)),
+                                       (qi.PHI_IDENTITY, (1, 3))])
+def test_korobov_exact_bruteforce(K, phi, shift):
+    for s in (1, 2, 5):
+        inst = _kor(K, s, phi, shift, seed=K + s)
+        ex = exact.product(inst)
+        X = oracle.matmul(inst)
+        assert X.shape == ((K - 1) ** 2, 3)
+        for r in range(inst.N):
+            for c in range(3):
+                assert abs(X[r, c] - float(ex[r][c])) <= 4e-16 * (1 + sum(abs(inst.A[:, c])))
+
+
+def test_korobov_blocks_are_korobov_lattice_rules():
+    """Block b is the lattice rule with generating vector (b^j mod K)_j
+    without its point n = 0 (Section 2.2, Y' stacks the Y'_g)."""
+    K, s = 31, 6
+    Y = oracle.Y_rows(_kor(K, s, qi.PHI_IDENTITY))
+    for b in range(1, K):
+        gen = [pow(b, j, K) for j in range(s)]
+        lat = oracle.explicit_Y(qi.RULE_LATTICE, K, np.array(gen), qi.PHI_IDENTITY)
+        np.testing.assert_array_equal(Y[(b - 1) * (K - 1):b * (K - 1)], lat[1:])
+
+
+@pytest.mark.parametrize("K", [7, 13, 31])
+def test_korobov_paper_ordering(K):
+    """The paper's ordering of Section 2.2: with a primitive root beta, its
+    point (n, g) is ({beta^(c_{g,j} - n) / K})_j with c_{g,j} read as
+    ((j-1)(g-1) mod (K-1)) + 1 in [1, K-1]; it is the conventional point of
+    block b = beta^(g-1) and row n' = beta^-(n-1).  The printed
+    (j-1)(g-1)+1 mod (K-1) agrees with that reading modulo K-1."""
+    s = 5
+    beta = literal.primitive_element(literal._group(qi.RULE_LATTICE, K, 0))
+    Y = oracle.Y_rows(_kor(K, s, qi.PHI_IDENTITY))
+    for g in range(1, K):
+        for n in range(1, K):
+            c = [((j - 1) * (g - 1)) % (K - 1) + 1 for j in range(1, s + 1)]
+            assert all(1 <= v <= K - 1 for v in c)
+            assert all((v - ((j - 1) * (g - 1) + 1)) % (K - 1) == 0 for j, v in zip(range(1, s + 1), c))
+            paper = [pow(beta, (v - n) % (K - 1), K) / K for v in c]
+            b = pow(beta, g - 1, K)
+            n_conv = pow(beta, (-(n - 1)) % (K - 1), K)
+            row = (b - 1) * (K - 1) + (n_conv - 1)
+            np.testing.assert_array_equal(Y[row], np.array(paper))
+
+
+@pytest.mark.parametrize("K", [5, 11, 101])
+def test_korobov_column_sums(K):
+    """Every block column is a permutation of the residues 1..K-1 (b^j is a
+    unit), so each column of Y sums to (K-1) times the sum of phi over the
+    nonzero residues: (K-1)^2/2 for the identity, 0 for x - 1/2, and
+    -(K-1) Phi^-1(1/(2K)) for the inverse normal CDF with shift 1/(2K)."""
+    s = 7
+    Yi = oracle.Y_rows(_kor(K, s, qi.PHI_IDENTITY))
+    num = np.rint(Yi * K).astype(np.int64)
+    for b in range(1, K):
+        blk = num[(b - 1) * (K - 1):b * (K - 1)]
+        for j in range(s):
+            assert sorted(blk[:, j]) == list(range(1, K))
+    np.testing.assert_array_equal(num.sum(axis=0), np.full(s, (K - 1) ** 2 * K // 2))
+    Yc = oracle.Y_rows(_kor(K, s, qi.PHI_CENTERED))
+    np.testing.assert_allclose(Yc.sum(axis=0), 0.0, atol=1e-12 * K * K)
+    Yn = oracle.Y_rows(_kor(K, s, qi.PHI_INVNORM, (1, 2 * K)))
+    expect = -(K - 1) * statistics.NormalDist().inv_cdf(1 / (2 * K))
+    np.testing.assert_allclose(Yn.sum(axis=0), expect, rtol=1e-12, atol=1e-10 * K)
+
+
+def _korobov_pins_pass(numer_fn) -> bool:
+    """The union's coordinate pins (exact values, block permutations, the
+    paper's ordering) run against a candidate numerator routine
+    numer_fn(K, exponents) -> (K-1)^2 x s array of (n b^e) mod K."""
+    K, s = 7, 4
+    num = numer_fn(K, np.arange(s))
+    # exact values of the definition (Fractions, Python's pow)
+    ex = exact.point_matrix(_kor(K, s, qi.PHI_IDENTITY))
+    if not all(Fraction(int(num[r, j]), K) == ex[r][j] for r in range((K - 1) ** 2) for j in range(s)):
+        return False
+    for b in range(1, K):  # every block column permutes 1..K-1
+        blk = num[(b - 1) * (K - 1):b * (K - 1)]
+        if any(sorted(blk[:, j]) != list(range(1, K)) for j in range(s)):
+            return False
+    beta = literal.primitive_element(literal._group(qi.RULE_LATTICE, K, 0))
+    for g in range(1, K):  # the paper's ordering
+        for n in range(1, K):
+            c = [((j - 1) * (g - 1)) % (K - 1) + 1 for j in range(1, s + 1)]
+            row = (pow(beta, g - 1, K) - 1) * (K - 1) + pow(beta, (-(n - 1)) % (K - 1), K) - 1
+            if [int(v) for v in num[row]] != [pow(beta, (v - n) % (K - 1), K) for v in c]:
+                return False
+    return True
+
+
+def test_korobov_planted_mistakes_are_caught():
+    """Mutated copies of the union's coordinate routine fail the pins: n
+    counted from 0, the exponent shifted by one, n-major block order."""
+    good = oracle.points.korobov_union_numerators
+    assert _korobov_pins_pass(good)
+
+    def mutate(f):
+        def numer(K, exps):
+            N = (K - 1) ** 2
+            return np.array([[f(K, r, int(e)) for e in exps] for r in range(N)])
+        return numer
+
+    bad_n0 = mutate(lambda K, r, e: (r % (K - 1)) * pow(r // (K - 1) + 1, e, K) % K)
+    bad_exp = mutate(lambda K, r, e: (r % (K - 1) + 1) * pow(r // (K - 1) + 1, e + 1, K) % K)
+    bad_major = mutate(lambda K, r, e: (r // (K - 1) + 1) * pow(r % (K - 1) + 1, e, K) % K)
+    for bad in (bad_n0, bad_exp, bad_major):
+        assert not _korobov_pins_pass(bad)
