@@ -94,6 +94,29 @@ def time_steps(fn, steps, torch):
     return time.perf_counter() - t0
 
 
+def roofline_of(name, model, per_launch, avg_s, dtype):
+    """Roofline entry of one kernel: ALU-bound above the ridge point."""
+    m = {k: v / per_launch for k, v in model[name].items()}
+    ai = m["flops"] / max(m["bytes"], 1)
+    ridge = VALU_PEAK_TFLOPS[dtype] * 1e12 / (HBM_PEAK_GBPS * 1e9)
+    if ai > ridge:
+        ach = m["flops"] / avg_s / 1e12
+        return {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_TFLOPS[dtype],
+                "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS[dtype], 4), "kernel": name}
+    ach = m["bytes"] / avg_s / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBPS, 4), "kernel": name}
+
+
+def korobov_model(info, pairs, t, w):
+    """Algorithmic bytes and flops of every kernel for all K - 1 blocks: each
+    block is a lattice product of K points with its own collapse of A."""
+    K = info["K"]
+    one = kernel_model({"M": info["M"], "M1": info["M1"], "M2": info["M2"],
+                        "rounds": info["rounds"]}, pairs, t, w, K - 1, info["s"])
+    return {k: {kk: vv * info["blocks"] for kk, vv in v.items()} for k, v in one.items()}
+
+
 def cpu_baseline(inst, budget_s=12.0):
     """The FP64 oracle (explicit Y rows, dense product) on a bounded sample."""
     import numpy as np
@@ -137,6 +160,7 @@ def main():
                     help="fixed launch tuning chunk_pairs,streams,nt_store,front instead of autotuning")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-korobov", action="store_true")
     ap.add_argument("--fft-only", action="store_true",
                     help="time only the FFT path (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -149,6 +173,7 @@ def main():
         sys.exit(2)
     if args.fft_only:
         args.no_dense = args.no_cpu = args.no_f64 = args.no_batched = args.no_adjoint = True
+        args.no_korobov = True
     if args.copy_calibration:
         import torch
         n = 1 << 28  # 2^28 float32 = 1 GiB
@@ -305,6 +330,42 @@ def main():
                              "graph_ms_per_batch": round(1e3 * eg / nb, 4)}
         log(f"batched 256 products: {1e3 * eb / nb:.3f} ms eager, {1e3 * eg / nb:.3f} ms graph")
         del batch, bA, bplans, g
+
+    if not args.no_korobov:
+        kin = qi.make_korobov(args.dtype)
+        U = q.KorobovUnion.from_instance(kin)
+        kinfo = U.info()
+        if not args.no_tune:
+            from paper_1501_06286_amd import autotune
+            kbest, _ = autotune.tune_korobov(U, kin.t)
+        kA = torch.from_numpy(kin.A).to(tdt).to(dev)
+        kX = torch.empty((kin.N, kin.t), dtype=tdt, device=dev)
+        kws = U.workspace(kin.t, dev)
+        kstep = lambda: q.korobov_matmul(U, kA, out=kX, workspace=kws)
+        kstep()
+        nk = max(3, args.steps // 2)
+        ek = time_steps(kstep, nk, torch)
+        U.plan.profile(True)
+        time_steps(kstep, nk, torch)
+        kprof = U.plan.profile_collect()
+        U.plan.profile(False)
+        kmodel = korobov_model(kinfo, (kin.t + 1) // 2, kin.t, w)
+        kdom = max(kprof, key=lambda k: kprof[k][0])
+        kroof = roofline_of(kdom, kmodel, kprof[kdom][1] / nk, kprof[kdom][0] / kprof[kdom][1] * 1e-3,
+                            args.dtype)
+        result["korobov_union"] = {
+            "workload": f"union of Korobov lattice rules K={kin.modulus} (N={kin.N}), s={kin.s}, "
+                        f"t={kin.t}, Phi^-1 shift 1/(2K)",
+            "value": kin.N * kin.t / (ek / nk), "unit": "entries/s (N*t per s)",
+            "ms_per_step": round(1e3 * ek / nk, 4), "chunk_blocks": kinfo["chunk_blocks"],
+            "hbm_GBps_algorithmic": round((kin.s + kin.N) * kin.t * w / (ek / nk) / 1e9, 1),
+            "roofline": kroof,
+            "kernels": {k: {"avg_ms": round(v[0] / v[1], 4), "ms_per_step": round(v[0] / nk, 4)}
+                        for k, v in kprof.items()}}
+        log(f"Korobov union {1e3 * ek / nk:.3f} ms/step")
+        if not args.no_cpu:
+            result["korobov_union"]["cpu_baseline"] = cpu_baseline(kin, budget_s=6.0)
+        del U, kA, kX, kws
 
     if not args.no_dense:
         Y = q.explicit_points(plan)

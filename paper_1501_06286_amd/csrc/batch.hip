@@ -23,7 +23,8 @@ struct BatchInst {
   void* X;
   int64_t lda, ldx, t, pairs;
   int64_t aT_off, C_off;  // byte offsets into the run's workspace
-  const int32_t* it_j;
+  const int32_t* it_ptr;
+  const int32_t* it_jl;
   const int32_t* it_e1;
   const int32_t* pow;
   const void* twit;
@@ -59,7 +60,7 @@ __global__ __launch_bounds__(256) void kb_collapse(const BatchInst* __restrict__
   for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
     const BatchInst I = D[find_inst(D, n, PASS_COLLAPSE, b)];
     const int64_t lb = b - I.off[PASS_COLLAPSE];
-    collapse_body<T>((const T*)I.A, I.lda, I.t, I.pairs, I.it_j, I.Upad,
+    collapse_body<T>((const T*)I.A, I.lda, I.t, I.pairs, I.it_ptr, I.it_jl, I.Upad,
                      (cx<T>*)(ws + I.aT_off), lb % I.gx_collapse, lb / I.gx_collapse, S,
                      opaque_tid());
     __syncthreads();
@@ -188,7 +189,8 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
     ws += al256(I.pairs * P->Upad * el);
     I.C_off = (int64_t)ws;
     ws += al256(I.pairs * lay.M * el);
-    I.it_j = P->d_it_j;
+    I.it_ptr = P->d_it_ptr;
+    I.it_jl = P->d_it_jl;
     I.it_e1 = P->d_it_e1;
     I.pow = P->d_pow;
     I.twit = P->d_twit;

@@ -33,10 +33,12 @@ namespace qmc {
 template <typename T>
 __global__ __launch_bounds__(256) void k_collapse_T(const T* __restrict__ A, int64_t lda,
                                                     int64_t t, int64_t P,
-                                                    const int32_t* __restrict__ it_j, int64_t Upad,
+                                                    const int32_t* __restrict__ it_ptr,
+                                                    const int32_t* __restrict__ it_jl, int64_t Upad,
                                                     cx<T>* __restrict__ aT) {
   __shared__ CollapseSmem<T> S;
-  collapse_body<T>(A, lda, t, P, it_j, Upad, aT, blockIdx.x, blockIdx.y, S, threadIdx.x);
+  collapse_body<T>(A, lda, t, P, it_ptr, it_jl, Upad, aT, blockIdx.x, blockIdx.y, S,
+                   threadIdx.x);
 }
 
 template <typename T, int R, bool SPARSE>
@@ -259,7 +261,7 @@ static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T*
   dim3 gT((unsigned)((P->Upad + 63) / 64), (unsigned)((pairs + 15) / 16));
   {
     ProfScope ps(P, PROF_COLLAPSE, st);
-    k_collapse_T<T><<<gT, 256, 0, st>>>(A, lda, t, pairs, P->d_it_j, P->Upad, aT);
+    k_collapse_T<T><<<gT, 256, 0, st>>>(A, lda, t, pairs, P->d_it_ptr, P->d_it_jl, P->Upad, aT);
   }
   int rc = hip_ok(hipGetLastError());
   if (rc != QMC_OK) return rc;

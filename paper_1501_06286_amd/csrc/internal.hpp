@@ -61,7 +61,8 @@ struct qmc_plan_s {
   void* d_twit = nullptr;       // M2*Upad: W_M^{slot_u w2} in [w2][u] order
   void* d_twb = nullptr;        // M2  : conj W_{M2}^{a q} table for the split back pass [a*Q2+q]
   int32_t* d_it_e1 = nullptr;   // Upad: e1 of item u (M1 for padding)
-  int32_t* d_it_j = nullptr;    // Upad: row j of A for item u (-1 for padding)
+  int32_t* d_it_ptr = nullptr;  // Upad+1: rows of item u are it_jl[it_ptr[u] .. it_ptr[u+1])
+  int32_t* d_it_jl = nullptr;   // s   : rows j grouped by item (increasing j)
   int32_t* d_inv_ptr = nullptr;    // L+1 : rows j with l_j = e are inv_j[inv_ptr[e] .. inv_ptr[e+1])
   int32_t* d_inv_j = nullptr;      // s
   std::vector<void*> owned;
@@ -81,7 +82,8 @@ struct qmc_korobov_s {
                                 // memory below); its own collapse schedule is unused
   int64_t K = 0, s = 0, blocks = 0;
   int64_t rounds = 0, Upad = 0;  // common collapse schedule size of every block
-  int32_t* d_it_j = nullptr;     // blocks*Upad
+  int32_t* d_it_ptr = nullptr;   // blocks*(Upad+1), offsets into the block's s rows
+  int32_t* d_it_jl = nullptr;    // blocks*s
   int32_t* d_it_e1 = nullptr;    // blocks*Upad
   void* d_twit = nullptr;        // blocks*M2*Upad: W_M^{slot w2} per block
   int32_t* d_rowmap = nullptr;   // L: pow[e] - 1 (row n - 1 of a block)
@@ -94,12 +96,13 @@ namespace qmc {
 int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st);
 int build_korobov_tables(qmc_korobov_s* U, hipStream_t st);
 
-// sparse collapse schedule for exponents l_j (j < s) on a layout: item u
-// carries row it_j[u] (-1: padding), reflected slot it_slot[u] = (L - l_j)
-// mod L and its residue it_e1[u] = slot mod M1 (M1 for padding)
+// sparse collapse schedule for exponents l_j (j < s) on a layout: item u is
+// one distinct reflected slot it_slot[u] = (L - l_j) mod L (-1: padding)
+// with residue it_e1[u] = slot mod M1 (M1 for padding) and the rows
+// it_jl[it_ptr[u] .. it_ptr[u+1]) of A that share it
 struct Schedule {
   int64_t rounds = 0, Upad = 0;
-  std::vector<int32_t> it_j, it_slot, it_e1;
+  std::vector<int32_t> it_slot, it_e1, it_ptr, it_jl;
 };
 Schedule make_schedule(const Layout& lay, int64_t L, int64_t s, const int32_t* ell);
 void pad_schedule(Schedule& sc, int64_t rounds, int64_t M1, int R);

@@ -27,7 +27,8 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
 }
 
 // ---------------------------------------------------------------------------
-// T: aT[pair][u] = A[j_u, 2 pair] + i A[j_u, 2 pair + 1]   (0 for padding)
+// T: aT[pair][u] = sum over the rows j of item u of
+//                  A[j, 2 pair] + i A[j, 2 pair + 1]   (0 for padding)
 // ---------------------------------------------------------------------------
 template <typename T>
 struct CollapseSmem {
@@ -36,9 +37,10 @@ struct CollapseSmem {
 
 template <typename T>
 __device__ __forceinline__ void collapse_body(const T* __restrict__ A, int64_t lda, int64_t t,
-                                              int64_t P, const int32_t* __restrict__ it_j,
-                                              int64_t Upad, cx<T>* __restrict__ aT, int64_t bx,
-                                              int64_t by, CollapseSmem<T>& S, int tid) {
+                                              int64_t P, const int32_t* __restrict__ it_ptr,
+                                              const int32_t* __restrict__ it_jl, int64_t Upad,
+                                              cx<T>* __restrict__ aT, int64_t bx, int64_t by,
+                                              CollapseSmem<T>& S, int tid) {
   auto& sm = S.sm;
   const int64_t u0 = bx * 64, p0 = by * 16;
   const int pl = tid & 15;
@@ -48,12 +50,11 @@ __device__ __forceinline__ void collapse_body(const T* __restrict__ A, int64_t l
     const int64_t u = u0 + ul, p = p0 + pl;
     cx<T> v = {(T)0, (T)0};
     if (u < Upad && p < P) {
-      const int j = it_j[u];
-      if (j >= 0) {
-        const T* row = A + (int64_t)j * lda;
-        const int64_t c = 2 * p;
-        v.x = row[c];
-        if (c + 1 < t) v.y = row[c + 1];
+      const int64_t c = 2 * p;
+      for (int32_t k = it_ptr[u]; k < it_ptr[u + 1]; ++k) {
+        const T* row = A + (int64_t)it_jl[k] * lda;
+        v.x += row[c];
+        if (c + 1 < t) v.y += row[c + 1];
       }
     }
     sm[ul][pl] = v;

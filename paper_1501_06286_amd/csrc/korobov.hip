@@ -16,13 +16,15 @@ namespace qmc {
 
 template <typename T>
 __global__ __launch_bounds__(256) void ku_collapse(const T* __restrict__ A, int64_t lda, int64_t t,
-                                                   int64_t P, const int32_t* __restrict__ it_j,
+                                                   int64_t P, int64_t s,
+                                                   const int32_t* __restrict__ it_ptr,
+                                                   const int32_t* __restrict__ it_jl,
                                                    int64_t Upad, cx<T>* __restrict__ aT,
                                                    int64_t gx, int64_t per_block) {
   __shared__ CollapseSmem<T> S;
   const int64_t b = blockIdx.x / per_block, lb = blockIdx.x % per_block;
-  collapse_body<T>(A, lda, t, P, it_j + b * Upad, Upad, aT + b * P * Upad, lb % gx, lb / gx, S,
-                   threadIdx.x);
+  collapse_body<T>(A, lda, t, P, it_ptr + b * (Upad + 1), it_jl + b * s, Upad,
+                   aT + b * P * Upad, lb % gx, lb / gx, S, threadIdx.x);
 }
 
 template <typename T, int R>
@@ -109,7 +111,8 @@ static int korobov_forward(const qmc_korobov_s* U, const T* A, int64_t t, int64_
       const int64_t gx = (U->Upad + 63) / 64, per_block = gx * ((pairs + 15) / 16);
       ProfScope ps(P, PROF_COLLAPSE, st);
       ku_collapse<T><<<dim3((unsigned)(nb * per_block)), 256, 0, st>>>(
-          A, lda, t, pairs, U->d_it_j + b0 * U->Upad, U->Upad, aT, gx, per_block);
+          A, lda, t, pairs, U->s, U->d_it_ptr + b0 * (U->Upad + 1), U->d_it_jl + b0 * U->s,
+          U->Upad, aT, gx, per_block);
     }
     switch (lay.R) {
       case 1: ku_middle_launch<T, 1>(U, aT, b0, nb, pairs, C, st); break;

@@ -411,14 +411,17 @@ static Layout choose_layout(int64_t L, int dtype, int* embedded) {
   return lay;
 }
 
-// collapse schedule: item u -> (row j, slot).  The residues e1 = slot mod M1
-// are owned by F slices (e1 mod F, one wavefront each); inside a slice every
-// residue's items (its "bucket", in increasing j: a fixed summation order)
-// go to one lane, buckets assigned longest-first to the least-loaded lane.
-// A lane accumulates one bucket in registers and writes it once.  The lane's
-// k-th item is u = ((k / PP * F + slice) * G + lane) * PP + k % PP, so its
-// items come in adjacent pairs; the item count per lane is padded to a
-// multiple of PP.
+// collapse schedule.  An item is one distinct reflected slot
+// (L - l_j) mod L; it carries every row j with that slot (CSR it_ptr/it_jl,
+// increasing j: the collapse sums them, the a' = P a of Section 2.1 with
+// its repeated exponents).  The residues e1 = slot mod M1 are owned by F
+// slices (e1 mod F, one wavefront each); inside a slice every residue's items
+// (its "bucket", in increasing slot: a fixed summation order) go to one lane,
+// buckets assigned longest-first to the least-loaded lane.  A lane
+// accumulates one bucket in registers and writes it once.  The lane's k-th
+// item is u = ((k / PP * F + slice) * G + lane) * PP + k % PP, so its items
+// come in adjacent pairs; the item count per lane is padded to a multiple of
+// PP.
 Schedule make_schedule(const Layout& lay, int64_t L, int64_t s, const int32_t* ell) {
   const int64_t M1 = lay.M1;
   const int R = lay.R;
@@ -426,17 +429,29 @@ Schedule make_schedule(const Layout& lay, int64_t L, int64_t s, const int32_t* e
   const int G = Q < 64 ? Q : 64;
   const int F = Q / G;
   const int PP = pair_pp(R);
-  // buckets: items of each residue e1, in increasing j
+  // distinct slots, each with its rows in increasing j
+  std::vector<std::pair<int64_t, int32_t>> sj(s);
+  for (int64_t j = 0; j < s; ++j) sj[j] = {(L - ell[j]) % L, (int32_t)j};
+  std::sort(sj.begin(), sj.end());
+  std::vector<int64_t> uslot, ufirst;  // slot and first index into sj of each distinct slot
+  for (int64_t k = 0; k < s; ++k)
+    if (k == 0 || sj[k].first != sj[k - 1].first) {
+      uslot.push_back(sj[k].first);
+      ufirst.push_back(k);
+    }
+  const int64_t nu = (int64_t)uslot.size();
+  ufirst.push_back(s);
+  // buckets: distinct slots of each residue e1 (increasing slot)
   std::vector<int64_t> start(M1 + 1, 0);
-  for (int64_t j = 0; j < s; ++j) start[((L - ell[j]) % L & (M1 - 1)) + 1]++;
+  for (int64_t i = 0; i < nu; ++i) start[(uslot[i] & (M1 - 1)) + 1]++;
   for (int64_t e = 0; e < M1; ++e) start[e + 1] += start[e];
-  std::vector<int32_t> members(s);
+  std::vector<int64_t> members(nu);
   {
     std::vector<int64_t> pos(start.begin(), start.end() - 1);
-    for (int64_t j = 0; j < s; ++j) members[pos[((L - ell[j]) % L) & (M1 - 1)]++] = (int32_t)j;
+    for (int64_t i = 0; i < nu; ++i) members[pos[uslot[i] & (M1 - 1)]++] = i;
   }
   // per slice: longest-first assignment of buckets to lanes
-  std::vector<std::vector<int32_t>> lane_items((size_t)F * G);  // j's in order
+  std::vector<std::vector<int64_t>> lane_items((size_t)F * G);  // distinct-slot ids in order
   std::vector<int64_t> load(G);
   std::vector<int64_t> order;
   for (int f = 0; f < F; ++f) {
@@ -450,7 +465,7 @@ Schedule make_schedule(const Layout& lay, int64_t L, int64_t s, const int32_t* e
     for (int64_t e : order) {
       const int ln = (int)(std::min_element(load.begin(), load.end()) - load.begin());
       load[ln] += start[e + 1] - start[e];
-      std::vector<int32_t>& li = lane_items[(size_t)f * G + ln];
+      std::vector<int64_t>& li = lane_items[(size_t)f * G + ln];
       for (int64_t k = start[e]; k < start[e + 1]; ++k) li.push_back(members[k]);
     }
   }
@@ -460,33 +475,38 @@ Schedule make_schedule(const Layout& lay, int64_t L, int64_t s, const int32_t* e
   rounds = (rounds + PP - 1) / PP * PP;  // whole item pairs
   sc.rounds = rounds;
   sc.Upad = rounds * Q;
-  sc.it_j.assign(sc.Upad, -1);
-  sc.it_slot.assign(sc.Upad, -1);
-  sc.it_e1.assign(sc.Upad, (int32_t)M1);
+  std::vector<int64_t> item_of(sc.Upad, -1);  // distinct-slot id of item u (-1: padding)
   for (int f = 0; f < F; ++f)
     for (int ln = 0; ln < G; ++ln) {
-      const std::vector<int32_t>& li = lane_items[(size_t)f * G + ln];
-      for (size_t k = 0; k < li.size(); ++k) {
-        const int64_t u = (((int64_t)k / PP * F + f) * G + ln) * PP + (int64_t)k % PP;
-        const int64_t j = li[k];
-        const int64_t slot = (L - ell[j]) % L;
-        sc.it_j[u] = (int32_t)j;
-        sc.it_slot[u] = (int32_t)slot;
-        sc.it_e1[u] = (int32_t)(slot & (M1 - 1));
-      }
+      const std::vector<int64_t>& li = lane_items[(size_t)f * G + ln];
+      for (size_t k = 0; k < li.size(); ++k)
+        item_of[(((int64_t)k / PP * F + f) * G + ln) * PP + (int64_t)k % PP] = li[k];
     }
+  sc.it_slot.assign(sc.Upad, -1);
+  sc.it_e1.assign(sc.Upad, (int32_t)M1);
+  sc.it_ptr.assign(sc.Upad + 1, 0);
+  sc.it_jl.reserve(s);
+  for (int64_t u = 0; u < sc.Upad; ++u) {
+    const int64_t i = item_of[u];
+    if (i >= 0) {
+      sc.it_slot[u] = (int32_t)uslot[i];
+      sc.it_e1[u] = (int32_t)(uslot[i] & (M1 - 1));
+      for (int64_t k = ufirst[i]; k < ufirst[i + 1]; ++k) sc.it_jl.push_back(sj[k].second);
+    }
+    sc.it_ptr[u + 1] = (int32_t)sc.it_jl.size();
+  }
   return sc;
 }
 
 void pad_schedule(Schedule& sc, int64_t rounds, int64_t M1, int R) {
   if (rounds <= sc.rounds) return;
   // the item index of a lane's k-th item does not depend on the round
-  // count: extra rounds are padding items appended at the end
+  // count: extra rounds are padding items (empty row lists) at the end
   sc.rounds = rounds;
   sc.Upad = rounds * R * R;
-  sc.it_j.resize(sc.Upad, -1);
   sc.it_slot.resize(sc.Upad, -1);
   sc.it_e1.resize(sc.Upad, (int32_t)M1);
+  sc.it_ptr.resize(sc.Upad + 1, sc.it_ptr.back());
 }
 
 template <typename T>
@@ -593,8 +613,8 @@ int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st) {
     Schedule sc = make_schedule(lay, L, s, ell.data());
     P->rounds = sc.rounds;
     P->Upad = sc.Upad;
-    const std::vector<int32_t>&it_j = sc.it_j, &it_slot = sc.it_slot, &it_e1 = sc.it_e1;
-    P->d_it_j = dev_alloc<int32_t>(P, P->Upad, &err);
+    P->d_it_ptr = dev_alloc<int32_t>(P, P->Upad + 1, &err);
+    P->d_it_jl = dev_alloc<int32_t>(P, s, &err);
     P->d_it_e1 = dev_alloc<int32_t>(P, P->Upad, &err);
     P->d_inv_ptr = dev_alloc<int32_t>(P, L + 1, &err);
     P->d_inv_j = dev_alloc<int32_t>(P, s, &err);
@@ -610,11 +630,16 @@ int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st) {
       std::vector<int32_t> pos(inv_ptr.begin(), inv_ptr.end() - 1);
       for (int64_t j = 0; j < s; ++j) inv_j[pos[ell[j]]++] = (int32_t)j;
     }
-    rc = hip_ok(hipMemcpyAsync(P->d_it_j, it_j.data(), P->Upad * 4, hipMemcpyHostToDevice, st));
+    rc = hip_ok(hipMemcpyAsync(P->d_it_ptr, sc.it_ptr.data(), (P->Upad + 1) * 4,
+                               hipMemcpyHostToDevice, st));
     if (rc == QMC_OK)
-      rc = hip_ok(hipMemcpyAsync(P->d_it_e1, it_e1.data(), P->Upad * 4, hipMemcpyHostToDevice, st));
+      rc = hip_ok(hipMemcpyAsync(P->d_it_jl, sc.it_jl.data(), s * 4, hipMemcpyHostToDevice, st));
     if (rc == QMC_OK)
-      rc = hip_ok(hipMemcpyAsync(d_slot, it_slot.data(), P->Upad * 4, hipMemcpyHostToDevice, st));
+      rc = hip_ok(hipMemcpyAsync(P->d_it_e1, sc.it_e1.data(), P->Upad * 4, hipMemcpyHostToDevice,
+                                 st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(d_slot, sc.it_slot.data(), P->Upad * 4, hipMemcpyHostToDevice,
+                                 st));
     if (rc == QMC_OK)
       rc = hip_ok(hipMemcpyAsync(P->d_inv_ptr, inv_ptr.data(), (L + 1) * 4, hipMemcpyHostToDevice, st));
     if (rc == QMC_OK)
@@ -681,16 +706,18 @@ int build_korobov_tables(qmc_korobov_s* U, hipStream_t st) {
   U->rounds = rounds;
   U->Upad = scs[0].Upad;
   const int64_t Upad = U->Upad;
-  std::vector<int32_t> it_j(nb * Upad), it_e1(nb * Upad), slot(nb * Upad);
+  std::vector<int32_t> it_ptr(nb * (Upad + 1)), it_jl(nb * s), it_e1(nb * Upad), slot(nb * Upad);
   for (int64_t b = 0; b < nb; ++b) {
-    std::copy(scs[b].it_j.begin(), scs[b].it_j.end(), it_j.begin() + b * Upad);
+    std::copy(scs[b].it_ptr.begin(), scs[b].it_ptr.end(), it_ptr.begin() + b * (Upad + 1));
+    std::copy(scs[b].it_jl.begin(), scs[b].it_jl.end(), it_jl.begin() + b * s);
     std::copy(scs[b].it_e1.begin(), scs[b].it_e1.end(), it_e1.begin() + b * Upad);
     std::copy(scs[b].it_slot.begin(), scs[b].it_slot.end(), slot.begin() + b * Upad);
   }
   scs.clear();
   int err = QMC_OK;
   const size_t el = P->dtype == QMC_F32 ? sizeof(cx<float>) : sizeof(cx<double>);
-  U->d_it_j = dev_alloc<int32_t>(P, nb * Upad, &err);
+  U->d_it_ptr = dev_alloc<int32_t>(P, nb * (Upad + 1), &err);
+  U->d_it_jl = dev_alloc<int32_t>(P, nb * s, &err);
   U->d_it_e1 = dev_alloc<int32_t>(P, nb * Upad, &err);
   U->d_rowmap = dev_alloc<int32_t>(P, L, &err);
   U->d_twit = dev_alloc<char>(P, nb * M2 * Upad * el, &err);
@@ -700,7 +727,11 @@ int build_korobov_tables(qmc_korobov_s* U, hipStream_t st) {
   do {
     if ((rc = hip_ok(hipMalloc(&d_slot, nb * Upad * sizeof(int32_t)))) != QMC_OK) break;
     if ((rc = hip_ok(hipMalloc(&dW, M * sizeof(cx<double>)))) != QMC_OK) break;
-    rc = hip_ok(hipMemcpyAsync(U->d_it_j, it_j.data(), nb * Upad * 4, hipMemcpyHostToDevice, st));
+    rc = hip_ok(hipMemcpyAsync(U->d_it_ptr, it_ptr.data(), nb * (Upad + 1) * 4,
+                               hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(U->d_it_jl, it_jl.data(), nb * s * 4, hipMemcpyHostToDevice,
+                                 st));
     if (rc == QMC_OK)
       rc = hip_ok(hipMemcpyAsync(U->d_it_e1, it_e1.data(), nb * Upad * 4, hipMemcpyHostToDevice,
                                  st));
