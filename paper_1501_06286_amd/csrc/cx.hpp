@@ -3,8 +3,8 @@
 // The circular convolutions of the fast QMC product (Section 2.1, eq. (ZPa):
 // Y' a = Z (P a) with Z circulant) are evaluated with FFTs.  Short DFTs
 // (length <= 64) run entirely in one lane's registers with compile-time
-// twiddle constants; longer transforms combine two of them across the 64
-// lanes of a wavefront (see conv.hip).
+// twiddle constants; longer transforms are built from them with LDS
+// exchanges between lanes (kernels.hpp).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
