@@ -61,10 +61,18 @@ def kernel_model(plan_info, pairs, t, w, N, s):
 
 
 def source_sha():
+    """Hash of the kernel sources with comments and blank space removed, so a
+    stored counter summary stays valid across comment-only edits."""
+    import re
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1501_06286_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_1501_06286_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+    d = os.path.join(ROOT, "paper_1501_06286_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), encoding="utf-8") as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(f.encode())
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 
