@@ -6,8 +6,9 @@
 // workgroup loops over logical blocks, finds its product by binary search in
 // the descriptors' block offsets, and runs the same device bodies as a single
 // product.  A run makes no host-to-device copies, so it can be captured in a
-// HIP graph and replayed.  Products are grouped by the on-chip transform size
-// R (one set of launches per group).
+// HIP graph and replayed.  Products are grouped by their layout (on-chip size
+// R and outer split P2 x Q2), one set of launches per group, so every kernel
+// is compiled for one transform size and keeps only the registers it needs.
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -85,7 +86,7 @@ __attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void kb_middle(const Bat
   }
 }
 
-template <typename T>
+template <typename T, int P2>
 __global__ __launch_bounds__(64) void kb_split(const BatchInst* __restrict__ D, int n,
                                                int64_t total, char* __restrict__ ws) {
   for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
@@ -93,22 +94,12 @@ __global__ __launch_bounds__(64) void kb_split(const BatchInst* __restrict__ D, 
     const int64_t lb = b - I.off[PASS_SPLIT];
     const int64_t bx = lb % I.gx_split, rest = lb / I.gx_split;
     const int64_t q = rest % I.Q2, pair = rest / I.Q2;
-    cx<T>* C = (cx<T>*)(ws + I.C_off);
-    const cx<T>* twb = (const cx<T>*)I.twb;
-    const int tid = opaque_tid();
-    switch (I.P2) {
-      case 2: split_body<T, 2, +1>(C, I.M1, I.M2, (int)I.Q2, twb, bx, q, pair, tid); break;
-      case 4: split_body<T, 4, +1>(C, I.M1, I.M2, (int)I.Q2, twb, bx, q, pair, tid); break;
-      case 8: split_body<T, 8, +1>(C, I.M1, I.M2, (int)I.Q2, twb, bx, q, pair, tid); break;
-      case 16: split_body<T, 16, +1>(C, I.M1, I.M2, (int)I.Q2, twb, bx, q, pair, tid); break;
-      case 32: split_body<T, 32, +1>(C, I.M1, I.M2, (int)I.Q2, twb, bx, q, pair, tid); break;
-      case 64: split_body<T, 64, +1>(C, I.M1, I.M2, (int)I.Q2, twb, bx, q, pair, tid); break;
-      default: break;
-    }
+    split_body<T, P2, +1>((cx<T>*)(ws + I.C_off), I.M1, I.M2, (int)I.Q2,
+                          (const cx<T>*)I.twb, bx, q, pair, opaque_tid());
   }
 }
 
-template <typename T>
+template <typename T, int Q>
 __global__ __launch_bounds__(256) void kb_back(const BatchInst* __restrict__ D, int n,
                                                int64_t total, char* __restrict__ ws) {
   __shared__ BackSmem<T> S;
@@ -117,22 +108,9 @@ __global__ __launch_bounds__(256) void kb_back(const BatchInst* __restrict__ D, 
     const int64_t lb = b - I.off[PASS_BACK];
     const int64_t bx = lb % I.gx_back, rest = lb / I.gx_back;
     const int64_t by = rest % I.gy_back, a = rest / I.gy_back;
-    const cx<T>* C = (const cx<T>*)(ws + I.C_off);
-    const int tid = opaque_tid();
-#define QMC_BB(QQ)                                                                              \
-  back_body<T, QQ, false, false>(C, I.M1, I.M2, I.P2, I.L, I.pairs, I.pow, nullptr, nullptr,   \
-                                 nullptr, (T)I.phi0, (T*)I.X, I.ldx, I.t, bx, by, a, S, tid)
-    switch (I.Q2) {
-      case 1: QMC_BB(1); break;
-      case 2: QMC_BB(2); break;
-      case 4: QMC_BB(4); break;
-      case 8: QMC_BB(8); break;
-      case 16: QMC_BB(16); break;
-      case 32: QMC_BB(32); break;
-      case 64: QMC_BB(64); break;
-      default: break;
-    }
-#undef QMC_BB
+    back_body<T, Q, false, false>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2, I.L, I.pairs,
+                                  I.pow, nullptr, nullptr, nullptr, (T)I.phi0, (T*)I.X, I.ldx,
+                                  I.t, bx, by, a, S, opaque_tid());
     __syncthreads();
   }
 }
@@ -145,7 +123,7 @@ struct qmc_batch_s {
   int dtype = QMC_F32;
   size_t ws_bytes = 0;
   struct Group {
-    int R = 0;
+    int R = 0, P2 = 1, Q2 = 1;
     int n = 0;
     BatchInst* d_desc = nullptr;
     int64_t total[NPASS] = {0, 0, 0, 0};
@@ -173,7 +151,8 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
   if (!B) return QMC_ERR_OOM;
   B->dtype = dtype;
   const size_t el = dtype == QMC_F32 ? sizeof(cx<float>) : sizeof(cx<double>);
-  std::vector<std::vector<BatchInst>> byR(17);
+  // products grouped by layout key (R, P2, Q2)
+  std::vector<std::pair<int64_t, std::vector<BatchInst>>> byKey;
   size_t ws = 0;
   for (int i = 0; i < count; ++i) {
     const qmc_plan_s* P = plans[i];
@@ -217,16 +196,27 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
     I.gx_back = (lay.M1 + 15) / 16;
     I.gy_back = (I.pairs + 15) / 16;
     I.nb[PASS_BACK] = I.gx_back * I.gy_back * lay.P2;
-    byR[lay.R].push_back(I);
+    const int64_t key = ((int64_t)lay.R << 32) | ((int64_t)lay.P2 << 16) | lay.Q2;
+    auto it = std::find_if(byKey.begin(), byKey.end(),
+                           [&](const std::pair<int64_t, std::vector<BatchInst>>& g) {
+                             return g.first == key;
+                           });
+    if (it == byKey.end()) {
+      byKey.push_back({key, {}});
+      it = byKey.end() - 1;
+    }
+    it->second.push_back(I);
   }
   B->ws_bytes = ws;
   hipStream_t st = (hipStream_t)stream;
   int rc = QMC_OK;
-  for (int R = 1; R <= 16 && rc == QMC_OK; R *= 2) {
-    std::vector<BatchInst>& v = byR[R];
-    if (v.empty()) continue;
+  for (auto& kv : byKey) {
+    if (rc != QMC_OK) break;
+    std::vector<BatchInst>& v = kv.second;
     qmc_batch_s::Group g;
-    g.R = R;
+    g.R = (int)(kv.first >> 32);
+    g.P2 = (int)((kv.first >> 16) & 0xffff);
+    g.Q2 = (int)(kv.first & 0xffff);
     g.n = (int)v.size();
     for (int p = 0; p < NPASS; ++p) {
       int64_t off = 0;
@@ -275,7 +265,7 @@ static inline unsigned grid_for(int64_t total, int64_t cap) {
 }
 
 template <typename T, int R>
-static void run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
+static int run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
   // persistent grids: a few resident workgroups per CU (256 CUs)
   if (g.total[PASS_COLLAPSE])
     kb_collapse<T><<<grid_for(g.total[PASS_COLLAPSE], 2048), 256, 0, st>>>(
@@ -283,24 +273,50 @@ static void run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
   if (g.total[PASS_MIDDLE])
     kb_middle<T, R><<<grid_for(g.total[PASS_MIDDLE], 1024), MidShape<R>::BLOCK, 0, st>>>(
         g.d_desc, g.n, g.total[PASS_MIDDLE], ws);
-  if (g.total[PASS_SPLIT])
-    kb_split<T><<<grid_for(g.total[PASS_SPLIT], 4096), 64, 0, st>>>(g.d_desc, g.n,
-                                                                     g.total[PASS_SPLIT], ws);
-  if (g.total[PASS_BACK])
-    kb_back<T><<<grid_for(g.total[PASS_BACK], 1024), 256, 0, st>>>(g.d_desc, g.n,
-                                                                   g.total[PASS_BACK], ws);
+  if (g.total[PASS_SPLIT]) {
+    const unsigned gs = grid_for(g.total[PASS_SPLIT], 4096);
+#define QMC_KBS(PP) kb_split<T, PP><<<gs, 64, 0, st>>>(g.d_desc, g.n, g.total[PASS_SPLIT], ws)
+    switch (g.P2) {
+      case 2: QMC_KBS(2); break;
+      case 4: QMC_KBS(4); break;
+      case 8: QMC_KBS(8); break;
+      case 16: QMC_KBS(16); break;
+      case 32: QMC_KBS(32); break;
+      case 64: QMC_KBS(64); break;
+      default: return QMC_ERR_UNSUPPORTED;
+    }
+#undef QMC_KBS
+  }
+  if (g.total[PASS_BACK]) {
+    const unsigned gb = grid_for(g.total[PASS_BACK], 1024);
+#define QMC_KBB(QQ) kb_back<T, QQ><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws)
+    switch (g.Q2) {
+      case 1: QMC_KBB(1); break;
+      case 2: QMC_KBB(2); break;
+      case 4: QMC_KBB(4); break;
+      case 8: QMC_KBB(8); break;
+      case 16: QMC_KBB(16); break;
+      case 32: QMC_KBB(32); break;
+      case 64: QMC_KBB(64); break;
+      default: return QMC_ERR_UNSUPPORTED;
+    }
+#undef QMC_KBB
+  }
+  return QMC_OK;
 }
 
 template <typename T>
 static int run_group(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
+  int rc = QMC_ERR_UNSUPPORTED;
   switch (g.R) {
-    case 1: run_group_r<T, 1>(g, ws, st); break;
-    case 2: run_group_r<T, 2>(g, ws, st); break;
-    case 4: run_group_r<T, 4>(g, ws, st); break;
-    case 8: run_group_r<T, 8>(g, ws, st); break;
-    case 16: run_group_r<T, 16>(g, ws, st); break;
-    default: return QMC_ERR_UNSUPPORTED;
+    case 1: rc = run_group_r<T, 1>(g, ws, st); break;
+    case 2: rc = run_group_r<T, 2>(g, ws, st); break;
+    case 4: rc = run_group_r<T, 4>(g, ws, st); break;
+    case 8: rc = run_group_r<T, 8>(g, ws, st); break;
+    case 16: rc = run_group_r<T, 16>(g, ws, st); break;
+    default: break;
   }
+  if (rc != QMC_OK) return rc;
   return hip_ok(hipGetLastError());
 }
 
