@@ -400,7 +400,10 @@ static Layout choose_layout(int64_t L, int dtype, int* embedded) {
   lay.R = R;
   lay.M1 = (int64_t)R * R * R;
   lay.M2 = M / lay.M1;
-  const int64_t back_max = 64;
+  // the outer inverse DFT of the back pass keeps Q2 values per thread; 32
+  // keeps its registers within an occupancy of 3-4 (64 fell to 1-2 and ran
+  // slower than an extra split pass)
+  const int64_t back_max = 32;
   if (lay.M2 <= back_max) {
     lay.P2 = 1;
     lay.Q2 = (int)lay.M2;
