@@ -181,6 +181,30 @@ int qmc_matmul(qmc_plan_t plan, const void* A, int64_t t, int64_t lda,
  * read back at the exponents l_j; the constant row adds phi(x_0) G[0,:].
  *   G   device, N x t (ldg >= t);  dA  device, s x t (ldda >= t), overwritten
  */
+/*
+ * qmc_matmul_epilogue -- X = Y A with an elementwise epilogue fused into the
+ * writes of X (the downstream steps of Sections 3.2 and 3.3):
+ *   QMC_EPI_AFFINE  X[n,c] = scale[c] * (bias[c] + (Y A)[n,c])
+ *                   (the stiffness entries b_{k,l} = a_{0,k,l} + Y a_{k,l},
+ *                   eq. (Ya), one column per (k, l));
+ *   QMC_EPI_EXP     X[n,c] = scale[c] * exp(bias[c] + (Y A)[n,c])
+ *                   (the log-normal coefficient a = exp(theta) with
+ *                   Theta = Psi^ + Y Psi, eqs. (fastB), (eq_as); scale may
+ *                   carry quadrature weight times basis gradients);
+ *   QMC_EPI_NONE    as qmc_matmul.
+ *   bias, scale  device vectors of t entries in the plan dtype, or NULL
+ *                (bias 0, scale 1); read only; must not overlap X or the
+ *                workspace.
+ * Other arguments, workspace and errors as qmc_matmul; QMC_ERR_ARG for an
+ * unknown epi_kind.
+ */
+#define QMC_EPI_NONE   0
+#define QMC_EPI_AFFINE 1
+#define QMC_EPI_EXP    2
+int qmc_matmul_epilogue(qmc_plan_t plan, const void* A, int64_t t, int64_t lda, void* X,
+                        int64_t ldx, int epi_kind, const void* bias, const void* scale,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
 int qmc_matmul_adjoint(qmc_plan_t plan, const void* G, int64_t t, int64_t ldg,
                        void* dA, int64_t ldda, void* workspace, size_t workspace_bytes,
                        void* stream);

@@ -17,7 +17,8 @@ multiplication"):
   CDF; x - 1/2 as in Experiment 2).
 * ``dense``   -- X = Y A and dA = Y^T G by forming Y explicitly and multiplying
   in FP64 (the "standard approach" of the paper's experiments), plus row- and
-  entry-sampled versions for sizes where Y does not fit.
+  entry-sampled versions for sizes where Y does not fit, and the elementwise
+  epilogue of the PDE applications (Sections 3.2, 3.3).
 * ``literal`` -- a second, independent route used only as a checker: the
   paper's own construction (primitive root beta, exponents c_j, the circulant
   Z and selection matrix P of eq. (ZPa), worked Example 1), evaluated as a
@@ -36,7 +37,8 @@ from .points import (PHI_IDENTITY, PHI_CENTERED, PHI_INVNORM, PHI_TENT,
                      RULE_LATTICE, RULE_POLY_GF2, RULE_KOROBOV_UNION, phi_apply, lattice_coords,
                      gf2_coords, gf2_digits_coords, coords, coords_rational, explicit_Y,
                      phi_residue_values, phi_rational)
-from .dense import matmul, adjoint, matmul_rows, adjoint_entries, Y_rows
+from .dense import (matmul, adjoint, matmul_rows, adjoint_entries, Y_rows, epilogue, EPI_NONE,
+                    EPI_AFFINE, EPI_EXP)
 from . import literal, exact
 
 __all__ = [
@@ -44,6 +46,7 @@ __all__ = [
     "RULE_LATTICE", "RULE_POLY_GF2", "RULE_KOROBOV_UNION", "phi_apply", "lattice_coords", "gf2_coords",
     "gf2_digits_coords", "coords", "coords_rational", "explicit_Y",
     "phi_residue_values", "phi_rational",
-    "matmul", "adjoint", "matmul_rows", "adjoint_entries", "Y_rows",
+    "matmul", "adjoint", "matmul_rows", "adjoint_entries", "Y_rows", "epilogue", "EPI_NONE",
+    "EPI_AFFINE", "EPI_EXP",
     "literal", "exact",
 ]

@@ -6,6 +6,11 @@ X = Y A (Section 1: the N x t product B = Y A whose rows are y_n A) and the
 adjoint dA = Y^T G, in FP64 with numpy's matmul as the one library step.  For
 sizes where the N x s matrix Y does not fit, ``matmul_rows`` forms only the
 requested rows of Y and ``adjoint_entries`` only the requested columns.
+
+``epilogue`` applies the downstream step of the PDE applications to X = Y A:
+the uniform case's b_{k,l} = a_{0,k,l} + Y a_{k,l} (Section 3.2, eq. (Ya)) and
+the log-normal case's exp(theta) with Theta = Psi^ + Y Psi (Section 3.3,
+eqs. (fastB), (eq_as)), per column c as scale[c] * f(bias[c] + X[:, c]).
 """
 from __future__ import annotations
 
@@ -57,3 +62,21 @@ def adjoint_entries(inst, entries, G=None, chunk: int = 1 << 15) -> np.ndarray:
         Yb = Y_rows(sub, rows)
         out += np.sum(Yb * G[rows][:, ks], axis=0)
     return out
+
+
+EPI_NONE, EPI_AFFINE, EPI_EXP = 0, 1, 2
+
+
+def epilogue(X, kind: int, bias=None, scale=None) -> np.ndarray:
+    """scale[c] * f(bias[c] + X[:, c]) with f = identity (EPI_AFFINE) or exp
+    (EPI_EXP); a missing bias is 0 and a missing scale 1; EPI_NONE returns X."""
+    X = np.asarray(X, dtype=np.float64)
+    if kind == EPI_NONE:
+        return X.copy()
+    b = 0.0 if bias is None else np.asarray(bias, dtype=np.float64)[None, :]
+    z = X + b
+    if kind == EPI_EXP:
+        z = np.exp(z)
+    elif kind != EPI_AFFINE:
+        raise ValueError(f"unknown epilogue {kind}")
+    return z if scale is None else z * np.asarray(scale, dtype=np.float64)[None, :]

@@ -32,7 +32,8 @@ F64 = 1
 
 EXPORTED = [
     "qmc_plan_create", "qmc_plan_destroy", "qmc_plan_info", "qmc_plan_tables",
-    "qmc_workspace_size", "qmc_matmul", "qmc_matmul_adjoint", "qmc_explicit_points",
+    "qmc_workspace_size", "qmc_matmul", "qmc_matmul_epilogue", "qmc_matmul_adjoint",
+    "qmc_explicit_points",
     "qmc_dense_matmul", "qmc_batched_workspace_size", "qmc_matmul_batched", "qmc_strerror",
     "qmc_profile_enable", "qmc_profile_collect", "qmc_profile_slot_name",
     "qmc_plan_set_tuning", "qmc_plan_get_tuning",
@@ -93,6 +94,7 @@ def lib() -> ctypes.CDLL:
         L.qmc_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
         L.qmc_matmul.argtypes = [vp, vp, i64, i64, vp, i64, vp, sz, vp]
         L.qmc_matmul_adjoint.argtypes = [vp, vp, i64, i64, vp, i64, vp, sz, vp]
+        L.qmc_matmul_epilogue.argtypes = [vp, vp, i64, i64, vp, i64, ip, vp, vp, vp, sz, vp]
         L.qmc_explicit_points.argtypes = [vp, vp, i64, vp]
         L.qmc_dense_matmul.argtypes = [vp, vp, i64, vp, i64, i64, vp, i64, vp]
         L.qmc_batched_workspace_size.argtypes = [ip, ctypes.POINTER(vp), ctypes.POINTER(i64),
@@ -274,18 +276,43 @@ def _check_tensor(x, plan: Plan, rows: int, name: str):
         raise ValueError(f"{name} must be a row-major {rows} x t matrix (unit column stride)")
 
 
-def matmul(plan: Plan, A, out=None, workspace=None, stream=None):
-    """X = Y A (N x t) on the GPU."""
+EPILOGUES = {None: 0, "none": 0, "affine": 1, "exp": 2}
+
+
+def _vec_ptr(v, plan: Plan, t: int, name: str):
+    if v is None:
+        return None
+    torch = _torch()
+    if not isinstance(v, torch.Tensor) or not v.is_cuda or v.dtype != plan.torch_dtype:
+        raise TypeError(f"{name} must be a CUDA tensor of the plan dtype")
+    if v.dim() != 1 or v.shape[0] != t or v.stride(0) != 1:
+        raise ValueError(f"{name} must be a contiguous vector of t = {t} entries")
+    return ctypes.c_void_p(v.data_ptr())
+
+
+def matmul(plan: Plan, A, out=None, workspace=None, stream=None, epilogue=None, bias=None,
+           scale=None):
+    """X = Y A (N x t) on the GPU.  epilogue "affine": X = scale * (bias + Y A),
+    "exp": X = scale * exp(bias + Y A), per column (Sections 3.2, 3.3)."""
     torch = _torch()
     _check_tensor(A, plan, plan.s, "A")
     t = A.shape[1]
     X = torch.empty((plan.N, t), dtype=A.dtype, device=A.device) if out is None else out
     _check_tensor(X, plan, plan.N, "out")
     ws = plan.workspace(t, A.device) if workspace is None else workspace
-    _check(lib().qmc_matmul(plan.handle, ctypes.c_void_p(A.data_ptr()), t, A.stride(0),
-                            ctypes.c_void_p(X.data_ptr()), X.stride(0),
-                            ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
-                            _stream_handle(stream)), "qmc_matmul")
+    kind = EPILOGUES[epilogue]
+    if kind == 0 and bias is None and scale is None:
+        _check(lib().qmc_matmul(plan.handle, ctypes.c_void_p(A.data_ptr()), t, A.stride(0),
+                                ctypes.c_void_p(X.data_ptr()), X.stride(0),
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                _stream_handle(stream)), "qmc_matmul")
+        return X
+    _check(lib().qmc_matmul_epilogue(plan.handle, ctypes.c_void_p(A.data_ptr()), t, A.stride(0),
+                                     ctypes.c_void_p(X.data_ptr()), X.stride(0), kind,
+                                     _vec_ptr(bias, plan, t, "bias"),
+                                     _vec_ptr(scale, plan, t, "scale"),
+                                     ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                     _stream_handle(stream)), "qmc_matmul_epilogue")
     return X
 
 

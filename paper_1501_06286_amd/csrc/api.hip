@@ -220,6 +220,25 @@ int qmc_matmul(qmc_plan_t P, const void* A, int64_t t, int64_t lda, void* X, int
   return launch_forward(P, A, t, lda, X, ldx, workspace, (hipStream_t)stream);
 }
 
+int qmc_matmul_epilogue(qmc_plan_t P, const void* A, int64_t t, int64_t lda, void* X,
+                        int64_t ldx, int epi_kind, const void* bias, const void* scale,
+                        void* workspace, size_t workspace_bytes_, void* stream) {
+  if (!P || !A || !X || t < 1 || lda < t || ldx < t) return QMC_ERR_ARG;
+  if (epi_kind < QMC_EPI_NONE || epi_kind > QMC_EPI_EXP) return QMC_ERR_ARG;
+  const size_t need = workspace_bytes(P, t);
+  if (!workspace || workspace_bytes_ < need) return QMC_ERR_WORKSPACE;
+  const size_t xa = matrix_extent(P->N, t, ldx, P->dtype);
+  const size_t aa = matrix_extent(P->s, t, lda, P->dtype);
+  const size_t va = matrix_extent(1, t, t, P->dtype);
+  if (ranges_overlap(X, xa, A, aa) || ranges_overlap(X, xa, workspace, need) ||
+      ranges_overlap(A, aa, workspace, need) || (bias && ranges_overlap(X, xa, bias, va)) ||
+      (scale && ranges_overlap(X, xa, scale, va)) || (bias && ranges_overlap(workspace, need, bias, va)) ||
+      (scale && ranges_overlap(workspace, need, scale, va)))
+    return QMC_ERR_ALIAS;
+  return launch_forward(P, A, t, lda, X, ldx, workspace, (hipStream_t)stream, epi_kind, bias,
+                        scale);
+}
+
 int qmc_matmul_adjoint(qmc_plan_t P, const void* G, int64_t t, int64_t ldg, void* dA,
                        int64_t ldda, void* workspace, size_t workspace_bytes_, void* stream) {
   if (!P || !G || !dA || t < 1 || ldg < t || ldda < t) return QMC_ERR_ARG;

@@ -60,17 +60,27 @@ __global__ __launch_bounds__(64) void k_outer_split(cx<T>* __restrict__ C, int64
   split_body<T, P2, DIR>(C, M1, M2, Q2, twb, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x);
 }
 
-template <typename T, int Q, bool ADJ, bool NT>
+template <typename T, int Q, bool ADJ, bool NT, bool EPI>
 __global__ __launch_bounds__(256) void k_back(const cx<T>* __restrict__ C, int64_t M1, int64_t M2,
                                               int64_t P2, int64_t L, int64_t P,
                                               const int32_t* __restrict__ rowmap,
                                               const int32_t* __restrict__ inv_ptr,
                                               const int32_t* __restrict__ inv_j,
                                               const T* __restrict__ G0, T phi0,
-                                              T* __restrict__ X, int64_t ldx, int64_t t) {
+                                              T* __restrict__ X, int64_t ldx, int64_t t,
+                                              Epi<T> epi) {
   __shared__ BackSmem<T> S;
-  back_body<T, Q, ADJ, NT>(C, M1, M2, P2, L, P, rowmap, inv_ptr, inv_j, G0, phi0, X, ldx, t,
-                           blockIdx.x, blockIdx.y, blockIdx.z, S, threadIdx.x);
+  back_body<T, Q, ADJ, NT, EPI>(C, M1, M2, P2, L, P, rowmap, inv_ptr, inv_j, G0, phi0, X, ldx,
+                                t, blockIdx.x, blockIdx.y, blockIdx.z, S, threadIdx.x, epi);
+}
+
+// the epilogue of row 0 (its values come from the fused pass's DC term)
+template <typename T>
+__global__ __launch_bounds__(256) void k_epi_row0(T* __restrict__ X, int64_t t, Epi<T> epi) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= t) return;
+  const EpiCols<T> ec(epi, c, t);
+  X[c] = ec.f0(X[c]);
 }
 
 template <typename T, int Q>
@@ -181,16 +191,16 @@ static int launch_split(const qmc_plan_s* P, cx<T>* C, int64_t pairs, int slot, 
   return hip_ok(hipGetLastError());
 }
 
-template <typename T, bool ADJ, bool NT = false>
+template <typename T, bool ADJ, bool NT = false, bool EPI = false>
 static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const int32_t* inv_ptr,
                        const int32_t* inv_j, const T* G0, T* X, int64_t ldx, int64_t t,
-                       hipStream_t st) {
+                       hipStream_t st, const Epi<T>& epi = Epi<T>()) {
   const Layout& lay = P->lay;
   dim3 grid((unsigned)((lay.M1 + 15) / 16), (unsigned)((pairs + 15) / 16), (unsigned)lay.P2);
   ProfScope ps(P, ADJ ? PROF_ADJ_BACK : PROF_BACK, st);
 #define QMC_BACK(QQ)                                                                          \
-  k_back<T, QQ, ADJ, NT><<<grid, 256, 0, st>>>(C, lay.M1, lay.M2, lay.P2, P->L, pairs, P->d_pow, \
-                                           inv_ptr, inv_j, G0, (T)P->phi0, X, ldx, t)
+  k_back<T, QQ, ADJ, NT, EPI><<<grid, 256, 0, st>>>(C, lay.M1, lay.M2, lay.P2, P->L, pairs, P->d_pow, \
+                                           inv_ptr, inv_j, G0, (T)P->phi0, X, ldx, t, epi)
   switch (lay.Q2) {
     case 1: QMC_BACK(1); break;
     case 2: QMC_BACK(2); break;
@@ -215,7 +225,14 @@ static int ensure_side_stream(const qmc_plan_s* P) {
 
 template <typename T>
 static int back_dispatch(const qmc_plan_s* P, const cx<T>* C, int64_t np, T* X, int64_t ldx,
-                         int64_t t, hipStream_t st) {
+                         int64_t t, hipStream_t st, const Epi<T>& epi) {
+  if (epi.kind != 0) {
+    if (P->tune.nt_store)
+      return launch_back<T, false, true, true>(P, C, np, nullptr, nullptr, nullptr, X, ldx, t, st,
+                                               epi);
+    return launch_back<T, false, false, true>(P, C, np, nullptr, nullptr, nullptr, X, ldx, t, st,
+                                              epi);
+  }
   if (P->tune.nt_store)
     return launch_back<T, false, true>(P, C, np, nullptr, nullptr, nullptr, X, ldx, t, st);
   return launch_back<T, false, false>(P, C, np, nullptr, nullptr, nullptr, X, ldx, t, st);
@@ -225,12 +242,18 @@ static int back_dispatch(const qmc_plan_s* P, const cx<T>* C, int64_t np, T* X, 
 // of column pairs.  With two streams the back pass of chunk c runs on the
 // plan's side stream while the caller's stream starts chunk c+1; the two
 // spectrum slots alternate and are released by events.
+// the epilogue of the columns from pair p0 on
+template <typename T>
+static Epi<T> chunk_epi(const Epi<T>& e, int64_t p0) {
+  return Epi<T>{e.kind, e.bias ? e.bias + 2 * p0 : nullptr, e.scale ? e.scale + 2 * p0 : nullptr};
+}
+
 // X = Y A with the dense outer front, per chunk of column pairs: gather and
 // transform the outer index into B, the fused pass (dense front) into C, the
 // outer split and the back pass.  One stream.
 template <typename T>
 static int forward_dense_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T* X,
-                           int64_t ldx, void* ws, hipStream_t st) {
+                           int64_t ldx, void* ws, hipStream_t st, const Epi<T>& epi) {
   const int64_t pairs = (t + 1) / 2;
   const int64_t chunk = (P->tune.chunk_pairs > 0 && P->tune.chunk_pairs < pairs)
                             ? P->tune.chunk_pairs : pairs;
@@ -240,11 +263,12 @@ static int forward_dense_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t l
     const int64_t np = std::min(chunk, pairs - p0), tc = t - 2 * p0;
     int rc = launch_outer_front<T>(P, A + 2 * p0, nullptr, lda, tc, np, B, st);
     if (rc != QMC_OK) return rc;
+    const Epi<T> ec = chunk_epi(epi, p0);
     rc = launch_middle<T, false>(P, B, np, C, X + 2 * p0, tc, PROF_MIDDLE, st);
     if (rc != QMC_OK) return rc;
     rc = launch_split<T, +1>(P, C, np, PROF_SPLIT, st);
     if (rc != QMC_OK) return rc;
-    rc = back_dispatch<T>(P, C, np, X + 2 * p0, ldx, tc, st);
+    rc = back_dispatch<T>(P, C, np, X + 2 * p0, ldx, tc, st, ec);
     if (rc != QMC_OK) return rc;
   }
   return QMC_OK;
@@ -252,8 +276,8 @@ static int forward_dense_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t l
 
 template <typename T>
 static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T* X, int64_t ldx,
-                     void* ws, hipStream_t st) {
-  if (dense_front(P)) return forward_dense_t<T>(P, A, t, lda, X, ldx, ws, st);
+                     void* ws, hipStream_t st, const Epi<T>& epi) {
+  if (dense_front(P)) return forward_dense_t<T>(P, A, t, lda, X, ldx, ws, st, epi);
   const int64_t pairs = (t + 1) / 2;
   const size_t el = sizeof(cx<T>);
   cx<T>* aT = (cx<T>*)ws;
@@ -284,6 +308,7 @@ static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T*
     if (two && c >= 2) {  // the back pass of chunk c-2 has released this slot
       if ((rc = hip_ok(hipStreamWaitEvent(st, P->ev[2 + slot], 0))) != QMC_OK) return rc;
     }
+    const Epi<T> ec = chunk_epi(epi, p0);
     rc = launch_middle<T, true>(P, aT + p0 * P->Upad, np, C, X + 2 * p0, t - 2 * p0,
                                 PROF_MIDDLE, st);
     if (rc != QMC_OK) return rc;
@@ -293,7 +318,7 @@ static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T*
       if ((rc = hip_ok(hipEventRecord(P->ev[slot], st))) != QMC_OK) return rc;
       if ((rc = hip_ok(hipStreamWaitEvent(sb, P->ev[slot], 0))) != QMC_OK) return rc;
     }
-    rc = back_dispatch<T>(P, C, np, X + 2 * p0, ldx, t - 2 * p0, sb);
+    rc = back_dispatch<T>(P, C, np, X + 2 * p0, ldx, t - 2 * p0, sb, ec);
     if (rc != QMC_OK) return rc;
     if (two) {
       if ((rc = hip_ok(hipEventRecord(P->ev[2 + slot], sb))) != QMC_OK) return rc;
@@ -306,11 +331,24 @@ static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T*
   return QMC_OK;
 }
 
+template <typename T>
+static int forward_epi_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T* X,
+                         int64_t ldx, void* ws, hipStream_t st, const Epi<T>& epi) {
+  int rc = forward_t<T>(P, A, t, lda, X, ldx, ws, st, epi);
+  if (rc != QMC_OK || epi.kind == 0) return rc;
+  // row 0 is the fused pass's DC term, in X on the same stream by now
+  k_epi_row0<T><<<(unsigned)((t + 255) / 256), 256, 0, st>>>(X, t, epi);
+  return hip_ok(hipGetLastError());
+}
+
 int launch_forward(const qmc_plan_s* P, const void* A, int64_t t, int64_t lda, void* X,
-                   int64_t ldx, void* ws, hipStream_t st) {
+                   int64_t ldx, void* ws, hipStream_t st, int epi_kind, const void* bias,
+                   const void* scale) {
   if (P->dtype == QMC_F32)
-    return forward_t<float>(P, (const float*)A, t, lda, (float*)X, ldx, ws, st);
-  return forward_t<double>(P, (const double*)A, t, lda, (double*)X, ldx, ws, st);
+    return forward_epi_t<float>(P, (const float*)A, t, lda, (float*)X, ldx, ws, st,
+                                Epi<float>{epi_kind, (const float*)bias, (const float*)scale});
+  return forward_epi_t<double>(P, (const double*)A, t, lda, (double*)X, ldx, ws, st,
+                               Epi<double>{epi_kind, (const double*)bias, (const double*)scale});
 }
 
 // dense outer front into B[pair][w2][e1]: the adjoint's gather of G

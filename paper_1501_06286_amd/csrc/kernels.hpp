@@ -87,6 +87,49 @@ __device__ __forceinline__ void collapse_body(const T* __restrict__ A, int64_t l
 // group of R lanes of one wavefront.
 // The conj W_M^{e1' w2} factor is the outer-step twiddle of M = M1 * M2.
 // ---------------------------------------------------------------------------
+// Epilogue of the forward product (Sections 3.2 and 3.3): entry (n, c) of
+// X = Y A becomes scale[c] * f(bias[c] + X[n, c]), f = identity (the
+// stiffness entries a_{0,k,l} + Y a_{k,l} of eq. (Ya)) or exp (the
+// log-normal coefficient exp(Psi^ + Y Psi) of eqs. (fastB), (eq_as)).
+// kind 0 leaves X as it is; a null bias is 0 and a null scale is 1.
+template <typename T>
+struct Epi {
+  int kind = 0;
+  const T* bias = nullptr;
+  const T* scale = nullptr;
+};
+__device__ __forceinline__ float exp_t(float v) { return expf(v); }
+__device__ __forceinline__ double exp_t(double v) { return exp(v); }
+
+// the epilogue of one thread's two columns col, col + 1 < t (loaded once;
+// columns at or beyond t are not read); row 0 gets it from k_epi_row0
+template <typename T>
+struct EpiCols {
+  int kind;
+  T b0 = 0, b1 = 0, s0 = 1, s1 = 1;
+  __device__ __forceinline__ EpiCols(const Epi<T>& e, int64_t col, int64_t t) : kind(e.kind) {
+    if (kind != 0 && col < t) {
+      const bool both = col + 1 < t;
+      if (e.bias) {
+        b0 = e.bias[col];
+        if (both) b1 = e.bias[col + 1];
+      }
+      if (e.scale) {
+        s0 = e.scale[col];
+        if (both) s1 = e.scale[col + 1];
+      }
+    }
+  }
+  __device__ __forceinline__ T f(T v, T b, T s) const {
+    if (kind == 0) return v;
+    T z = b + v;
+    if (kind == 2) z = exp_t(z);
+    return s * z;
+  }
+  __device__ __forceinline__ T f0(T v) const { return f(v, b0, s0); }
+  __device__ __forceinline__ T f1(T v) const { return f(v, b1, s1); }
+};
+
 // orders this wavefront's LDS accesses before and after the call (LDS
 // operations of one wavefront complete in issue order)
 __device__ __forceinline__ void wave_lds_sync() {
@@ -178,7 +221,7 @@ __device__ __forceinline__ void middle_body(
   // The first twiddles and the spectrum are loaded ahead of use, so their
   // latency hides behind the front and the steps in between.
   cx<T> tw_a[R], tw_b[R], hv[R];
-  load_paired<T, R>(tw_a, twf1, q, Q);
+  if constexpr (SPARSE) load_paired<T, R>(tw_a, twf1, q, Q);  // the dense front's loads come first
   // the R x R roots W_{R^2}^{a g} of the middle steps live in LDS (first
   // read after the barriers of step 1); twf2 holds value g of thread a
   for (int i = tid; i < R * R; i += S::BLOCK)
@@ -256,6 +299,7 @@ __device__ __forceinline__ void middle_body(
       if (c > 0) v = cmulc(v, two[w2 * R + c]);
       x[c] = v;
     }
+    load_paired<T, R>(tw_a, twf1, q, Q);
   }
 
   // ---- forward step 1: thread e1' = q, DFT over c -> f --------------------
@@ -389,7 +433,7 @@ __device__ __forceinline__ void store_pair(T* p, T x, T y) {
     *reinterpret_cast<vec2_t<T>*>(p) = v;
 }
 
-template <typename T, int Q, bool ADJ, bool NT>
+template <typename T, int Q, bool ADJ, bool NT, bool EPI = false>
 __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M1, int64_t M2,
                                           int64_t P2, int64_t L, int64_t P,
                                           const int32_t* __restrict__ rowmap,
@@ -397,13 +441,16 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
                                           const int32_t* __restrict__ inv_j,
                                           const T* __restrict__ G0, T phi0,
                                           T* __restrict__ X, int64_t ldx, int64_t t, int64_t bx,
-                                          int64_t by, int64_t a, BackSmem<T>& S, int tid) {
+                                          int64_t by, int64_t a, BackSmem<T>& S, int tid,
+                                          const Epi<T> epi = Epi<T>()) {
   constexpr int PB = 16, EB = 16;
   constexpr int CH = Q < BACK_CH ? Q : BACK_CH;
   auto& sm = S.sm;
   const int64_t e1_0 = bx * EB, p0 = by * PB;
   const int el = tid % EB, pl = tid / EB;
   const bool v2 = pairs_aligned(X, ldx);
+  // the epilogue of the columns this thread writes (EPI only)
+  const EpiCols<T> ec(EPI ? epi : Epi<T>(), 2 * (p0 + tid % PB), t);
   {
     const int64_t e1 = e1_0 + el, pair = p0 + pl;
     cx<T> v[Q];
@@ -431,14 +478,15 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
             const bool both = col + 1 < t;
             if constexpr (!ADJ) {
               T* row = X + (int64_t)rowmap[e] * ldx;
+              const T ox = EPI ? ec.f0(o.x) : o.x, oy = EPI ? ec.f1(o.y) : o.y;
               if (v2 && both) {
-                store_pair<T, NT>(row + col, o.x, o.y);
+                store_pair<T, NT>(row + col, ox, oy);
               } else if constexpr (NT) {
-                __builtin_nontemporal_store(o.x, row + col);
-                if (both) __builtin_nontemporal_store(o.y, row + col + 1);
+                __builtin_nontemporal_store(ox, row + col);
+                if (both) __builtin_nontemporal_store(oy, row + col + 1);
               } else {
-                row[col] = o.x;
-                if (both) row[col + 1] = o.y;
+                row[col] = ox;
+                if (both) row[col + 1] = oy;
               }
             } else {
               const T g0 = phi0 * G0[col];

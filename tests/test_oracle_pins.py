@@ -433,3 +433,96 @@ def test_korobov_planted_mistakes_are_caught():
     bad_major = mutate(lambda K, r, e: (r // (K - 1) + 1) * pow(r % (K - 1) + 1, e, K) % K)
     for bad in (bad_n0, bad_exp, bad_major):
         assert not _korobov_pins_pass(bad)
+
+
+# ---------------------------------------------------------------------------
+# epilogues of the PDE applications (Sections 3.2 and 3.3)
+# ---------------------------------------------------------------------------
+
+def _fe_1d(n_el):
+    """Piecewise linear hat functions on the uniform mesh of (0, 1): the
+    stiffness pairs (k, l) with a common element, k, l = 1..n_el-1."""
+    h = 1.0 / n_el
+    pairs = [(k, k) for k in range(1, n_el)] + [(k, k + 1) for k in range(1, n_el - 1)]
+    return h, pairs
+
+
+def _psi(j, x):
+    return (1.0 + x) if j == 0 else np.sin(j * np.pi * x) / (j * j)
+
+
+def _psi_elem_integral(j, a, b):
+    """Closed form of the integral of psi_j over [a, b]."""
+    if j == 0:
+        return (b - a) + (b * b - a * a) / 2
+    return (np.cos(j * np.pi * a) - np.cos(j * np.pi * b)) / (j * np.pi) / (j * j)
+
+
+def test_uniform_pde_stiffness_entries():
+    """b_{n,k,l} = a_{0,k,l} + y_n . a_{k,l} (eq. (Ya)) with the closed-form
+    a_{j,k,l} equals the stiffness integral of a(x, y_n) grad phi_k grad phi_l
+    computed by Gauss-Legendre quadrature on every element."""
+    n_el, s = 9, 6
+    h, pairs = _fe_1d(n_el)
+    nodes = np.linspace(0.0, 1.0, n_el + 1)
+
+    def a_entry(j, k, l):  # integral of psi_j phi_k' phi_l'
+        if k == l:
+            return (_psi_elem_integral(j, nodes[k - 1], nodes[k]) +
+                    _psi_elem_integral(j, nodes[k], nodes[k + 1])) / h ** 2
+        return -_psi_elem_integral(j, nodes[k], nodes[k + 1]) / h ** 2
+
+    A = np.array([[a_entry(j, k, l) for (k, l) in pairs] for j in range(1, s + 1)])
+    bias = np.array([a_entry(0, k, l) for (k, l) in pairs])
+    inst = qi.small_lattice(31, s, len(pairs), phi=qi.PHI_CENTERED, dtype="f64", seed=3)
+    inst = dataclasses.replace(inst, A=A, t=len(pairs))
+    b = oracle.epilogue(oracle.matmul(inst), oracle.EPI_AFFINE, bias)
+    Y = oracle.Y_rows(inst)  # y_n in [-1/2, 1/2]^s (Section 3.2)
+    gx, gw = np.polynomial.legendre.leggauss(20)
+    for n in range(inst.N):
+        for c, (k, l) in enumerate(pairs):
+            elems = [k - 1, k] if k == l else [k]
+            sign = 1.0 if k == l else -1.0
+            total = 0.0
+            for e in elems:
+                x = nodes[e] + (gx + 1) * h / 2
+                a = _psi(0, x) + sum(Y[n, j - 1] * _psi(j, x) for j in range(1, s + 1))
+                total += sign * np.sum(gw * a) * h / 2 / h ** 2
+            assert abs(b[n, c] - total) <= 1e-10 * (1 + abs(total))
+
+
+def test_lognormal_coefficient_and_weighted_entries():
+    """exp(Psi^ + Y Psi) (eqs. (fastB), (eq_as)) at quadrature points x_i,
+    scaled by the quadrature weight times grad phi_k grad phi_l, is the
+    coefficient exp(psi_0(x_i) + sum_j y_j psi_j(x_i)) point by point, and
+    its sum over the points of an element is the quadrature (def:b nkl) of
+    the element's stiffness entry, close to the integral by a finer rule."""
+    n_el, s, I = 5, 4, 6
+    h = 1.0 / n_el
+    gx, gw = np.polynomial.legendre.leggauss(I)
+    e = 2  # the element [x_2, x_3]; entry (k, l) = (2, 3): grad product -1/h^2
+    xq = 2 * h + (gx + 1) * h / 2
+    wq = gw * h / 2 * (-1.0 / h ** 2)
+    Psi = np.array([[_psi(j, x) for x in xq] for j in range(1, s + 1)])
+    inst = qi.small_lattice(37, s, I, phi=qi.PHI_INVNORM, shift=(1, 74), dtype="f64", seed=4)
+    inst = dataclasses.replace(inst, A=Psi, t=I)
+    th = oracle.epilogue(oracle.matmul(inst), oracle.EPI_EXP, _psi(0, xq), wq)
+    Y = oracle.Y_rows(inst)
+    for n in range(inst.N):
+        direct = [wq[i] * math.exp(_psi(0, xq[i]) + sum(Y[n, j] * Psi[j, i] for j in range(s)))
+                  for i in range(I)]
+        np.testing.assert_allclose(th[n], direct, rtol=1e-13)
+        fx, fw = np.polynomial.legendre.leggauss(40)
+        xf = 2 * h + (fx + 1) * h / 2
+        fine = np.sum(fw * h / 2 * (-1.0 / h ** 2) * np.exp(
+            _psi(0, xf) + sum(Y[n, j] * _psi(j + 1, xf) for j in range(s))))
+        assert abs(th[n].sum() - fine) <= 1e-6 * abs(fine)
+
+
+def test_epilogue_definitions():
+    X = np.array([[0.5, -1.0], [2.0, 0.25]])
+    b, w = np.array([1.0, -2.0]), np.array([3.0, 0.5])
+    np.testing.assert_array_equal(oracle.epilogue(X, oracle.EPI_NONE), X)
+    np.testing.assert_array_equal(oracle.epilogue(X, oracle.EPI_AFFINE, b), X + b)
+    np.testing.assert_array_equal(oracle.epilogue(X, oracle.EPI_AFFINE, None, w), X * w)
+    np.testing.assert_allclose(oracle.epilogue(X, oracle.EPI_EXP, b, w), w * np.exp(X + b))
