@@ -169,6 +169,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-korobov", action="store_true")
+    ap.add_argument("--no-pde", action="store_true")
     ap.add_argument("--fft-only", action="store_true",
                     help="time only the FFT path (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -181,7 +182,7 @@ def main():
         sys.exit(2)
     if args.fft_only:
         args.no_dense = args.no_cpu = args.no_f64 = args.no_batched = args.no_adjoint = True
-        args.no_korobov = True
+        args.no_korobov = args.no_pde = True
     if args.copy_calibration:
         import torch
         n = 1 << 28  # 2^28 float32 = 1 GiB
@@ -338,6 +339,38 @@ def main():
                              "graph_ms_per_batch": round(1e3 * eg / nb, 4)}
         log(f"batched 256 products: {1e3 * eb / nb:.3f} ms eager, {1e3 * eg / nb:.3f} ms graph")
         del batch, bA, bplans, g
+
+    if not args.no_pde:
+        # Section 3.3 on the Gaussian workload: the log-normal coefficient
+        # exp(Y A) written by the same pass
+        ee = time_steps(lambda: q.matmul(plan, A, out=X, workspace=ws, epilogue="exp"), args.steps,
+                        torch)
+        # Section 3.2 on the PDE field workload: a = psi_0 + Y A with psi_0 = 1
+        c3 = qi.make_c3(args.dtype)
+        p3 = q.Plan.from_instance(c3)
+        if not args.no_tune:
+            from paper_1501_06286_amd import autotune
+            autotune.tune(p3, c3.t, reps=3)
+        A3 = torch.from_numpy(c3.A).to(tdt).to(dev)
+        X3 = torch.empty((c3.N, c3.t), dtype=tdt, device=dev)
+        ws3 = p3.workspace(c3.t, dev)
+        one = torch.ones(c3.t, dtype=tdt, device=dev)
+        q.matmul(p3, A3, out=X3, workspace=ws3)
+        n3 = max(3, args.steps // 2)
+        e3 = time_steps(lambda: q.matmul(p3, A3, out=X3, workspace=ws3), n3, torch)
+        e3a = time_steps(lambda: q.matmul(p3, A3, out=X3, workspace=ws3, epilogue="affine",
+                                          bias=one), n3, torch)
+        result["pde"] = {
+            "lognormal_exp_epilogue": {"workload": workload, "ms_per_step": round(1e3 * ee / args.steps, 4),
+                                       "plain_ms_per_step": round(ms_step, 4)},
+            "uniform_field": {"workload": f"{c3.name}: GF(2) N=2^16, s=16384, t=4096, phi=y-1/2",
+                              "value": c3.N * c3.t / (e3 / n3), "unit": "entries/s (N*t per s)",
+                              "ms_per_step": round(1e3 * e3 / n3, 4),
+                              "affine_epilogue_ms_per_step": round(1e3 * e3a / n3, 4),
+                              "tuning": p3.get_tuning()}}
+        log(f"PDE: exp epilogue {1e3 * ee / args.steps:.3f} ms; field {1e3 * e3 / n3:.3f} ms, "
+            f"with psi_0 {1e3 * e3a / n3:.3f} ms")
+        del p3, A3, X3, ws3
 
     if not args.no_korobov:
         kin = qi.make_korobov(args.dtype)

@@ -98,7 +98,9 @@ struct Epi {
   const T* bias = nullptr;
   const T* scale = nullptr;
 };
-__device__ __forceinline__ float exp_t(float v) { return expf(v); }
+// FP32: the hardware base-2 exponential (relative error a few ulp times
+// |v|, far inside the FP32 product's tolerance); FP64: the full-precision one
+__device__ __forceinline__ float exp_t(float v) { return __expf(v); }
 __device__ __forceinline__ double exp_t(double v) { return exp(v); }
 
 // the epilogue of one thread's two columns col, col + 1 < t (loaded once;
