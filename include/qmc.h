@@ -131,8 +131,8 @@ int qmc_plan_tables(qmc_plan_t plan, int32_t* pow_out, int32_t* log_out,
 
 /*
  * Launch tuning of a plan (chosen by paper_1501_06286_amd/autotune.py):
- *   chunk_pairs  column pairs per chunk of the fused and back passes; the
- *                intermediate spectrum buffer then holds one or two chunks
+ *   chunk_pairs  column pairs per chunk of the passes of qmc_matmul; the
+ *                intermediate spectrum buffers then hold one or two chunks
  *                instead of all pairs (0 = one chunk of all pairs)
  *   streams      1, or 2 to run the back pass of chunk c on a second stream,
  *                overlapping the fused pass of chunk c+1 (needs chunk_pairs > 0)

@@ -130,6 +130,9 @@ bool dense_front(const qmc_plan_s* P) {
   return P->s > 8 * P->lay.M1;
 }
 
+// column pairs per chunk of the adjoint
+static int64_t adj_chunk(const qmc_plan_s*, int64_t pairs) { return pairs; }
+
 size_t workspace_bytes(const qmc_plan_s* P, int64_t t) {
   const size_t el = (P->dtype == QMC_F32) ? sizeof(cx<float>) : sizeof(cx<double>);
   const int64_t pairs = (t + 1) / 2;
@@ -138,7 +141,7 @@ size_t workspace_bytes(const qmc_plan_s* P, int64_t t) {
                             ? P->tune.chunk_pairs : pairs;
   const size_t fwd = dense_front(P) ? 2 * align256(chunk * P->lay.M * el)
                                     : aT + align256(fwd_c_pairs(P, pairs) * P->lay.M * el);
-  const size_t adj = aT + 2 * align256(pairs * P->lay.M * el);
+  const size_t adj = 2 * align256(adj_chunk(P, pairs) * P->lay.M * el);
   return std::max(fwd, adj);
 }
 
@@ -386,20 +389,30 @@ static int launch_outer_front(const qmc_plan_s* P, const T* A, const T* G, int64
   return launch_split<T, -1>(P, B, pairs, fwd ? PROF_DFRONT_SPLIT : PROF_ADJ_SPLIT, st);
 }
 
+// dA = Y^T G: gather and transform G into B, the fused pass into C, the
+// outer split and the read-back at the exponents l_j.  All column pairs in
+// one chunk (chunks that keep B and C in the Infinity Cache measured no
+// faster: these passes are not bound by the intermediate traffic).
 template <typename T>
 static int adjoint_t(const qmc_plan_s* P, const T* G, int64_t t, int64_t ldg, T* dA,
                      int64_t ldda, void* ws, hipStream_t st) {
   const int64_t pairs = (t + 1) / 2;
-  const size_t el = sizeof(cx<T>);
-  cx<T>* B = (cx<T>*)((char*)ws + align256(pairs * P->Upad * el));
-  cx<T>* C = (cx<T>*)((char*)B + align256(pairs * P->lay.M * el));
-  int rc = launch_outer_front<T>(P, nullptr, G, ldg, t, pairs, B, st);
-  if (rc != QMC_OK) return rc;
-  rc = launch_middle<T, false>(P, B, pairs, C, nullptr, t, PROF_ADJ_MIDDLE, st);
-  if (rc != QMC_OK) return rc;
-  rc = launch_split<T, +1>(P, C, pairs, PROF_SPLIT, st);
-  if (rc != QMC_OK) return rc;
-  return launch_back<T, true>(P, C, pairs, P->d_inv_ptr, P->d_inv_j, G, dA, ldda, t, st);
+  const int64_t chunk = adj_chunk(P, pairs);
+  cx<T>* B = (cx<T>*)ws;
+  cx<T>* C = (cx<T>*)((char*)ws + align256(chunk * P->lay.M * sizeof(cx<T>)));
+  for (int64_t p0 = 0; p0 < pairs; p0 += chunk) {
+    const int64_t np = std::min(chunk, pairs - p0), tc = t - 2 * p0;
+    int rc = launch_outer_front<T>(P, nullptr, G + 2 * p0, ldg, tc, np, B, st);
+    if (rc != QMC_OK) return rc;
+    rc = launch_middle<T, false>(P, B, np, C, nullptr, tc, PROF_ADJ_MIDDLE, st);
+    if (rc != QMC_OK) return rc;
+    rc = launch_split<T, +1>(P, C, np, PROF_SPLIT, st);
+    if (rc != QMC_OK) return rc;
+    rc = launch_back<T, true>(P, C, np, P->d_inv_ptr, P->d_inv_j, G + 2 * p0, dA + 2 * p0, ldda,
+                              tc, st);
+    if (rc != QMC_OK) return rc;
+  }
+  return QMC_OK;
 }
 
 int launch_adjoint(const qmc_plan_s* P, const void* G, int64_t t, int64_t ldg, void* dA,
