@@ -54,12 +54,33 @@ __device__ __forceinline__ int find_inst(const BatchInst* __restrict__ D, int n,
   return __builtin_amdgcn_readfirstlane(lo);  // uniform: descriptor loads stay scalar
 }
 
+// The persistent workgroups stride through the logical blocks of a pass
+// together, so the products' tables are shared in L2 while they run (dealing
+// contiguous ranges measured slower); a workgroup searches the descriptors
+// only when its next block leaves the product it is in.
+struct InstCursor {
+  int i = 0;
+  int64_t lo = 1, hi = 0;  // logical blocks of product i (empty at the start)
+};
+__device__ __forceinline__ int inst_at(const BatchInst* __restrict__ D, int n, int pass, int64_t b,
+                                       InstCursor& c) {
+  if (b < c.lo || b >= c.hi) {
+    c.i = find_inst(D, n, pass, b);
+    c.lo = D[c.i].off[pass];
+    c.hi = c.lo + D[c.i].nb[pass];
+  }
+  return c.i;
+}
+#define QMC_FOR_BLOCKS(b, total) \
+  for (int64_t b = blockIdx.x; b < (total); b += gridDim.x)
+
 template <typename T>
 __global__ __launch_bounds__(256) void kb_collapse(const BatchInst* __restrict__ D, int n,
                                                    int64_t total, char* __restrict__ ws) {
   __shared__ CollapseSmem<T> S;
-  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
-    const BatchInst I = D[find_inst(D, n, PASS_COLLAPSE, b)];
+  InstCursor cur;
+  QMC_FOR_BLOCKS(b, total) {
+    const BatchInst I = D[inst_at(D, n, PASS_COLLAPSE, b, cur)];
     const int64_t lb = b - I.off[PASS_COLLAPSE];
     collapse_body<T>((const T*)I.A, I.lda, I.t, I.pairs, I.it_ptr, I.it_jl, I.Upad,
                      (cx<T>*)(ws + I.aT_off), lb % I.gx_collapse, lb / I.gx_collapse, S,
@@ -74,8 +95,9 @@ __attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void kb_middle(const Bat
                                                                 int n, int64_t total,
                                                                 char* __restrict__ ws) {
   __shared__ MidSmem<T, R> S;
-  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
-    const BatchInst I = D[find_inst(D, n, PASS_MIDDLE, b)];
+  InstCursor cur;
+  QMC_FOR_BLOCKS(b, total) {
+    const BatchInst I = D[inst_at(D, n, PASS_MIDDLE, b, cur)];
     const int64_t lb = b - I.off[PASS_MIDDLE];
     middle_body<T, R, true>((const cx<T>*)(ws + I.aT_off), I.Upad, I.rounds, I.it_e1,
                             (const cx<T>*)I.twit, (const cx<T>*)I.twf1, (const cx<T>*)I.twf2,
@@ -89,8 +111,9 @@ __attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void kb_middle(const Bat
 template <typename T, int P2>
 __global__ __launch_bounds__(64) void kb_split(const BatchInst* __restrict__ D, int n,
                                                int64_t total, char* __restrict__ ws) {
-  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
-    const BatchInst I = D[find_inst(D, n, PASS_SPLIT, b)];
+  InstCursor cur;
+  QMC_FOR_BLOCKS(b, total) {
+    const BatchInst I = D[inst_at(D, n, PASS_SPLIT, b, cur)];
     const int64_t lb = b - I.off[PASS_SPLIT];
     const int64_t bx = lb % I.gx_split, rest = lb / I.gx_split;
     const int64_t q = rest % I.Q2, pair = rest / I.Q2;
@@ -103,8 +126,9 @@ template <typename T, int Q>
 __global__ __launch_bounds__(256) void kb_back(const BatchInst* __restrict__ D, int n,
                                                int64_t total, char* __restrict__ ws) {
   __shared__ BackSmem<T> S;
-  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
-    const BatchInst I = D[find_inst(D, n, PASS_BACK, b)];
+  InstCursor cur;
+  QMC_FOR_BLOCKS(b, total) {
+    const BatchInst I = D[inst_at(D, n, PASS_BACK, b, cur)];
     const int64_t lb = b - I.off[PASS_BACK];
     const int64_t bx = lb % I.gx_back, rest = lb / I.gx_back;
     const int64_t by = rest % I.gy_back, a = rest / I.gy_back;
