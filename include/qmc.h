@@ -115,6 +115,7 @@ typedef struct {
     uint64_t beta;          /* primitive element (lattice: smallest primitive root; GF(2): x = 2) */
     int rule, phi_kind, dtype, embedded;
     double phi0;            /* phi of the point of row 0 (the constant first row, Section 2.1) */
+    int P2, Q2;             /* outer split M2 = P2 x Q2 of the current tuning */
 } qmc_plan_info_t;
 int qmc_plan_info(qmc_plan_t plan, qmc_plan_info_t* info);
 
@@ -143,15 +144,21 @@ int qmc_plan_tables(qmc_plan_t plan, int32_t* pow_out, int32_t* log_out,
  *                2 = dense: a gather pass collapses A into length-M columns and
  *                transforms the outer index (extra passes over M per pair,
  *                one stream); 0 = dense when s > 8 M1, else sparse
+ *   outer_q      the outer radix: the outer DFT of length M2 (qmc_plan_info)
+ *                is split as M2 = P2 x Q2 with Q2 = min(outer_q, M2) values
+ *                per thread of the back pass and one extra split pass when
+ *                P2 > 1; a power of two <= 64 with P2 <= 64, or 0 for the
+ *                default (32, or M2/64 when larger)
  * The workspace size depends on the tuning: query it after setting it.
  * Returns QMC_ERR_ARG for negative chunks, streams outside {1, 2}, nt_store
- * outside {0, 1} or front outside {0, 1, 2}.
+ * outside {0, 1}, front outside {0, 1, 2} or an invalid outer_q.
  */
 typedef struct {
     int64_t chunk_pairs;
     int streams;
     int nt_store;
     int front;
+    int outer_q;
 } qmc_tuning_t;
 int qmc_plan_set_tuning(qmc_plan_t plan, const qmc_tuning_t* tuning);
 int qmc_plan_get_tuning(qmc_plan_t plan, qmc_tuning_t* tuning);

@@ -52,7 +52,7 @@ class QMCError(RuntimeError):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk_pairs", ctypes.c_int64), ("streams", ctypes.c_int), ("nt_store", ctypes.c_int),
-                ("front", ctypes.c_int)]
+                ("front", ctypes.c_int), ("outer_q", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -60,7 +60,8 @@ class PlanInfo(ctypes.Structure):
                 ("M", ctypes.c_int64), ("M1", ctypes.c_int64), ("M2", ctypes.c_int64),
                 ("rounds", ctypes.c_int64), ("beta", ctypes.c_uint64),
                 ("rule", ctypes.c_int), ("phi_kind", ctypes.c_int), ("dtype", ctypes.c_int),
-                ("embedded", ctypes.c_int), ("phi0", ctypes.c_double)]
+                ("embedded", ctypes.c_int), ("phi0", ctypes.c_double), ("P2", ctypes.c_int),
+                ("Q2", ctypes.c_int)]
 
 
 class KorobovInfo(ctypes.Structure):
@@ -226,16 +227,16 @@ class Plan:
         return pw, lg, el, ph
 
     def set_tuning(self, chunk_pairs: int = 0, streams: int = 1, nt_store: int = 0,
-                   front: int = 0) -> None:
+                   front: int = 0, outer_q: int = 0) -> None:
         """Launch tuning (see autotune.py); changes the workspace size."""
-        tu = Tuning(int(chunk_pairs), int(streams), int(nt_store), int(front))
+        tu = Tuning(int(chunk_pairs), int(streams), int(nt_store), int(front), int(outer_q))
         _check(lib().qmc_plan_set_tuning(self.handle, ctypes.byref(tu)), "qmc_plan_set_tuning")
 
     def get_tuning(self) -> dict:
         tu = Tuning()
         _check(lib().qmc_plan_get_tuning(self.handle, ctypes.byref(tu)), "qmc_plan_get_tuning")
         return {"chunk_pairs": tu.chunk_pairs, "streams": tu.streams, "nt_store": tu.nt_store,
-                "front": tu.front}
+                "front": tu.front, "outer_q": tu.outer_q}
 
     def profile(self, on: bool = True) -> None:
         """Bracket every kernel launch of this plan with HIP events."""

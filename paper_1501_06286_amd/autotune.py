@@ -1,8 +1,9 @@
 """Launch-configuration autotuner.
 
 For a plan and a column count t it times the candidate launch tunings of
-``qmc_plan_set_tuning`` (sparse or dense outer front, chunk of column pairs
-per pass, one or two streams, plain or non-temporal stores of X) on the GPU
+``qmc_plan_set_tuning`` (sparse or dense outer front, outer radix, chunk of
+column pairs per pass, one or two streams, plain or non-temporal stores of X)
+on the GPU
 with HIP events, keeps the fastest, and caches the choice in a JSON file keyed
 by the GPU architecture and the plan's shape (rule, L, M, s, t, dtype).
 """
@@ -16,18 +17,24 @@ CACHE = os.environ.get("QMC_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "qmcfast", "autotune.json"))
 
 
-def candidates(pairs: int) -> List[Dict[str, int]]:
+def candidates(pairs: int, M2: int = 1) -> List[Dict[str, int]]:
     """Sparse front: every chunk, one or two streams, plain or non-temporal
-    stores.  Dense front (one stream): every chunk, both store kinds."""
+    stores.  Dense front (one stream): every chunk, both store kinds.  Where
+    the outer length M2 exceeds 16, each of those with the outer radix
+    (values per back-pass thread) 16, 32 or 64 as far as the split allows."""
     chunks = [0] + [c for c in (8, 16, 32, 64, 128, 256, 512, 1024) if c < pairs]
+    qs = [0] + [q for q in (16, 64) if M2 > 16 and M2 // q <= 64 and q < M2]
     out = []
-    for c in chunks:
-        for streams in ((1, 2) if c else (1,)):
+    for q in qs:
+        for c in chunks:
+            for streams in ((1, 2) if c else (1,)):
+                for nt in (0, 1):
+                    out.append({"chunk_pairs": c, "streams": streams, "nt_store": nt, "front": 1,
+                                "outer_q": q})
+        for c in chunks:
             for nt in (0, 1):
-                out.append({"chunk_pairs": c, "streams": streams, "nt_store": nt, "front": 1})
-    for c in chunks:
-        for nt in (0, 1):
-            out.append({"chunk_pairs": c, "streams": 1, "nt_store": nt, "front": 2})
+                out.append({"chunk_pairs": c, "streams": 1, "nt_store": nt, "front": 2,
+                            "outer_q": q})
     return out
 
 
@@ -93,7 +100,7 @@ def tune(plan, t: int, reps: int = 3, use_cache: bool = True,
     A = torch.randn((plan.s, t), dtype=plan.torch_dtype, device="cuda")
     X = torch.empty((plan.N, t), dtype=plan.torch_dtype, device="cuda")
     results = []
-    for cfg in (cands or candidates((t + 1) // 2)):
+    for cfg in (cands or candidates((t + 1) // 2, plan.info()["M2"])):
         results.append((cfg, time_config(plan, A, X, cfg, reps)))
     best = min(results, key=lambda r: r[1])[0]
     plan.set_tuning(**best)

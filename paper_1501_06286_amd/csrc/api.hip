@@ -158,6 +158,10 @@ int qmc_plan_set_tuning(qmc_plan_t P, const qmc_tuning_t* tu) {
   if (tu->chunk_pairs < 0 || (tu->streams != 1 && tu->streams != 2) ||
       (tu->nt_store != 0 && tu->nt_store != 1) || tu->front < 0 || tu->front > 2)
     return QMC_ERR_ARG;
+  Layout lay = P->lay;
+  const int rc = set_outer_split(lay, tu->outer_q);
+  if (rc != QMC_OK) return rc;
+  P->lay = lay;
   P->tune = *tu;
   return QMC_OK;
 }
@@ -184,6 +188,8 @@ int qmc_plan_info(qmc_plan_t P, qmc_plan_info_t* info) {
   info->dtype = P->dtype;
   info->embedded = P->embedded;
   info->phi0 = P->phi0;
+  info->P2 = P->lay.P2;
+  info->Q2 = P->lay.Q2;
   return QMC_OK;
 }
 

@@ -59,14 +59,14 @@ struct qmc_plan_s {
   void* d_twi3 = nullptr;       // M   : conj W_M^{e1' (f M2 + w2)}, [w2] then thread a + R f value bb, e1' = a + R bb (paired)
   void* d_two = nullptr;        // M2*R: conj W_M^{R^2 c w2} in [w2][c] order
   void* d_twit = nullptr;       // M2*Upad: W_M^{slot_u w2} in [w2][u] order
-  void* d_twb = nullptr;        // M2  : conj W_{M2}^{a q} table for the split back pass [a*Q2+q]
+  void* d_twb = nullptr;        // M2  : conj W_{M2}^k, the outer split's twiddles at k = a q mod M2
   int32_t* d_it_e1 = nullptr;   // Upad: e1 of item u (M1 for padding)
   int32_t* d_it_ptr = nullptr;  // Upad+1: rows of item u are it_jl[it_ptr[u] .. it_ptr[u+1])
   int32_t* d_it_jl = nullptr;   // s   : rows j grouped by item (increasing j)
   int32_t* d_inv_ptr = nullptr;    // L+1 : rows j with l_j = e are inv_j[inv_ptr[e] .. inv_ptr[e+1])
   int32_t* d_inv_j = nullptr;      // s
   std::vector<void*> owned;
-  qmc_tuning_t tune = {0, 1, 0, 0};
+  qmc_tuning_t tune = {0, 1, 0, 0, 0};
   // second stream and events for the two-stream chunk pipeline (created lazily)
   mutable hipStream_t side = nullptr;
   mutable hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -94,6 +94,9 @@ namespace qmc {
 
 // tables.hip
 int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st);
+// split the outer length M2 = P2 Q2 with at most q values per back-pass
+// thread (q = 0: the default); QMC_ERR_ARG if q or the split is invalid
+int set_outer_split(Layout& lay, int q);
 int build_korobov_tables(qmc_korobov_s* U, hipStream_t st);
 
 // sparse collapse schedule for exponents l_j (j < s) on a layout: item u is

@@ -397,7 +397,7 @@ __device__ __forceinline__ void split_body(cx<T>* __restrict__ C, int64_t M1, in
   reg_fft<T, P2, DIR>(v);
   if constexpr (DIR > 0) {
 #pragma unroll
-    for (int a = 1; a < P2; ++a) v[a] = cmul(v[a], twb[a * Q2 + q]);
+    for (int a = 1; a < P2; ++a) v[a] = cmul(v[a], twb[(a * q) & (M2 - 1)]);
   }
 #pragma unroll
   for (int a = 0; a < P2; ++a) base[(q + (int64_t)Q2 * a) * M1] = v[a];
@@ -598,7 +598,7 @@ __device__ __forceinline__ void outer_front_body(const Gather& gather, int64_t M
   reg_fft<T, Q, -1>(v);
   if (P2 > 1) {
 #pragma unroll
-    for (int q = 1; q < Q; ++q) v[q] = cmulc(v[q], twb[a * Q + q]);
+    for (int q = 1; q < Q; ++q) v[q] = cmulc(v[q], twb[(a * q) & (M2 - 1)]);
   }
   const int64_t e1 = e1_0 + el, pair = p0 + pl;
   if (pair < P && e1 < M1) {

@@ -359,15 +359,14 @@ __global__ void k_minus1(int32_t* out, const int32_t* in, int64_t n) {
   if (i < n) out[i] = in[i] - 1;
 }
 
-// twb[a][q] = conj W_{M2}^{a q} for the split outer inverse (M2 = P2 Q2)
+// twb[k] = conj W_{M2}^k, k < M2: the twiddles of any split M2 = P2 Q2 of the
+// outer DFT, read at k = a q mod M2
 template <typename T>
-__global__ void k_tw_back(cx<T>* twb, const cx<double>* W, int P2, int Q2, int64_t M,
-                          int64_t M2) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= P2 * Q2) return;
-  const int64_t a = i / Q2, q = i % Q2;
-  const cx<double> w = W[(a * q * (M / M2)) & (M - 1)];
-  twb[i] = to_t<T>({w.x, -w.y});
+__global__ void k_tw_back(cx<T>* twb, const cx<double>* W, int64_t M, int64_t M2) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M2) return;
+  const cx<double> w = W[(k * (M / M2)) & (M - 1)];
+  twb[k] = to_t<T>({w.x, -w.y});
 }
 
 static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
@@ -400,18 +399,22 @@ static Layout choose_layout(int64_t L, int dtype, int* embedded) {
   lay.R = R;
   lay.M1 = (int64_t)R * R * R;
   lay.M2 = M / lay.M1;
-  // the outer inverse DFT of the back pass keeps Q2 values per thread; 32
-  // keeps its registers within an occupancy of 3-4 (64 fell to 1-2 and ran
-  // slower than an extra split pass)
-  const int64_t back_max = 32;
-  if (lay.M2 <= back_max) {
-    lay.P2 = 1;
-    lay.Q2 = (int)lay.M2;
-  } else {
-    lay.Q2 = (int)back_max;
-    lay.P2 = (int)(lay.M2 / back_max);
-  }
+  if (set_outer_split(lay, 0) != QMC_OK) lay.P2 = lay.Q2 = 0;  // too long: unsupported
   return lay;
+}
+
+int set_outer_split(Layout& lay, int q) {
+  // the outer inverse DFT of the back pass keeps Q2 values per thread and
+  // the split pass P2 = M2 / Q2, both at most 64.  The default q = 0 takes
+  // 32 (registers for an occupancy of 3-4; 64 fell to 1-2 and ran slower than
+  // an extra split pass at M2 = 512), more only when M2 > 32 * 64
+  if (q < 0 || q > 64 || (q & (q - 1))) return QMC_ERR_ARG;
+  const int64_t qmax = q > 0 ? q : std::max<int64_t>(32, lay.M2 / 64);
+  const int64_t Q2 = std::min<int64_t>(qmax, lay.M2);
+  if (Q2 > 64 || lay.M2 / Q2 > 64) return QMC_ERR_ARG;
+  lay.Q2 = (int)Q2;
+  lay.P2 = (int)(lay.M2 / Q2);
+  return QMC_OK;
 }
 
 // collapse schedule.  An item is one distinct reflected slot
@@ -525,7 +528,7 @@ static int build_spectral_tables(qmc_plan_s* P, const cx<double>* dW, const cx<d
   cx<T>* twi3 = dev_alloc<cx<T>>(P, M, &err);
   cx<T>* two = dev_alloc<cx<T>>(P, M2 * R, &err);
   cx<T>* twit = dev_alloc<cx<T>>(P, M2 * P->Upad, &err);
-  cx<T>* twb = dev_alloc<cx<T>>(P, (size_t)lay.P2 * lay.Q2, &err);
+  cx<T>* twb = dev_alloc<cx<T>>(P, (size_t)M2, &err);
   if (err != QMC_OK) return err;
   k_spectrum_layout<T><<<nblk(M), 256, 0, st>>>(Hs, dH, R, M, M2);
   k_tw_f1<T><<<nblk(R * R * R), 256, 0, st>>>(twf1, dW, R, M, M2);
@@ -533,7 +536,7 @@ static int build_spectral_tables(qmc_plan_s* P, const cx<double>* dW, const cx<d
   k_tw_i3<T><<<nblk(M), 256, 0, st>>>(twi3, dW, R, M, M2);
   k_tw_outer<T><<<nblk(M2 * R), 256, 0, st>>>(two, dW, R, M, M2);
   k_tw_items<T><<<nblk(M2 * P->Upad), 256, 0, st>>>(twit, dW, dslot, P->Upad, M, M2, 1);
-  k_tw_back<T><<<nblk((int64_t)lay.P2 * lay.Q2), 256, 0, st>>>(twb, dW, lay.P2, lay.Q2, M, M2);
+  k_tw_back<T><<<nblk(M2), 256, 0, st>>>(twb, dW, M, M2);
   QMC_HIP(hipGetLastError());
   P->d_Hs = Hs;
   P->d_twf1 = twf1;
@@ -570,6 +573,7 @@ int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st) {
   }
   P->lay = choose_layout(L, P->dtype, &P->embedded);
   const Layout& lay = P->lay;
+  if (lay.P2 < 1) return QMC_ERR_UNSUPPORTED;  // outer length beyond 64 x 64
 
   // ---- bit-exact group tables ------------------------------------------
   P->d_pow = dev_alloc<int32_t>(P, L, &err);

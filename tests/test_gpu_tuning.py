@@ -24,7 +24,7 @@ def test_tuned_forward(chunk, streams, nt, front, dtype):
     p = plan_of(inst)
     p.set_tuning(chunk_pairs=chunk, streams=streams, nt_store=nt, front=front)
     assert p.get_tuning() == {"chunk_pairs": chunk, "streams": streams, "nt_store": nt,
-                              "front": front}
+                              "front": front, "outer_q": 0}
     A = to_dev(inst.A, dtype)
     X1 = q.matmul(p, A)
     X2 = q.matmul(p, A)  # back-to-back calls reuse the slots and events
@@ -84,3 +84,39 @@ def test_dense_front_matches_oracle_and_sparse(kind, n, s, t, dtype):
     ref = oracle.matmul(inst)
     assert_close(Xd.double().cpu().numpy(), ref, inst.A, inst, dtype, "dense front")
     assert_close(Xs.double().cpu().numpy(), ref, inst.A, inst, dtype, "sparse front")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("q,front", [(0, 1), (2, 1), (16, 1), (64, 1), (64, 2), (4, 2)])
+def test_outer_radix(q, front, dtype):
+    """Every split M2 = P2 x Q2 of the outer DFT (M = 2^19, M2 = 128) gives the
+    oracle's product and adjoint."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q_
+    inst = qi.small_lattice(139999, 100, 5, phi=qi.PHI_INVNORM, shift=(1, 279998), dtype=dtype,
+                            seed=9)
+    announce(f"outer radix q={q} front={front} {dtype}")
+    p = plan_of(inst)
+    p.set_tuning(outer_q=q, front=front)
+    info = p.info()
+    assert info["M2"] == 128 and info["P2"] * info["Q2"] == 128
+    assert info["Q2"] == (q if q else 32)
+    A = to_dev(inst.A, dtype)
+    X = q_.matmul(p, A)
+    rg = np.random.default_rng(1)
+    G = rg.standard_normal((inst.N, 5))
+    dA = q_.matmul_adjoint(p, to_dev(G, dtype))
+    torch.cuda.synchronize()
+    assert_close(X.double().cpu().numpy(), oracle.matmul(inst), inst.A, inst, dtype, "forward")
+    Gr = G.astype(np.float32).astype(np.float64) if dtype == "f32" else G
+    assert_close(dA.double().cpu().numpy(), oracle.adjoint(inst, Gr), Gr, inst, dtype, "adjoint")
+
+
+def test_outer_radix_rejects_bad_values():
+    torch_cuda()
+    import paper_1501_06286_amd as q
+    p = plan_of(qi.small_lattice(139999, 20, 2))  # M2 = 128
+    for bad in (3, 128, 1, -2):  # not a power of two, above 64, P2 = 128 > 64, negative
+        with pytest.raises(q.QMCError):
+            p.set_tuning(outer_q=bad)
+    assert p.info()["Q2"] == 32  # unchanged by the rejected calls
