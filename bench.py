@@ -317,6 +317,11 @@ def main():
         insts = qi.make_c4(dtype=args.dtype)
         bplans = [q.Plan.from_instance(i) for i in insts]
         bA = [torch.from_numpy(i.A).to(tdt).to(dev) for i in insts]
+        btune = {}
+        if not args.no_tune:
+            from paper_1501_06286_amd import autotune
+            btune, _ = autotune.tune_batch(bplans, bA)
+            log(f"batched outer radix per outer length: {btune}")
         batch = q.Batch(bplans, bA)
         batch.run()
         nb = 5
@@ -336,7 +341,8 @@ def main():
                              "entries": ent, "value": ent / (eb / nb),
                              "ms_per_batch": round(1e3 * eb / nb, 4),
                              "graph_value": ent / (eg / nb),
-                             "graph_ms_per_batch": round(1e3 * eg / nb, 4)}
+                             "graph_ms_per_batch": round(1e3 * eg / nb, 4),
+                             "outer_radix_by_M2": {str(k): v for k, v in btune.items()}}
         log(f"batched 256 products: {1e3 * eb / nb:.3f} ms eager, {1e3 * eg / nb:.3f} ms graph")
         del batch, bA, bplans, g
 

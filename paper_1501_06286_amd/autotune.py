@@ -135,3 +135,48 @@ def tune_korobov(U, t: int, reps: int = 3, chunks=(0, 16, 32, 64, 128, 256)) -> 
     best = min(results, key=lambda r: r[1])[0]
     U.set_chunk(best)
     return best, results
+
+
+def tune_batch(plans, As, reps: int = 3, qs=(0, 16, 64)) -> Tuple[Dict[int, int], List]:
+    """Pick the outer radix of a batch's products by timing whole batched runs:
+    for each outer length M2 in the batch, every admissible outer_q with the
+    other products at the default; the products of one M2 form their own
+    launch groups, so the choices are made one M2 at a time.  Sets the
+    plans' tunings and returns ({M2: outer_q}, timings)."""
+    import torch
+    import paper_1501_06286_amd as q
+
+    def run_ms():
+        b = q.Batch(plans, As)
+        b.run()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            b.run()
+        e1.record()
+        e1.synchronize()
+        b.close()
+        return e0.elapsed_time(e1) / reps
+
+    m2s = sorted({p.info()["M2"] for p in plans})
+    best, timings = {}, []
+    for p in plans:
+        p.set_tuning(**{**p.get_tuning(), "outer_q": 0})
+    for m2 in m2s:
+        if m2 <= 16:
+            continue
+        group = [p for p in plans if p.info()["M2"] == m2]
+        res = []
+        for oq in qs:
+            if oq and (oq >= m2 or m2 // oq > 64):
+                continue
+            for p in group:
+                p.set_tuning(**{**p.get_tuning(), "outer_q": oq})
+            res.append((oq, run_ms()))
+        choice = min(res, key=lambda r: r[1])[0]
+        for p in group:
+            p.set_tuning(**{**p.get_tuning(), "outer_q": choice})
+        best[m2] = choice
+        timings.append((m2, res))
+    return best, timings

@@ -104,3 +104,23 @@ def test_batched_config_full():
         rows = np.unique(np.concatenate([[0, inst.N - 1], rg.integers(0, inst.N, size=3)]))
         got = X[torch.from_numpy(rows).cuda()].double().cpu().numpy()
         assert_close(got, oracle.matmul_rows(inst, rows), inst.A, inst, "f32", inst.name)
+
+
+def test_batch_autotune_outer_radix():
+    """The batch tuner sets an admissible outer radix per outer length, and
+    the tuned batch still gives the single products' bits."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    from paper_1501_06286_amd import autotune
+    insts = _instances("f32", seed=7)
+    announce("batch outer radix tuning")
+    plans = [plan_of(i) for i in insts]
+    As = [to_dev(i.A, "f32") for i in insts]
+    best, timings = autotune.tune_batch(plans, As, reps=1)
+    for p in plans:
+        m2 = p.info()["M2"]
+        if m2 in best:
+            assert p.get_tuning()["outer_q"] == best[m2]
+    Xs = q.Batch(plans, As).run()
+    for p, A, X in zip(plans, As, Xs):
+        assert torch.equal(q.matmul(p, A), X)
