@@ -177,8 +177,9 @@ def main():
                          "for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the columns of A "
-              f"shard across GPUs without communication, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the column pairs "
+              f"of A are independent, so a multi-GPU run would give each GPU a slice of them "
+              f"with a replicated plan and no communication", file=sys.stderr)
         sys.exit(2)
     if args.fft_only:
         args.no_dense = args.no_cpu = args.no_f64 = args.no_batched = args.no_adjoint = True
