@@ -24,10 +24,18 @@ def sample_rows(N, k, seed):
     return np.array(sorted(rows))
 
 
-def _forward_sampled(inst, dtype, nrows=48):
+def _forward_sampled(inst, dtype, nrows=48, tuning=None, autotuned=False):
+    """tuning: a fixed launch tuning; autotuned: the one bench.py's autotuner
+    picks for this plan (the configuration the benchmark times)."""
     torch = torch_cuda()
     import paper_1501_06286_amd as q
     p = plan_of(inst)
+    if autotuned:
+        from paper_1501_06286_amd import autotune
+        best, _ = autotune.tune(p, inst.t, reps=3, use_cache=False)
+        announce(f"  autotuned launch {best}")
+    elif tuning:
+        p.set_tuning(**tuning)
     A = to_dev(inst.A, dtype)
     X = q.matmul(p, A)
     rows = sample_rows(inst.N, nrows, inst.N + inst.s)
@@ -46,10 +54,12 @@ def _forward_sampled(inst, dtype, nrows=48):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_c2_gaussian_full(dtype):
+@pytest.mark.parametrize("how", ["default", "autotuned", "chunk256_nt"])
+def test_c2_gaussian_full(dtype, how):
     inst = qi.make_c2(dtype)
-    announce(f"C2 full size {dtype}")
-    _forward_sampled(inst, dtype)
+    announce(f"C2 full size {dtype} {how}")
+    _forward_sampled(inst, dtype, autotuned=how == "autotuned",
+                     tuning={"chunk_pairs": 256, "nt_store": 1} if how == "chunk256_nt" else None)
 
 
 def test_c2_matches_dense_baseline():
@@ -68,10 +78,11 @@ def test_c2_matches_dense_baseline():
     assert err < 2 * TOL["f32"]
 
 
-def test_c3_pde_gf2_full():
+@pytest.mark.parametrize("how", ["default", "autotuned"])
+def test_c3_pde_gf2_full(how):
     inst = qi.make_c3("f32")
-    announce("C3 full size (GF(2), m=16, s=16384, t=4096)")
-    _forward_sampled(inst, "f32", nrows=24)
+    announce(f"C3 full size (GF(2), m=16, s=16384, t=4096) {how}")
+    _forward_sampled(inst, "f32", nrows=24, autotuned=how == "autotuned")
 
 
 def test_c5_forward_adjoint_fd():
