@@ -459,7 +459,17 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
     const bool ok = pair < P && e1 < M1;
     const cx<T>* base = C + (ok ? pair : 0) * M2 * M1 + (ok ? e1 : 0);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) v[q] = ok ? base[(q + Q * a) * M1] : cx<T>{(T)0, (T)0};
+    for (int q = 0; q < Q; ++q) {
+      // C is dead after this read: a non-temporal load keeps it from
+      // displacing lines that are still wanted
+      cx<T> c = {(T)0, (T)0};
+      if (ok) {
+        const vec2_t<T> w = __builtin_nontemporal_load(
+            reinterpret_cast<const vec2_t<T>*>(base + (q + Q * a) * M1));
+        c = {w.x, w.y};
+      }
+      v[q] = c;
+    }
     reg_fft<T, Q, +1>(v);
     const int pw = tid % PB, ew = tid / PB;
     const int64_t pairw = p0 + pw, e1w = e1_0 + ew;
