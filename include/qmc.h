@@ -149,9 +149,14 @@ int qmc_plan_tables(qmc_plan_t plan, int32_t* pow_out, int32_t* log_out,
  *                per thread of the back pass and one extra split pass when
  *                P2 > 1; a power of two <= 64 with P2 <= 64, or 0 for the
  *                default (32, or M2/64 when larger)
+ *   nt_inter     stores of the intermediate spectrum by the fused pass: 1 =
+ *                cached, 2 = streaming (non-temporal), 0 = streaming when one
+ *                launch's intermediate exceeds 128 MiB (it would not stay in
+ *                the Infinity Cache for the back pass anyway)
  * The workspace size depends on the tuning: query it after setting it.
  * Returns QMC_ERR_ARG for negative chunks, streams outside {1, 2}, nt_store
- * outside {0, 1}, front outside {0, 1, 2} or an invalid outer_q.
+ * outside {0, 1}, front outside {0, 1, 2}, an invalid outer_q or nt_inter
+ * outside {0, 1, 2}.
  */
 typedef struct {
     int64_t chunk_pairs;
@@ -159,6 +164,7 @@ typedef struct {
     int nt_store;
     int front;
     int outer_q;
+    int nt_inter;
 } qmc_tuning_t;
 int qmc_plan_set_tuning(qmc_plan_t plan, const qmc_tuning_t* tuning);
 int qmc_plan_get_tuning(qmc_plan_t plan, qmc_tuning_t* tuning);

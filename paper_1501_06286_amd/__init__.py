@@ -52,7 +52,7 @@ class QMCError(RuntimeError):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("chunk_pairs", ctypes.c_int64), ("streams", ctypes.c_int), ("nt_store", ctypes.c_int),
-                ("front", ctypes.c_int), ("outer_q", ctypes.c_int)]
+                ("front", ctypes.c_int), ("outer_q", ctypes.c_int), ("nt_inter", ctypes.c_int)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -227,16 +227,17 @@ class Plan:
         return pw, lg, el, ph
 
     def set_tuning(self, chunk_pairs: int = 0, streams: int = 1, nt_store: int = 0,
-                   front: int = 0, outer_q: int = 0) -> None:
+                   front: int = 0, outer_q: int = 0, nt_inter: int = 0) -> None:
         """Launch tuning (see autotune.py); changes the workspace size."""
-        tu = Tuning(int(chunk_pairs), int(streams), int(nt_store), int(front), int(outer_q))
+        tu = Tuning(int(chunk_pairs), int(streams), int(nt_store), int(front), int(outer_q),
+                    int(nt_inter))
         _check(lib().qmc_plan_set_tuning(self.handle, ctypes.byref(tu)), "qmc_plan_set_tuning")
 
     def get_tuning(self) -> dict:
         tu = Tuning()
         _check(lib().qmc_plan_get_tuning(self.handle, ctypes.byref(tu)), "qmc_plan_get_tuning")
         return {"chunk_pairs": tu.chunk_pairs, "streams": tu.streams, "nt_store": tu.nt_store,
-                "front": tu.front, "outer_q": tu.outer_q}
+                "front": tu.front, "outer_q": tu.outer_q, "nt_inter": tu.nt_inter}
 
     def profile(self, on: bool = True) -> None:
         """Bracket every kernel launch of this plan with HIP events."""

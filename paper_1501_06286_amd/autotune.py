@@ -19,22 +19,24 @@ CACHE = os.environ.get("QMC_AUTOTUNE_CACHE",
 
 def candidates(pairs: int, M2: int = 1) -> List[Dict[str, int]]:
     """Sparse front: every chunk, one or two streams, plain or non-temporal
-    stores.  Dense front (one stream): every chunk, both store kinds.  Where
-    the outer length M2 exceeds 16, each of those with the outer radix
-    (values per back-pass thread) 16, 32 or 64 as far as the split allows."""
+    stores of X.  Dense front (one stream): every chunk, both store kinds.
+    Each with cached or streaming stores of the intermediate, and where the
+    outer length M2 exceeds 16, with the outer radix (values per back-pass
+    thread) 16, 32 or 64 as far as the split allows."""
     chunks = [0] + [c for c in (8, 16, 32, 64, 128, 256, 512, 1024) if c < pairs]
     qs = [0] + [q for q in (16, 64) if M2 > 16 and M2 // q <= 64 and q < M2]
     out = []
     for q in qs:
-        for c in chunks:
-            for streams in ((1, 2) if c else (1,)):
+        for ni in (1, 2):  # cached or streaming stores of the intermediate
+            for c in chunks:
+                for streams in ((1, 2) if c else (1,)):
+                    for nt in (0, 1):
+                        out.append({"chunk_pairs": c, "streams": streams, "nt_store": nt,
+                                    "front": 1, "outer_q": q, "nt_inter": ni})
+            for c in chunks:
                 for nt in (0, 1):
-                    out.append({"chunk_pairs": c, "streams": streams, "nt_store": nt, "front": 1,
-                                "outer_q": q})
-        for c in chunks:
-            for nt in (0, 1):
-                out.append({"chunk_pairs": c, "streams": 1, "nt_store": nt, "front": 2,
-                            "outer_q": q})
+                    out.append({"chunk_pairs": c, "streams": 1, "nt_store": nt, "front": 2,
+                                "outer_q": q, "nt_inter": ni})
     return out
 
 

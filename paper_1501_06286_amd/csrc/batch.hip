@@ -93,7 +93,8 @@ template <typename T, int R>
 __global__ __launch_bounds__(MidShape<R>::BLOCK)
 __attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void kb_middle(const BatchInst* __restrict__ D,
                                                                 int n, int64_t total,
-                                                                char* __restrict__ ws) {
+                                                                char* __restrict__ ws,
+                                                                int nt_c) {
   __shared__ MidSmem<T, R> S;
   InstCursor cur;
   QMC_FOR_BLOCKS(b, total) {
@@ -103,7 +104,7 @@ __attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void kb_middle(const Bat
                             (const cx<T>*)I.twit, (const cx<T>*)I.twf1, (const cx<T>*)I.twf2,
                             (const cx<T>*)I.Hs, (const cx<T>*)I.twi3, (const cx<T>*)I.two, I.M2,
                             I.pairs, (cx<T>*)(ws + I.C_off), (T*)I.X, I.t, (T)I.phi0, lb, S,
-                            opaque_tid());
+                            opaque_tid(), nt_c != 0);
     __syncthreads();
   }
 }
@@ -148,6 +149,7 @@ struct qmc_batch_s {
   size_t ws_bytes = 0;
   struct Group {
     int R = 0, P2 = 1, Q2 = 1;
+    int nt_c = 0;  // streaming stores of the group's intermediate (too large for the cache)
     int n = 0;
     BatchInst* d_desc = nullptr;
     int64_t total[NPASS] = {0, 0, 0, 0};
@@ -242,6 +244,15 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
     g.P2 = (int)((kv.first >> 16) & 0xffff);
     g.Q2 = (int)(kv.first & 0xffff);
     g.n = (int)v.size();
+    {
+      // the group's intermediate spectra, written by the middle pass and read
+      // by the back pass: streaming stores when they cannot stay in the
+      // 256 MB Infinity Cache in between
+      const size_t elc = dtype == QMC_F32 ? sizeof(cx<float>) : sizeof(cx<double>);
+      int64_t cbytes = 0;
+      for (const BatchInst& I : v) cbytes += I.pairs * I.M1 * I.M2 * (int64_t)elc;
+      g.nt_c = cbytes > ((int64_t)128 << 20) ? 1 : 0;
+    }
     for (int p = 0; p < NPASS; ++p) {
       int64_t off = 0;
       for (BatchInst& I : v) {
@@ -296,7 +307,7 @@ static int run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
         g.d_desc, g.n, g.total[PASS_COLLAPSE], ws);
   if (g.total[PASS_MIDDLE])
     kb_middle<T, R><<<grid_for(g.total[PASS_MIDDLE], 1024), MidShape<R>::BLOCK, 0, st>>>(
-        g.d_desc, g.n, g.total[PASS_MIDDLE], ws);
+        g.d_desc, g.n, g.total[PASS_MIDDLE], ws, g.nt_c);
   if (g.total[PASS_SPLIT]) {
     const unsigned gs = grid_for(g.total[PASS_SPLIT], 4096);
 #define QMC_KBS(PP) kb_split<T, PP><<<gs, 64, 0, st>>>(g.d_desc, g.n, g.total[PASS_SPLIT], ws)

@@ -48,10 +48,11 @@ __attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void k_middle(
     const cx<T>* __restrict__ twit, const cx<T>* __restrict__ twf1,
     const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs,
     const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M2, int64_t P,
-    cx<T>* __restrict__ C, T* __restrict__ X, int64_t t, T phi0) {
+    cx<T>* __restrict__ C, T* __restrict__ X, int64_t t, T phi0, int nt_c) {
   __shared__ MidSmem<T, R> S;
   middle_body<T, R, SPARSE>(src, Upad, rounds, it_e1, twit, twf1, twf2, Hs, twi3, two, M2,
-                            P, C, X, t, phi0, xcd_remap(blockIdx.x, gridDim.x), S, threadIdx.x);
+                            P, C, X, t, phi0, xcd_remap(blockIdx.x, gridDim.x), S, threadIdx.x,
+                            nt_c != 0);
 }
 
 template <typename T, int P2, int DIR>
@@ -130,6 +131,14 @@ bool dense_front(const qmc_plan_s* P) {
   return P->s > 8 * P->lay.M1;
 }
 
+// whether the fused pass writes the intermediate spectrum C with streaming
+// stores (tuning nt_inter: 0 = when C of one launch, c_bytes, is too large to
+// stay in the 256 MB Infinity Cache for the back pass, 1 = never, 2 = always)
+static bool nt_inter(const qmc_plan_s* P, int64_t c_bytes) {
+  if (P->tune.nt_inter != 0) return P->tune.nt_inter == 2;
+  return c_bytes > ((int64_t)128 << 20);
+}
+
 // column pairs per chunk of the adjoint
 static int64_t adj_chunk(const qmc_plan_s*, int64_t pairs) { return pairs; }
 
@@ -157,7 +166,8 @@ static void launch_middle_r(const qmc_plan_s* P, const cx<T>* src, int64_t pairs
       src, P->Upad, P->rounds, P->d_it_e1, (const cx<T>*)P->d_twit, (const cx<T>*)P->d_twf1,
       (const cx<T>*)P->d_twf2, (const cx<T>*)P->d_Hs,
       (const cx<T>*)P->d_twi3,
-      (const cx<T>*)P->d_two, lay.M2, pairs, C, X, t, (T)P->phi0);
+      (const cx<T>*)P->d_two, lay.M2, pairs, C, X, t, (T)P->phi0,
+      nt_inter(P, pairs * lay.M * (int64_t)sizeof(cx<T>)) ? 1 : 0);
 }
 
 // X != nullptr: forward product, the DC term of each pair goes to row 0

@@ -66,7 +66,7 @@ struct qmc_plan_s {
   int32_t* d_inv_ptr = nullptr;    // L+1 : rows j with l_j = e are inv_j[inv_ptr[e] .. inv_ptr[e+1])
   int32_t* d_inv_j = nullptr;      // s
   std::vector<void*> owned;
-  qmc_tuning_t tune = {0, 1, 0, 0, 0};
+  qmc_tuning_t tune = {0, 1, 0, 0, 0, 0};
   // second stream and events for the two-stream chunk pipeline (created lazily)
   mutable hipStream_t side = nullptr;
   mutable hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};

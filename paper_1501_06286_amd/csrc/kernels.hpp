@@ -157,6 +157,8 @@ template <typename T>
 struct alignas(4 * sizeof(T)) cx2 {
   cx<T> a, b;
 };
+template <typename T>
+using vec2_t = T __attribute__((ext_vector_type(2)));
 
 // v[h] = table value h of thread q, h = 0..R-1
 template <typename T, int R>
@@ -207,7 +209,7 @@ __device__ __forceinline__ void middle_body(
     const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs,
     const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M2, int64_t P,
     cx<T>* __restrict__ C, T* __restrict__ X, int64_t t, T phi0, int64_t b, MidSmem<T, R>& SM,
-    int tid) {
+    int tid, bool nt_c = false) {
   typedef MidShape<R> S;
   constexpr int Q = S::Q, M1 = R * R * R, PB = R * (R + 1);
   cx<T>* lds = SM.lds;
@@ -372,7 +374,14 @@ __device__ __forceinline__ void middle_body(
   if (active) {
     cx<T>* cp = C + (pair * M2 + w2) * M1;
 #pragma unroll
-    for (int c = 0; c < R; ++c) cp[q + Q * c] = x[c];
+    for (int c = 0; c < R; ++c) {
+      if (nt_c) {  // streaming stores: C skips the caches on its way out
+        const vec2_t<T> w = {x[c].x, x[c].y};
+        __builtin_nontemporal_store(w, reinterpret_cast<vec2_t<T>*>(cp + q + Q * c));
+      } else {
+        cp[q + Q * c] = x[c];
+      }
+    }
   }
 }
 
@@ -424,8 +433,6 @@ template <typename T>
 __device__ __forceinline__ bool pairs_aligned(const T* p, int64_t ld) {
   return (ld % 2 == 0) && (reinterpret_cast<uintptr_t>(p) % (2 * sizeof(T)) == 0);
 }
-template <typename T>
-using vec2_t = T __attribute__((ext_vector_type(2)));
 template <typename T, bool NT>
 __device__ __forceinline__ void store_pair(T* p, T x, T y) {
   const vec2_t<T> v = {x, y};

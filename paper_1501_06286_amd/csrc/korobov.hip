@@ -34,13 +34,14 @@ __attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void ku_middle(
     const cx<T>* __restrict__ twit, const cx<T>* __restrict__ twf1,
     const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs,
     const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M1, int64_t M2,
-    int64_t P, cx<T>* __restrict__ C, int64_t per_block) {
+    int64_t P, cx<T>* __restrict__ C, int64_t per_block, int nt_c) {
   __shared__ MidSmem<T, R> S;
   const int64_t id = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t b = id / per_block, lb = id % per_block;
   middle_body<T, R, true>(aT + b * P * Upad, Upad, rounds, it_e1 + b * Upad,
                           twit + b * M2 * Upad, twf1, twf2, Hs, twi3, two, M2, P,
-                          C + b * P * M1 * M2, (T*)nullptr, 0, (T)0, lb, S, threadIdx.x);
+                          C + b * P * M1 * M2, (T*)nullptr, 0, (T)0, lb, S, threadIdx.x,
+                          nt_c != 0);
 }
 
 template <typename T, int P2>
@@ -93,7 +94,10 @@ static void ku_middle_launch(const qmc_korobov_s* U, const cx<T>* aT, int64_t b0
       aT, U->Upad, U->rounds, U->d_it_e1 + b0 * U->Upad,
       (const cx<T>*)U->d_twit + b0 * lay.M2 * U->Upad, (const cx<T>*)P->d_twf1,
       (const cx<T>*)P->d_twf2, (const cx<T>*)P->d_Hs, (const cx<T>*)P->d_twi3,
-      (const cx<T>*)P->d_two, lay.M1, lay.M2, pairs, C, per_block);
+      (const cx<T>*)P->d_two, lay.M1, lay.M2, pairs, C, per_block,
+      // streaming stores when a run's intermediate cannot stay in the 256 MB
+      // Infinity Cache until the back pass reads it
+      nb * pairs * lay.M * (int64_t)sizeof(cx<T>) > ((int64_t)128 << 20) ? 1 : 0);
 }
 
 template <typename T>

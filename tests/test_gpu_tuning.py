@@ -24,7 +24,7 @@ def test_tuned_forward(chunk, streams, nt, front, dtype):
     p = plan_of(inst)
     p.set_tuning(chunk_pairs=chunk, streams=streams, nt_store=nt, front=front)
     assert p.get_tuning() == {"chunk_pairs": chunk, "streams": streams, "nt_store": nt,
-                              "front": front, "outer_q": 0}
+                              "front": front, "outer_q": 0, "nt_inter": 0}
     A = to_dev(inst.A, dtype)
     X1 = q.matmul(p, A)
     X2 = q.matmul(p, A)  # back-to-back calls reuse the slots and events
@@ -38,7 +38,7 @@ def test_tuning_rejects_bad_values():
     import paper_1501_06286_amd as q
     p = plan_of(qi.small_lattice(101, 5, 2))
     for bad in ({"chunk_pairs": -1}, {"streams": 3}, {"nt_store": 2}, {"front": 3},
-                {"front": -1}):
+                {"front": -1}, {"nt_inter": 3}, {"nt_inter": -1}):
         with pytest.raises(q.QMCError):
             p.set_tuning(**bad)
 
@@ -120,3 +120,22 @@ def test_outer_radix_rejects_bad_values():
         with pytest.raises(q.QMCError):
             p.set_tuning(outer_q=bad)
     assert p.info()["Q2"] == 32  # unchanged by the rejected calls
+
+
+@pytest.mark.parametrize("ni", [1, 2])
+@pytest.mark.parametrize("chunk,front", [(0, 1), (5, 1), (0, 2), (3, 2)])
+def test_intermediate_store_kinds(ni, chunk, front):
+    """Cached and streaming stores of the intermediate give the same bits."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    inst = qi.small_lattice(8209, 300, 21, phi=qi.PHI_INVNORM, shift=(1, 16418), dtype="f32")
+    announce(f"intermediate stores {ni} chunk={chunk} front={front}")
+    p = plan_of(inst)
+    A = to_dev(inst.A, "f32")
+    p.set_tuning(chunk_pairs=chunk, front=front, nt_inter=1)
+    X1 = q.matmul(p, A)
+    p.set_tuning(chunk_pairs=chunk, front=front, nt_inter=ni)
+    X2 = q.matmul(p, A)
+    torch.cuda.synchronize()
+    assert torch.equal(X1, X2)
+    assert_close(X2.double().cpu().numpy(), oracle.matmul(inst), inst.A, inst, "f32", "nt_inter")
