@@ -386,10 +386,11 @@ __device__ __forceinline__ void middle_body(
 }
 
 // ---------------------------------------------------------------------------
-// outer split (only when M2 = P2 * Q2 > 64), in place on C[pair][w2][e1]:
+// outer split (only when the tuning splits M2 = P2 * Q2 with P2 > 1), in place
+// on C[pair][w2][e1]:
 //   DIR = +1 (forward product, first half of the inverse over w2):
 //     w2 = q + Q2 p'  ->  index a, times conj W_{M2}^{a q}
-//   DIR = -1 (adjoint front, second half of the forward DFT over e2):
+//   DIR = -1 (dense outer fronts, second half of the forward DFT over e2):
 //     the values at q + Q2 a (already twiddled by W_{M2}^{a q}) -> p',
 //     stored at w2 = q + Q2 p'
 // ---------------------------------------------------------------------------
