@@ -165,7 +165,8 @@ def main():
     ap.add_argument("--no-f64", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch tuning")
     ap.add_argument("--tuning", default=None,
-                    help="fixed launch tuning chunk_pairs,streams,nt_store,front instead of autotuning")
+                    help="fixed launch tuning chunk_pairs,streams,nt_store,front[,outer_q,nt_inter] "
+                         "instead of autotuning")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-korobov", action="store_true")
@@ -213,8 +214,11 @@ def main():
     X = torch.empty((N, t), dtype=tdt, device=dev)
     tuning = plan.get_tuning()
     if args.tuning:
-        c, st, nt, fr = (int(v) for v in args.tuning.split(","))
-        plan.set_tuning(chunk_pairs=c, streams=st, nt_store=nt, front=fr)
+        keys = ("chunk_pairs", "streams", "nt_store", "front", "outer_q", "nt_inter")
+        vals = [int(v) for v in args.tuning.split(",")]
+        if len(vals) not in (4, 6):
+            ap.error("--tuning takes 4 or 6 comma-separated integers")
+        plan.set_tuning(**dict(zip(keys, vals)))
         tuning = plan.get_tuning()
         log(f"fixed launch tuning: {tuning}")
     elif not args.no_tune:
