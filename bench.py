@@ -328,6 +328,10 @@ def main():
             btune, _ = autotune.tune_batch(bplans, bA)
             log(f"batched outer radix per outer length: {btune}")
         batch = q.Batch(bplans, bA)
+        bchunk = (q.BATCH_CHUNK_DEFAULT, 0)
+        if not args.no_tune:
+            bchunk, _ = autotune.tune_batch_chunk(batch)
+            log(f"batched run size {bchunk[0] >> 20} MiB of intermediates, nt_inter {bchunk[1]}")
         batch.run()
         nb = 5
         eb = time_steps(batch.run, nb, torch)
@@ -347,7 +351,8 @@ def main():
                              "ms_per_batch": round(1e3 * eb / nb, 4),
                              "graph_value": ent / (eg / nb),
                              "graph_ms_per_batch": round(1e3 * eg / nb, 4),
-                             "outer_radix_by_M2": {str(k): v for k, v in btune.items()}}
+                             "outer_radix_by_M2": {str(k): v for k, v in btune.items()},
+                             "run_bytes": bchunk[0], "nt_inter": bchunk[1]}
         log(f"batched 256 products: {1e3 * eb / nb:.3f} ms eager, {1e3 * eg / nb:.3f} ms graph")
         del batch, bA, bplans, g
 

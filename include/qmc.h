@@ -144,11 +144,14 @@ int qmc_plan_tables(qmc_plan_t plan, int32_t* pow_out, int32_t* log_out,
  *                2 = dense: a gather pass collapses A into length-M columns and
  *                transforms the outer index (extra passes over M per pair,
  *                one stream); 0 = dense when s > 8 M1, else sparse
- *   outer_q      the outer radix: the outer DFT of length M2 (qmc_plan_info)
- *                is split as M2 = P2 x Q2 with Q2 = min(outer_q, M2) values
- *                per thread of the back pass and one extra split pass when
- *                P2 > 1; a power of two <= 64 with P2 <= 64, or 0 for the
- *                default (32, or M2/64 when larger)
+ *   outer_q      the outer radix: the outer inverse DFT of length M2
+ *                (qmc_plan_info) is split as M2 = P2 x Q2 with
+ *                Q2 = min(outer_q, M2) values of w2 per output column of the
+ *                back pass and one extra split pass when P2 > 1; Q2 <= 32 is
+ *                held in registers, 64 and 128 in LDS (128: FP32 plans only).
+ *                A power of two <= 128 with P2 <= 64, or 0 for the default
+ *                (32, or M2/64 when larger).  The dense fronts' forward split
+ *                uses min(Q2, 64)
  *   nt_inter     stores of the intermediate spectrum by the fused pass: 1 =
  *                cached, 2 = streaming (non-temporal), 0 = streaming when one
  *                launch's intermediate exceeds 128 MiB (it would not stay in
@@ -250,11 +253,25 @@ int qmc_dense_matmul(qmc_plan_t plan, const void* Y, int64_t ldy, const void* A,
  * and makes no host-to-device copies, so it can be captured in a HIP graph
  * and replayed.  Workspace: qmc_batch_workspace_size bytes, caller-owned.
  * Errors: QMC_ERR_ARG (bad arguments or mixed dtypes), QMC_ERR_WORKSPACE.
+ *
+ * qmc_batch_set_chunk splits each group into runs of consecutive products
+ * whose intermediate spectra (pairs x M complex values each) take at most
+ * chunk_bytes together, one set of launches per run, so that the
+ * intermediate can stay in the Infinity Cache between the passes that write
+ * and read it (a product larger than chunk_bytes runs alone; 0 = one run per
+ * group).  nt_inter chooses the stores of the intermediates as in
+ * qmc_tuning_t (0: streaming for runs whose intermediates exceed 128 MiB).  A
+ * new batch starts with QMC_BATCH_CHUNK_DEFAULT and nt_inter 0.  The runs
+ * share the workspace, whose size changes with the chunk: query it
+ * afterwards.  Uploads the new descriptors and synchronises `stream`.
+ * QMC_ERR_ARG for a negative chunk or nt_inter outside {0, 1, 2}.
  */
+#define QMC_BATCH_CHUNK_DEFAULT ((int64_t)256 << 20)
 typedef struct qmc_batch_s* qmc_batch_t;
 int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const int64_t* t,
                      const void* const* A, const int64_t* lda, void* const* X,
                      const int64_t* ldx, void* stream);
+int qmc_batch_set_chunk(qmc_batch_t batch, int64_t chunk_bytes, int nt_inter, void* stream);
 int qmc_batch_workspace_size(qmc_batch_t batch, size_t* bytes);
 int qmc_batch_run(qmc_batch_t batch, void* workspace, size_t workspace_bytes, void* stream);
 void qmc_batch_destroy(qmc_batch_t batch);

@@ -37,11 +37,13 @@ EXPORTED = [
     "qmc_dense_matmul", "qmc_batched_workspace_size", "qmc_matmul_batched", "qmc_strerror",
     "qmc_profile_enable", "qmc_profile_collect", "qmc_profile_slot_name",
     "qmc_plan_set_tuning", "qmc_plan_get_tuning",
-    "qmc_batch_create", "qmc_batch_workspace_size", "qmc_batch_run", "qmc_batch_destroy",
+    "qmc_batch_create", "qmc_batch_set_chunk", "qmc_batch_workspace_size", "qmc_batch_run",
+    "qmc_batch_destroy",
     "qmc_korobov_create", "qmc_korobov_destroy", "qmc_korobov_info", "qmc_korobov_set_chunk",
     "qmc_korobov_workspace_size", "qmc_korobov_plan", "qmc_korobov_matmul",
 ]
 PROF_SLOTS = 10
+BATCH_CHUNK_DEFAULT = 256 << 20  # QMC_BATCH_CHUNK_DEFAULT
 
 
 class QMCError(RuntimeError):
@@ -108,6 +110,7 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(i64), ctypes.POINTER(vp),
                                        ctypes.POINTER(i64), ctypes.POINTER(vp),
                                        ctypes.POINTER(i64), vp]
+        L.qmc_batch_set_chunk.argtypes = [vp, i64, ip, vp]
         L.qmc_batch_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
         L.qmc_batch_run.argtypes = [vp, vp, sz, vp]
         L.qmc_batch_destroy.argtypes = [vp]
@@ -396,7 +399,7 @@ class Batch:
     (torch.cuda.graph) and replayed.  The plans and tensors must stay alive."""
 
     def __init__(self, plans: Sequence[Plan], As: Sequence, Xs: Optional[Sequence] = None,
-                 stream=None):
+                 stream=None, chunk_bytes: Optional[int] = None):
         torch = _torch()
         self.plans = list(plans)
         self.As = list(As)
@@ -420,9 +423,27 @@ class Batch:
         _check(lib().qmc_batch_create(ctypes.byref(h), n, hs, tt, ap, la, xp, lx,
                                       _stream_handle(stream)), "qmc_batch_create")
         self._h = h
+        self._stream = stream
+        if chunk_bytes is not None:
+            self.set_chunk(chunk_bytes)
+        else:
+            self._alloc_workspace()
+
+    def _alloc_workspace(self) -> None:
+        torch = _torch()
         nb = ctypes.c_size_t()
-        _check(lib().qmc_batch_workspace_size(h, ctypes.byref(nb)), "qmc_batch_workspace_size")
+        _check(lib().qmc_batch_workspace_size(self._h, ctypes.byref(nb)),
+               "qmc_batch_workspace_size")
         self.workspace = torch.empty(max(1, nb.value), dtype=torch.uint8, device="cuda")
+
+    def set_chunk(self, chunk_bytes: int, nt_inter: int = 0) -> None:
+        """Runs of products whose intermediates take at most chunk_bytes
+        together (0: one run per layout group), with cached (1), streaming (2)
+        or automatic (0) stores of the intermediates; reallocates the
+        workspace."""
+        _check(lib().qmc_batch_set_chunk(self._h, int(chunk_bytes), int(nt_inter),
+                                         _stream_handle(self._stream)), "qmc_batch_set_chunk")
+        self._alloc_workspace()
 
     def run(self, stream=None) -> List:
         _check(lib().qmc_batch_run(self._h, ctypes.c_void_p(self.workspace.data_ptr()),

@@ -2,7 +2,8 @@
 
 For a plan and a column count t it times the candidate launch tunings of
 ``qmc_plan_set_tuning`` (sparse or dense outer front, outer radix, chunk of
-column pairs per pass, one or two streams, plain or non-temporal stores of X)
+column pairs per pass, one or two streams, plain or non-temporal stores of X
+and of the intermediate)
 on the GPU
 with HIP events, keeps the fastest, and caches the choice in a JSON file keyed
 by the GPU architecture and the plan's shape (rule, L, M, s, t, dtype).
@@ -17,14 +18,25 @@ CACHE = os.environ.get("QMC_AUTOTUNE_CACHE",
                        os.path.join(os.path.expanduser("~"), ".cache", "qmcfast", "autotune.json"))
 
 
-def candidates(pairs: int, M2: int = 1) -> List[Dict[str, int]]:
+def outer_radices(M2: int, qmax: int = 128) -> List[int]:
+    """outer_q values worth trying for an outer length M2: the default (0:
+    32 values of w2 per back-pass output column), 16, and the LDS back pass's
+    64 and 128 (up to qmax, the dtype's limit), as far as the split allows."""
+    return [0] + [q for q in (16, 64, 128)
+                  if M2 > 16 and q <= M2 and M2 // q <= 64 and q <= qmax]
+
+
+def qmax_of(plan) -> int:
+    return 128 if plan.torch_dtype.itemsize == 4 else 64
+
+
+def candidates(pairs: int, M2: int = 1, qmax: int = 128) -> List[Dict[str, int]]:
     """Sparse front: every chunk, one or two streams, plain or non-temporal
     stores of X.  Dense front (one stream): every chunk, both store kinds.
-    Each with cached or streaming stores of the intermediate, and where the
-    outer length M2 exceeds 16, with the outer radix (values per back-pass
-    thread) 16, 32 or 64 as far as the split allows."""
+    Each with cached or streaming stores of the intermediate and every outer
+    radix of ``outer_radices``."""
     chunks = [0] + [c for c in (8, 16, 32, 64, 128, 256, 512, 1024) if c < pairs]
-    qs = [0] + [q for q in (16, 64) if M2 > 16 and M2 // q <= 64 and q < M2]
+    qs = outer_radices(M2, qmax)
     out = []
     for q in qs:
         for ni in (1, 2):  # cached or streaming stores of the intermediate
@@ -102,7 +114,7 @@ def tune(plan, t: int, reps: int = 3, use_cache: bool = True,
     A = torch.randn((plan.s, t), dtype=plan.torch_dtype, device="cuda")
     X = torch.empty((plan.N, t), dtype=plan.torch_dtype, device="cuda")
     results = []
-    for cfg in (cands or candidates((t + 1) // 2, plan.info()["M2"])):
+    for cfg in (cands or candidates((t + 1) // 2, plan.info()["M2"], qmax_of(plan))):
         results.append((cfg, time_config(plan, A, X, cfg, reps)))
     best = min(results, key=lambda r: r[1])[0]
     plan.set_tuning(**best)
@@ -139,7 +151,7 @@ def tune_korobov(U, t: int, reps: int = 3, chunks=(0, 16, 32, 64, 128, 256)) -> 
     return best, results
 
 
-def tune_batch(plans, As, reps: int = 3, qs=(0, 16, 64)) -> Tuple[Dict[int, int], List]:
+def tune_batch(plans, As, reps: int = 3, qs=None) -> Tuple[Dict[int, int], List]:
     """Pick the outer radix of a batch's products by timing whole batched runs:
     for each outer length M2 in the batch, every admissible outer_q with the
     other products at the default; the products of one M2 form their own
@@ -170,8 +182,9 @@ def tune_batch(plans, As, reps: int = 3, qs=(0, 16, 64)) -> Tuple[Dict[int, int]
             continue
         group = [p for p in plans if p.info()["M2"] == m2]
         res = []
-        for oq in qs:
-            if oq and (oq >= m2 or m2 // oq > 64):
+        qmax = min(qmax_of(p) for p in group)
+        for oq in (qs if qs is not None else outer_radices(m2, qmax)):
+            if oq and (oq > m2 or m2 // oq > 64 or oq > qmax):
                 continue
             for p in group:
                 p.set_tuning(**{**p.get_tuning(), "outer_q": oq})
@@ -182,3 +195,28 @@ def tune_batch(plans, As, reps: int = 3, qs=(0, 16, 64)) -> Tuple[Dict[int, int]
         best[m2] = choice
         timings.append((m2, res))
     return best, timings
+
+
+def tune_batch_chunk(batch, reps: int = 3, chunks_mib=(128, 256, 384, 512),
+                     nts=(0, 2)) -> Tuple[Tuple[int, int], List]:
+    """Pick the run size of a batch (intermediates per run, in MiB) and the
+    store kind of its intermediates (automatic or streaming) by timing whole
+    runs of the batch; sets the fastest and returns ((chunk_bytes, nt_inter),
+    timings)."""
+    import torch
+    results = []
+    for mib in chunks_mib:
+        for nt in nts:
+            batch.set_chunk(mib << 20, nt)
+            batch.run()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                batch.run()
+            e1.record()
+            e1.synchronize()
+            results.append(((mib << 20, nt), e0.elapsed_time(e1) / reps))
+    best = min(results, key=lambda r: r[1])[0]
+    batch.set_chunk(*best)
+    return best, results

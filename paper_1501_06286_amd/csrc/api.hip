@@ -160,7 +160,7 @@ int qmc_plan_set_tuning(qmc_plan_t P, const qmc_tuning_t* tu) {
       tu->nt_inter < 0 || tu->nt_inter > 2)
     return QMC_ERR_ARG;
   Layout lay = P->lay;
-  const int rc = set_outer_split(lay, tu->outer_q);
+  const int rc = set_outer_split(lay, tu->outer_q, max_outer_q(P->dtype));
   if (rc != QMC_OK) return rc;
   P->lay = lay;
   P->tune = *tu;

@@ -140,6 +140,24 @@ __global__ __launch_bounds__(256) void kb_back(const BatchInst* __restrict__ D, 
   }
 }
 
+template <typename T, int Q>
+__global__ __launch_bounds__(256) void kb_back_lds(const BatchInst* __restrict__ D, int n,
+                                                   int64_t total, char* __restrict__ ws) {
+  __shared__ BackLdsSmem<T, Q> S;
+  InstCursor cur;
+  QMC_FOR_BLOCKS(b, total) {
+    const BatchInst I = D[inst_at(D, n, PASS_BACK, b, cur)];
+    const int64_t lb = b - I.off[PASS_BACK];
+    const int64_t bx = lb % I.gx_back, rest = lb / I.gx_back;
+    const int64_t by = rest % I.gy_back, a = rest / I.gy_back;
+    back_lds_body<T, Q, false, false>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2, I.L,
+                                      I.pairs, (const cx<T>*)I.twb, I.pow, nullptr, nullptr,
+                                      nullptr, (T)I.phi0, (T*)I.X, I.ldx, I.t, bx, by, a, S,
+                                      opaque_tid());
+    __syncthreads();
+  }
+}
+
 }  // namespace qmc
 
 using namespace qmc;
@@ -147,17 +165,89 @@ using namespace qmc;
 struct qmc_batch_s {
   int dtype = QMC_F32;
   size_t ws_bytes = 0;
+  int64_t chunk_bytes = 0;
+  int nt_inter = 0;  // stores of the intermediates: 0 auto, 1 cached, 2 streaming
+  // one run of products of one layout: a set of launches, one per pass
   struct Group {
     int R = 0, P2 = 1, Q2 = 1;
-    int nt_c = 0;  // streaming stores of the group's intermediate (too large for the cache)
+    int nt_c = 0;  // streaming stores of the run's intermediate (too large for the cache)
     int n = 0;
     BatchInst* d_desc = nullptr;
     int64_t total[NPASS] = {0, 0, 0, 0};
   };
   std::vector<Group> groups;
+  // the products by layout key (R, P2, Q2), in input order, for regrouping
+  std::vector<std::pair<int64_t, std::vector<BatchInst>>> byKey;
 };
 
 static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+
+static void free_runs(qmc_batch_s* B) {
+  for (auto& g : B->groups)
+    if (g.d_desc) hipFree(g.d_desc);
+  B->groups.clear();
+}
+
+// Splits every layout group into runs of consecutive products whose
+// intermediate spectra C together take at most `chunk` bytes (0: one run per
+// group; a product larger than `chunk` runs alone), so that C can stay in the
+// 256 MB Infinity Cache between the fused pass that writes it and the back
+// pass that reads it.  The runs execute one after another on one stream and
+// share the workspace from offset 0.  Uploads the descriptors and
+// synchronises `st`.
+static int build_runs(qmc_batch_s* B, int64_t chunk, int nt_inter, hipStream_t st) {
+  free_runs(B);
+  const size_t el = B->dtype == QMC_F32 ? sizeof(cx<float>) : sizeof(cx<double>);
+  size_t ws = 0;
+  for (auto& kv : B->byKey) {
+    const std::vector<BatchInst>& all = kv.second;
+    for (size_t i0 = 0; i0 < all.size();) {
+      size_t i1 = i0;
+      int64_t cbytes = 0;
+      while (i1 < all.size()) {
+        const int64_t c = all[i1].pairs * all[i1].M1 * all[i1].M2 * (int64_t)el;
+        if (chunk > 0 && i1 > i0 && cbytes + c > chunk) break;
+        cbytes += c;
+        ++i1;
+      }
+      std::vector<BatchInst> v(all.begin() + i0, all.begin() + i1);
+      i0 = i1;
+      size_t off = 0;
+      for (BatchInst& I : v) {
+        I.aT_off = (int64_t)off;
+        off += al256(I.pairs * I.Upad * el);
+        I.C_off = (int64_t)off;
+        off += al256(I.pairs * I.M1 * I.M2 * el);
+      }
+      ws = std::max(ws, off);
+      qmc_batch_s::Group g;
+      g.R = (int)(kv.first >> 32);
+      g.P2 = (int)((kv.first >> 16) & 0xffff);
+      g.Q2 = (int)(kv.first & 0xffff);
+      g.n = (int)v.size();
+      // streaming stores of C when it cannot stay in the cache anyway
+      g.nt_c = nt_inter ? (nt_inter == 2) : (cbytes > ((int64_t)128 << 20));
+      for (int p = 0; p < NPASS; ++p) {
+        int64_t o = 0;
+        for (BatchInst& I : v) {
+          I.off[p] = o;
+          o += I.nb[p];
+        }
+        g.total[p] = o;
+      }
+      if (hipMalloc(&g.d_desc, v.size() * sizeof(BatchInst)) != hipSuccess) return QMC_ERR_OOM;
+      B->groups.push_back(g);
+      int rc = hip_ok(hipMemcpyAsync(g.d_desc, v.data(), v.size() * sizeof(BatchInst),
+                                     hipMemcpyHostToDevice, st));
+      if (rc == QMC_OK) rc = hip_ok(hipStreamSynchronize(st));  // v is freed next
+      if (rc != QMC_OK) return rc;
+    }
+  }
+  B->ws_bytes = ws;
+  B->chunk_bytes = chunk;
+  B->nt_inter = nt_inter;
+  return QMC_OK;
+}
 
 extern "C" {
 
@@ -176,10 +266,8 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
   qmc_batch_s* B = new (std::nothrow) qmc_batch_s();
   if (!B) return QMC_ERR_OOM;
   B->dtype = dtype;
-  const size_t el = dtype == QMC_F32 ? sizeof(cx<float>) : sizeof(cx<double>);
   // products grouped by layout key (R, P2, Q2)
-  std::vector<std::pair<int64_t, std::vector<BatchInst>>> byKey;
-  size_t ws = 0;
+  auto& byKey = B->byKey;
   for (int i = 0; i < count; ++i) {
     const qmc_plan_s* P = plans[i];
     const Layout& lay = P->lay;
@@ -190,10 +278,6 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
     I.ldx = ldx ? ldx[i] : t[i];
     I.t = t[i];
     I.pairs = (t[i] + 1) / 2;
-    I.aT_off = (int64_t)ws;
-    ws += al256(I.pairs * P->Upad * el);
-    I.C_off = (int64_t)ws;
-    ws += al256(I.pairs * lay.M * el);
     I.it_ptr = P->d_it_ptr;
     I.it_jl = P->d_it_jl;
     I.it_e1 = P->d_it_e1;
@@ -219,8 +303,9 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
     I.nb[PASS_MIDDLE] = ((I.pairs + tpb - 1) / tpb) * lay.M2;
     I.gx_split = (lay.M1 + 63) / 64;
     I.nb[PASS_SPLIT] = lay.P2 > 1 ? I.gx_split * lay.Q2 * I.pairs : 0;
-    I.gx_back = (lay.M1 + 15) / 16;
-    I.gy_back = (I.pairs + 15) / 16;
+    const int64_t tb = lay.Q2 >= 64 ? 8 : 16;  // back tile (LDS or register outer DFT)
+    I.gx_back = (lay.M1 + tb - 1) / tb;
+    I.gy_back = (I.pairs + tb - 1) / tb;
     I.nb[PASS_BACK] = I.gx_back * I.gy_back * lay.P2;
     const int64_t key = ((int64_t)lay.R << 32) | ((int64_t)lay.P2 << 16) | lay.Q2;
     auto it = std::find_if(byKey.begin(), byKey.end(),
@@ -233,43 +318,7 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
     }
     it->second.push_back(I);
   }
-  B->ws_bytes = ws;
-  hipStream_t st = (hipStream_t)stream;
-  int rc = QMC_OK;
-  for (auto& kv : byKey) {
-    if (rc != QMC_OK) break;
-    std::vector<BatchInst>& v = kv.second;
-    qmc_batch_s::Group g;
-    g.R = (int)(kv.first >> 32);
-    g.P2 = (int)((kv.first >> 16) & 0xffff);
-    g.Q2 = (int)(kv.first & 0xffff);
-    g.n = (int)v.size();
-    {
-      // the group's intermediate spectra, written by the middle pass and read
-      // by the back pass: streaming stores when they cannot stay in the
-      // 256 MB Infinity Cache in between
-      const size_t elc = dtype == QMC_F32 ? sizeof(cx<float>) : sizeof(cx<double>);
-      int64_t cbytes = 0;
-      for (const BatchInst& I : v) cbytes += I.pairs * I.M1 * I.M2 * (int64_t)elc;
-      g.nt_c = cbytes > ((int64_t)128 << 20) ? 1 : 0;
-    }
-    for (int p = 0; p < NPASS; ++p) {
-      int64_t off = 0;
-      for (BatchInst& I : v) {
-        I.off[p] = off;
-        off += I.nb[p];
-      }
-      g.total[p] = off;
-    }
-    if (hipMalloc(&g.d_desc, v.size() * sizeof(BatchInst)) != hipSuccess) {
-      rc = QMC_ERR_OOM;
-      break;
-    }
-    B->groups.push_back(g);
-    rc = hip_ok(hipMemcpyAsync(g.d_desc, v.data(), v.size() * sizeof(BatchInst),
-                               hipMemcpyHostToDevice, st));
-    if (rc == QMC_OK) rc = hip_ok(hipStreamSynchronize(st));  // v is freed on return
-  }
+  const int rc = build_runs(B, QMC_BATCH_CHUNK_DEFAULT, 0, (hipStream_t)stream);
   if (rc != QMC_OK) {
     qmc_batch_destroy(B);
     return rc;
@@ -280,9 +329,13 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
 
 void qmc_batch_destroy(qmc_batch_t B) {
   if (!B) return;
-  for (auto& g : B->groups)
-    if (g.d_desc) hipFree(g.d_desc);
+  free_runs(B);
   delete B;
+}
+
+int qmc_batch_set_chunk(qmc_batch_t B, int64_t chunk_bytes, int nt_inter, void* stream) {
+  if (!B || chunk_bytes < 0 || nt_inter < 0 || nt_inter > 2) return QMC_ERR_ARG;
+  return build_runs(B, chunk_bytes, nt_inter, (hipStream_t)stream);
 }
 
 int qmc_batch_workspace_size(qmc_batch_t B, size_t* bytes) {
@@ -325,6 +378,7 @@ static int run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
   if (g.total[PASS_BACK]) {
     const unsigned gb = grid_for(g.total[PASS_BACK], 1024);
 #define QMC_KBB(QQ) kb_back<T, QQ><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws)
+#define QMC_KBL(QQ) kb_back_lds<T, QQ><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws)
     switch (g.Q2) {
       case 1: QMC_KBB(1); break;
       case 2: QMC_KBB(2); break;
@@ -332,9 +386,16 @@ static int run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
       case 8: QMC_KBB(8); break;
       case 16: QMC_KBB(16); break;
       case 32: QMC_KBB(32); break;
-      case 64: QMC_KBB(64); break;
+      case 64: QMC_KBL(64); break;
+      case 128:
+        if constexpr (sizeof(T) == 4) {
+          QMC_KBL(128);
+          break;
+        }
+        return QMC_ERR_UNSUPPORTED;
       default: return QMC_ERR_UNSUPPORTED;
     }
+#undef QMC_KBL
 #undef QMC_KBB
   }
   return QMC_OK;

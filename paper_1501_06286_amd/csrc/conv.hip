@@ -75,6 +75,24 @@ __global__ __launch_bounds__(256) void k_back(const cx<T>* __restrict__ C, int64
                                 t, blockIdx.x, blockIdx.y, blockIdx.z, S, threadIdx.x, epi);
 }
 
+template <typename T, int Q, bool ADJ, bool NT, bool EPI>
+__global__ __launch_bounds__(256) void k_back_lds(const cx<T>* __restrict__ C, int64_t M1,
+                                                  int64_t M2, int64_t P2, int64_t L, int64_t P,
+                                                  const cx<T>* __restrict__ twb,
+                                                  const int32_t* __restrict__ rowmap,
+                                                  const int32_t* __restrict__ inv_ptr,
+                                                  const int32_t* __restrict__ inv_j,
+                                                  const T* __restrict__ G0, T phi0,
+                                                  T* __restrict__ X, int64_t ldx, int64_t t,
+                                                  Epi<T> epi) {
+  __shared__ BackLdsSmem<T, Q> S;
+  int64_t bx, by, a;
+  back_lds_tile(blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z),
+                gridDim.x, gridDim.y, gridDim.z, bx, by, a);
+  back_lds_body<T, Q, ADJ, NT, EPI>(C, M1, M2, P2, L, P, twb, rowmap, inv_ptr, inv_j, G0, phi0,
+                                    X, ldx, t, bx, by, a, S, threadIdx.x, epi);
+}
+
 // the epilogue of row 0 (its values come from the fused pass's DC term)
 template <typename T>
 __global__ __launch_bounds__(256) void k_epi_row0(T* __restrict__ X, int64_t t, Epi<T> epi) {
@@ -188,17 +206,19 @@ static int launch_middle(const qmc_plan_s* P, const cx<T>* src, int64_t pairs, c
 template <typename T, int DIR>
 static int launch_split(const qmc_plan_s* P, cx<T>* C, int64_t pairs, int slot, hipStream_t st) {
   const Layout& lay = P->lay;
-  if (lay.P2 == 1) return QMC_OK;
-  dim3 grid((unsigned)((lay.M1 + 63) / 64), (unsigned)lay.Q2, (unsigned)pairs);
+  // the back pass's split (DIR = +1) or the dense fronts' (DIR = -1)
+  const int p2 = DIR > 0 ? lay.P2 : lay.Pf, q2 = DIR > 0 ? lay.Q2 : lay.Qf;
+  if (p2 == 1) return QMC_OK;
+  dim3 grid((unsigned)((lay.M1 + 63) / 64), (unsigned)q2, (unsigned)pairs);
   const cx<T>* twb = (const cx<T>*)P->d_twb;
   ProfScope ps(P, slot, st);
-  switch (lay.P2) {
-    case 2: k_outer_split<T, 2, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
-    case 4: k_outer_split<T, 4, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
-    case 8: k_outer_split<T, 8, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
-    case 16: k_outer_split<T, 16, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
-    case 32: k_outer_split<T, 32, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
-    case 64: k_outer_split<T, 64, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, lay.Q2, twb); break;
+  switch (p2) {
+    case 2: k_outer_split<T, 2, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, q2, twb); break;
+    case 4: k_outer_split<T, 4, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, q2, twb); break;
+    case 8: k_outer_split<T, 8, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, q2, twb); break;
+    case 16: k_outer_split<T, 16, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, q2, twb); break;
+    case 32: k_outer_split<T, 32, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, q2, twb); break;
+    case 64: k_outer_split<T, 64, DIR><<<grid, 64, 0, st>>>(C, lay.M1, lay.M2, q2, twb); break;
     default: return QMC_ERR_UNSUPPORTED;
   }
   return hip_ok(hipGetLastError());
@@ -209,8 +229,25 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
                        const int32_t* inv_j, const T* G0, T* X, int64_t ldx, int64_t t,
                        hipStream_t st, const Epi<T>& epi = Epi<T>()) {
   const Layout& lay = P->lay;
-  dim3 grid((unsigned)((lay.M1 + 15) / 16), (unsigned)((pairs + 15) / 16), (unsigned)lay.P2);
   ProfScope ps(P, ADJ ? PROF_ADJ_BACK : PROF_BACK, st);
+  if (lay.Q2 >= 64) {  // the outer factor through LDS, tiles of 8 e1 x 8 pairs
+    dim3 gl((unsigned)((lay.M1 + 7) / 8), (unsigned)((pairs + 7) / 8), (unsigned)lay.P2);
+#define QMC_BACKL(QQ)                                                                        \
+  k_back_lds<T, QQ, ADJ, NT, EPI><<<gl, 256, 0, st>>>(                                       \
+      C, lay.M1, lay.M2, lay.P2, P->L, pairs, (const cx<T>*)P->d_twb, P->d_pow, inv_ptr, inv_j, \
+      G0, (T)P->phi0, X, ldx, t, epi)
+    if (lay.Q2 == 64) {
+      QMC_BACKL(64);
+    } else if constexpr (sizeof(T) == 4) {
+      if (lay.Q2 != 128) return QMC_ERR_UNSUPPORTED;
+      QMC_BACKL(128);
+    } else {
+      return QMC_ERR_UNSUPPORTED;
+    }
+#undef QMC_BACKL
+    return hip_ok(hipGetLastError());
+  }
+  dim3 grid((unsigned)((lay.M1 + 15) / 16), (unsigned)((pairs + 15) / 16), (unsigned)lay.P2);
 #define QMC_BACK(QQ)                                                                          \
   k_back<T, QQ, ADJ, NT, EPI><<<grid, 256, 0, st>>>(C, lay.M1, lay.M2, lay.P2, P->L, pairs, P->d_pow, \
                                            inv_ptr, inv_j, G0, (T)P->phi0, X, ldx, t, epi)
@@ -221,7 +258,6 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
     case 8: QMC_BACK(8); break;
     case 16: QMC_BACK(16); break;
     case 32: QMC_BACK(32); break;
-    case 64: QMC_BACK(64); break;
     default: return QMC_ERR_UNSUPPORTED;
   }
 #undef QMC_BACK
@@ -370,19 +406,19 @@ template <typename T>
 static int launch_outer_front(const qmc_plan_s* P, const T* A, const T* G, int64_t ld,
                               int64_t t, int64_t pairs, cx<T>* B, hipStream_t st) {
   const Layout& lay = P->lay;
-  dim3 grid((unsigned)((lay.M1 + 15) / 16), (unsigned)((pairs + 15) / 16), (unsigned)lay.P2);
+  dim3 grid((unsigned)((lay.M1 + 15) / 16), (unsigned)((pairs + 15) / 16), (unsigned)lay.Pf);
   const cx<T>* twb = (const cx<T>*)P->d_twb;
   const bool fwd = A != nullptr;
   {
     ProfScope ps(P, fwd ? PROF_DFRONT : PROF_ADJ_FRONT, st);
 #define QMC_OFRONT(QQ)                                                                         \
   if (fwd)                                                                                     \
-    k_fwd_front<T, QQ><<<grid, 256, 0, st>>>(A, ld, t, lay.M1, lay.M2, lay.P2, P->L, pairs,   \
+    k_fwd_front<T, QQ><<<grid, 256, 0, st>>>(A, ld, t, lay.M1, lay.M2, lay.Pf, P->L, pairs,   \
                                              P->d_inv_ptr, P->d_inv_j, twb, B);               \
   else                                                                                         \
-    k_adj_front<T, QQ><<<grid, 256, 0, st>>>(G, ld, t, lay.M1, lay.M2, lay.P2, P->L, pairs,   \
+    k_adj_front<T, QQ><<<grid, 256, 0, st>>>(G, ld, t, lay.M1, lay.M2, lay.Pf, P->L, pairs,   \
                                              P->d_pow, twb, B)
-    switch (lay.Q2) {
+    switch (lay.Qf) {
       case 1: QMC_OFRONT(1); break;
       case 2: QMC_OFRONT(2); break;
       case 4: QMC_OFRONT(4); break;

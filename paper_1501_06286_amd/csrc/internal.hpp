@@ -16,7 +16,10 @@ struct Layout {
   int64_t M = 1, M1 = 1, M2 = 1;
   int R = 1;        // M1 = R * R * R, R <= 16
   int P2 = 1;       // outer inverse split M2 = P2 * Q2 (P2 = 1: single back pass)
-  int Q2 = 1;
+  int Q2 = 1;       // values of w2 per output column of the back pass (<= 64 in registers,
+                    // 64 and 128 through LDS)
+  int Pf = 1;       // outer forward split of the dense fronts M2 = Pf * Qf (Qf <= 64)
+  int Qf = 1;
 };
 
 // per-kernel timing slots (HIP events recorded around each launch when on)
@@ -96,7 +99,10 @@ namespace qmc {
 int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st);
 // split the outer length M2 = P2 Q2 with at most q values per back-pass
 // thread (q = 0: the default); QMC_ERR_ARG if q or the split is invalid
-int set_outer_split(Layout& lay, int q);
+int set_outer_split(Layout& lay, int q, int qmax);
+// the longest outer factor of the LDS back pass for a dtype (its tile of
+// Q x 64 values must fit 64 KB)
+inline int max_outer_q(int dtype) { return dtype == QMC_F32 ? 128 : 64; }
 int build_korobov_tables(qmc_korobov_s* U, hipStream_t st);
 
 // sparse collapse schedule for exponents l_j (j < s) on a layout: item u is

@@ -443,6 +443,54 @@ __device__ __forceinline__ void store_pair(T* p, T x, T y) {
     *reinterpret_cast<vec2_t<T>*>(p) = v;
 }
 
+// one output value pair o of group-order index e < L in column pair pairw:
+//   forward: X[rowmap[e]][2 pairw .. 2 pairw + 1] = f(o)  (f: the epilogue)
+//   adjoint: dA[j][...] = o + phi0 G[0][...] for every j with l_j = e
+// forward: the value pair o to X[r][2 pairw .. 2 pairw + 1], through the epilogue
+template <typename T, bool NT, bool EPI>
+__device__ __forceinline__ void put_row(cx<T> o, int64_t r, int64_t pairw, T* __restrict__ X,
+                                        int64_t ldx, int64_t t, bool v2, const EpiCols<T>& ec) {
+  const int64_t col = 2 * pairw;
+  const bool both = col + 1 < t;
+  T* row = X + r * ldx;
+  const T ox = EPI ? ec.f0(o.x) : o.x, oy = EPI ? ec.f1(o.y) : o.y;
+  if (v2 && both) {
+    store_pair<T, NT>(row + col, ox, oy);
+  } else if constexpr (NT) {
+    __builtin_nontemporal_store(ox, row + col);
+    if (both) __builtin_nontemporal_store(oy, row + col + 1);
+  } else {
+    row[col] = ox;
+    if (both) row[col + 1] = oy;
+  }
+}
+
+template <typename T, bool ADJ, bool NT, bool EPI>
+__device__ __forceinline__ void put_out(cx<T> o, int64_t e, int64_t pairw,
+                                        const int32_t* __restrict__ rowmap,
+                                        const int32_t* __restrict__ inv_ptr,
+                                        const int32_t* __restrict__ inv_j,
+                                        const T* __restrict__ G0, T phi0, T* __restrict__ X,
+                                        int64_t ldx, int64_t t, bool v2, const EpiCols<T>& ec) {
+  const int64_t col = 2 * pairw;
+  const bool both = col + 1 < t;
+  if constexpr (!ADJ) {
+    put_row<T, NT, EPI>(o, (int64_t)rowmap[e], pairw, X, ldx, t, v2, ec);
+  } else {
+    const T g0 = phi0 * G0[col];
+    const T g1 = both ? phi0 * G0[col + 1] : (T)0;
+    for (int32_t jj = inv_ptr[e]; jj < inv_ptr[e + 1]; ++jj) {
+      T* row = X + (int64_t)inv_j[jj] * ldx;
+      if (v2 && both) {
+        store_pair<T, false>(row + col, o.x + g0, o.y + g1);
+      } else {
+        row[col] = o.x + g0;
+        if (both) row[col + 1] = o.y + g1;
+      }
+    }
+  }
+}
+
 template <typename T, int Q, bool ADJ, bool NT, bool EPI = false>
 __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M1, int64_t M2,
                                           int64_t P2, int64_t L, int64_t P,
@@ -492,38 +540,158 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
         for (int c = 0; c < CH; ++c) {
           const int64_t e2 = a + P2 * (c0 + c);
           const int64_t e = e1w + M1 * e2;
-          if (e < L) {
-            const cx<T> o = sm[c][ew][pw];
-            const int64_t col = 2 * pairw;
-            const bool both = col + 1 < t;
-            if constexpr (!ADJ) {
-              T* row = X + (int64_t)rowmap[e] * ldx;
-              const T ox = EPI ? ec.f0(o.x) : o.x, oy = EPI ? ec.f1(o.y) : o.y;
-              if (v2 && both) {
-                store_pair<T, NT>(row + col, ox, oy);
-              } else if constexpr (NT) {
-                __builtin_nontemporal_store(ox, row + col);
-                if (both) __builtin_nontemporal_store(oy, row + col + 1);
-              } else {
-                row[col] = ox;
-                if (both) row[col + 1] = oy;
-              }
-            } else {
-              const T g0 = phi0 * G0[col];
-              const T g1 = both ? phi0 * G0[col + 1] : (T)0;
-              for (int32_t jj = inv_ptr[e]; jj < inv_ptr[e + 1]; ++jj) {
-                T* row = X + (int64_t)inv_j[jj] * ldx;
-                if (v2 && both) {
-                  store_pair<T, false>(row + col, o.x + g0, o.y + g1);
-                } else {
-                  row[col] = o.x + g0;
-                  if (both) row[col + 1] = o.y + g1;
-                }
-              }
-            }
-          }
+          if (e < L)
+            put_out<T, ADJ, NT, EPI>(sm[c][ew][pw], e, pairw, rowmap, inv_ptr, inv_j, G0, phi0,
+                                     X, ldx, t, v2, ec);
         }
       }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// B for a long outer factor (Q = 64 or 128 values of w2 per output column):
+// the same result as back_body<Q>, with the length-Q inverse DFT done as two
+// register passes through LDS instead of Q values per thread.  A workgroup
+// owns a tile of 8 e1 x 8 column pairs (64 "columns" k = e1l + 8 pl) for one
+// a and keeps the tile's Q x 64 values in LDS.  With Q = F1 F2,
+//   q = u + F2 v (u < F2, v < F1),   b = c + F1 d (c < F1, d < F2):
+//   pass 1, per (k, u): over v -> c, times W_Q^{u c}    (from global C)
+//   pass 2, per (k, c): over u -> d, in place in LDS    (slot u + F2 c)
+// then the rows e = e1 + M1 (a + P2 b) are written from LDS with the column
+// pairs fastest, so one row's 8 pairs leave as one 8-pair segment.  Thread
+// (pl, eo, w) writes the outputs b = w + 4 j of e1 = e1_0 + eo, pair pl.
+// ---------------------------------------------------------------------------
+template <int Q>
+struct BackLdsShape {
+  static constexpr int F1 = 8;
+  static constexpr int F2 = Q / F1;
+  static constexpr int TB = 8;  // e1 and column pairs per tile
+  static constexpr int K = TB * TB;
+  static constexpr int BLOCK = 256;
+  static_assert(F1 * F2 == Q && F2 % (BLOCK / K) == 0 && F1 % (BLOCK / K) == 0,
+                "outer factor split");
+};
+
+// Workgroup order of the LDS back pass: the workgroups of one XCD take a
+// contiguous run of logical tiles (xcd_remap), and inside it the tiles go in
+// pairs of column-pair tiles (by, by + 1) per e1 tile, e1 tiles next: the two
+// 8-pair halves of a 16-pair row segment of X, and the two 8-e1 halves of a
+// 16-e1 segment of C, are then handled by one L2 at about the same time.
+__device__ __forceinline__ void back_lds_tile(int64_t hw, int64_t gx, int64_t gy, int64_t gz,
+                                              int64_t& bx, int64_t& by, int64_t& a) {
+  const int64_t per = gx * gy;
+  const int64_t lg = xcd_remap(hw, per * gz);
+  a = lg / per;
+  const int64_t l = lg % per, full = (gy / 2) * 2 * gx;
+  if (l < full) {
+    const int64_t r = l % (2 * gx);
+    bx = r / 2;
+    by = 2 * (l / (2 * gx)) + r % 2;
+  } else {  // odd gy: the last row of pair tiles alone
+    bx = l - full;
+    by = gy - 1;
+  }
+}
+
+template <typename T, int Q>
+struct BackLdsSmem {
+  cx<T> v[Q * BackLdsShape<Q>::K];
+};
+
+template <typename T, int Q, bool ADJ, bool NT, bool EPI = false>
+__device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64_t M1, int64_t M2,
+                                              int64_t P2, int64_t L, int64_t P,
+                                              const cx<T>* __restrict__ twb,
+                                              const int32_t* __restrict__ rowmap,
+                                              const int32_t* __restrict__ inv_ptr,
+                                              const int32_t* __restrict__ inv_j,
+                                              const T* __restrict__ G0, T phi0,
+                                              T* __restrict__ X, int64_t ldx, int64_t t,
+                                              int64_t bx, int64_t by, int64_t a,
+                                              BackLdsSmem<T, Q>& S, int tid,
+                                              const Epi<T> epi = Epi<T>()) {
+  typedef BackLdsShape<Q> B;
+  constexpr int F1 = B::F1, F2 = B::F2, TB = B::TB, K = B::K, NW = B::BLOCK / K;
+  constexpr int T1 = F2 / NW, T2 = F1 / NW;  // pass-1 and pass-2 tasks per thread
+  constexpr int NO = Q / NW;                 // output values per thread
+  cx<T>* lds = S.v;
+  const int64_t e1_0 = bx * TB, p0 = by * TB;
+  const int k = tid % K, w = tid / K;  // this thread's column and its first task
+  // output mapping: column pair pl, e1 = e1_0 + eo, b = w + NW j
+  const int pl = tid % TB, eo = (tid / TB) % TB;
+  const int64_t e1o = e1_0 + eo, pairw = p0 + pl;
+  // Every global load of the workgroup is issued before the first use: the
+  // output rows (forward), then the tile of C; the workgroup then waits for
+  // memory once.
+  int32_t rows[ADJ ? 1 : NO];
+  if constexpr (!ADJ) {
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      const int64_t e = e1o + M1 * (a + P2 * (w + NW * j));
+      rows[j] = (e1o < M1 && e < L) ? rowmap[e] : -1;
+    }
+  }
+  {
+    const int64_t e1 = e1_0 + k % TB, pair = p0 + k / TB;
+    const bool ok = pair < P && e1 < M1;
+    const cx<T>* base = C + (ok ? pair : 0) * M2 * M1 + (ok ? e1 : 0) + Q * a * M1;
+    const int64_t tstep = M2 / Q;  // W_Q^{j} = twb[j M2 / Q]
+    // ---- pass 1: per u, the F1 values q = u + F2 v -------------------------
+    cx<T> v[T1][F1];
+#pragma unroll
+    for (int it = 0; it < T1; ++it) {
+      const int u = w + NW * it;
+#pragma unroll
+      for (int j = 0; j < F1; ++j) {
+        cx<T> c = {(T)0, (T)0};
+        if (ok) {  // C is dead after this read
+          const vec2_t<T> x = __builtin_nontemporal_load(
+              reinterpret_cast<const vec2_t<T>*>(base + (int64_t)(u + F2 * j) * M1));
+          c = {x.x, x.y};
+        }
+        v[it][j] = c;
+      }
+    }
+#pragma unroll
+    for (int it = 0; it < T1; ++it) {
+      const int u = w + NW * it;
+      reg_fft<T, F1, +1>(v[it]);
+#pragma unroll
+      for (int c = 1; c < F1; ++c)
+        v[it][c] = cmul(v[it][c], twb[(int64_t)(u * c) * tstep & (M2 - 1)]);
+#pragma unroll
+      for (int c = 0; c < F1; ++c) lds[(u + F2 * c) * K + k] = v[it][c];
+    }
+  }
+  __syncthreads();
+  // ---- pass 2: per c, the F2 values of slots u + F2 c, in place ------------
+#pragma unroll
+  for (int it = 0; it < T2; ++it) {
+    const int c = w + NW * it;
+    cx<T> v[F2];
+#pragma unroll
+    for (int u = 0; u < F2; ++u) v[u] = lds[(u + F2 * c) * K + k];
+    reg_fft<T, F2, +1>(v);
+#pragma unroll
+    for (int d = 0; d < F2; ++d) lds[(d + F2 * c) * K + k] = v[d];
+  }
+  __syncthreads();
+  // ---- rows: output b = c + F1 d sits in slot d + F2 c ---------------------
+  const bool v2 = pairs_aligned(X, ldx);
+  const EpiCols<T> ec(EPI ? epi : Epi<T>(), 2 * pairw, t);
+  if (pairw >= P) return;
+#pragma unroll
+  for (int j = 0; j < NO; ++j) {
+    const int b = w + NW * j;
+    const cx<T> o = lds[(b / F1 + F2 * (b % F1)) * K + eo + TB * pl];
+    if constexpr (!ADJ) {
+      if (rows[j] >= 0) put_row<T, NT, EPI>(o, rows[j], pairw, X, ldx, t, v2, ec);
+    } else {
+      const int64_t e = e1o + M1 * (a + P2 * b);
+      if (e1o < M1 && e < L)
+        put_out<T, ADJ, NT, EPI>(o, e, pairw, rowmap, inv_ptr, inv_j, G0, phi0, X, ldx, t, v2,
+                                 ec);
     }
   }
 }

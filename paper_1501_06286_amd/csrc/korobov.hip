@@ -69,6 +69,22 @@ __global__ __launch_bounds__(256) void ku_back(const cx<T>* __restrict__ C, int6
                                 rest / gy, S, threadIdx.x);
 }
 
+template <typename T, int Q>
+__global__ __launch_bounds__(256) void ku_back_lds(const cx<T>* __restrict__ C, int64_t M1,
+                                                   int64_t M2, int64_t P2, int64_t L, int64_t P,
+                                                   const cx<T>* __restrict__ twb,
+                                                   const int32_t* __restrict__ rowmap,
+                                                   T* __restrict__ X, int64_t ldx, int64_t t,
+                                                   int64_t block_rows, int64_t gx, int64_t gy,
+                                                   int64_t per_block) {
+  __shared__ BackLdsSmem<T, Q> S;
+  const int64_t b = blockIdx.x / per_block, lb = blockIdx.x % per_block;
+  const int64_t bx = lb % gx, rest = lb / gx;
+  back_lds_body<T, Q, false, false>(C + b * P * M1 * M2, M1, M2, P2, L, P, twb, rowmap, nullptr,
+                                    nullptr, nullptr, (T)0, X + b * block_rows * ldx, ldx, t,
+                                    bx, rest % gy, rest / gy, S, threadIdx.x);
+}
+
 static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
 static int64_t chunk_of(const qmc_korobov_s* U) {
@@ -146,13 +162,18 @@ static int korobov_forward(const qmc_korobov_s* U, const T* A, int64_t t, int64_
 #undef QMC_KSPLIT
     }
     {
-      const int64_t gx = (lay.M1 + 15) / 16, gy = (pairs + 15) / 16;
+      const int64_t tb = lay.Q2 >= 64 ? 8 : 16;  // back tile (LDS or register outer DFT)
+      const int64_t gx = (lay.M1 + tb - 1) / tb, gy = (pairs + tb - 1) / tb;
       const int64_t per_block = gx * gy * lay.P2;
       T* Xb = X + b0 * (K - 1) * ldx;
       ProfScope ps(P, PROF_BACK, st);
 #define QMC_KBACK(QQ)                                                                             \
   ku_back<T, QQ><<<dim3((unsigned)(nb * per_block)), 256, 0, st>>>(                               \
       C, lay.M1, lay.M2, lay.P2, P->L, pairs, U->d_rowmap, Xb, ldx, t, K - 1, gx, gy, per_block)
+#define QMC_KBACKL(QQ)                                                                            \
+  ku_back_lds<T, QQ><<<dim3((unsigned)(nb * per_block)), 256, 0, st>>>(                           \
+      C, lay.M1, lay.M2, lay.P2, P->L, pairs, (const cx<T>*)P->d_twb, U->d_rowmap, Xb, ldx, t,    \
+      K - 1, gx, gy, per_block)
       switch (lay.Q2) {
         case 1: QMC_KBACK(1); break;
         case 2: QMC_KBACK(2); break;
@@ -160,9 +181,16 @@ static int korobov_forward(const qmc_korobov_s* U, const T* A, int64_t t, int64_
         case 8: QMC_KBACK(8); break;
         case 16: QMC_KBACK(16); break;
         case 32: QMC_KBACK(32); break;
-        case 64: QMC_KBACK(64); break;
+        case 64: QMC_KBACKL(64); break;
+        case 128:
+          if constexpr (sizeof(T) == 4) {
+            QMC_KBACKL(128);
+            break;
+          }
+          return QMC_ERR_UNSUPPORTED;
         default: return QMC_ERR_UNSUPPORTED;
       }
+#undef QMC_KBACKL
 #undef QMC_KBACK
     }
     const int rc = hip_ok(hipGetLastError());

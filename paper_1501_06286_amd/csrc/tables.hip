@@ -392,28 +392,34 @@ static Layout choose_layout(int64_t L, int dtype, int* embedded) {
     *embedded = 1;
   }
   lay.M = M;
-  (void)dtype;
   const int rmax = 16;
   int R = 1;
   while (2 * R <= rmax && (int64_t)(2 * R) * (2 * R) * (2 * R) <= M) R *= 2;
   lay.R = R;
   lay.M1 = (int64_t)R * R * R;
   lay.M2 = M / lay.M1;
-  if (set_outer_split(lay, 0) != QMC_OK) lay.P2 = lay.Q2 = 0;  // too long: unsupported
+  if (set_outer_split(lay, 0, max_outer_q(dtype)) != QMC_OK)  // too long: unsupported
+    lay.P2 = lay.Q2 = lay.Pf = lay.Qf = 0;
   return lay;
 }
 
-int set_outer_split(Layout& lay, int q) {
-  // the outer inverse DFT of the back pass keeps Q2 values per thread and
-  // the split pass P2 = M2 / Q2, both at most 64.  The default q = 0 takes
-  // 32 (registers for an occupancy of 3-4; 64 fell to 1-2 and ran slower than
-  // an extra split pass at M2 = 512), more only when M2 > 32 * 64
-  if (q < 0 || q > 64 || (q & (q - 1))) return QMC_ERR_ARG;
-  const int64_t qmax = q > 0 ? q : std::max<int64_t>(32, lay.M2 / 64);
-  const int64_t Q2 = std::min<int64_t>(qmax, lay.M2);
-  if (Q2 > 64 || lay.M2 / Q2 > 64) return QMC_ERR_ARG;
+int set_outer_split(Layout& lay, int q, int qmax) {
+  // The outer inverse DFT of the back pass takes Q2 values of w2 per output
+  // column and the split pass P2 = M2 / Q2 (at most 64).  Q2 <= 32 stays in
+  // registers (32: occupancy 3-4), 64 and 128 go through LDS (qmax: what the
+  // LDS tile of the dtype allows).  The default q = 0 takes 32, more only when
+  // M2 > 32 * 64.  The dense fronts' forward split keeps at most 64 values
+  // per thread in registers: Qf = min(Q2, 64).
+  if (q < 0 || q > qmax || (q & (q - 1))) return QMC_ERR_ARG;
+  const int64_t qdef = std::max<int64_t>(32, lay.M2 / 64);
+  const int64_t Q2 = std::min<int64_t>(q > 0 ? q : qdef, lay.M2);
+  if (Q2 > qmax || lay.M2 / Q2 > 64) return QMC_ERR_ARG;
+  const int64_t Qf = std::min<int64_t>(Q2, 64);
+  if (lay.M2 / Qf > 64) return QMC_ERR_ARG;
   lay.Q2 = (int)Q2;
   lay.P2 = (int)(lay.M2 / Q2);
+  lay.Qf = (int)Qf;
+  lay.Pf = (int)(lay.M2 / Qf);
   return QMC_OK;
 }
 

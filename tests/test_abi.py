@@ -34,6 +34,15 @@ def test_library_exports_every_declared_symbol():
     assert set(_declared()) == set(q.EXPORTED)
 
 
+def test_header_constants_match_the_binding():
+    with open(os.path.join(ROOT, "include", "qmc.h")) as f:
+        text = f.read()
+    m = re.search(r"#define QMC_BATCH_CHUNK_DEFAULT \(\(int64_t\)(\d+) << (\d+)\)", text)
+    assert m and int(m.group(1)) << int(m.group(2)) == q.BATCH_CHUNK_DEFAULT
+    m = re.search(r"#define QMC_PROF_SLOTS (\d+)", text)
+    assert m and int(m.group(1)) == q.PROF_SLOTS
+
+
 def test_strerror_strings():
     L = q.lib()
     for code in range(0, -10, -1):

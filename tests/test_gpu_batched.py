@@ -42,6 +42,57 @@ def test_batch_mixed(dtype):
         assert torch.equal(X, X2)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_lds_back(dtype):
+    """Products whose back pass holds the outer factor in LDS (M2 = 128 with
+    Q2 = 64 after one split, or Q2 = 128 with none) batched beside
+    register-back products: each matches the oracle and its single product."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    N = 139999
+    insts = [qi.small_lattice(N, 100, t, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype,
+                              seed=20 + t) for t in (3, 19, 1)]
+    insts.append(qi.small_lattice(8209, 300, 9, phi=qi.PHI_INVNORM, shift=(1, 16418),
+                                  dtype=dtype, seed=7))
+    announce(f"batch lds back {dtype}")
+    plans = [plan_of(i) for i in insts]
+    qs = (64, 128 if dtype == "f32" else 64, 64, 0)
+    for p, oq in zip(plans, qs):
+        p.set_tuning(outer_q=oq)
+    As = [to_dev(i.A, dtype) for i in insts]
+    Xs = q.Batch(plans, As).run()
+    torch.cuda.synchronize()
+    for inst, p, A, X in zip(insts, plans, As, Xs):
+        assert_close(X.double().cpu().numpy(), oracle.matmul(inst), inst.A, inst, dtype, inst.name)
+        assert torch.equal(q.matmul(p, A), X)
+
+
+@pytest.mark.parametrize("chunk", [0, 1, 3 << 20])
+def test_batch_chunks(chunk):
+    """Runs of products sized by their intermediates (0: one run per layout
+    group; 1 byte: every product alone; 3 MiB: a few per run) give the same
+    bits as the single products, and the workspace shrinks with the chunk."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    insts = _instances("f32", seed=11)
+    announce(f"batch chunk {chunk}")
+    plans = [plan_of(i) for i in insts]
+    As = [to_dev(i.A, "f32") for i in insts]
+    b = q.Batch(plans, As, chunk_bytes=chunk)
+    ws = b.workspace.numel()
+    Xs = b.run()
+    torch.cuda.synchronize()
+    for p, A, X in zip(plans, As, Xs):
+        assert torch.equal(q.matmul(p, A), X)
+    b.set_chunk(0)
+    assert b.workspace.numel() >= ws
+    Xs0 = [X.clone() for X in b.run()]
+    torch.cuda.synchronize()
+    for X, X0 in zip(Xs, Xs0):
+        assert torch.equal(X, X0)
+    b.close()
+
+
 def test_batch_matches_single_products():
     torch = torch_cuda()
     import paper_1501_06286_amd as q
@@ -121,6 +172,9 @@ def test_batch_autotune_outer_radix():
         m2 = p.info()["M2"]
         if m2 in best:
             assert p.get_tuning()["outer_q"] == best[m2]
-    Xs = q.Batch(plans, As).run()
+    b = q.Batch(plans, As)
+    (chunk, nt), res = autotune.tune_batch_chunk(b, reps=1, chunks_mib=(1, 256))
+    assert (chunk, nt) in [c for c, _ in res]
+    Xs = b.run()
     for p, A, X in zip(plans, As, Xs):
         assert torch.equal(q.matmul(p, A), X)

@@ -87,16 +87,22 @@ def test_dense_front_matches_oracle_and_sparse(kind, n, s, t, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("q,front", [(0, 1), (2, 1), (16, 1), (64, 1), (64, 2), (4, 2)])
+@pytest.mark.parametrize("q,front", [(0, 1), (2, 1), (16, 1), (64, 1), (64, 2), (4, 2),
+                                     (128, 1), (128, 2)])
 def test_outer_radix(q, front, dtype):
     """Every split M2 = P2 x Q2 of the outer DFT (M = 2^19, M2 = 128) gives the
-    oracle's product and adjoint."""
+    oracle's product and adjoint; Q2 = 64 and 128 take the back pass that
+    holds the outer factor in LDS (128: FP32 only)."""
     torch = torch_cuda()
     import paper_1501_06286_amd as q_
     inst = qi.small_lattice(139999, 100, 5, phi=qi.PHI_INVNORM, shift=(1, 279998), dtype=dtype,
                             seed=9)
     announce(f"outer radix q={q} front={front} {dtype}")
     p = plan_of(inst)
+    if q == 128 and dtype == "f64":
+        with pytest.raises(q_.QMCError):
+            p.set_tuning(outer_q=q, front=front)
+        return
     p.set_tuning(outer_q=q, front=front)
     info = p.info()
     assert info["M2"] == 128 and info["P2"] * info["Q2"] == 128
@@ -116,26 +122,32 @@ def test_outer_radix_rejects_bad_values():
     torch_cuda()
     import paper_1501_06286_amd as q
     p = plan_of(qi.small_lattice(139999, 20, 2))  # M2 = 128
-    for bad in (3, 128, 1, -2):  # not a power of two, above 64, P2 = 128 > 64, negative
+    for bad in (3, 256, 1, -2):  # not a power of two, above 128, P2 = 128 > 64, negative
         with pytest.raises(q.QMCError):
             p.set_tuning(outer_q=bad)
     assert p.info()["Q2"] == 32  # unchanged by the rejected calls
 
 
-@pytest.mark.parametrize("ni", [1, 2])
-@pytest.mark.parametrize("chunk,front", [(0, 1), (5, 1), (0, 2), (3, 2)])
-def test_intermediate_store_kinds(ni, chunk, front):
-    """Cached and streaming stores of the intermediate give the same bits."""
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("q", [64, 128])
+@pytest.mark.parametrize("t", [37, 1])
+def test_lds_back_tiles(q, t, dtype):
+    """The LDS back pass over several and ragged tiles of 8 column pairs (t =
+    37: 19 pairs) and over one column, at M2 = 128 with one split (Q2 = 64)
+    and none (Q2 = 128, FP32 only), forward and adjoint."""
     torch = torch_cuda()
-    import paper_1501_06286_amd as q
-    inst = qi.small_lattice(8209, 300, 21, phi=qi.PHI_INVNORM, shift=(1, 16418), dtype="f32")
-    announce(f"intermediate stores {ni} chunk={chunk} front={front}")
+    import paper_1501_06286_amd as q_
+    if q == 128 and dtype == "f64":
+        pytest.skip("Q2 = 128 is FP32 only (rejected for FP64 in test_outer_radix)")
+    N = 139999
+    inst = qi.small_lattice(N, 60, t, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype, seed=4)
+    announce(f"lds back q={q} t={t} {dtype}")
     p = plan_of(inst)
-    A = to_dev(inst.A, "f32")
-    p.set_tuning(chunk_pairs=chunk, front=front, nt_inter=1)
-    X1 = q.matmul(p, A)
-    p.set_tuning(chunk_pairs=chunk, front=front, nt_inter=ni)
-    X2 = q.matmul(p, A)
+    p.set_tuning(outer_q=q)
+    X = q_.matmul(p, to_dev(inst.A, dtype))
+    G = np.random.default_rng(5).standard_normal((N, t))
+    dA = q_.matmul_adjoint(p, to_dev(G, dtype))
     torch.cuda.synchronize()
-    assert torch.equal(X1, X2)
-    assert_close(X2.double().cpu().numpy(), oracle.matmul(inst), inst.A, inst, "f32", "nt_inter")
+    assert_close(X.double().cpu().numpy(), oracle.matmul(inst), inst.A, inst, dtype, "forward")
+    Gr = G.astype(np.float32).astype(np.float64) if dtype == "f32" else G
+    assert_close(dA.double().cpu().numpy(), oracle.adjoint(inst, Gr), Gr, inst, dtype, "adjoint")
