@@ -173,6 +173,8 @@ def main():
     ap.add_argument("--no-pde", action="store_true")
     ap.add_argument("--fft-only", action="store_true",
                     help="time only the FFT path (for profiler runs)")
+    ap.add_argument("--dense-only", action="store_true",
+                    help="time only the dense MFMA GEMM baseline (for profiler runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (reference "
                          "for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -203,6 +205,21 @@ def main():
 
     dev = torch.device("cuda:0")
     inst = qi.make_c2(args.dtype, s=args.s)
+    if args.dense_only:
+        tdt = torch.float32 if args.dtype == "f32" else torch.float64
+        plan = q.Plan.from_instance(inst)
+        A = torch.from_numpy(inst.A).to(tdt).to(dev)
+        Y = q.explicit_points(plan)
+        Xd = torch.empty((inst.N, inst.t), dtype=tdt, device=dev)
+        dstep = lambda: q.dense_matmul(plan, Y, A, out=Xd)
+        for _ in range(args.warmup):
+            dstep()
+        ed = time_steps(dstep, args.steps, torch)
+        flops = 2.0 * inst.N * inst.s * inst.t
+        print(json.dumps({"dense_gemm_ms": round(1e3 * ed / args.steps, 3),
+                          "TFLOPs": round(flops / (ed / args.steps) / 1e12, 2),
+                          "workload": inst.name, "dtype": args.dtype}), flush=True)
+        return
     N, s, t = inst.N, inst.s, inst.t
     w = 4 if args.dtype == "f32" else 8
     tdt = torch.float32 if args.dtype == "f32" else torch.float64
