@@ -175,6 +175,8 @@ def main():
                     help="time only the FFT path (for profiler runs)")
     ap.add_argument("--dense-only", action="store_true",
                     help="time only the dense MFMA GEMM baseline (for profiler runs)")
+    ap.add_argument("--vendor-context", action="store_true",
+                    help="with --dense-only: also time torch.matmul of the same shape")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (reference "
                          "for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -216,9 +218,16 @@ def main():
             dstep()
         ed = time_steps(dstep, args.steps, torch)
         flops = 2.0 * inst.N * inst.s * inst.t
-        print(json.dumps({"dense_gemm_ms": round(1e3 * ed / args.steps, 3),
-                          "TFLOPs": round(flops / (ed / args.steps) / 1e12, 2),
-                          "workload": inst.name, "dtype": args.dtype}), flush=True)
+        out = {"dense_gemm_ms": round(1e3 * ed / args.steps, 3),
+               "TFLOPs": round(flops / (ed / args.steps) / 1e12, 2),
+               "workload": inst.name, "dtype": args.dtype}
+        if args.vendor_context:  # torch.matmul of the same shape, timing context only
+            Xv = torch.empty_like(Xd)
+            torch.matmul(Y, A, out=Xv)
+            ev = time_steps(lambda: torch.matmul(Y, A, out=Xv), args.steps, torch)
+            out["vendor_ms"] = round(1e3 * ev / args.steps, 3)
+            out["vendor_max_diff"] = float((Xv - Xd).abs().max())
+        print(json.dumps(out), flush=True)
         return
     N, s, t = inst.N, inst.s, inst.t
     w = 4 if args.dtype == "f32" else 8
@@ -451,12 +460,23 @@ def main():
         flops = 2.0 * N * s * t
         dval = N * t / (ed / nd)
         err = float((Xd - X).abs().max()) / (float(A.abs().sum(0).max()) * float(Y.abs().max()))
+        # the vendor library's GEMM of the same shape, as timing context only
+        # (torch.matmul; never part of the library's path)
+        Xv = torch.empty_like(Xd)
+        vstep = lambda: torch.matmul(Y, A, out=Xv)
+        vstep()
+        ev = time_steps(vstep, nd, torch)
         result["dense_gemm"] = {"value": dval, "ms_per_step": round(1e3 * ed / nd, 3),
                                 "TFLOPs": round(flops / (ed / nd) / 1e12, 2),
                                 "mfma_frac": round(flops / (ed / nd) / 1e12 / MFMA_PEAK_TFLOPS[args.dtype], 4),
                                 "fft_speedup": round(value / dval, 2),
-                                "max_norm_diff_vs_fft": err}
-        log(f"dense MFMA GEMM {1e3 * ed / nd:.2f} ms/step; speed-up {value / dval:.1f}x")
+                                "max_norm_diff_vs_fft": err,
+                                "vendor_context": {"what": "torch.matmul of the same Y and A",
+                                                   "ms_per_step": round(1e3 * ev / nd, 3),
+                                                   "TFLOPs": round(flops / (ev / nd) / 1e12, 2)}}
+        log(f"dense MFMA GEMM {1e3 * ed / nd:.2f} ms/step; speed-up {value / dval:.1f}x; "
+            f"vendor GEMM (context) {1e3 * ev / nd:.2f} ms")
+        del Xv
         del Y, Xd
 
     if not args.no_cpu:

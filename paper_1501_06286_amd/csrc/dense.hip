@@ -50,8 +50,9 @@ int launch_explicit_points(const qmc_plan_s* P, void* Y, int64_t ldy, hipStream_
 // ---------------------------------------------------------------------------
 // MFMA GEMM  X (M x Nc) = Y (M x K) A (K x Nc), row-major, FP32 or FP64.
 // 128 x 128 block tile, 4 wavefronts of 64 x 64, v_mfma 16x16x4 (FP32 or
-// FP64), K-tiles of 16 staged through LDS with a register prefetch of the
-// next tile.  Operand layout of the 16x16x4 MFMA: lane l supplies
+// FP64); K-tiles of BK (32 FP32, 16 FP64) staged through LDS, the next tile
+// prefetched into registers with 16-byte loads while the current one is
+// multiplied.  Operand layout of the 16x16x4 MFMA: lane l supplies
 // A[l % 16][l / 16] and B[l / 16][l % 16]; it receives D[4 (l / 16) + r][l % 16]
 // in FP32 and D[l / 16 + 4 r][l % 16] in FP64 (r = 0..3).
 // ---------------------------------------------------------------------------
@@ -74,24 +75,28 @@ struct Mfma<double> {
   static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
 };
 
+// 16 bytes of T
+template <typename T>
+struct alignas(16) Vec16 {
+  static constexpr int N = 16 / sizeof(T);
+  T v[N];
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t K, int64_t Nc,
                                               const T* __restrict__ Y, int64_t ldy,
                                               const T* __restrict__ A, int64_t lda,
-                                              T* __restrict__ X, int64_t ldx) {
+                                              T* __restrict__ X, int64_t ldx, int vec_ok) {
   typedef typename Mfma<T>::v4 v4;
-  constexpr int BM = 128, BN = 128, BK = 16, PAD = 4;
-  __shared__ T As[BK][BM + PAD];  // transposed: As[k][i]
-  __shared__ T Bs[BK][BN + PAD];
+  constexpr int BM = 128, BN = 128, VEC = Vec16<T>::N, BK = 8 * VEC, PAD = 4;
+  // per thread per K-tile: NA vectors of the Y tile, NB of the A tile
+  constexpr int NA = BM * BK / VEC / 256, NB = BK * BN / VEC / 256;
+  __shared__ alignas(16) T As[BK][BM + PAD];  // transposed: As[k][i]
+  __shared__ alignas(16) T Bs[BK][BN + PAD];    // rows of 16-byte multiples
   const int64_t bn0 = (int64_t)blockIdx.x * BN, bm0 = (int64_t)blockIdx.y * BM;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int wm = wave >> 1, wn = wave & 1;
   const int li = lane & 15, lk = lane >> 4;
-
-  // loader mapping: A tile rows (tid >> 1), k = (tid & 1) * 8 .. +8
-  const int ar = tid >> 1, ak = (tid & 1) * 8;
-  // B tile: k = tid >> 4, cols (tid & 15) * 8 .. +8
-  const int bk = tid >> 4, bc = (tid & 15) * 8;
 
   v4 acc[4][4];
 #pragma unroll
@@ -99,28 +104,62 @@ __global__ __launch_bounds__(256) void k_gemm(int64_t M, int64_t K, int64_t Nc,
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = v4{0, 0, 0, 0};
 
-  T ra[8], rb[8];
+  // vector c of the Y tile: row (tid + 256 c) / 8, k = VEC ((tid + 256 c) % 8)
+  // vector c of the A tile: k-row (tid + 256 c) / (BN / VEC), cols VEC (... % (BN / VEC))
+  Vec16<T> ra[NA], rb[NB];
+  // interior K-tiles of an interior block tile: 16-byte loads only
+  const bool inner = vec_ok && bm0 + BM <= M && bn0 + BN <= Nc;
+  auto load_vec = [&](int64_t k0) {
+#pragma unroll
+    for (int c = 0; c < NA; ++c) {
+      const int v = tid + 256 * c;
+      ra[c] = *reinterpret_cast<const Vec16<T>*>(Y + (bm0 + v / 8) * ldy + k0 + VEC * (v % 8));
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const int v = tid + 256 * c;
+      rb[c] = *reinterpret_cast<const Vec16<T>*>(A + (k0 + v / (BN / VEC)) * lda + bn0 +
+                                                 VEC * (v % (BN / VEC)));
+    }
+  };
+  auto load_any = [&](int64_t k0) {  // element loads with bounds checks
+#pragma unroll
+    for (int c = 0; c < NA; ++c) {
+      const int v = tid + 256 * c;
+      const int64_t gi = bm0 + v / 8, gk = k0 + VEC * (v % 8);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+        ra[c].v[e] = (gi < M && gk + e < K) ? Y[gi * ldy + gk + e] : (T)0;
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const int v = tid + 256 * c;
+      const int64_t gk = k0 + v / (BN / VEC), gj = bn0 + VEC * (v % (BN / VEC));
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+        rb[c].v[e] = (gk < K && gj + e < Nc) ? A[gk * lda + gj + e] : (T)0;
+    }
+  };
   auto load = [&](int64_t k0) {
-    const int64_t gi = bm0 + ar;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t gk = k0 + ak + q;
-      ra[q] = (gi < M && gk < K) ? Y[gi * ldy + gk] : (T)0;
-    }
-    const int64_t gk = k0 + bk;
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int64_t gj = bn0 + bc + q;
-      rb[q] = (gk < K && gj < Nc) ? A[gk * lda + gj] : (T)0;
-    }
+    if (inner && k0 + BK <= K)
+      load_vec(k0);
+    else
+      load_any(k0);
   };
   load(0);
   for (int64_t k0 = 0; k0 < K; k0 += BK) {
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < 8; ++q) As[ak + q][ar] = ra[q];
+    for (int c = 0; c < NA; ++c) {
+      const int v = tid + 256 * c;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) Bs[bk][bc + q] = rb[q];
+      for (int e = 0; e < VEC; ++e) As[VEC * (v % 8) + e][v / 8] = ra[c].v[e];
+    }
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const int v = tid + 256 * c;
+      *reinterpret_cast<Vec16<T>*>(&Bs[v / (BN / VEC)][VEC * (v % (BN / VEC))]) = rb[c];
+    }
     __syncthreads();
     if (k0 + BK < K) load(k0 + BK);
 #pragma unroll
@@ -153,12 +192,16 @@ int launch_dense_gemm(int dtype, int64_t M, int64_t K, int64_t Nc, const void* Y
   const int64_t gx = (Nc + 127) / 128, gy = (M + 127) / 128;
   if (gy > 65535 || gx > 65535) return QMC_ERR_UNSUPPORTED;
   dim3 grid((unsigned)gx, (unsigned)gy);
+  // 16-byte loads need 16-byte aligned rows of Y and A
+  const size_t w = dtype == QMC_F32 ? 4 : 8;
+  const int vec_ok = ((uintptr_t)Y % 16 == 0) && ((uintptr_t)A % 16 == 0) &&
+                     ((ldy * w) % 16 == 0) && ((lda * w) % 16 == 0);
   if (dtype == QMC_F32)
     k_gemm<float><<<grid, 256, 0, st>>>(M, K, Nc, (const float*)Y, ldy, (const float*)A, lda,
-                                        (float*)X, ldx);
+                                        (float*)X, ldx, vec_ok);
   else
     k_gemm<double><<<grid, 256, 0, st>>>(M, K, Nc, (const double*)Y, ldy, (const double*)A, lda,
-                                         (double*)X, ldx);
+                                         (double*)X, ldx, vec_ok);
   return hip_ok(hipGetLastError());
 }
 

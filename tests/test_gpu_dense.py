@@ -22,7 +22,8 @@ def test_explicit_points_bit_exact(rule):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-@pytest.mark.parametrize("N,s,t", [(7, 3, 3), (257, 100, 129), (2003, 500, 1), (4099, 1000, 300)])
+@pytest.mark.parametrize("N,s,t", [(7, 3, 3), (257, 100, 129), (2003, 500, 1), (4099, 1000, 300),
+                                   (1021, 77, 45), (4099, 256, 256)])
 def test_dense_gemm(N, s, t, dtype):
     torch_cuda()
     import paper_1501_06286_amd as q
