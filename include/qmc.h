@@ -132,9 +132,10 @@ int qmc_plan_tables(qmc_plan_t plan, int32_t* pow_out, int32_t* log_out,
 
 /*
  * Launch tuning of a plan (chosen by paper_1501_06286_amd/autotune.py):
- *   chunk_pairs  column pairs per chunk of the passes of qmc_matmul; the
- *                intermediate spectrum buffers then hold one or two chunks
- *                instead of all pairs (0 = one chunk of all pairs)
+ *   chunk_pairs  column pairs per chunk of the passes of qmc_matmul and
+ *                qmc_matmul_adjoint; the intermediate spectrum buffers then
+ *                hold one or two chunks instead of all pairs (0 = one chunk
+ *                of all pairs)
  *   streams      1, or 2 to run the back pass of chunk c on a second stream,
  *                overlapping the fused pass of chunk c+1 (needs chunk_pairs > 0)
  *   nt_store     1 = write X with non-temporal stores
@@ -154,8 +155,9 @@ int qmc_plan_tables(qmc_plan_t plan, int32_t* pow_out, int32_t* log_out,
  *                uses min(Q2, 64)
  *   nt_inter     stores of the intermediate spectrum by the fused pass: 1 =
  *                cached, 2 = streaming (non-temporal), 0 = streaming when one
- *                launch's intermediate exceeds 128 MiB (it would not stay in
- *                the Infinity Cache for the back pass anyway)
+ *                launch's intermediates (with the dense fronts: both
+ *                buffers) exceed 128 MiB (they would not stay in the
+ *                Infinity Cache for the back pass anyway)
  * The workspace size depends on the tuning: query it after setting it.
  * Returns QMC_ERR_ARG for negative chunks, streams outside {1, 2}, nt_store
  * outside {0, 1}, front outside {0, 1, 2}, an invalid outer_q or nt_inter

@@ -150,15 +150,19 @@ bool dense_front(const qmc_plan_s* P) {
 }
 
 // whether the fused pass writes the intermediate spectrum C with streaming
-// stores (tuning nt_inter: 0 = when C of one launch, c_bytes, is too large to
-// stay in the 256 MB Infinity Cache for the back pass, 1 = never, 2 = always)
+// stores (tuning nt_inter: 0 = when the intermediates of one launch, c_bytes
+// (C, and B with the dense fronts), are too large to stay in the 256 MB
+// Infinity Cache for the back pass, 1 = never, 2 = always)
 static bool nt_inter(const qmc_plan_s* P, int64_t c_bytes) {
   if (P->tune.nt_inter != 0) return P->tune.nt_inter == 2;
   return c_bytes > ((int64_t)128 << 20);
 }
 
-// column pairs per chunk of the adjoint
-static int64_t adj_chunk(const qmc_plan_s*, int64_t pairs) { return pairs; }
+// column pairs per chunk of the adjoint: the tuning's chunk, as for the
+// forward product (B and C of a chunk then stay in the Infinity Cache)
+static int64_t adj_chunk(const qmc_plan_s* P, int64_t pairs) {
+  return (P->tune.chunk_pairs > 0 && P->tune.chunk_pairs < pairs) ? P->tune.chunk_pairs : pairs;
+}
 
 size_t workspace_bytes(const qmc_plan_s* P, int64_t t) {
   const size_t el = (P->dtype == QMC_F32) ? sizeof(cx<float>) : sizeof(cx<double>);
@@ -185,7 +189,7 @@ static void launch_middle_r(const qmc_plan_s* P, const cx<T>* src, int64_t pairs
       (const cx<T>*)P->d_twf2, (const cx<T>*)P->d_Hs,
       (const cx<T>*)P->d_twi3,
       (const cx<T>*)P->d_two, lay.M2, pairs, C, X, t, (T)P->phi0,
-      nt_inter(P, pairs * lay.M * (int64_t)sizeof(cx<T>)) ? 1 : 0);
+      nt_inter(P, (SPARSE ? 1 : 2) * pairs * lay.M * (int64_t)sizeof(cx<T>)) ? 1 : 0);
 }
 
 // X != nullptr: forward product, the DC term of each pair goes to row 0
@@ -436,9 +440,9 @@ static int launch_outer_front(const qmc_plan_s* P, const T* A, const T* G, int64
 }
 
 // dA = Y^T G: gather and transform G into B, the fused pass into C, the
-// outer split and the read-back at the exponents l_j.  All column pairs in
-// one chunk (chunks that keep B and C in the Infinity Cache measured no
-// faster: these passes are not bound by the intermediate traffic).
+// outer split and the read-back at the exponents l_j, per chunk of column
+// pairs (chunks too small to fill the GPU, under about 128 pairs at M1 =
+// 4096, run slower than one chunk).
 template <typename T>
 static int adjoint_t(const qmc_plan_s* P, const T* G, int64_t t, int64_t ldg, T* dA,
                      int64_t ldda, void* ws, hipStream_t st) {

@@ -33,6 +33,28 @@ def test_tuned_forward(chunk, streams, nt, front, dtype):
     assert_close(X1.double().cpu().numpy(), oracle.matmul(inst), inst.A, inst, dtype, "tuned")
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("chunk", [0, 1, 5, 16])
+def test_chunked_adjoint(chunk, dtype):
+    """The adjoint in chunks of column pairs (chunk_pairs applies to it too;
+    17 pairs: ragged chunks) matches the oracle and the unchunked adjoint."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    N, s, t = 8209, 400, 33
+    inst = qi.small_lattice(N, s, t, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype, seed=3)
+    announce(f"chunked adjoint chunk={chunk} {dtype}")
+    p = plan_of(inst)
+    G = np.random.default_rng(8).standard_normal((N, t))
+    Gd = to_dev(G, dtype)
+    dA0 = q.matmul_adjoint(p, Gd)
+    p.set_tuning(chunk_pairs=chunk)
+    dA = q.matmul_adjoint(p, Gd)
+    torch.cuda.synchronize()
+    assert torch.equal(dA, dA0)
+    Gr = G.astype(np.float32).astype(np.float64) if dtype == "f32" else G
+    assert_close(dA.double().cpu().numpy(), oracle.adjoint(inst, Gr), Gr, inst, dtype, "adjoint")
+
+
 def test_tuning_rejects_bad_values():
     torch_cuda()
     import paper_1501_06286_amd as q
