@@ -26,6 +26,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "Y*A entries/sec (N*t per s), FFT vs dense GEMM, N=65537 s=t=4096; HBM GB/s"
+# The paper's own timings (Section 4, Experiment 1, Table 1: mean of 5 runs) on
+# its hardware, for the shape closest to the Gaussian workload, as entries/s
+# = N t / time: another machine and another shape, context only.
+PAPER_CONTEXT = {
+    "source": "Section 4, Table 1", "hardware": "Intel Xeon E5-2650v2 2.6 GHz, Matlab R2013b",
+    "shape": "N=64007, s=t=1000, normal points",
+    "fast_s": 9.827, "std_s": 8.349,
+    "fast_entries_per_s": round(64007 * 1000 / 9.827), "std_entries_per_s": round(64007 * 1000 / 8.349),
+}
 HBM_PEAK_GBPS = 8000.0
 # FP32 vector FMA peak without packed FP32 instructions (which this build does
 # not use): 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s
@@ -312,6 +321,7 @@ def main():
         "hbm_GBps_algorithmic": round(alg_bytes / (elapsed / args.steps) / 1e9, 1),
         "roofline": roof,
         "kernels": kernels,
+        "paper_context": PAPER_CONTEXT,
     }
 
     if not args.no_f64 and args.dtype == "f32":
