@@ -26,6 +26,17 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
   return (xcd < rem) ? xcd * (q + 1) + idx : rem * (q + 1) + (xcd - rem) * q + idx;
 }
 
+// two adjacent values of T as one vector access
+template <typename T>
+using vec2_t = T __attribute__((ext_vector_type(2)));
+
+// whether element pairs (2k, 2k+1) of every row of a row-major matrix are
+// aligned for one vector access
+template <typename T>
+__device__ __forceinline__ bool pairs_aligned(const T* p, int64_t ld) {
+  return (ld % 2 == 0) && (reinterpret_cast<uintptr_t>(p) % (2 * sizeof(T)) == 0);
+}
+
 // ---------------------------------------------------------------------------
 // T: aT[pair][u] = sum over the rows j of item u of
 //                  A[j, 2 pair] + i A[j, 2 pair + 1]   (0 for padding)
@@ -44,20 +55,37 @@ __device__ __forceinline__ void collapse_body(const T* __restrict__ A, int64_t l
   auto& sm = S.sm;
   const int64_t u0 = bx * 64, p0 = by * 16;
   const int pl = tid & 15;
+  const int64_t c = 2 * (p0 + pl);  // this thread's columns c, c + 1
+  const bool pc = p0 + pl < P, both = c + 1 < t;
+  const bool v2 = both && pairs_aligned(A, lda);
+  auto row_pair = [&](int32_t j) -> cx<T> {
+    const T* row = A + (int64_t)j * lda + c;
+    if (v2) {
+      const vec2_t<T> w = *reinterpret_cast<const vec2_t<T>*>(row);
+      return {w.x, w.y};
+    }
+    return {row[0], both ? row[1] : (T)0};
+  };
+  // the four items of this thread: bounds, then each item's first row, then
+  // the rest (an item has one row unless exponents collide), so the loads of
+  // the four items are in flight together
+  int32_t kb[4], ke[4], j0[4];
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int ul = (tid >> 4) + 16 * i;
-    const int64_t u = u0 + ul, p = p0 + pl;
-    cx<T> v = {(T)0, (T)0};
-    if (u < Upad && p < P) {
-      const int64_t c = 2 * p;
-      for (int32_t k = it_ptr[u]; k < it_ptr[u + 1]; ++k) {
-        const T* row = A + (int64_t)it_jl[k] * lda;
-        v.x += row[c];
-        if (c + 1 < t) v.y += row[c + 1];
-      }
-    }
-    sm[ul][pl] = v;
+    const int64_t u = u0 + (tid >> 4) + 16 * i;
+    const bool ok = u < Upad && pc;
+    kb[i] = ok ? it_ptr[u] : 0;
+    ke[i] = ok ? it_ptr[u + 1] : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) j0[i] = kb[i] < ke[i] ? it_jl[kb[i]] : -1;
+  cx<T> v[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) v[i] = j0[i] >= 0 ? row_pair(j0[i]) : cx<T>{(T)0, (T)0};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    for (int32_t k = kb[i] + 1; k < ke[i]; ++k) v[i] = v[i] + row_pair(it_jl[k]);
+    sm[(tid >> 4) + 16 * i][pl] = v[i];
   }
   __syncthreads();
   const int ul = tid & 63;
@@ -157,8 +185,6 @@ template <typename T>
 struct alignas(4 * sizeof(T)) cx2 {
   cx<T> a, b;
 };
-template <typename T>
-using vec2_t = T __attribute__((ext_vector_type(2)));
 
 // v[h] = table value h of thread q, h = 0..R-1
 template <typename T, int R>
@@ -428,12 +454,6 @@ struct BackSmem {
   cx<T> sm[BACK_CH][16][17];
 };
 
-// whether element pairs (2k, 2k+1) of every row of a row-major matrix are
-// aligned for one vector access
-template <typename T>
-__device__ __forceinline__ bool pairs_aligned(const T* p, int64_t ld) {
-  return (ld % 2 == 0) && (reinterpret_cast<uintptr_t>(p) % (2 * sizeof(T)) == 0);
-}
 template <typename T, bool NT>
 __device__ __forceinline__ void store_pair(T* p, T x, T y) {
   const vec2_t<T> v = {x, y};
