@@ -749,13 +749,20 @@ struct RowPairReader {  // columns 2 pair, 2 pair + 1 of a row-major matrix
   }
 };
 
+// The gathers run in three steps so that a thread's loads for several m are
+// in flight together: bounds(m) (the first table lookup), first(b) (the
+// first row), value(b, row, pair).
 template <typename T>
 struct AdjGather {
   RowPairReader<T> G;
   const int32_t* __restrict__ pow;
   int64_t L;
-  __device__ __forceinline__ cx<T> operator()(int64_t m, int64_t pair) const {
-    return G((int64_t)pow[(L - m) % L], pair);
+  __device__ __forceinline__ int2 bounds(int64_t m) const {
+    return {pow[(L - m) % L], 0};
+  }
+  __device__ __forceinline__ int32_t first(int2 b) const { return b.x; }
+  __device__ __forceinline__ cx<T> value(int2, int32_t row, int64_t pair) const {
+    return G(row, pair);
   }
 };
 
@@ -765,10 +772,16 @@ struct FwdGather {
   const int32_t* __restrict__ inv_ptr;
   const int32_t* __restrict__ inv_j;
   int64_t L;
-  __device__ __forceinline__ cx<T> operator()(int64_t m, int64_t pair) const {
+  __device__ __forceinline__ int2 bounds(int64_t m) const {
     const int64_t e = (L - m) % L;
+    return {inv_ptr[e], inv_ptr[e + 1]};
+  }
+  __device__ __forceinline__ int32_t first(int2 b) const { return b.x < b.y ? inv_j[b.x] : -1; }
+  __device__ __forceinline__ cx<T> value(int2 b, int32_t row, int64_t pair) const {
     cx<T> acc = {(T)0, (T)0};
-    for (int32_t jj = inv_ptr[e]; jj < inv_ptr[e + 1]; ++jj) acc = acc + A(inv_j[jj], pair);
+    if (row < 0) return acc;
+    acc = A(row, pair);
+    for (int32_t jj = b.x + 1; jj < b.y; ++jj) acc = acc + A(inv_j[jj], pair);
     return acc;
   }
 };
@@ -790,13 +803,18 @@ __device__ __forceinline__ void outer_front_body(const Gather& gather, int64_t M
 #pragma unroll
   for (int c0 = 0; c0 < Q; c0 += CH) {
     __syncthreads();
+    int2 bd[CH];
+    int32_t row[CH];
 #pragma unroll
     for (int c = 0; c < CH; ++c) {
       const int64_t e = e1w + M1 * (a + P2 * (c0 + c));
-      cx<T> g = {(T)0, (T)0};
-      if (pairw < P && e1w < M1 && e < L) g = gather(e, pairw);
-      sm[c][ew][pw] = g;
+      bd[c] = (pairw < P && e1w < M1 && e < L) ? gather.bounds(e) : int2{-1, -1};
     }
+#pragma unroll
+    for (int c = 0; c < CH; ++c) row[c] = bd[c].x >= 0 ? gather.first(bd[c]) : -1;
+#pragma unroll
+    for (int c = 0; c < CH; ++c)
+      sm[c][ew][pw] = row[c] >= 0 ? gather.value(bd[c], row[c], pairw) : cx<T>{(T)0, (T)0};
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < CH; ++c) v[c0 + c] = sm[c][el][pl];
