@@ -1,6 +1,6 @@
 """GPU parity of the forward product X = Y A against the CPU oracle.
 
-Tolerance (the benchmark spec): max_n |X - X_oracle| <= tau max|Y| ||A[:, k]||_1 per
+Tolerance: max_n |X - X_oracle| <= tau max|Y| ||A[:, k]||_1 per
 column k, tau = 1e-12 in FP64 and 1e-5 in FP32; the oracle reads the same
 (already rounded) A.  Integer tables are compared bit for bit.
 """
