@@ -265,8 +265,10 @@ int qmc_dense_matmul(qmc_plan_t plan, const void* Y, int64_t ldy, const void* A,
  * qmc_tuning_t (0: streaming for runs whose intermediates exceed 128 MiB).  A
  * new batch starts with QMC_BATCH_CHUNK_DEFAULT and nt_inter 0.  The runs
  * share the workspace, whose size changes with the chunk: query it
- * afterwards.  Uploads the new descriptors and synchronises `stream`.
- * QMC_ERR_ARG for a negative chunk or nt_inter outside {0, 1, 2}.
+ * afterwards.  Uploads the new descriptors and synchronises `stream`; the
+ * old descriptors are freed, so no run of the batch may be in flight (and a
+ * graph that captured a run must be captured again).  QMC_ERR_ARG for a
+ * negative chunk or nt_inter outside {0, 1, 2}.
  */
 #define QMC_BATCH_CHUNK_DEFAULT ((int64_t)256 << 20)
 typedef struct qmc_batch_s* qmc_batch_t;
