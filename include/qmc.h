@@ -268,7 +268,9 @@ int qmc_dense_matmul(qmc_plan_t plan, const void* Y, int64_t ldy, const void* A,
  * afterwards.  Uploads the new descriptors and synchronises `stream`; the
  * old descriptors are freed, so no run of the batch may be in flight (and a
  * graph that captured a run must be captured again).  QMC_ERR_ARG for a
- * negative chunk or nt_inter outside {0, 1, 2}.
+ * negative chunk or nt_inter outside {0, 1, 2}; after any other failure the
+ * batch holds no runs and qmc_batch_run returns QMC_ERR_ARG until a
+ * regrouping succeeds.
  */
 #define QMC_BATCH_CHUNK_DEFAULT ((int64_t)256 << 20)
 typedef struct qmc_batch_s* qmc_batch_t;

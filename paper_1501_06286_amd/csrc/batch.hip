@@ -167,6 +167,7 @@ struct qmc_batch_s {
   size_t ws_bytes = 0;
   int64_t chunk_bytes = 0;
   int nt_inter = 0;  // stores of the intermediates: 0 auto, 1 cached, 2 streaming
+  bool ready = false;  // the runs are built (a failed regrouping leaves none)
   // one run of products of one layout: a set of launches, one per pass
   struct Group {
     int R = 0, P2 = 1, Q2 = 1;
@@ -197,6 +198,7 @@ static void free_runs(qmc_batch_s* B) {
 // synchronises `st`.
 static int build_runs(qmc_batch_s* B, int64_t chunk, int nt_inter, hipStream_t st) {
   free_runs(B);
+  B->ready = false;
   const size_t el = B->dtype == QMC_F32 ? sizeof(cx<float>) : sizeof(cx<double>);
   size_t ws = 0;
   for (auto& kv : B->byKey) {
@@ -235,17 +237,24 @@ static int build_runs(qmc_batch_s* B, int64_t chunk, int nt_inter, hipStream_t s
         }
         g.total[p] = o;
       }
-      if (hipMalloc(&g.d_desc, v.size() * sizeof(BatchInst)) != hipSuccess) return QMC_ERR_OOM;
+      if (hipMalloc(&g.d_desc, v.size() * sizeof(BatchInst)) != hipSuccess) {
+        free_runs(B);
+        return QMC_ERR_OOM;
+      }
       B->groups.push_back(g);
       int rc = hip_ok(hipMemcpyAsync(g.d_desc, v.data(), v.size() * sizeof(BatchInst),
                                      hipMemcpyHostToDevice, st));
       if (rc == QMC_OK) rc = hip_ok(hipStreamSynchronize(st));  // v is freed next
-      if (rc != QMC_OK) return rc;
+      if (rc != QMC_OK) {
+        free_runs(B);
+        return rc;
+      }
     }
   }
   B->ws_bytes = ws;
   B->chunk_bytes = chunk;
   B->nt_inter = nt_inter;
+  B->ready = true;
   return QMC_OK;
 }
 
@@ -421,7 +430,7 @@ static int run_group(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
 extern "C" {
 
 int qmc_batch_run(qmc_batch_t B, void* workspace, size_t workspace_bytes, void* stream) {
-  if (!B) return QMC_ERR_ARG;
+  if (!B || !B->ready) return QMC_ERR_ARG;
   if (!workspace || workspace_bytes < B->ws_bytes) return QMC_ERR_WORKSPACE;
   hipStream_t st = (hipStream_t)stream;
   for (const auto& g : B->groups) {
