@@ -69,13 +69,19 @@ def kernel_model(plan_info, pairs, t, w, N, s):
     return out
 
 
+# the sources of the single-plan kernels whose traffic is recorded (device
+# bodies, launches, table layouts)
+TRAFFIC_SOURCES = ("conv.hip", "cx.hpp", "internal.hpp", "kernels.hpp", "tables.hip")
+
+
 def source_sha():
-    """Hash of the kernel sources with comments and blank space removed, so a
-    stored counter summary stays valid across comment-only edits."""
+    """Hash of the single-plan kernel sources with comments and blank space
+    removed, so a stored counter summary stays valid across comment-only
+    edits and edits of the other passes (batched, union, dense, ABI)."""
     import re
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1501_06286_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in TRAFFIC_SOURCES:
         with open(os.path.join(d, f), encoding="utf-8") as fh:
             text = fh.read()
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
