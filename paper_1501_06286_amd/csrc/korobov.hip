@@ -20,11 +20,18 @@ __global__ __launch_bounds__(256) void ku_collapse(const T* __restrict__ A, int6
                                                    const int32_t* __restrict__ it_ptr,
                                                    const int32_t* __restrict__ it_jl,
                                                    int64_t Upad, cx<T>* __restrict__ aT,
-                                                   int64_t gx, int64_t per_block) {
+                                                   int64_t gx, int64_t per_block,
+                                                   int64_t total) {
+  // a grid of a few workgroups per CU striding over the tiles of all blocks
+  // (the tiles are small: one workgroup per tile would be bound by the
+  // workgroup dispatch rate)
   __shared__ CollapseSmem<T> S;
-  const int64_t b = blockIdx.x / per_block, lb = blockIdx.x % per_block;
-  collapse_body<T>(A, lda, t, P, it_ptr + b * (Upad + 1), it_jl + b * s, Upad,
-                   aT + b * P * Upad, lb % gx, lb / gx, S, threadIdx.x);
+  for (int64_t id = blockIdx.x; id < total; id += gridDim.x) {
+    const int64_t b = id / per_block, lb = id % per_block;
+    collapse_body<T>(A, lda, t, P, it_ptr + b * (Upad + 1), it_jl + b * s, Upad,
+                     aT + b * P * Upad, lb % gx, lb / gx, S, threadIdx.x);
+    __syncthreads();  // S is reused by the next tile
+  }
 }
 
 template <typename T, int R>
@@ -130,9 +137,10 @@ static int korobov_forward(const qmc_korobov_s* U, const T* A, int64_t t, int64_
     {
       const int64_t gx = (U->Upad + 63) / 64, per_block = gx * ((pairs + 15) / 16);
       ProfScope ps(P, PROF_COLLAPSE, st);
-      ku_collapse<T><<<dim3((unsigned)(nb * per_block)), 256, 0, st>>>(
+      const int64_t total = nb * per_block;
+      ku_collapse<T><<<dim3((unsigned)std::min<int64_t>(total, 2048)), 256, 0, st>>>(
           A, lda, t, pairs, U->s, U->d_it_ptr + b0 * (U->Upad + 1), U->d_it_jl + b0 * U->s,
-          U->Upad, aT, gx, per_block);
+          U->Upad, aT, gx, per_block, total);
     }
     switch (lay.R) {
       case 1: ku_middle_launch<T, 1>(U, aT, b0, nb, pairs, C, st); break;
