@@ -98,6 +98,10 @@ typedef struct qmc_plan_s* qmc_plan_t;
  *   dtype      QMC_F32 or QMC_F64
  *   stream     HIP stream for the plan-building kernels; the call
  *              synchronises that stream before returning.
+ * The convolution length M (N - 1 when that is a power of two, else the
+ * power of two >= 2N - 3) must split as M = M1 x M2 with M1 <= 4096 on chip
+ * and M2 <= 64 x 64; longer rules (N - 1 > 2^23 when not a power of two, or
+ * above 2^24) return QMC_ERR_UNSUPPORTED before any device work.
  * The plan owns its device memory; release it with qmc_plan_destroy.
  */
 int qmc_plan_create(qmc_plan_t* out, int rule, int64_t N, int64_t s,

@@ -579,7 +579,7 @@ int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st) {
   }
   P->lay = choose_layout(L, P->dtype, &P->embedded);
   const Layout& lay = P->lay;
-  if (lay.P2 < 1) return QMC_ERR_UNSUPPORTED;  // outer length beyond 64 x 64
+  if (lay.P2 < 1) return QMC_ERR_UNSUPPORTED;  // outer length beyond the longest split
 
   // ---- bit-exact group tables ------------------------------------------
   P->d_pow = dev_alloc<int32_t>(P, L, &err);

@@ -74,6 +74,11 @@ def _create(rule=0, N=7, gen=(1, 5, 3), modulus=0, phi=0, snum=0, sden=1, dtype=
     (dict(rule=1, N=16, gen=(0, 2), modulus=0b10011), -4),  # q = 0
     (dict(rule=1, N=16, gen=(16, 2), modulus=0b10011), -4), # q outside the field
     (dict(rule=2), -1),
+    # the first lengths past the longest outer split (M = 4096 x 64 x 64):
+    # refused before any device work
+    (dict(N=8388617, gen=(1, 5)), -9),
+    (dict(N=8388617, gen=(1, 5), dtype=1), -9),
+    (dict(rule=1, N=1 << 25, gen=(1, 2), modulus=(1 << 25) | 0b1001), -9),  # x^25+x^3+1
 ])
 def test_plan_create_rejects_bad_input(kw, code):
     rc, h = _create(**kw)

@@ -142,3 +142,28 @@ def test_split_outer_pass_gf2():
     announce("split outer pass GF(2) m=19")
     p, A, X, _ = _forward_sampled(inst, "f64", nrows=24)
     assert p.info()["M2"] == 256
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_largest_supported_length(dtype):
+    """The largest prime N with N - 1 not a power of two that a plan supports
+    (N = 8388593: M = 2^24, outer length M2 = 4096): the split passes at
+    their widest (P2 = 64) and the LDS back pass (Q2 = 64); sampled rows, the
+    column sums and the adjoint (G on sampled rows) against the oracle."""
+    N, q2 = 8388593, 64
+    assert qi.is_prime(N)
+    inst = qi.small_lattice(N, 8, 3, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype, seed=2)
+    announce(f"largest length N={N} {dtype}")
+    p, A, X, _ = _forward_sampled(inst, dtype, nrows=32)
+    info = p.info()
+    assert info["M"] == 1 << 24
+    assert info["Q2"] == q2 and info["P2"] == 64
+    import paper_1501_06286_amd as q
+    # G nonzero on 1024 sampled rows (row 0 among them), so the oracle's
+    # Y^T G needs only those rows of Y
+    rows = np.unique(np.concatenate([[0], sample_rows(N, 1023, 7)]))
+    G = np.zeros((N, inst.t))
+    G[rows] = qi.randn((len(rows), inst.t), seed=5, dtype=dtype)
+    dA = q.matmul_adjoint(p, to_dev(G, dtype)).double().cpu().numpy()
+    ref = oracle.Y_rows(inst, rows).T @ G[rows]
+    assert_close(dA, ref, G, inst, dtype, "adjoint")
