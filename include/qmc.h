@@ -135,6 +135,22 @@ int qmc_plan_tables(qmc_plan_t plan, int32_t* pow_out, int32_t* log_out,
                     int32_t* ell_out, double* phi_out);
 
 /*
+ * qmc_plan_set_row_order -- the order of the rows of X (qmc_matmul,
+ * qmc_matmul_epilogue, batches) and of G (qmc_matmul_adjoint):
+ *   QMC_ROWS_CONVENTIONAL (default): row n is point n, x_n = {n g / N + D}
+ *   QMC_ROWS_GROUP: row 0 is point 0, row 1 + e is the point of group element
+ *                   beta^e (pow_out[e] of qmc_plan_tables), e < L
+ * A QMC rule does not depend on the order of its points (Section 2.1), so a
+ * caller that only averages over the rows can skip the un-permutation's
+ * scatter; the group order is the circulant's own order (eq. (ZPa)).  The
+ * first switch to the group order allocates and fills an L-entry row table
+ * (synchronous).  QMC_ERR_ARG for an unknown order.
+ */
+#define QMC_ROWS_CONVENTIONAL 0
+#define QMC_ROWS_GROUP        1
+int qmc_plan_set_row_order(qmc_plan_t plan, int order);
+
+/*
  * Launch tuning of a plan (chosen by paper_1501_06286_amd/autotune.py):
  *   chunk_pairs  column pairs per chunk of the passes of qmc_matmul and
  *                qmc_matmul_adjoint; the intermediate spectrum buffers then

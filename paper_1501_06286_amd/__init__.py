@@ -36,7 +36,7 @@ EXPORTED = [
     "qmc_explicit_points",
     "qmc_dense_matmul", "qmc_batched_workspace_size", "qmc_matmul_batched", "qmc_strerror",
     "qmc_profile_enable", "qmc_profile_collect", "qmc_profile_slot_name",
-    "qmc_plan_set_tuning", "qmc_plan_get_tuning",
+    "qmc_plan_set_tuning", "qmc_plan_get_tuning", "qmc_plan_set_row_order",
     "qmc_batch_create", "qmc_batch_set_chunk", "qmc_batch_workspace_size", "qmc_batch_run",
     "qmc_batch_destroy",
     "qmc_korobov_create", "qmc_korobov_destroy", "qmc_korobov_info", "qmc_korobov_set_chunk",
@@ -44,6 +44,7 @@ EXPORTED = [
 ]
 PROF_SLOTS = 10
 BATCH_CHUNK_DEFAULT = 256 << 20  # QMC_BATCH_CHUNK_DEFAULT
+ROWS_CONVENTIONAL, ROWS_GROUP = 0, 1
 
 
 class QMCError(RuntimeError):
@@ -116,6 +117,7 @@ def lib() -> ctypes.CDLL:
         L.qmc_batch_destroy.argtypes = [vp]
         L.qmc_batch_destroy.restype = None
         L.qmc_plan_set_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
+        L.qmc_plan_set_row_order.argtypes = [vp, ip]
         L.qmc_plan_get_tuning.argtypes = [vp, ctypes.POINTER(Tuning)]
         L.qmc_profile_enable.argtypes = [vp, ip]
         L.qmc_profile_collect.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
@@ -235,6 +237,11 @@ class Plan:
         tu = Tuning(int(chunk_pairs), int(streams), int(nt_store), int(front), int(outer_q),
                     int(nt_inter))
         _check(lib().qmc_plan_set_tuning(self.handle, ctypes.byref(tu)), "qmc_plan_set_tuning")
+
+    def set_row_order(self, order: int) -> None:
+        """ROWS_CONVENTIONAL (row n = point n) or ROWS_GROUP (row 1 + e = the
+        point of beta^e) for X and, in the adjoint, G."""
+        _check(lib().qmc_plan_set_row_order(self.handle, int(order)), "qmc_plan_set_row_order")
 
     def get_tuning(self) -> dict:
         tu = Tuning()

@@ -167,6 +167,23 @@ int qmc_plan_set_tuning(qmc_plan_t P, const qmc_tuning_t* tu) {
   return QMC_OK;
 }
 
+int qmc_plan_set_row_order(qmc_plan_t P, int order) {
+  if (!P || (order != QMC_ROWS_CONVENTIONAL && order != QMC_ROWS_GROUP)) return QMC_ERR_ARG;
+  if (order == QMC_ROWS_GROUP && !P->d_grp) {
+    std::vector<int32_t> rows(P->L);
+    for (int64_t e = 0; e < P->L; ++e) rows[e] = (int32_t)(e + 1);
+    int err = QMC_OK;
+    int32_t* d = dev_alloc<int32_t>(P, P->L, &err);
+    if (err != QMC_OK) return err;
+    const int rc = hip_ok(hipMemcpy(d, rows.data(), P->L * sizeof(int32_t),
+                                    hipMemcpyHostToDevice));
+    if (rc != QMC_OK) return rc;
+    P->d_grp = d;
+  }
+  P->row_order = order;
+  return QMC_OK;
+}
+
 int qmc_plan_get_tuning(qmc_plan_t P, qmc_tuning_t* tu) {
   if (!P || !tu) return QMC_ERR_ARG;
   *tu = P->tune;

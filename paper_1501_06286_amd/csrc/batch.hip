@@ -290,7 +290,7 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
     I.it_ptr = P->d_it_ptr;
     I.it_jl = P->d_it_jl;
     I.it_e1 = P->d_it_e1;
-    I.pow = P->d_pow;
+    I.pow = out_rows(P);
     I.twit = P->d_twit;
     I.twf1 = P->d_twf1;
     I.twf2 = P->d_twf2;

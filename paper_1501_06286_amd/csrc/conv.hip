@@ -238,7 +238,7 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
     dim3 gl((unsigned)((lay.M1 + 7) / 8), (unsigned)((pairs + 7) / 8), (unsigned)lay.P2);
 #define QMC_BACKL(QQ)                                                                        \
   k_back_lds<T, QQ, ADJ, NT, EPI><<<gl, 256, 0, st>>>(                                       \
-      C, lay.M1, lay.M2, lay.P2, P->L, pairs, (const cx<T>*)P->d_twb, P->d_pow, inv_ptr, inv_j, \
+      C, lay.M1, lay.M2, lay.P2, P->L, pairs, (const cx<T>*)P->d_twb, out_rows(P), inv_ptr, inv_j, \
       G0, (T)P->phi0, X, ldx, t, epi)
     if (lay.Q2 == 64) {
       QMC_BACKL(64);
@@ -253,7 +253,7 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
   }
   dim3 grid((unsigned)((lay.M1 + 15) / 16), (unsigned)((pairs + 15) / 16), (unsigned)lay.P2);
 #define QMC_BACK(QQ)                                                                          \
-  k_back<T, QQ, ADJ, NT, EPI><<<grid, 256, 0, st>>>(C, lay.M1, lay.M2, lay.P2, P->L, pairs, P->d_pow, \
+  k_back<T, QQ, ADJ, NT, EPI><<<grid, 256, 0, st>>>(C, lay.M1, lay.M2, lay.P2, P->L, pairs, out_rows(P), \
                                            inv_ptr, inv_j, G0, (T)P->phi0, X, ldx, t, epi)
   switch (lay.Q2) {
     case 1: QMC_BACK(1); break;
@@ -421,7 +421,7 @@ static int launch_outer_front(const qmc_plan_s* P, const T* A, const T* G, int64
                                              P->d_inv_ptr, P->d_inv_j, twb, B);               \
   else                                                                                         \
     k_adj_front<T, QQ><<<grid, 256, 0, st>>>(G, ld, t, lay.M1, lay.M2, lay.Pf, P->L, pairs,   \
-                                             P->d_pow, twb, B)
+                                             out_rows(P), twb, B)
     switch (lay.Qf) {
       case 1: QMC_OFRONT(1); break;
       case 2: QMC_OFRONT(2); break;

@@ -52,6 +52,8 @@ struct qmc_plan_s {
 
   // device tables (owned)
   int32_t* d_pow = nullptr;     // L   : pow[e] = conventional row of beta^e
+  int32_t* d_grp = nullptr;     // L   : 1 + e, the rows of the group order (made on request)
+  int row_order = 0;            // 0: conventional rows pow[e]; 1: group order, row 1 + e
   int32_t* d_log = nullptr;     // N   : log[pow[e]] = e, log[0] = -1
   int32_t* d_ell = nullptr;     // s   : l_j
   uint32_t* d_gen = nullptr;    // s   : g_j mod N (lattice) or q_j (GF(2))
@@ -165,6 +167,11 @@ struct ProfScope {
     }
   }
 };
+
+// the row of X (and of G for the adjoint) that holds group element beta^e
+inline const int32_t* out_rows(const qmc_plan_s* P) {
+  return P->row_order ? P->d_grp : P->d_pow;
+}
 
 template <typename T>
 T* dev_alloc(qmc_plan_s* P, size_t count, int* err) {
