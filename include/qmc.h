@@ -300,6 +300,18 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
                      const void* const* A, const int64_t* lda, void* const* X,
                      const int64_t* ldx, void* stream);
 int qmc_batch_set_chunk(qmc_batch_t batch, int64_t chunk_bytes, int nt_inter, void* stream);
+
+/*
+ * qmc_batch_set_epilogue -- the epilogue of qmc_matmul_epilogue (Sections 3.2
+ * and 3.3) for every product of the batch: X_i = scale_i * f(bias_i + Y_i A_i)
+ * per column, one kind for all (QMC_EPI_*), bias[i] / scale[i] device arrays
+ * of t[i] values in the plans' dtype (a NULL array, or a NULL entry, means
+ * bias 0 / scale 1).  The vectors must outlive the batch's runs and must not
+ * overlap X_i (QMC_ERR_ALIAS).  Re-uploads the descriptors and synchronises
+ * `stream`, with the same restrictions as qmc_batch_set_chunk.
+ */
+int qmc_batch_set_epilogue(qmc_batch_t batch, int kind, const void* const* bias,
+                           const void* const* scale, void* stream);
 int qmc_batch_workspace_size(qmc_batch_t batch, size_t* bytes);
 int qmc_batch_run(qmc_batch_t batch, void* workspace, size_t workspace_bytes, void* stream);
 void qmc_batch_destroy(qmc_batch_t batch);

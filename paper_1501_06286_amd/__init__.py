@@ -37,7 +37,8 @@ EXPORTED = [
     "qmc_dense_matmul", "qmc_batched_workspace_size", "qmc_matmul_batched", "qmc_strerror",
     "qmc_profile_enable", "qmc_profile_collect", "qmc_profile_slot_name",
     "qmc_plan_set_tuning", "qmc_plan_get_tuning", "qmc_plan_set_row_order",
-    "qmc_batch_create", "qmc_batch_set_chunk", "qmc_batch_workspace_size", "qmc_batch_run",
+    "qmc_batch_create", "qmc_batch_set_chunk", "qmc_batch_set_epilogue",
+    "qmc_batch_workspace_size", "qmc_batch_run",
     "qmc_batch_destroy",
     "qmc_korobov_create", "qmc_korobov_destroy", "qmc_korobov_info", "qmc_korobov_set_chunk",
     "qmc_korobov_workspace_size", "qmc_korobov_plan", "qmc_korobov_matmul",
@@ -112,6 +113,7 @@ def lib() -> ctypes.CDLL:
                                        ctypes.POINTER(i64), ctypes.POINTER(vp),
                                        ctypes.POINTER(i64), vp]
         L.qmc_batch_set_chunk.argtypes = [vp, i64, ip, vp]
+        L.qmc_batch_set_epilogue.argtypes = [vp, ip, ctypes.POINTER(vp), ctypes.POINTER(vp), vp]
         L.qmc_batch_workspace_size.argtypes = [vp, ctypes.POINTER(sz)]
         L.qmc_batch_run.argtypes = [vp, vp, sz, vp]
         L.qmc_batch_destroy.argtypes = [vp]
@@ -451,6 +453,26 @@ class Batch:
         _check(lib().qmc_batch_set_chunk(self._h, int(chunk_bytes), int(nt_inter),
                                          _stream_handle(self._stream)), "qmc_batch_set_chunk")
         self._alloc_workspace()
+
+    def set_epilogue(self, epilogue, biases=None, scales=None) -> None:
+        """One epilogue kind ("affine", "exp" or None) for every product, with
+        per-product bias and scale vectors (device tensors of t_i values, or
+        None); the vectors must stay alive while the batch is run."""
+        kind = EPILOGUES[epilogue]
+        n = len(self.plans)
+
+        def ptrs(vs, what):
+            if vs is None:
+                return None
+            out = []
+            for i, (v, p, A) in enumerate(zip(vs, self.plans, self.As)):
+                out.append(None if v is None else _vec_ptr(v, p, A.shape[1], f"{what}[{i}]").value)
+            return (ctypes.c_void_p * n)(*out)
+
+        self._epi = (biases, scales)  # keep the vectors referenced
+        _check(lib().qmc_batch_set_epilogue(self._h, kind, ptrs(biases, "bias"),
+                                            ptrs(scales, "scale"), _stream_handle(self._stream)),
+               "qmc_batch_set_epilogue")
 
     def run(self, stream=None) -> List:
         _check(lib().qmc_batch_run(self._h, ctypes.c_void_p(self.workspace.data_ptr()),

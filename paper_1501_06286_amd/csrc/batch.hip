@@ -40,7 +40,25 @@ struct BatchInst {
   int64_t off[NPASS];  // first logical block of this product in each pass
   int64_t nb[NPASS];   // logical blocks of this product in each pass
   int64_t gx_collapse, gx_split, gx_back, gy_back;
+  // the epilogue of the product's writes (kind 0: none), per column
+  int epi_kind;
+  const void* epi_bias;
+  const void* epi_scale;
 };
+
+// the epilogue of row 0 of one product's columns [c0, c0 + nc) (its values
+// are the fused pass's DC terms, written by the previous launch); run by the
+// back-pass workgroups of the first e1 tile, each for its own column pairs
+template <typename T>
+__device__ __forceinline__ void batch_row0_epi(const BatchInst& I, int64_t c0, int nc, int tid) {
+  if (I.epi_kind == 0 || tid >= nc) return;
+  const int64_t c = c0 + tid;
+  if (c >= I.t) return;
+  const Epi<T> e{I.epi_kind, (const T*)I.epi_bias, (const T*)I.epi_scale};
+  const EpiCols<T> ec(e, c, I.t);
+  T* x = (T*)I.X + c;
+  *x = ec.f0(*x);
+}
 
 // largest i with D[i].off[pass] <= b (the product owning logical block b)
 __device__ __forceinline__ int find_inst(const BatchInst* __restrict__ D, int n, int pass,
@@ -133,9 +151,11 @@ __global__ __launch_bounds__(256) void kb_back(const BatchInst* __restrict__ D, 
     const int64_t lb = b - I.off[PASS_BACK];
     const int64_t bx = lb % I.gx_back, rest = lb / I.gx_back;
     const int64_t by = rest % I.gy_back, a = rest / I.gy_back;
-    back_body<T, Q, false, false>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2, I.L, I.pairs,
-                                  I.pow, nullptr, nullptr, nullptr, (T)I.phi0, (T*)I.X, I.ldx,
-                                  I.t, bx, by, a, S, opaque_tid());
+    const Epi<T> epi{I.epi_kind, (const T*)I.epi_bias, (const T*)I.epi_scale};
+    back_body<T, Q, false, false, true>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2, I.L,
+                                        I.pairs, I.pow, nullptr, nullptr, nullptr, (T)I.phi0,
+                                        (T*)I.X, I.ldx, I.t, bx, by, a, S, opaque_tid(), epi);
+    if (bx == 0 && a == 0) batch_row0_epi<T>(I, 32 * by, 32, opaque_tid());
     __syncthreads();
   }
 }
@@ -150,10 +170,12 @@ __global__ __launch_bounds__(256) void kb_back_lds(const BatchInst* __restrict__
     const int64_t lb = b - I.off[PASS_BACK];
     const int64_t bx = lb % I.gx_back, rest = lb / I.gx_back;
     const int64_t by = rest % I.gy_back, a = rest / I.gy_back;
-    back_lds_body<T, Q, false, false>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2, I.L,
-                                      I.pairs, (const cx<T>*)I.twb, I.pow, nullptr, nullptr,
-                                      nullptr, (T)I.phi0, (T*)I.X, I.ldx, I.t, bx, by, a, S,
-                                      opaque_tid());
+    const Epi<T> epi{I.epi_kind, (const T*)I.epi_bias, (const T*)I.epi_scale};
+    back_lds_body<T, Q, false, false, true>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2,
+                                            I.L, I.pairs, (const cx<T>*)I.twb, I.pow, nullptr,
+                                            nullptr, nullptr, (T)I.phi0, (T*)I.X, I.ldx, I.t, bx,
+                                            by, a, S, opaque_tid(), epi);
+    if (bx == 0 && a == 0) batch_row0_epi<T>(I, 16 * by, 16, opaque_tid());
     __syncthreads();
   }
 }
@@ -177,8 +199,10 @@ struct qmc_batch_s {
     int64_t total[NPASS] = {0, 0, 0, 0};
   };
   std::vector<Group> groups;
-  // the products by layout key (R, P2, Q2), in input order, for regrouping
+  // the products by layout key (R, P2, Q2), in input order, for regrouping,
+  // and each one's position in the caller's list
   std::vector<std::pair<int64_t, std::vector<BatchInst>>> byKey;
+  std::vector<std::vector<int>> input_index;
 };
 
 static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -323,9 +347,11 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
                            });
     if (it == byKey.end()) {
       byKey.push_back({key, {}});
+      B->input_index.push_back({});
       it = byKey.end() - 1;
     }
     it->second.push_back(I);
+    B->input_index[it - byKey.begin()].push_back(i);
   }
   const int rc = build_runs(B, QMC_BATCH_CHUNK_DEFAULT, 0, (hipStream_t)stream);
   if (rc != QMC_OK) {
@@ -340,6 +366,28 @@ void qmc_batch_destroy(qmc_batch_t B) {
   if (!B) return;
   free_runs(B);
   delete B;
+}
+
+int qmc_batch_set_epilogue(qmc_batch_t B, int kind, const void* const* bias,
+                           const void* const* scale, void* stream) {
+  if (!B || kind < QMC_EPI_NONE || kind > QMC_EPI_EXP) return QMC_ERR_ARG;
+  // bias[i], scale[i] belong to the caller's product i (input_index)
+  for (size_t g = 0; g < B->byKey.size(); ++g) {
+    for (size_t k = 0; k < B->byKey[g].second.size(); ++k) {
+      BatchInst& I = B->byKey[g].second[k];
+      const int i = B->input_index[g][k];
+      const void* b = (kind && bias) ? bias[i] : nullptr;
+      const void* c = (kind && scale) ? scale[i] : nullptr;
+      const size_t xa = matrix_extent(I.L + 1, I.t, I.ldx, B->dtype);  // N = L + 1 rows
+      const size_t va = matrix_extent(1, I.t, I.t, B->dtype);
+      if ((b && ranges_overlap(I.X, xa, b, va)) || (c && ranges_overlap(I.X, xa, c, va)))
+        return QMC_ERR_ALIAS;
+      I.epi_kind = kind;
+      I.epi_bias = b;
+      I.epi_scale = c;
+    }
+  }
+  return build_runs(B, B->chunk_bytes, B->nt_inter, (hipStream_t)stream);
 }
 
 int qmc_batch_set_chunk(qmc_batch_t B, int64_t chunk_bytes, int nt_inter, void* stream) {

@@ -93,6 +93,44 @@ def test_batch_chunks(chunk):
     b.close()
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("epi", ["affine", "exp"])
+def test_batch_epilogue(epi, dtype):
+    """Per-product epilogues in a batch (Sections 3.2, 3.3) give the bits of
+    qmc_matmul_epilogue on each product: register and LDS back passes, some
+    products without a bias or a scale, runs of one product each."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    insts = _instances(dtype, seed=21)
+    N = 139999
+    insts.append(qi.small_lattice(N, 100, 19, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype,
+                                  seed=22))
+    announce(f"batch epilogue {epi} {dtype}")
+    plans = [plan_of(i) for i in insts]
+    plans[-1].set_tuning(outer_q=64)  # the LDS back pass
+    for inst in insts:  # keep exp's argument moderate
+        inst.A = qi._round_to(inst.A / np.sqrt(inst.s), dtype)
+    As = [to_dev(i.A, dtype) for i in insts]
+    rg = np.random.default_rng(3)
+    biases = [None if k % 3 == 1 else to_dev(0.3 * rg.standard_normal(i.t), dtype)
+              for k, i in enumerate(insts)]
+    scales = [None if k % 4 == 2 else to_dev(rg.uniform(0.5, 2.0, i.t), dtype)
+              for k, i in enumerate(insts)]
+    b = q.Batch(plans, As, chunk_bytes=1)
+    b.set_epilogue(epi, biases, scales)
+    Xs = b.run()
+    torch.cuda.synchronize()
+    for p, A, X, bi, sc in zip(plans, As, Xs, biases, scales):
+        ref = q.matmul(p, A, epilogue=epi, bias=bi, scale=sc)
+        torch.cuda.synchronize()
+        assert torch.equal(X, ref)
+    b.set_epilogue(None)  # back to the plain products
+    Xs = b.run()
+    for p, A, X in zip(plans, As, Xs):
+        assert torch.equal(X, q.matmul(p, A))
+    b.close()
+
+
 def test_batch_matches_single_products():
     torch = torch_cuda()
     import paper_1501_06286_amd as q
