@@ -356,6 +356,8 @@ int qmc_matmul_batched(int count, const qmc_plan_t* plans, const void* const* A,
  * qmc_korobov_matmul -- X = Y A: A device s x t (row stride lda >= t), X
  *   device N x t (ldx >= t), every entry written; asynchronous on `stream`.
  *   Errors: QMC_ERR_ARG, QMC_ERR_ALIAS (X overlaps A), QMC_ERR_WORKSPACE.
+ * qmc_korobov_matmul_epilogue -- the same with the per-column epilogue of
+ *   qmc_matmul_epilogue (Sections 3.2, 3.3) in the writes of X.
  */
 typedef struct qmc_korobov_s* qmc_korobov_t;
 typedef struct {
@@ -374,6 +376,10 @@ int qmc_korobov_workspace_size(qmc_korobov_t U, int64_t t, size_t* bytes);
 qmc_plan_t qmc_korobov_plan(qmc_korobov_t U);
 int qmc_korobov_matmul(qmc_korobov_t U, const void* A, int64_t t, int64_t lda, void* X,
                        int64_t ldx, void* workspace, size_t workspace_bytes, void* stream);
+int qmc_korobov_matmul_epilogue(qmc_korobov_t U, const void* A, int64_t t, int64_t lda,
+                                void* X, int64_t ldx, int epi_kind, const void* bias,
+                                const void* scale, void* workspace, size_t workspace_bytes,
+                                void* stream);
 void qmc_korobov_destroy(qmc_korobov_t U);
 
 /*

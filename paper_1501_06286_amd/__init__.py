@@ -42,6 +42,7 @@ EXPORTED = [
     "qmc_batch_destroy",
     "qmc_korobov_create", "qmc_korobov_destroy", "qmc_korobov_info", "qmc_korobov_set_chunk",
     "qmc_korobov_workspace_size", "qmc_korobov_plan", "qmc_korobov_matmul",
+    "qmc_korobov_matmul_epilogue",
 ]
 PROF_SLOTS = 10
 BATCH_CHUNK_DEFAULT = 256 << 20  # QMC_BATCH_CHUNK_DEFAULT
@@ -134,6 +135,8 @@ def lib() -> ctypes.CDLL:
         L.qmc_korobov_plan.argtypes = [vp]
         L.qmc_korobov_plan.restype = vp
         L.qmc_korobov_matmul.argtypes = [vp, vp, i64, i64, vp, i64, vp, sz, vp]
+        L.qmc_korobov_matmul_epilogue.argtypes = [vp, vp, i64, i64, vp, i64, ip, vp, vp, vp, sz,
+                                                  vp]
         for name in EXPORTED:
             if name not in ("qmc_plan_destroy", "qmc_strerror", "qmc_profile_slot_name",
                             "qmc_batch_destroy", "qmc_korobov_destroy", "qmc_korobov_plan"):
@@ -565,18 +568,22 @@ class KorobovUnion:
         return self._ws
 
 
-def korobov_matmul(U: KorobovUnion, A, out=None, workspace=None, stream=None):
-    """X = Y A for the union of Korobov lattice point sets ((K-1)^2 x t)."""
+def korobov_matmul(U: KorobovUnion, A, out=None, workspace=None, stream=None, epilogue=None,
+                   bias=None, scale=None):
+    """X = Y A for the union of Korobov lattice point sets ((K-1)^2 x t), with
+    the optional per-column epilogue of ``matmul``."""
     torch = _torch()
     _check_tensor(A, U, U.s, "A")
     t = A.shape[1]
     X = torch.empty((U.N, t), dtype=A.dtype, device=A.device) if out is None else out
     _check_tensor(X, U, U.N, "out")
     ws = U.workspace(t, A.device) if workspace is None else workspace
-    _check(lib().qmc_korobov_matmul(U.handle, ctypes.c_void_p(A.data_ptr()), t, A.stride(0),
-                                    ctypes.c_void_p(X.data_ptr()), X.stride(0),
-                                    ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
-                                    _stream_handle(stream)), "qmc_korobov_matmul")
+    kind = EPILOGUES[epilogue]
+    _check(lib().qmc_korobov_matmul_epilogue(
+        U.handle, ctypes.c_void_p(A.data_ptr()), t, A.stride(0), ctypes.c_void_p(X.data_ptr()),
+        X.stride(0), kind, _vec_ptr(bias, U, t, "bias"), _vec_ptr(scale, U, t, "scale"),
+        ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), _stream_handle(stream)),
+        "qmc_korobov_matmul_epilogue")
     return X
 
 

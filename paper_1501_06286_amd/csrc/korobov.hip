@@ -67,13 +67,13 @@ __global__ __launch_bounds__(256) void ku_back(const cx<T>* __restrict__ C, int6
                                                const int32_t* __restrict__ rowmap,
                                                T* __restrict__ X, int64_t ldx, int64_t t,
                                                int64_t block_rows, int64_t gx, int64_t gy,
-                                               int64_t per_block) {
+                                               int64_t per_block, Epi<T> epi) {
   __shared__ BackSmem<T> S;
   const int64_t b = blockIdx.x / per_block, lb = blockIdx.x % per_block;
   const int64_t bx = lb % gx, rest = lb / gx;
-  back_body<T, Q, false, false>(C + b * P * M1 * M2, M1, M2, P2, L, P, rowmap, nullptr, nullptr,
-                                nullptr, (T)0, X + b * block_rows * ldx, ldx, t, bx, rest % gy,
-                                rest / gy, S, threadIdx.x);
+  back_body<T, Q, false, false, true>(C + b * P * M1 * M2, M1, M2, P2, L, P, rowmap, nullptr,
+                                      nullptr, nullptr, (T)0, X + b * block_rows * ldx, ldx, t,
+                                      bx, rest % gy, rest / gy, S, threadIdx.x, epi);
 }
 
 template <typename T, int Q>
@@ -83,13 +83,14 @@ __global__ __launch_bounds__(256) void ku_back_lds(const cx<T>* __restrict__ C, 
                                                    const int32_t* __restrict__ rowmap,
                                                    T* __restrict__ X, int64_t ldx, int64_t t,
                                                    int64_t block_rows, int64_t gx, int64_t gy,
-                                                   int64_t per_block) {
+                                                   int64_t per_block, Epi<T> epi) {
   __shared__ BackLdsSmem<T, Q> S;
   const int64_t b = blockIdx.x / per_block, lb = blockIdx.x % per_block;
   const int64_t bx = lb % gx, rest = lb / gx;
-  back_lds_body<T, Q, false, false>(C + b * P * M1 * M2, M1, M2, P2, L, P, twb, rowmap, nullptr,
-                                    nullptr, nullptr, (T)0, X + b * block_rows * ldx, ldx, t,
-                                    bx, rest % gy, rest / gy, S, threadIdx.x);
+  back_lds_body<T, Q, false, false, true>(C + b * P * M1 * M2, M1, M2, P2, L, P, twb, rowmap,
+                                          nullptr, nullptr, nullptr, (T)0,
+                                          X + b * block_rows * ldx, ldx, t, bx, rest % gy,
+                                          rest / gy, S, threadIdx.x, epi);
 }
 
 static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -125,7 +126,7 @@ static void ku_middle_launch(const qmc_korobov_s* U, const cx<T>* aT, int64_t b0
 
 template <typename T>
 static int korobov_forward(const qmc_korobov_s* U, const T* A, int64_t t, int64_t lda, T* X,
-                           int64_t ldx, void* ws, hipStream_t st) {
+                           int64_t ldx, void* ws, hipStream_t st, const Epi<T>& epi) {
   const qmc_plan_s* P = U->base;
   const Layout& lay = P->lay;
   const int64_t pairs = (t + 1) / 2, chunk = chunk_of(U), K = U->K;
@@ -177,11 +178,12 @@ static int korobov_forward(const qmc_korobov_s* U, const T* A, int64_t t, int64_
       ProfScope ps(P, PROF_BACK, st);
 #define QMC_KBACK(QQ)                                                                             \
   ku_back<T, QQ><<<dim3((unsigned)(nb * per_block)), 256, 0, st>>>(                               \
-      C, lay.M1, lay.M2, lay.P2, P->L, pairs, U->d_rowmap, Xb, ldx, t, K - 1, gx, gy, per_block)
+      C, lay.M1, lay.M2, lay.P2, P->L, pairs, U->d_rowmap, Xb, ldx, t, K - 1, gx, gy, per_block, \
+      epi)
 #define QMC_KBACKL(QQ)                                                                            \
   ku_back_lds<T, QQ><<<dim3((unsigned)(nb * per_block)), 256, 0, st>>>(                           \
       C, lay.M1, lay.M2, lay.P2, P->L, pairs, (const cx<T>*)P->d_twb, U->d_rowmap, Xb, ldx, t,    \
-      K - 1, gx, gy, per_block)
+      K - 1, gx, gy, per_block, epi)
       switch (lay.Q2) {
         case 1: QMC_KBACK(1); break;
         case 2: QMC_KBACK(2); break;
@@ -280,21 +282,38 @@ int qmc_korobov_workspace_size(qmc_korobov_t U, int64_t t, size_t* bytes) {
 
 qmc_plan_t qmc_korobov_plan(qmc_korobov_t U) { return U ? U->base : nullptr; }
 
-int qmc_korobov_matmul(qmc_korobov_t U, const void* A, int64_t t, int64_t lda, void* X,
-                       int64_t ldx, void* workspace, size_t workspace_bytes, void* stream) {
+int qmc_korobov_matmul_epilogue(qmc_korobov_t U, const void* A, int64_t t, int64_t lda,
+                                void* X, int64_t ldx, int epi_kind, const void* bias,
+                                const void* scale, void* workspace, size_t workspace_bytes,
+                                void* stream) {
   if (!U || !A || !X || t < 1 || lda < t || ldx < t) return QMC_ERR_ARG;
+  if (epi_kind < QMC_EPI_NONE || epi_kind > QMC_EPI_EXP) return QMC_ERR_ARG;
   const size_t need = korobov_ws(U, t);
   if (!workspace || workspace_bytes < need) return QMC_ERR_WORKSPACE;
   const int dt = U->base->dtype;
   const int64_t N = (U->K - 1) * (U->K - 1);
   const size_t xa = matrix_extent(N, t, ldx, dt), aa = matrix_extent(U->s, t, lda, dt);
+  const size_t va = matrix_extent(1, t, t, dt);
   if (ranges_overlap(X, xa, A, aa) || ranges_overlap(X, xa, workspace, need) ||
-      ranges_overlap(A, aa, workspace, need))
+      ranges_overlap(A, aa, workspace, need) || (bias && ranges_overlap(X, xa, bias, va)) ||
+      (scale && ranges_overlap(X, xa, scale, va)) ||
+      (bias && ranges_overlap(workspace, need, bias, va)) ||
+      (scale && ranges_overlap(workspace, need, scale, va)))
     return QMC_ERR_ALIAS;
   hipStream_t st = (hipStream_t)stream;
   if (dt == QMC_F32)
-    return korobov_forward<float>(U, (const float*)A, t, lda, (float*)X, ldx, workspace, st);
-  return korobov_forward<double>(U, (const double*)A, t, lda, (double*)X, ldx, workspace, st);
+    return korobov_forward<float>(
+        U, (const float*)A, t, lda, (float*)X, ldx, workspace, st,
+        Epi<float>{epi_kind, (const float*)bias, (const float*)scale});
+  return korobov_forward<double>(
+      U, (const double*)A, t, lda, (double*)X, ldx, workspace, st,
+      Epi<double>{epi_kind, (const double*)bias, (const double*)scale});
+}
+
+int qmc_korobov_matmul(qmc_korobov_t U, const void* A, int64_t t, int64_t lda, void* X,
+                       int64_t ldx, void* workspace, size_t workspace_bytes, void* stream) {
+  return qmc_korobov_matmul_epilogue(U, A, t, lda, X, ldx, QMC_EPI_NONE, nullptr, nullptr,
+                                     workspace, workspace_bytes, stream);
 }
 
 }  // extern "C"

@@ -107,3 +107,26 @@ def test_korobov_full_size_sampled_rows():
                                      rg.integers(0, inst.N, size=512)]))
     got = X[torch.from_numpy(rows).cuda()].double().cpu().numpy()
     assert_close(got, oracle.matmul_rows(inst, rows), inst.A, inst, "f32", "korobov full")
+
+
+@pytest.mark.parametrize("epi", ["affine", "exp"])
+def test_korobov_epilogue(epi):
+    """The union with the per-column epilogue (Sections 3.2, 3.3) against the
+    oracle's product and epilogue; no row 0 in the union, so every row goes
+    through the back pass."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    inst = qi.small_korobov(31, 40, 7, phi=qi.PHI_INVNORM, shift=(1, 62), dtype="f64", seed=4)
+    announce(f"korobov epilogue {epi}")
+    inst.A = inst.A / np.sqrt(inst.s)
+    U = q.KorobovUnion.from_instance(inst)
+    rg = np.random.default_rng(9)
+    bias = rg.standard_normal(inst.t) * 0.3
+    scale = rg.uniform(0.5, 2.0, inst.t)
+    X = q.korobov_matmul(U, to_dev(inst.A, "f64"), epilogue=epi, bias=to_dev(bias, "f64"),
+                         scale=to_dev(scale, "f64"))
+    torch.cuda.synchronize()
+    kind = oracle.EPI_AFFINE if epi == "affine" else oracle.EPI_EXP
+    ref = oracle.epilogue(oracle.matmul(inst), kind, bias, scale)
+    err = np.abs(X.cpu().numpy() - ref) / np.maximum(1.0, np.abs(ref))
+    assert float(err.max()) < 1e-11
