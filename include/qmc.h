@@ -348,7 +348,8 @@ int qmc_matmul_batched(int count, const qmc_plan_t* plans, const void* const* A,
  * qmc_korobov_info -- N, s, K, L = K-1, the convolution layout and beta.
  * qmc_korobov_set_chunk -- blocks per run of the passes (0: all blocks);
  *   the workspace holds one run.
- * qmc_korobov_workspace_size -- device bytes qmc_korobov_matmul needs for t.
+ * qmc_korobov_workspace_size -- device bytes qmc_korobov_matmul (and its
+ *   epilogue and adjoint variants) need for t.
  * qmc_korobov_plan -- the lattice plan of K points whose spectrum and tables
  *   every block shares (owned by the union: valid until qmc_korobov_destroy;
  *   for qmc_plan_tables and the timing instrumentation, which also covers
@@ -358,6 +359,11 @@ int qmc_matmul_batched(int count, const qmc_plan_t* plans, const void* const* A,
  *   Errors: QMC_ERR_ARG, QMC_ERR_ALIAS (X overlaps A), QMC_ERR_WORKSPACE.
  * qmc_korobov_matmul_epilogue -- the same with the per-column epilogue of
  *   qmc_matmul_epilogue (Sections 3.2, 3.3) in the writes of X.
+ * qmc_korobov_matmul_adjoint -- dA = Y^T G: G device N x t (ldg >= t), dA
+ *   device s x t (ldda >= t), every entry written; the blocks' parts are
+ *   summed in increasing block order (so the result depends on the chunk of
+ *   blocks only through rounding).  Same workspace query; QMC_ERR_UNSUPPORTED
+ *   when the outer split keeps more than 32 values per back-pass column.
  */
 typedef struct qmc_korobov_s* qmc_korobov_t;
 typedef struct {
@@ -380,6 +386,9 @@ int qmc_korobov_matmul_epilogue(qmc_korobov_t U, const void* A, int64_t t, int64
                                 void* X, int64_t ldx, int epi_kind, const void* bias,
                                 const void* scale, void* workspace, size_t workspace_bytes,
                                 void* stream);
+int qmc_korobov_matmul_adjoint(qmc_korobov_t U, const void* G, int64_t t, int64_t ldg, void* dA,
+                               int64_t ldda, void* workspace, size_t workspace_bytes,
+                               void* stream);
 void qmc_korobov_destroy(qmc_korobov_t U);
 
 /*

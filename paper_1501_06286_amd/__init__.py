@@ -42,7 +42,7 @@ EXPORTED = [
     "qmc_batch_destroy",
     "qmc_korobov_create", "qmc_korobov_destroy", "qmc_korobov_info", "qmc_korobov_set_chunk",
     "qmc_korobov_workspace_size", "qmc_korobov_plan", "qmc_korobov_matmul",
-    "qmc_korobov_matmul_epilogue",
+    "qmc_korobov_matmul_epilogue", "qmc_korobov_matmul_adjoint",
 ]
 PROF_SLOTS = 10
 BATCH_CHUNK_DEFAULT = 256 << 20  # QMC_BATCH_CHUNK_DEFAULT
@@ -137,6 +137,7 @@ def lib() -> ctypes.CDLL:
         L.qmc_korobov_matmul.argtypes = [vp, vp, i64, i64, vp, i64, vp, sz, vp]
         L.qmc_korobov_matmul_epilogue.argtypes = [vp, vp, i64, i64, vp, i64, ip, vp, vp, vp, sz,
                                                   vp]
+        L.qmc_korobov_matmul_adjoint.argtypes = [vp, vp, i64, i64, vp, i64, vp, sz, vp]
         for name in EXPORTED:
             if name not in ("qmc_plan_destroy", "qmc_strerror", "qmc_profile_slot_name",
                             "qmc_batch_destroy", "qmc_korobov_destroy", "qmc_korobov_plan"):
@@ -585,6 +586,21 @@ def korobov_matmul(U: KorobovUnion, A, out=None, workspace=None, stream=None, ep
         ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(), _stream_handle(stream)),
         "qmc_korobov_matmul_epilogue")
     return X
+
+
+def korobov_matmul_adjoint(U: KorobovUnion, G, out=None, workspace=None, stream=None):
+    """dA = Y^T G for the union of Korobov lattice point sets (s x t)."""
+    torch = _torch()
+    _check_tensor(G, U, U.N, "G")
+    t = G.shape[1]
+    dA = torch.empty((U.s, t), dtype=G.dtype, device=G.device) if out is None else out
+    _check_tensor(dA, U, U.s, "out")
+    ws = U.workspace(t, G.device) if workspace is None else workspace
+    _check(lib().qmc_korobov_matmul_adjoint(
+        U.handle, ctypes.c_void_p(G.data_ptr()), t, G.stride(0), ctypes.c_void_p(dA.data_ptr()),
+        dA.stride(0), ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+        _stream_handle(stream)), "qmc_korobov_matmul_adjoint")
+    return dA
 
 
 def _autograd():

@@ -92,6 +92,8 @@ struct qmc_korobov_s {
   int32_t* d_it_e1 = nullptr;    // blocks*Upad
   void* d_twit = nullptr;        // blocks*M2*Upad: W_M^{slot w2} per block
   int32_t* d_rowmap = nullptr;   // L: pow[e] - 1 (row n - 1 of a block)
+  int32_t* d_inv_ptr = nullptr;  // blocks*(L+1): per block, CSR of the rows j with l_{b,j} = e
+  int32_t* d_inv_j = nullptr;    // blocks*s
   int64_t chunk_blocks = 0;      // blocks per run (0: chosen from the shape)
 };
 

@@ -497,8 +497,10 @@ __device__ __forceinline__ void put_out(cx<T> o, int64_t e, int64_t pairw,
   if constexpr (!ADJ) {
     put_row<T, NT, EPI>(o, (int64_t)rowmap[e], pairw, X, ldx, t, v2, ec);
   } else {
-    const T g0 = phi0 * G0[col];
-    const T g1 = both ? phi0 * G0[col + 1] : (T)0;
+    // the constant row's part phi(x_0) G[0] (none when G0 is null: a point
+    // set without the point 0)
+    const T g0 = G0 ? phi0 * G0[col] : (T)0;
+    const T g1 = (G0 && both) ? phi0 * G0[col + 1] : (T)0;
     for (int32_t jj = inv_ptr[e]; jj < inv_ptr[e + 1]; ++jj) {
       T* row = X + (int64_t)inv_j[jj] * ldx;
       if (v2 && both) {

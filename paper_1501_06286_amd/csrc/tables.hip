@@ -707,6 +707,9 @@ int build_korobov_tables(qmc_korobov_s* U, hipStream_t st) {
   if (rc != QMC_OK) return rc;
   std::vector<Schedule> scs(nb);
   std::vector<int32_t> ell(s);
+  // the adjoint's read-back: per block, the rows j of each exponent e
+  // (counting sort by l_{b,j}, increasing j inside an exponent)
+  std::vector<int32_t> inv_ptr(nb * (L + 1)), inv_j(nb * s);
   int64_t rounds = 0;
   for (int64_t b = 1; b <= nb; ++b) {
     const int64_t lam = logt[b];
@@ -714,6 +717,12 @@ int build_korobov_tables(qmc_korobov_s* U, hipStream_t st) {
     for (int64_t j = 0; j < s; ++j) ell[j] = (int32_t)((j % L) * lam % L);
     scs[b - 1] = make_schedule(lay, L, s, ell.data());
     rounds = std::max(rounds, scs[b - 1].rounds);
+    int32_t* ip = inv_ptr.data() + (b - 1) * (L + 1);
+    int32_t* ij = inv_j.data() + (b - 1) * s;
+    for (int64_t j = 0; j < s; ++j) ++ip[ell[j] + 1];
+    for (int64_t e = 0; e < L; ++e) ip[e + 1] += ip[e];
+    std::vector<int32_t> fill(ip, ip + L);
+    for (int64_t j = 0; j < s; ++j) ij[fill[ell[j]]++] = (int32_t)j;
   }
   for (Schedule& sc : scs) pad_schedule(sc, rounds, lay.M1, lay.R);
   U->rounds = rounds;
@@ -734,6 +743,8 @@ int build_korobov_tables(qmc_korobov_s* U, hipStream_t st) {
   U->d_it_e1 = dev_alloc<int32_t>(P, nb * Upad, &err);
   U->d_rowmap = dev_alloc<int32_t>(P, L, &err);
   U->d_twit = dev_alloc<char>(P, nb * M2 * Upad * el, &err);
+  U->d_inv_ptr = dev_alloc<int32_t>(P, nb * (L + 1), &err);
+  U->d_inv_j = dev_alloc<int32_t>(P, nb * s, &err);
   if (err != QMC_OK) return err;
   int32_t* d_slot = nullptr;
   cx<double>* dW = nullptr;
@@ -750,6 +761,12 @@ int build_korobov_tables(qmc_korobov_s* U, hipStream_t st) {
                                  st));
     if (rc == QMC_OK)
       rc = hip_ok(hipMemcpyAsync(d_slot, slot.data(), nb * Upad * 4, hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(U->d_inv_ptr, inv_ptr.data(), nb * (L + 1) * 4,
+                                 hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(U->d_inv_j, inv_j.data(), nb * s * 4, hipMemcpyHostToDevice,
+                                 st));
     if (rc != QMC_OK) break;
     k_twiddle<<<nblk(M), 256, 0, st>>>(dW, M);
     if (P->dtype == QMC_F32)

@@ -130,3 +130,40 @@ def test_korobov_epilogue(epi):
     ref = oracle.epilogue(oracle.matmul(inst), kind, bias, scale)
     err = np.abs(X.cpu().numpy() - ref) / np.maximum(1.0, np.abs(ref))
     assert float(err.max()) < 1e-11
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("K,s,t,chunk", [(13, 5, 3, 0), (31, 40, 7, 0), (31, 40, 7, 4),
+                                         (31, 70, 1, 7), (61, 100, 16, 0)])
+def test_korobov_adjoint_matches_oracle(K, s, t, chunk, dtype):
+    """dA = Y^T G for the union against the oracle's explicit Y (the blocks'
+    parts summed over runs of `chunk` blocks)."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    inst = qi.small_korobov(K, s, t, phi=qi.PHI_INVNORM, shift=(1, 2 * K), dtype=dtype, seed=K)
+    announce(f"korobov adjoint K={K} s={s} t={t} chunk={chunk} {dtype}")
+    U = q.KorobovUnion.from_instance(inst)
+    U.set_chunk(chunk)
+    G = qi.randn((inst.N, t), seed=K + 1, dtype=dtype)
+    dA = q.korobov_matmul_adjoint(U, to_dev(G, dtype))
+    torch.cuda.synchronize()
+    assert_close(dA.double().cpu().numpy(), oracle.adjoint(inst, G), G, inst, dtype, "adjoint")
+
+
+def test_korobov_adjoint_full_size_dot_product():
+    """At the full union (K = 1021, s = 512, t = 256, FP32): <Y A, G> equals
+    <A, Y^T G> with both sides from the GPU."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    inst = qi.make_korobov("f32")
+    announce("korobov adjoint full size")
+    U = q.KorobovUnion.from_instance(inst)
+    A = to_dev(inst.A, "f32")
+    G = torch.randn((inst.N, inst.t), dtype=torch.float32, device="cuda", generator=torch.Generator(
+        device="cuda").manual_seed(5))
+    X = q.korobov_matmul(U, A)
+    dA = q.korobov_matmul_adjoint(U, G)
+    lhs = float((X.double() * G.double()).sum())
+    rhs = float((A.double() * dA.double()).sum())
+    scale = float(X.double().abs().sum() * G.double().abs().max())
+    assert abs(lhs - rhs) <= 1e-5 * scale
