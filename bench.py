@@ -462,6 +462,17 @@ def main():
             "kernels": {k: {"avg_ms": round(v[0] / v[1], 4), "ms_per_step": round(v[0] / nk, 4)}
                         for k, v in kprof.items()}}
         log(f"Korobov union {1e3 * ek / nk:.3f} ms/step")
+        if not args.no_adjoint:
+            kG = torch.randn((kin.N, kin.t), dtype=tdt, device=dev)
+            kdA = torch.empty((kin.s, kin.t), dtype=tdt, device=dev)
+            kastep = lambda: q.korobov_matmul_adjoint(U, kG, out=kdA, workspace=kws)
+            kastep()
+            eka = time_steps(kastep, nk, torch)
+            result["korobov_union"]["adjoint"] = {
+                "value": kin.N * kin.t / (eka / nk), "unit": "entries/s (N*t per s)",
+                "ms_per_step": round(1e3 * eka / nk, 4)}
+            log(f"Korobov union adjoint {1e3 * eka / nk:.3f} ms/step")
+            del kG, kdA
         if not args.no_cpu:
             result["korobov_union"]["cpu_baseline"] = cpu_baseline(kin, budget_s=6.0)
         del U, kA, kX, kws
