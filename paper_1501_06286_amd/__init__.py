@@ -618,7 +618,19 @@ def _autograd():
         def backward(ctx, gX):
             return matmul_adjoint(ctx.plan, gX.contiguous()), None
 
-    return QMCMatmul
+    class KorobovMatmul(torch.autograd.Function):
+        """The union's X = Y A with dA = Y^T dX in backward."""
+
+        @staticmethod
+        def forward(ctx, A, U):
+            ctx.U = U
+            return korobov_matmul(U, A.contiguous())
+
+        @staticmethod
+        def backward(ctx, gX):
+            return korobov_matmul_adjoint(ctx.U, gX.contiguous()), None
+
+    return QMCMatmul, KorobovMatmul
 
 
 _QMC_FN = None
@@ -629,4 +641,12 @@ def qmc_matmul(A, plan: Plan):
     global _QMC_FN
     if _QMC_FN is None:
         _QMC_FN = _autograd()
-    return _QMC_FN.apply(A, plan)
+    return _QMC_FN[0].apply(A, plan)
+
+
+def korobov_qmc_matmul(A, U: KorobovUnion):
+    """Differentiable X = Y A for the union of Korobov lattice point sets."""
+    global _QMC_FN
+    if _QMC_FN is None:
+        _QMC_FN = _autograd()
+    return _QMC_FN[1].apply(A, U)

@@ -167,3 +167,19 @@ def test_korobov_adjoint_full_size_dot_product():
     rhs = float((A.double() * dA.double()).sum())
     scale = float(X.double().abs().sum() * G.double().abs().max())
     assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+def test_korobov_autograd():
+    """backward of the union's product is its adjoint: the gradient of
+    <X(A), W> is Y^T W (oracle)."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    inst = qi.small_korobov(31, 40, 5, phi=qi.PHI_INVNORM, shift=(1, 62), dtype="f64", seed=8)
+    announce("korobov autograd")
+    U = q.KorobovUnion.from_instance(inst)
+    A = to_dev(inst.A, "f64").requires_grad_(True)
+    W = qi.randn((inst.N, inst.t), seed=2, dtype="f64")
+    X = q.korobov_qmc_matmul(A, U)
+    (X * to_dev(W, "f64")).sum().backward()
+    torch.cuda.synchronize()
+    assert_close(A.grad.cpu().numpy(), oracle.adjoint(inst, W), W, inst, "f64", "grad")
