@@ -141,7 +141,9 @@ __global__ __launch_bounds__(64) void kb_split(const BatchInst* __restrict__ D, 
   }
 }
 
-template <typename T, int Q>
+// EPI: some product of the run has an epilogue (compiled apart: its per-column
+// registers would lower the occupancy of the plain back pass)
+template <typename T, int Q, bool EPI>
 __global__ __launch_bounds__(256) void kb_back(const BatchInst* __restrict__ D, int n,
                                                int64_t total, char* __restrict__ ws) {
   __shared__ BackSmem<T> S;
@@ -152,15 +154,15 @@ __global__ __launch_bounds__(256) void kb_back(const BatchInst* __restrict__ D, 
     const int64_t bx = lb % I.gx_back, rest = lb / I.gx_back;
     const int64_t by = rest % I.gy_back, a = rest / I.gy_back;
     const Epi<T> epi{I.epi_kind, (const T*)I.epi_bias, (const T*)I.epi_scale};
-    back_body<T, Q, false, false, true>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2, I.L,
-                                        I.pairs, I.pow, nullptr, nullptr, nullptr, (T)I.phi0,
-                                        (T*)I.X, I.ldx, I.t, bx, by, a, S, opaque_tid(), epi);
-    if (bx == 0 && a == 0) batch_row0_epi<T>(I, 32 * by, 32, opaque_tid());
+    back_body<T, Q, false, false, EPI>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2, I.L,
+                                       I.pairs, I.pow, nullptr, nullptr, nullptr, (T)I.phi0,
+                                       (T*)I.X, I.ldx, I.t, bx, by, a, S, opaque_tid(), epi);
+    if (EPI && bx == 0 && a == 0) batch_row0_epi<T>(I, 32 * by, 32, opaque_tid());
     __syncthreads();
   }
 }
 
-template <typename T, int Q>
+template <typename T, int Q, bool EPI>
 __global__ __launch_bounds__(256) void kb_back_lds(const BatchInst* __restrict__ D, int n,
                                                    int64_t total, char* __restrict__ ws) {
   __shared__ BackLdsSmem<T, Q> S;
@@ -171,11 +173,11 @@ __global__ __launch_bounds__(256) void kb_back_lds(const BatchInst* __restrict__
     const int64_t bx = lb % I.gx_back, rest = lb / I.gx_back;
     const int64_t by = rest % I.gy_back, a = rest / I.gy_back;
     const Epi<T> epi{I.epi_kind, (const T*)I.epi_bias, (const T*)I.epi_scale};
-    back_lds_body<T, Q, false, false, true>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2,
-                                            I.L, I.pairs, (const cx<T>*)I.twb, I.pow, nullptr,
-                                            nullptr, nullptr, (T)I.phi0, (T*)I.X, I.ldx, I.t, bx,
-                                            by, a, S, opaque_tid(), epi);
-    if (bx == 0 && a == 0) batch_row0_epi<T>(I, 16 * by, 16, opaque_tid());
+    back_lds_body<T, Q, false, false, EPI>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2,
+                                           I.L, I.pairs, (const cx<T>*)I.twb, I.pow, nullptr,
+                                           nullptr, nullptr, (T)I.phi0, (T*)I.X, I.ldx, I.t, bx,
+                                           by, a, S, opaque_tid(), epi);
+    if (EPI && bx == 0 && a == 0) batch_row0_epi<T>(I, 16 * by, 16, opaque_tid());
     __syncthreads();
   }
 }
@@ -194,6 +196,7 @@ struct qmc_batch_s {
   struct Group {
     int R = 0, P2 = 1, Q2 = 1;
     int nt_c = 0;  // streaming stores of the run's intermediate (too large for the cache)
+    int epi = 0;   // some product of the run has an epilogue
     int n = 0;
     BatchInst* d_desc = nullptr;
     int64_t total[NPASS] = {0, 0, 0, 0};
@@ -253,6 +256,7 @@ static int build_runs(qmc_batch_s* B, int64_t chunk, int nt_inter, hipStream_t s
       g.n = (int)v.size();
       // streaming stores of C when it cannot stay in the cache anyway
       g.nt_c = nt_inter ? (nt_inter == 2) : (cbytes > ((int64_t)128 << 20));
+      for (const BatchInst& I : v) g.epi |= I.epi_kind != 0;
       for (int p = 0; p < NPASS; ++p) {
         int64_t o = 0;
         for (BatchInst& I : v) {
@@ -434,8 +438,12 @@ static int run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
   }
   if (g.total[PASS_BACK]) {
     const unsigned gb = grid_for(g.total[PASS_BACK], 1024);
-#define QMC_KBB(QQ) kb_back<T, QQ><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws)
-#define QMC_KBL(QQ) kb_back_lds<T, QQ><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws)
+#define QMC_KBB(QQ)                                                                           \
+  (g.epi ? kb_back<T, QQ, true><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws)     \
+         : kb_back<T, QQ, false><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws))
+#define QMC_KBL(QQ)                                                                           \
+  (g.epi ? kb_back_lds<T, QQ, true><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws) \
+         : kb_back_lds<T, QQ, false><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws))
     switch (g.Q2) {
       case 1: QMC_KBB(1); break;
       case 2: QMC_KBB(2); break;
