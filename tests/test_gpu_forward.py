@@ -195,3 +195,29 @@ def test_errors_on_gpu_calls():
     with pytest.raises(q.QMCError) as e:
         q.matmul(p, Aview, out=Xview)
     assert e.value.code == -5
+
+
+def test_empty_and_degenerate_inputs():
+    """t = 0 columns is refused (QMC_ERR_ARG) before any launch; the smallest
+    rules (N = 2: L = 1; N = 3) and one dimension give the oracle's product;
+    A = 0 gives X = 0 exactly."""
+    torch = torch_cuda()
+    import ctypes
+    import paper_1501_06286_amd as q
+    inst = qi.small_lattice(101, 10, 2, dtype="f64")
+    p = plan_of(inst)
+    A = to_dev(inst.A, "f64")
+    X = torch.empty((101, 2), dtype=torch.float64, device="cuda")
+    ws = p.workspace(2, "cuda")
+    L = q.lib()
+    rc = L.qmc_matmul(p.handle, ctypes.c_void_p(A.data_ptr()), 0, 2, ctypes.c_void_p(X.data_ptr()),
+                      2, ctypes.c_void_p(ws.data_ptr()), ws.numel(), None)
+    assert rc == -1
+    for N, s, t in ((2, 1, 1), (2, 3, 2), (3, 1, 3), (5, 1, 1)):
+        inst = qi.small_lattice(N, s, t, phi=qi.PHI_CENTERED, dtype="f64", seed=N + s)
+        announce(f"degenerate N={N} s={s} t={t}")
+        got = q.matmul(plan_of(inst), to_dev(inst.A, "f64")).cpu().numpy()
+        assert_close(got, oracle.matmul(inst), inst.A, inst, "f64", f"N={N}")
+    Z = torch.zeros((10, 3), dtype=torch.float64, device="cuda")
+    p3 = plan_of(qi.small_lattice(101, 10, 3, dtype="f64"))
+    assert torch.count_nonzero(q.matmul(p3, Z)) == 0
