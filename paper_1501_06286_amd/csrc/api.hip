@@ -96,8 +96,9 @@ int qmc_plan_create(qmc_plan_t* out, int rule, int64_t N, int64_t s, const uint6
 
 static void prof_clear(qmc_plan_t P) {
   for (int k = 0; k < PROF_NSLOTS; ++k) {
-    for (hipEvent_t e : P->prof[k].start) hipEventDestroy(e);
-    for (hipEvent_t e : P->prof[k].stop) hipEventDestroy(e);
+    // release paths: a failed release leaves nothing to recover
+    for (hipEvent_t e : P->prof[k].start) (void)hipEventDestroy(e);
+    for (hipEvent_t e : P->prof[k].stop) (void)hipEventDestroy(e);
     P->prof[k].start.clear();
     P->prof[k].stop.clear();
   }
@@ -107,12 +108,12 @@ void qmc_plan_destroy(qmc_plan_t plan) {
   if (!plan) return;
   prof_clear(plan);
   if (plan->side) {
-    hipStreamSynchronize(plan->side);
-    hipStreamDestroy(plan->side);
+    (void)hipStreamSynchronize(plan->side);
+    (void)hipStreamDestroy(plan->side);
   }
   for (hipEvent_t e : plan->ev)
-    if (e) hipEventDestroy(e);
-  for (void* p : plan->owned) hipFree(p);
+    if (e) (void)hipEventDestroy(e);
+  for (void* p : plan->owned) (void)hipFree(p);
   delete plan;
 }
 

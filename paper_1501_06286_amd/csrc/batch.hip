@@ -212,7 +212,7 @@ static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 
 static void free_runs(qmc_batch_s* B) {
   for (auto& g : B->groups)
-    if (g.d_desc) hipFree(g.d_desc);
+    if (g.d_desc) (void)hipFree(g.d_desc);
   B->groups.clear();
 }
 
