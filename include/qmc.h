@@ -172,9 +172,10 @@ int qmc_plan_set_row_order(qmc_plan_t plan, int order);
  *                Q2 = min(outer_q, M2) values of w2 per output column of the
  *                back pass and one extra split pass when P2 > 1; Q2 <= 32 is
  *                held in registers, 64 and 128 in LDS (128: FP32 plans only).
- *                A power of two <= 128 with P2 <= 64, or 0 for the default
- *                (32, or M2/64 when larger).  The dense fronts' forward split
- *                uses min(Q2, 64)
+ *                A power of two <= 128 with P2 <= 64, or 0 for the default:
+ *                all of M2 when that fits one back pass (M2 <= 128 in FP32,
+ *                64 in FP64: no split pass), else 32, or M2/64 when larger.
+ *                The dense fronts' forward split uses min(Q2, 64)
  *   nt_inter     stores of the intermediate spectrum by the fused pass: 1 =
  *                cached, 2 = streaming (non-temporal), 0 = streaming when one
  *                launch's intermediates (with the dense fronts: both

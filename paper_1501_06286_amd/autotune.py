@@ -20,10 +20,13 @@ CACHE = os.environ.get("QMC_AUTOTUNE_CACHE",
 
 def outer_radices(M2: int, qmax: int = 128) -> List[int]:
     """outer_q values worth trying for an outer length M2: the default (0:
-    32 values of w2 per back-pass output column), 16, and the LDS back pass's
-    64 and 128 (up to qmax, the dtype's limit), as far as the split allows."""
-    return [0] + [q for q in (16, 64, 128)
-                  if M2 > 16 and q <= M2 and M2 // q <= 64 and q <= qmax]
+    all of M2 in one back pass when M2 <= qmax, else 32 values of w2 per
+    back-pass output column), and the other splits: 16 and 32 in registers,
+    the LDS back pass's 64 and 128 (up to qmax, the dtype's limit), as far as
+    the split allows.  A value equal to the default is not tried twice."""
+    qdef = M2 if M2 <= qmax else max(32, M2 // 64)
+    return [0] + [q for q in (16, 32, 64, 128)
+                  if M2 > 16 and q < M2 and M2 // q <= 64 and q <= qmax and q != qdef]
 
 
 def qmax_of(plan) -> int:

@@ -406,12 +406,15 @@ static Layout choose_layout(int64_t L, int dtype, int* embedded) {
 int set_outer_split(Layout& lay, int q, int qmax) {
   // The outer inverse DFT of the back pass takes Q2 values of w2 per output
   // column and the split pass P2 = M2 / Q2 (at most 64).  Q2 <= 32 stays in
-  // registers (32: occupancy 3-4), 64 and 128 go through LDS (qmax: what the
-  // LDS tile of the dtype allows).  The default q = 0 takes 32, more only when
-  // M2 > 32 * 64.  The dense fronts' forward split keeps at most 64 values
-  // per thread in registers: Qf = min(Q2, 64).
+  // registers (32: occupancy 3), 64 and 128 go through LDS (qmax: what the
+  // LDS tile of the dtype allows).  The default q = 0 takes the whole of M2
+  // when it fits one back pass (M2 <= qmax: no split pass; the LDS back pass
+  // costs less than a split pass plus a register back pass), else 32, more
+  // only when M2 > 32 * 64 (with a split pass anyway, the register back pass
+  // is the faster one).  The dense fronts' forward split keeps at most 64
+  // values per thread in registers: Qf = min(Q2, 64).
   if (q < 0 || q > qmax || (q & (q - 1))) return QMC_ERR_ARG;
-  const int64_t qdef = std::max<int64_t>(32, lay.M2 / 64);
+  const int64_t qdef = lay.M2 <= qmax ? lay.M2 : std::max<int64_t>(32, lay.M2 / 64);
   const int64_t Q2 = std::min<int64_t>(q > 0 ? q : qdef, lay.M2);
   if (Q2 > qmax || lay.M2 / Q2 > 64) return QMC_ERR_ARG;
   const int64_t Qf = std::min<int64_t>(Q2, 64);

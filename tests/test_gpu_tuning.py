@@ -109,12 +109,12 @@ def test_dense_front_matches_oracle_and_sparse(kind, n, s, t, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("q,front", [(0, 1), (2, 1), (16, 1), (64, 1), (64, 2), (4, 2),
+@pytest.mark.parametrize("q,front", [(0, 1), (2, 1), (16, 1), (32, 1), (64, 1), (64, 2), (4, 2),
                                      (128, 1), (128, 2)])
 def test_outer_radix(q, front, dtype):
     """Every split M2 = P2 x Q2 of the outer DFT (M = 2^19, M2 = 128) gives the
     oracle's product and adjoint; Q2 = 64 and 128 take the back pass that
-    holds the outer factor in LDS (128: FP32 only)."""
+    holds the outer factor in LDS (128: FP32 only, and FP32's default)."""
     torch = torch_cuda()
     import paper_1501_06286_amd as q_
     inst = qi.small_lattice(139999, 100, 5, phi=qi.PHI_INVNORM, shift=(1, 279998), dtype=dtype,
@@ -128,7 +128,7 @@ def test_outer_radix(q, front, dtype):
     p.set_tuning(outer_q=q, front=front)
     info = p.info()
     assert info["M2"] == 128 and info["P2"] * info["Q2"] == 128
-    assert info["Q2"] == (q if q else 32)
+    assert info["Q2"] == (q if q else (128 if dtype == "f32" else 32))
     A = to_dev(inst.A, dtype)
     X = q_.matmul(p, A)
     rg = np.random.default_rng(1)
@@ -147,7 +147,32 @@ def test_outer_radix_rejects_bad_values():
     for bad in (3, 256, 1, -2):  # not a power of two, above 128, P2 = 128 > 64, negative
         with pytest.raises(q.QMCError):
             p.set_tuning(outer_q=bad)
-    assert p.info()["Q2"] == 32  # unchanged by the rejected calls
+    assert p.info()["Q2"] == 32  # FP64 default, unchanged by the rejected calls
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("N", [100003, 139999])
+def test_default_outer_split(N, dtype):
+    """The default split: one back pass over all of M2 when it fits (M2 = 64:
+    both dtypes; M2 = 128: FP32), else Q2 = 32 after a split pass (FP64 at
+    M2 = 128); product and adjoint match the oracle either way."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q_
+    inst = qi.small_lattice(N, 70, 6, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype, seed=12)
+    announce(f"default outer split N={N} {dtype}")
+    p = plan_of(inst)
+    info = p.info()
+    M2 = info["M2"]
+    assert M2 == (64 if N == 100003 else 128)
+    fits = M2 <= (128 if dtype == "f32" else 64)
+    assert (info["P2"], info["Q2"]) == ((1, M2) if fits else (M2 // 32, 32))
+    X = q_.matmul(p, to_dev(inst.A, dtype))
+    G = np.random.default_rng(13).standard_normal((N, 6))
+    dA = q_.matmul_adjoint(p, to_dev(G, dtype))
+    torch.cuda.synchronize()
+    assert_close(X.double().cpu().numpy(), oracle.matmul(inst), inst.A, inst, dtype, "forward")
+    Gr = G.astype(np.float32).astype(np.float64) if dtype == "f32" else G
+    assert_close(dA.double().cpu().numpy(), oracle.adjoint(inst, Gr), Gr, inst, dtype, "adjoint")
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
