@@ -163,9 +163,10 @@ __global__ __launch_bounds__(256) void kb_back(const BatchInst* __restrict__ D, 
 }
 
 template <typename T, int Q, bool EPI>
-__global__ __launch_bounds__(256) void kb_back_lds(const BatchInst* __restrict__ D, int n,
-                                                   int64_t total, char* __restrict__ ws) {
-  __shared__ BackLdsSmem<T, Q> S;
+__global__ __launch_bounds__((BackLdsShape<Q, back_lds_te<T>()>::BLOCK)) void kb_back_lds(
+    const BatchInst* __restrict__ D, int n, int64_t total, char* __restrict__ ws) {
+  constexpr int TE = back_lds_te<T>();
+  __shared__ BackLdsSmem<T, Q, TE> S;
   InstCursor cur;
   QMC_FOR_BLOCKS(b, total) {
     const BatchInst I = D[inst_at(D, n, PASS_BACK, b, cur)];
@@ -173,7 +174,7 @@ __global__ __launch_bounds__(256) void kb_back_lds(const BatchInst* __restrict__
     const int64_t bx = lb % I.gx_back, rest = lb / I.gx_back;
     const int64_t by = rest % I.gy_back, a = rest / I.gy_back;
     const Epi<T> epi{I.epi_kind, (const T*)I.epi_bias, (const T*)I.epi_scale};
-    back_lds_body<T, Q, false, false, EPI>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2,
+    back_lds_body<T, Q, false, false, EPI, TE>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2,
                                            I.L, I.pairs, (const cx<T>*)I.twb, I.pow, nullptr,
                                            nullptr, nullptr, (T)I.phi0, (T*)I.X, I.ldx, I.t, bx,
                                            by, a, S, opaque_tid(), epi);
@@ -340,9 +341,11 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
     I.nb[PASS_MIDDLE] = ((I.pairs + tpb - 1) / tpb) * lay.M2;
     I.gx_split = (lay.M1 + 63) / 64;
     I.nb[PASS_SPLIT] = lay.P2 > 1 ? I.gx_split * lay.Q2 * I.pairs : 0;
-    const int64_t tb = lay.Q2 >= 64 ? 8 : 16;  // back tile (LDS or register outer DFT)
-    I.gx_back = (lay.M1 + tb - 1) / tb;
-    I.gy_back = (I.pairs + tb - 1) / tb;
+    // back tile: e1 x column pairs (LDS outer DFT: 16 or 8 x 8, register: 16 x 16)
+    const int64_t te = lay.Q2 >= 64 ? (P->dtype == QMC_F32 ? 16 : 8) : 16;
+    const int64_t tp = lay.Q2 >= 64 ? 8 : 16;
+    I.gx_back = (lay.M1 + te - 1) / te;
+    I.gy_back = (I.pairs + tp - 1) / tp;
     I.nb[PASS_BACK] = I.gx_back * I.gy_back * lay.P2;
     const int64_t key = ((int64_t)lay.R << 32) | ((int64_t)lay.P2 << 16) | lay.Q2;
     auto it = std::find_if(byKey.begin(), byKey.end(),
@@ -441,9 +444,11 @@ static int run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
 #define QMC_KBB(QQ)                                                                           \
   (g.epi ? kb_back<T, QQ, true><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws)     \
          : kb_back<T, QQ, false><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws))
-#define QMC_KBL(QQ)                                                                           \
-  (g.epi ? kb_back_lds<T, QQ, true><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws) \
-         : kb_back_lds<T, QQ, false><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws))
+#define QMC_KBL(QQ)                                                                  \
+  (g.epi ? kb_back_lds<T, QQ, true><<<gb, BackLdsShape<QQ, back_lds_te<T>()>::BLOCK, 0, st>>>( \
+               g.d_desc, g.n, g.total[PASS_BACK], ws)                                \
+         : kb_back_lds<T, QQ, false><<<gb, BackLdsShape<QQ, back_lds_te<T>()>::BLOCK, 0, st>>>( \
+               g.d_desc, g.n, g.total[PASS_BACK], ws))
     switch (g.Q2) {
       case 1: QMC_KBB(1); break;
       case 2: QMC_KBB(2); break;

@@ -75,8 +75,8 @@ __global__ __launch_bounds__(256) void k_back(const cx<T>* __restrict__ C, int64
                                 t, blockIdx.x, blockIdx.y, blockIdx.z, S, threadIdx.x, epi);
 }
 
-template <typename T, int Q, bool ADJ, bool NT, bool EPI>
-__global__ __launch_bounds__(256) void k_back_lds(const cx<T>* __restrict__ C, int64_t M1,
+template <typename T, int Q, bool ADJ, bool NT, bool EPI, int TE>
+__global__ __launch_bounds__((BackLdsShape<Q, TE>::BLOCK)) void k_back_lds(const cx<T>* __restrict__ C, int64_t M1,
                                                   int64_t M2, int64_t P2, int64_t L, int64_t P,
                                                   const cx<T>* __restrict__ twb,
                                                   const int32_t* __restrict__ rowmap,
@@ -85,12 +85,12 @@ __global__ __launch_bounds__(256) void k_back_lds(const cx<T>* __restrict__ C, i
                                                   const T* __restrict__ G0, T phi0,
                                                   T* __restrict__ X, int64_t ldx, int64_t t,
                                                   Epi<T> epi) {
-  __shared__ BackLdsSmem<T, Q> S;
+  __shared__ BackLdsSmem<T, Q, TE> S;
   int64_t bx, by, a;
   back_lds_tile(blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z),
                 gridDim.x, gridDim.y, gridDim.z, bx, by, a);
-  back_lds_body<T, Q, ADJ, NT, EPI>(C, M1, M2, P2, L, P, twb, rowmap, inv_ptr, inv_j, G0, phi0,
-                                    X, ldx, t, bx, by, a, S, threadIdx.x, epi);
+  back_lds_body<T, Q, ADJ, NT, EPI, TE>(C, M1, M2, P2, L, P, twb, rowmap, inv_ptr, inv_j, G0,
+                                        phi0, X, ldx, t, bx, by, a, S, threadIdx.x, epi);
 }
 
 // the epilogue of row 0 (its values come from the fused pass's DC term)
@@ -234,10 +234,11 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
                        hipStream_t st, const Epi<T>& epi = Epi<T>()) {
   const Layout& lay = P->lay;
   ProfScope ps(P, ADJ ? PROF_ADJ_BACK : PROF_BACK, st);
-  if (lay.Q2 >= 64) {  // the outer factor through LDS, tiles of 8 e1 x 8 pairs
-    dim3 gl((unsigned)((lay.M1 + 7) / 8), (unsigned)((pairs + 7) / 8), (unsigned)lay.P2);
+  if (lay.Q2 >= 64) {  // the outer factor through LDS, tiles of TE e1 x 8 pairs
+    constexpr int TE = back_lds_te<T>();
+    dim3 gl((unsigned)((lay.M1 + TE - 1) / TE), (unsigned)((pairs + 7) / 8), (unsigned)lay.P2);
 #define QMC_BACKL(QQ)                                                                        \
-  k_back_lds<T, QQ, ADJ, NT, EPI><<<gl, 256, 0, st>>>(                                       \
+  k_back_lds<T, QQ, ADJ, NT, EPI, TE><<<gl, BackLdsShape<QQ, TE>::BLOCK, 0, st>>>(           \
       C, lay.M1, lay.M2, lay.P2, P->L, pairs, (const cx<T>*)P->d_twb, out_rows(P), inv_ptr, inv_j, \
       G0, (T)P->phi0, X, ldx, t, epi)
     if (lay.Q2 == 64) {

@@ -575,8 +575,9 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
 // B for a long outer factor (Q = 64 or 128 values of w2 per output column):
 // the same result as back_body<Q>, with the length-Q inverse DFT done as two
 // register passes through LDS instead of Q values per thread.  A workgroup
-// owns a tile of 8 e1 x 8 column pairs (64 "columns" k = e1l + 8 pl) for one
-// a and keeps the tile's Q x 64 values in LDS.  With Q = F1 F2,
+// (4 threads per column) owns a tile of TE e1 x 8 column pairs (K = 8 TE
+// "columns" (e1l, pl)) for one a and keeps the tile's Q x K values in LDS.
+// With Q = F1 F2,
 //   q = u + F2 v (u < F2, v < F1),   b = c + F1 d (c < F1, d < F2):
 //   pass 1, per (k, u): over v -> c, times W_Q^{u c}    (from global C)
 //   pass 2, per (k, c): over u -> d, in place in LDS    (slot u + F2 c)
@@ -584,22 +585,30 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
 // pairs fastest, so one row's 8 pairs leave as one 8-pair segment.  Thread
 // (pl, eo, w) writes the outputs b = w + 4 j of e1 = e1_0 + eo, pair pl.
 // ---------------------------------------------------------------------------
-template <int Q>
+template <int Q, int TE = 8>
 struct BackLdsShape {
   static constexpr int F1 = 8;
   static constexpr int F2 = Q / F1;
-  static constexpr int TB = 8;  // e1 and column pairs per tile
-  static constexpr int K = TB * TB;
-  static constexpr int BLOCK = 256;
-  static_assert(F1 * F2 == Q && F2 % (BLOCK / K) == 0 && F1 % (BLOCK / K) == 0,
-                "outer factor split");
+  static constexpr int TP = 8;        // column pairs per tile
+  static constexpr int K = TE * TP;   // columns per tile (TE values of e1)
+  static constexpr int NW = 4;        // threads per column
+  static constexpr int BLOCK = NW * K;
+  static_assert(F1 * F2 == Q && F2 % NW == 0 && F1 % NW == 0, "outer factor split");
+  static_assert(TE == 8 || TE == 16, "tile width");
+  // LDS column of (e1 offset el, pair offset pl): with 16 e1 per tile the
+  // rows of e1 are rotated by 4 per two pairs, so that the output reads (8
+  // pairs x 8 e1 per wave) spread over the banks as the loads (16 e1 x 4
+  // pairs) do
+  static __device__ __forceinline__ int col(int el, int pl) {
+    return TE == 16 ? ((el + 4 * (pl >> 1)) & 15) + 16 * pl : el + TE * pl;
+  }
 };
 
 // Workgroup order of the LDS back pass: the workgroups of one XCD take a
 // contiguous run of logical tiles (xcd_remap), and inside it the tiles go in
 // pairs of column-pair tiles (by, by + 1) per e1 tile, e1 tiles next: the two
-// 8-pair halves of a 16-pair row segment of X, and the two 8-e1 halves of a
-// 16-e1 segment of C, are then handled by one L2 at about the same time.
+// 8-pair halves of a 16-pair row segment of X, and (8-e1 tiles) the two halves
+// of a 16-e1 segment of C, are then handled by one L2 at about the same time.
 __device__ __forceinline__ void back_lds_tile(int64_t hw, int64_t gx, int64_t gy, int64_t gz,
                                               int64_t& bx, int64_t& by, int64_t& a) {
   const int64_t per = gx * gy;
@@ -616,12 +625,20 @@ __device__ __forceinline__ void back_lds_tile(int64_t hw, int64_t gx, int64_t gy
   }
 }
 
-template <typename T, int Q>
+// e1 per tile of the LDS back pass: 16 in FP32 (C is read in whole 128-byte
+// lines; 64 or 128 KB of LDS per workgroup), 8 in FP64 (where 16 would halve
+// the occupancy for no gain)
+template <typename T>
+constexpr int back_lds_te() {
+  return sizeof(T) == 4 ? 16 : 8;
+}
+
+template <typename T, int Q, int TE = 8>
 struct BackLdsSmem {
-  cx<T> v[Q * BackLdsShape<Q>::K];
+  cx<T> v[Q * BackLdsShape<Q, TE>::K];
 };
 
-template <typename T, int Q, bool ADJ, bool NT, bool EPI = false>
+template <typename T, int Q, bool ADJ, bool NT, bool EPI = false, int TE = 8>
 __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64_t M1, int64_t M2,
                                               int64_t P2, int64_t L, int64_t P,
                                               const cx<T>* __restrict__ twb,
@@ -631,17 +648,20 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
                                               const T* __restrict__ G0, T phi0,
                                               T* __restrict__ X, int64_t ldx, int64_t t,
                                               int64_t bx, int64_t by, int64_t a,
-                                              BackLdsSmem<T, Q>& S, int tid,
+                                              BackLdsSmem<T, Q, TE>& S, int tid,
                                               const Epi<T> epi = Epi<T>()) {
-  typedef BackLdsShape<Q> B;
-  constexpr int F1 = B::F1, F2 = B::F2, TB = B::TB, K = B::K, NW = B::BLOCK / K;
+  typedef BackLdsShape<Q, TE> B;
+  constexpr int F1 = B::F1, F2 = B::F2, TP = B::TP, K = B::K, NW = B::NW;
   constexpr int T1 = F2 / NW, T2 = F1 / NW;  // pass-1 and pass-2 tasks per thread
   constexpr int NO = Q / NW;                 // output values per thread
   cx<T>* lds = S.v;
-  const int64_t e1_0 = bx * TB, p0 = by * TB;
-  const int k = tid % K, w = tid / K;  // this thread's column and its first task
+  const int64_t e1_0 = bx * TE, p0 = by * TP;
+  const int w = tid / K;  // this thread's first task
+  // load mapping: e1 = e1_0 + tid % TE (fastest: C is contiguous in e1),
+  // pair p0 + (tid / TE) % TP; LDS column kc
+  const int kc = B::col(tid % TE, (tid / TE) % TP);
   // output mapping: column pair pl, e1 = e1_0 + eo, b = w + NW j
-  const int pl = tid % TB, eo = (tid / TB) % TB;
+  const int pl = tid % TP, eo = (tid / TP) % TE;
   const int64_t e1o = e1_0 + eo, pairw = p0 + pl;
   // Every global load of the workgroup is issued before the first use: the
   // output rows (forward), then the tile of C; the workgroup then waits for
@@ -655,7 +675,7 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
     }
   }
   {
-    const int64_t e1 = e1_0 + k % TB, pair = p0 + k / TB;
+    const int64_t e1 = e1_0 + tid % TE, pair = p0 + (tid / TE) % TP;
     const bool ok = pair < P && e1 < M1;
     const cx<T>* base = C + (ok ? pair : 0) * M2 * M1 + (ok ? e1 : 0) + Q * a * M1;
     const int64_t tstep = M2 / Q;  // W_Q^{j} = twb[j M2 / Q]
@@ -683,7 +703,7 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
       for (int c = 1; c < F1; ++c)
         v[it][c] = cmul(v[it][c], twb[(int64_t)(u * c) * tstep & (M2 - 1)]);
 #pragma unroll
-      for (int c = 0; c < F1; ++c) lds[(u + F2 * c) * K + k] = v[it][c];
+      for (int c = 0; c < F1; ++c) lds[(u + F2 * c) * K + kc] = v[it][c];
     }
   }
   __syncthreads();
@@ -693,10 +713,10 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
     const int c = w + NW * it;
     cx<T> v[F2];
 #pragma unroll
-    for (int u = 0; u < F2; ++u) v[u] = lds[(u + F2 * c) * K + k];
+    for (int u = 0; u < F2; ++u) v[u] = lds[(u + F2 * c) * K + kc];
     reg_fft<T, F2, +1>(v);
 #pragma unroll
-    for (int d = 0; d < F2; ++d) lds[(d + F2 * c) * K + k] = v[d];
+    for (int d = 0; d < F2; ++d) lds[(d + F2 * c) * K + kc] = v[d];
   }
   __syncthreads();
   // ---- rows: output b = c + F1 d sits in slot d + F2 c ---------------------
@@ -706,7 +726,7 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
 #pragma unroll
   for (int j = 0; j < NO; ++j) {
     const int b = w + NW * j;
-    const cx<T> o = lds[(b / F1 + F2 * (b % F1)) * K + eo + TB * pl];
+    const cx<T> o = lds[(b / F1 + F2 * (b % F1)) * K + B::col(eo, pl)];
     if constexpr (!ADJ) {
       if (rows[j] >= 0) put_row<T, NT, EPI>(o, rows[j], pairw, X, ldx, t, v2, ec);
     } else {
