@@ -773,14 +773,15 @@ struct RowPairReader {  // columns 2 pair, 2 pair + 1 of a row-major matrix
 
 // The gathers run in three steps so that a thread's loads for several m are
 // in flight together: bounds(m) (the first table lookup), first(b) (the
-// first row), value(b, row, pair).
+// first row), value(b, row, pair).  bounds is only called with 0 <= m < L.
 template <typename T>
 struct AdjGather {
   RowPairReader<T> G;
   const int32_t* __restrict__ pow;
   int64_t L;
+  // m in [0, L): the reflected index (L - m) mod L without a division
   __device__ __forceinline__ int2 bounds(int64_t m) const {
-    return {pow[(L - m) % L], 0};
+    return {pow[m == 0 ? 0 : L - m], 0};
   }
   __device__ __forceinline__ int32_t first(int2 b) const { return b.x; }
   __device__ __forceinline__ cx<T> value(int2, int32_t row, int64_t pair) const {
@@ -794,8 +795,8 @@ struct FwdGather {
   const int32_t* __restrict__ inv_ptr;
   const int32_t* __restrict__ inv_j;
   int64_t L;
-  __device__ __forceinline__ int2 bounds(int64_t m) const {
-    const int64_t e = (L - m) % L;
+  __device__ __forceinline__ int2 bounds(int64_t m) const {  // m in [0, L)
+    const int64_t e = m == 0 ? 0 : L - m;
     return {inv_ptr[e], inv_ptr[e + 1]};
   }
   __device__ __forceinline__ int32_t first(int2 b) const { return b.x < b.y ? inv_j[b.x] : -1; }
