@@ -239,8 +239,9 @@ __device__ __forceinline__ void middle_body(
   typedef MidShape<R> S;
   constexpr int Q = S::Q, M1 = R * R * R, PB = R * (R + 1);
   cx<T>* lds = SM.lds;
-  const int64_t w2 = b % M2;
-  const int64_t pg = b / M2;
+  // M2 is a power of two (M and M1 are): mask and shift, no division
+  const int64_t w2 = b & (M2 - 1);
+  const int64_t pg = b >> __builtin_ctzll((unsigned long long)M2);
   const int tr = tid / Q, q = tid % Q;
   const int64_t pair = pg * S::TPB + tr;
   const bool active = pair < P;
