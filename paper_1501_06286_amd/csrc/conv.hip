@@ -62,7 +62,8 @@ __global__ __launch_bounds__(64) void k_outer_split(cx<T>* __restrict__ C, int64
 }
 
 template <typename T, int Q, bool ADJ, bool NT, bool EPI>
-__global__ __launch_bounds__(256) void k_back(const cx<T>* __restrict__ C, int64_t M1, int64_t M2,
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(back_waves<T, Q>()))) void k_back(const cx<T>* __restrict__ C, int64_t M1, int64_t M2,
                                               int64_t P2, int64_t L, int64_t P,
                                               const int32_t* __restrict__ rowmap,
                                               const int32_t* __restrict__ inv_ptr,

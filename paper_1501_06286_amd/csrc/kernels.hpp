@@ -486,32 +486,50 @@ __device__ __forceinline__ void put_row(cx<T> o, int64_t r, int64_t pairw, T* __
   }
 }
 
-template <typename T, bool ADJ, bool NT, bool EPI>
-__device__ __forceinline__ void put_out(cx<T> o, int64_t e, int64_t pairw,
-                                        const int32_t* __restrict__ rowmap,
-                                        const int32_t* __restrict__ inv_ptr,
-                                        const int32_t* __restrict__ inv_j,
-                                        const T* __restrict__ G0, T phi0, T* __restrict__ X,
-                                        int64_t ldx, int64_t t, bool v2, const EpiCols<T>& ec) {
-  const int64_t col = 2 * pairw;
+// the adjoint's writes for one output e whose rows j (l_j = e) are
+// inv_j[lo .. hi): dA[j] = o + phi(x_0) G[0] (g0, g1: the second term, for
+// columns col and col + 1).  lo, hi and g0, g1 are loaded by the caller
+// together with its other loads, ahead of the transform.
+template <typename T>
+__device__ __forceinline__ void put_adj(cx<T> o, int32_t lo, int32_t hi, int64_t col, T g0, T g1,
+                                        const int32_t* __restrict__ inv_j, T* __restrict__ X,
+                                        int64_t ldx, int64_t t, bool v2) {
   const bool both = col + 1 < t;
-  if constexpr (!ADJ) {
-    put_row<T, NT, EPI>(o, (int64_t)rowmap[e], pairw, X, ldx, t, v2, ec);
-  } else {
-    // the constant row's part phi(x_0) G[0] (none when G0 is null: a point
-    // set without the point 0)
-    const T g0 = G0 ? phi0 * G0[col] : (T)0;
-    const T g1 = (G0 && both) ? phi0 * G0[col + 1] : (T)0;
-    for (int32_t jj = inv_ptr[e]; jj < inv_ptr[e + 1]; ++jj) {
-      T* row = X + (int64_t)inv_j[jj] * ldx;
-      if (v2 && both) {
-        store_pair<T, false>(row + col, o.x + g0, o.y + g1);
-      } else {
-        row[col] = o.x + g0;
-        if (both) row[col + 1] = o.y + g1;
-      }
+  for (int32_t jj = lo; jj < hi; ++jj) {
+    T* row = X + (int64_t)inv_j[jj] * ldx;
+    if (v2 && both) {
+      store_pair<T, false>(row + col, o.x + g0, o.y + g1);
+    } else {
+      row[col] = o.x + g0;
+      if (both) row[col + 1] = o.y + g1;
     }
   }
+}
+
+// the adjoint's per-thread ranges: (lo, hi) of output e (an empty range when
+// e is out of bounds), and the constant row's part for column pair pw
+template <typename T>
+struct AdjRows {
+  T g0 = (T)0, g1 = (T)0;
+  __device__ __forceinline__ void load_g0(const T* __restrict__ G0, T phi0, int64_t pw,
+                                          int64_t t, bool ok) {
+    // no part when G0 is null: a point set without the point 0
+    if (ok && G0) {
+      g0 = phi0 * G0[2 * pw];
+      if (2 * pw + 1 < t) g1 = phi0 * G0[2 * pw + 1];
+    }
+  }
+  static __device__ __forceinline__ int2 range(const int32_t* __restrict__ inv_ptr, int64_t e,
+                                               bool ok) {
+    return ok ? int2{inv_ptr[e], inv_ptr[e + 1]} : int2{0, 0};
+  }
+};
+
+// waves per SIMD the register back pass is compiled for: 32 values of w2 per
+// thread in FP64 would otherwise take all 256 registers (one wave)
+template <typename T, int Q>
+constexpr int back_waves() {
+  return (sizeof(T) == 8 && Q == 32) ? 2 : 1;
 }
 
 template <typename T, int Q, bool ADJ, bool NT, bool EPI = false>
@@ -532,6 +550,25 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
   const bool v2 = pairs_aligned(X, ldx);
   // the epilogue of the columns this thread writes (EPI only)
   const EpiCols<T> ec(EPI ? epi : Epi<T>(), 2 * (p0 + tid % PB), t);
+  const int pw = tid % PB, ew = tid / PB;
+  const int64_t pairw = p0 + pw, e1w = e1_0 + ew;
+  // adjoint: the CSR ranges of this thread's outputs, issued before C (two
+  // registers per output: up to 16 outputs; 32 would cost an occupancy step
+  // that the early loads do not repay, so there they are loaded at the write)
+  constexpr bool PRE = ADJ && Q <= 16;
+  int2 rng[PRE ? Q : 1];
+  AdjRows<T> ar;
+  const bool okw = pairw < P && e1w < M1;
+  if constexpr (ADJ) {
+    if constexpr (PRE) {
+#pragma unroll
+      for (int c = 0; c < Q; ++c) {
+        const int64_t e = e1w + M1 * (a + P2 * c);
+        rng[c] = AdjRows<T>::range(inv_ptr, e, okw && e < L);
+      }
+    }
+    ar.load_g0(G0, phi0, pairw, t, okw);
+  }
   {
     const int64_t e1 = e1_0 + el, pair = p0 + pl;
     cx<T> v[Q];
@@ -550,8 +587,6 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
       v[q] = c;
     }
     reg_fft<T, Q, +1>(v);
-    const int pw = tid % PB, ew = tid / PB;
-    const int64_t pairw = p0 + pw, e1w = e1_0 + ew;
 #pragma unroll
     for (int c0 = 0; c0 < Q; c0 += CH) {
       __syncthreads();
@@ -563,9 +598,11 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
         for (int c = 0; c < CH; ++c) {
           const int64_t e2 = a + P2 * (c0 + c);
           const int64_t e = e1w + M1 * e2;
-          if (e < L)
-            put_out<T, ADJ, NT, EPI>(sm[c][ew][pw], e, pairw, rowmap, inv_ptr, inv_j, G0, phi0,
-                                     X, ldx, t, v2, ec);
+          if constexpr (ADJ) {
+            const int2 r = PRE ? rng[PRE ? c0 + c : 0] : AdjRows<T>::range(inv_ptr, e, e < L);
+            put_adj<T>(sm[c][ew][pw], r.x, r.y, 2 * pairw, ar.g0, ar.g1, inv_j, X, ldx, t, v2);
+          } else if (e < L)
+            put_row<T, NT, EPI>(sm[c][ew][pw], (int64_t)rowmap[e], pairw, X, ldx, t, v2, ec);
         }
       }
     }
@@ -668,12 +705,21 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
   // output rows (forward), then the tile of C; the workgroup then waits for
   // memory once.
   int32_t rows[ADJ ? 1 : NO];
+  int2 rng[ADJ ? NO : 1];  // adjoint: the CSR ranges of the outputs
+  AdjRows<T> ar;
   if constexpr (!ADJ) {
 #pragma unroll
     for (int j = 0; j < NO; ++j) {
       const int64_t e = e1o + M1 * (a + P2 * (w + NW * j));
       rows[j] = (e1o < M1 && e < L) ? rowmap[e] : -1;
     }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NO; ++j) {
+      const int64_t e = e1o + M1 * (a + P2 * (w + NW * j));
+      rng[j] = AdjRows<T>::range(inv_ptr, e, pairw < P && e1o < M1 && e < L);
+    }
+    ar.load_g0(G0, phi0, pairw, t, pairw < P && e1o < M1);
   }
   {
     const int64_t e1 = e1_0 + tid % TE, pair = p0 + (tid / TE) % TP;
@@ -731,10 +777,7 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
     if constexpr (!ADJ) {
       if (rows[j] >= 0) put_row<T, NT, EPI>(o, rows[j], pairw, X, ldx, t, v2, ec);
     } else {
-      const int64_t e = e1o + M1 * (a + P2 * b);
-      if (e1o < M1 && e < L)
-        put_out<T, ADJ, NT, EPI>(o, e, pairw, rowmap, inv_ptr, inv_j, G0, phi0, X, ldx, t, v2,
-                                 ec);
+      put_adj<T>(o, rng[j].x, rng[j].y, 2 * pairw, ar.g0, ar.g1, inv_j, X, ldx, t, v2);
     }
   }
 }
