@@ -866,25 +866,35 @@ __device__ __forceinline__ void outer_front_body(const Gather& gather, int64_t M
   const int pw = tid % PB, ew = tid / PB;     // gather mapping (pair-fast)
   const int el = tid % EB, pl = tid / EB;     // transform mapping (e1-fast)
   const int64_t pairw = p0 + pw, e1w = e1_0 + ew;
+  // GQ values of the thread's gather column are loaded before the first wait
+  // (all of them up to 16; beyond that the registers go to the transform)
+  // and then transposed through LDS CH at a time
+  constexpr int GQ = Q <= 16 ? Q : CH;
   cx<T> v[Q];
 #pragma unroll
-  for (int c0 = 0; c0 < Q; c0 += CH) {
-    __syncthreads();
-    int2 bd[CH];
-    int32_t row[CH];
+  for (int g0 = 0; g0 < Q; g0 += GQ) {
+    int2 bd[GQ];
+    int32_t row[GQ];
+    cx<T> gv[GQ];
 #pragma unroll
-    for (int c = 0; c < CH; ++c) {
-      const int64_t e = e1w + M1 * (a + P2 * (c0 + c));
+    for (int c = 0; c < GQ; ++c) {
+      const int64_t e = e1w + M1 * (a + P2 * (g0 + c));
       bd[c] = (pairw < P && e1w < M1 && e < L) ? gather.bounds(e) : int2{-1, -1};
     }
 #pragma unroll
-    for (int c = 0; c < CH; ++c) row[c] = bd[c].x >= 0 ? gather.first(bd[c]) : -1;
+    for (int c = 0; c < GQ; ++c) row[c] = bd[c].x >= 0 ? gather.first(bd[c]) : -1;
 #pragma unroll
-    for (int c = 0; c < CH; ++c)
-      sm[c][ew][pw] = row[c] >= 0 ? gather.value(bd[c], row[c], pairw) : cx<T>{(T)0, (T)0};
-    __syncthreads();
+    for (int c = 0; c < GQ; ++c)
+      gv[c] = row[c] >= 0 ? gather.value(bd[c], row[c], pairw) : cx<T>{(T)0, (T)0};
 #pragma unroll
-    for (int c = 0; c < CH; ++c) v[c0 + c] = sm[c][el][pl];
+    for (int c0 = 0; c0 < GQ; c0 += CH) {
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < CH; ++c) sm[c][ew][pw] = gv[c0 + c];
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < CH; ++c) v[g0 + c0 + c] = sm[c][el][pl];
+    }
   }
   reg_fft<T, Q, -1>(v);
   if (P2 > 1) {
