@@ -869,7 +869,7 @@ __device__ __forceinline__ void outer_front_body(const Gather& gather, int64_t M
   // GQ values of the thread's gather column are loaded before the first wait
   // (all of them up to 16; beyond that the registers go to the transform)
   // and then transposed through LDS CH at a time
-  constexpr int GQ = Q <= 16 ? Q : CH;
+  constexpr int GQ = Q <= 16 ? Q : 16;
   cx<T> v[Q];
 #pragma unroll
   for (int g0 = 0; g0 < Q; g0 += GQ) {
