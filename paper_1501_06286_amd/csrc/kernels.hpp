@@ -46,6 +46,28 @@ struct CollapseSmem {
   cx<T> sm[64][17];
 };
 
+// acc + the rows idx[k], k in [k0, k1), added in increasing k (the fixed
+// summation order); the loads go out 8 rows at a time, so an item carrying
+// many rows (repeated exponents) waits for memory once per 8 rows, not per row
+template <typename T, typename Row>
+__device__ __forceinline__ cx<T> add_rows(cx<T> acc, const int32_t* __restrict__ idx, int32_t k0,
+                                          int32_t k1, const Row& row) {
+  constexpr int B = 8;
+  int32_t k = k0;
+  for (; k + B <= k1; k += B) {
+    int32_t j[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) j[i] = idx[k + i];
+    cx<T> r[B];
+#pragma unroll
+    for (int i = 0; i < B; ++i) r[i] = row(j[i]);
+#pragma unroll
+    for (int i = 0; i < B; ++i) acc = acc + r[i];
+  }
+  for (; k < k1; ++k) acc = acc + row(idx[k]);
+  return acc;
+}
+
 template <typename T>
 __device__ __forceinline__ void collapse_body(const T* __restrict__ A, int64_t lda, int64_t t,
                                               int64_t P, const int32_t* __restrict__ it_ptr,
@@ -84,7 +106,7 @@ __device__ __forceinline__ void collapse_body(const T* __restrict__ A, int64_t l
   for (int i = 0; i < 4; ++i) v[i] = j0[i] >= 0 ? row_pair(j0[i]) : cx<T>{(T)0, (T)0};
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    for (int32_t k = kb[i] + 1; k < ke[i]; ++k) v[i] = v[i] + row_pair(it_jl[k]);
+    if (kb[i] + 1 < ke[i]) v[i] = add_rows<T>(v[i], it_jl, kb[i] + 1, ke[i], row_pair);
     sm[(tid >> 4) + 16 * i][pl] = v[i];
   }
   __syncthreads();
@@ -848,7 +870,8 @@ struct FwdGather {
     cx<T> acc = {(T)0, (T)0};
     if (row < 0) return acc;
     acc = A(row, pair);
-    for (int32_t jj = b.x + 1; jj < b.y; ++jj) acc = acc + A(inv_j[jj], pair);
+    if (b.x + 1 < b.y)
+      acc = add_rows<T>(acc, inv_j, b.x + 1, b.y, [&](int32_t j) { return A(j, pair); });
     return acc;
   }
 };
