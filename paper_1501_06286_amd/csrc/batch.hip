@@ -163,9 +163,9 @@ __global__ __launch_bounds__(256) void kb_back(const BatchInst* __restrict__ D, 
 }
 
 template <typename T, int Q, bool EPI>
-__global__ __launch_bounds__((BackLdsShape<Q, back_lds_te<T>()>::BLOCK)) void kb_back_lds(
-    const BatchInst* __restrict__ D, int n, int64_t total, char* __restrict__ ws) {
-  constexpr int TE = back_lds_te<T>();
+__global__ __launch_bounds__((BackLdsShape<Q, back_lds_te<T>(), back_lds_nw<T, Q, false>()>::BLOCK))
+void kb_back_lds(const BatchInst* __restrict__ D, int n, int64_t total, char* __restrict__ ws) {
+  constexpr int TE = back_lds_te<T>(), NW = back_lds_nw<T, Q, false>();
   __shared__ BackLdsSmem<T, Q, TE> S;
   InstCursor cur;
   QMC_FOR_BLOCKS(b, total) {
@@ -174,7 +174,7 @@ __global__ __launch_bounds__((BackLdsShape<Q, back_lds_te<T>()>::BLOCK)) void kb
     const int64_t bx = lb % I.gx_back, rest = lb / I.gx_back;
     const int64_t by = rest % I.gy_back, a = rest / I.gy_back;
     const Epi<T> epi{I.epi_kind, (const T*)I.epi_bias, (const T*)I.epi_scale};
-    back_lds_body<T, Q, false, false, EPI, TE>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2,
+    back_lds_body<T, Q, false, false, EPI, TE, NW>((const cx<T>*)(ws + I.C_off), I.M1, I.M2, I.P2,
                                            I.L, I.pairs, (const cx<T>*)I.twb, I.pow, nullptr,
                                            nullptr, nullptr, (T)I.phi0, (T*)I.X, I.ldx, I.t, bx,
                                            by, a, S, opaque_tid(), epi);
@@ -445,10 +445,12 @@ static int run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
   (g.epi ? kb_back<T, QQ, true><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws)     \
          : kb_back<T, QQ, false><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws))
 #define QMC_KBL(QQ)                                                                  \
-  (g.epi ? kb_back_lds<T, QQ, true><<<gb, BackLdsShape<QQ, back_lds_te<T>()>::BLOCK, 0, st>>>( \
-               g.d_desc, g.n, g.total[PASS_BACK], ws)                                \
-         : kb_back_lds<T, QQ, false><<<gb, BackLdsShape<QQ, back_lds_te<T>()>::BLOCK, 0, st>>>( \
-               g.d_desc, g.n, g.total[PASS_BACK], ws))
+  (g.epi ? kb_back_lds<T, QQ, true>                                                  \
+               <<<gb, BackLdsShape<QQ, back_lds_te<T>(), back_lds_nw<T, QQ, false>()>::BLOCK, 0, \
+                  st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws)                       \
+         : kb_back_lds<T, QQ, false>                                                 \
+               <<<gb, BackLdsShape<QQ, back_lds_te<T>(), back_lds_nw<T, QQ, false>()>::BLOCK, 0, \
+                  st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws))
     switch (g.Q2) {
       case 1: QMC_KBB(1); break;
       case 2: QMC_KBB(2); break;

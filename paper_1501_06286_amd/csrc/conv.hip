@@ -76,8 +76,8 @@ __attribute__((amdgpu_waves_per_eu(back_waves<T, Q>()))) void k_back(const cx<T>
                                 t, blockIdx.x, blockIdx.y, blockIdx.z, S, threadIdx.x, epi);
 }
 
-template <typename T, int Q, bool ADJ, bool NT, bool EPI, int TE>
-__global__ __launch_bounds__((BackLdsShape<Q, TE>::BLOCK)) void k_back_lds(const cx<T>* __restrict__ C, int64_t M1,
+template <typename T, int Q, bool ADJ, bool NT, bool EPI, int TE, int NW>
+__global__ __launch_bounds__((BackLdsShape<Q, TE, NW>::BLOCK)) void k_back_lds(const cx<T>* __restrict__ C, int64_t M1,
                                                   int64_t M2, int64_t P2, int64_t L, int64_t P,
                                                   const cx<T>* __restrict__ twb,
                                                   const int32_t* __restrict__ rowmap,
@@ -90,7 +90,7 @@ __global__ __launch_bounds__((BackLdsShape<Q, TE>::BLOCK)) void k_back_lds(const
   int64_t bx, by, a;
   back_lds_tile(blockIdx.x + (int64_t)gridDim.x * (blockIdx.y + (int64_t)gridDim.y * blockIdx.z),
                 gridDim.x, gridDim.y, gridDim.z, bx, by, a);
-  back_lds_body<T, Q, ADJ, NT, EPI, TE>(C, M1, M2, P2, L, P, twb, rowmap, inv_ptr, inv_j, G0,
+  back_lds_body<T, Q, ADJ, NT, EPI, TE, NW>(C, M1, M2, P2, L, P, twb, rowmap, inv_ptr, inv_j, G0,
                                         phi0, X, ldx, t, bx, by, a, S, threadIdx.x, epi);
 }
 
@@ -239,9 +239,10 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
     constexpr int TE = back_lds_te<T>();
     dim3 gl((unsigned)((lay.M1 + TE - 1) / TE), (unsigned)((pairs + 7) / 8), (unsigned)lay.P2);
 #define QMC_BACKL(QQ)                                                                        \
-  k_back_lds<T, QQ, ADJ, NT, EPI, TE><<<gl, BackLdsShape<QQ, TE>::BLOCK, 0, st>>>(           \
-      C, lay.M1, lay.M2, lay.P2, P->L, pairs, (const cx<T>*)P->d_twb, out_rows(P), inv_ptr, inv_j, \
-      G0, (T)P->phi0, X, ldx, t, epi)
+  k_back_lds<T, QQ, ADJ, NT, EPI, TE, back_lds_nw<T, QQ, ADJ>()>                               \
+      <<<gl, BackLdsShape<QQ, TE, back_lds_nw<T, QQ, ADJ>()>::BLOCK, 0, st>>>(                \
+          C, lay.M1, lay.M2, lay.P2, P->L, pairs, (const cx<T>*)P->d_twb, out_rows(P), inv_ptr, \
+          inv_j, G0, (T)P->phi0, X, ldx, t, epi)
     if (lay.Q2 == 64) {
       QMC_BACKL(64);
     } else if constexpr (sizeof(T) == 4) {

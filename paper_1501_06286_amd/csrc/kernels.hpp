@@ -635,7 +635,7 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
 // B for a long outer factor (Q = 64 or 128 values of w2 per output column):
 // the same result as back_body<Q>, with the length-Q inverse DFT done as two
 // register passes through LDS instead of Q values per thread.  A workgroup
-// (4 threads per column) owns a tile of TE e1 x 8 column pairs (K = 8 TE
+// (NW threads per column) owns a tile of TE e1 x 8 column pairs (K = 8 TE
 // "columns" (e1l, pl)) for one a and keeps the tile's Q x K values in LDS.
 // With Q = F1 F2,
 //   q = u + F2 v (u < F2, v < F1),   b = c + F1 d (c < F1, d < F2):
@@ -643,15 +643,15 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
 //   pass 2, per (k, c): over u -> d, in place in LDS    (slot u + F2 c)
 // then the rows e = e1 + M1 (a + P2 b) are written from LDS with the column
 // pairs fastest, so one row's 8 pairs leave as one 8-pair segment.  Thread
-// (pl, eo, w) writes the outputs b = w + 4 j of e1 = e1_0 + eo, pair pl.
+// (pl, eo, w) writes the outputs b = w + NW j of e1 = e1_0 + eo, pair pl.
 // ---------------------------------------------------------------------------
-template <int Q, int TE = 8>
+template <int Q, int TE = 8, int NW_ = 4>
 struct BackLdsShape {
   static constexpr int F1 = 8;
   static constexpr int F2 = Q / F1;
   static constexpr int TP = 8;        // column pairs per tile
   static constexpr int K = TE * TP;   // columns per tile (TE values of e1)
-  static constexpr int NW = 4;        // threads per column
+  static constexpr int NW = NW_;      // threads per column
   static constexpr int BLOCK = NW * K;
   static_assert(F1 * F2 == Q && F2 % NW == 0 && F1 % NW == 0, "outer factor split");
   static_assert(TE == 8 || TE == 16, "tile width");
@@ -693,12 +693,20 @@ constexpr int back_lds_te() {
   return sizeof(T) == 4 ? 16 : 8;
 }
 
+// threads per column of the LDS back pass: 8 (1024- or 512-thread
+// workgroups, half the registers per thread and twice the waves of 4), but 4
+// for the FP32 adjoint at Q = 64, which measured faster so
+template <typename T, int Q, bool ADJ>
+constexpr int back_lds_nw() {
+  return (ADJ && sizeof(T) == 4 && Q == 64) ? 4 : 8;
+}
+
 template <typename T, int Q, int TE = 8>
 struct BackLdsSmem {
   cx<T> v[Q * BackLdsShape<Q, TE>::K];
 };
 
-template <typename T, int Q, bool ADJ, bool NT, bool EPI = false, int TE = 8>
+template <typename T, int Q, bool ADJ, bool NT, bool EPI = false, int TE = 8, int NW_ = 4>
 __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64_t M1, int64_t M2,
                                               int64_t P2, int64_t L, int64_t P,
                                               const cx<T>* __restrict__ twb,
@@ -710,7 +718,7 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
                                               int64_t bx, int64_t by, int64_t a,
                                               BackLdsSmem<T, Q, TE>& S, int tid,
                                               const Epi<T> epi = Epi<T>()) {
-  typedef BackLdsShape<Q, TE> B;
+  typedef BackLdsShape<Q, TE, NW_> B;
   constexpr int F1 = B::F1, F2 = B::F2, TP = B::TP, K = B::K, NW = B::NW;
   constexpr int T1 = F2 / NW, T2 = F1 / NW;  // pass-1 and pass-2 tasks per thread
   constexpr int NO = Q / NW;                 // output values per thread
