@@ -171,7 +171,8 @@ int qmc_plan_set_row_order(qmc_plan_t plan, int order);
  *                (qmc_plan_info) is split as M2 = P2 x Q2 with
  *                Q2 = min(outer_q, M2) values of w2 per output column of the
  *                back pass and one extra split pass when P2 > 1; Q2 <= 32 is
- *                held in registers, 64 and 128 in LDS (128: FP32 plans only).
+ *                held in registers (FP64: up to 16), the larger ones in LDS
+ *                (128: FP32 plans only).
  *                A power of two <= 128 with P2 <= 64, or 0 for the default:
  *                all of M2 when that fits one back pass (M2 <= 128 in FP32,
  *                64 in FP64: no split pass), else 32, or M2/64 when larger.

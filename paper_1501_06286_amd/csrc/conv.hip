@@ -235,7 +235,10 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
                        hipStream_t st, const Epi<T>& epi = Epi<T>()) {
   const Layout& lay = P->lay;
   ProfScope ps(P, ADJ ? PROF_ADJ_BACK : PROF_BACK, st);
-  if (lay.Q2 >= 64) {  // the outer factor through LDS, tiles of TE e1 x 8 pairs
+  // the outer factor through LDS, tiles of TE e1 x 8 pairs: Q2 = 64 and 128,
+  // and 32 in FP64 (its register variant takes all 256 registers and spills;
+  // in FP32 the register variant is the faster one)
+  if (lay.Q2 >= 64 || (sizeof(T) == 8 && lay.Q2 == 32)) {
     constexpr int TE = back_lds_te<T>();
     dim3 gl((unsigned)((lay.M1 + TE - 1) / TE), (unsigned)((pairs + 7) / 8), (unsigned)lay.P2);
 #define QMC_BACKL(QQ)                                                                        \
@@ -249,7 +252,8 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
       if (lay.Q2 != 128) return QMC_ERR_UNSUPPORTED;
       QMC_BACKL(128);
     } else {
-      return QMC_ERR_UNSUPPORTED;
+      if (lay.Q2 != 32) return QMC_ERR_UNSUPPORTED;
+      QMC_BACKL(32);
     }
 #undef QMC_BACKL
     return hip_ok(hipGetLastError());

@@ -698,7 +698,7 @@ constexpr int back_lds_te() {
 // for the FP32 adjoint at Q = 64, which measured faster so
 template <typename T, int Q, bool ADJ>
 constexpr int back_lds_nw() {
-  return (ADJ && sizeof(T) == 4 && Q == 64) ? 4 : 8;
+  return (Q == 32 || (ADJ && sizeof(T) == 4 && Q == 64)) ? 4 : 8;
 }
 
 template <typename T, int Q, int TE = 8>
