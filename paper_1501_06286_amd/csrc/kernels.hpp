@@ -703,7 +703,7 @@ constexpr int back_lds_nw() {
 
 template <typename T, int Q, int TE = 8>
 struct BackLdsSmem {
-  cx<T> v[Q * BackLdsShape<Q, TE>::K];
+  cx<T> v[Q * TE * 8];  // Q x K values, K = TE x 8 column pairs
 };
 
 template <typename T, int Q, bool ADJ, bool NT, bool EPI = false, int TE = 8, int NW_ = 4>
