@@ -342,8 +342,9 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
     I.gx_split = (lay.M1 + 63) / 64;
     I.nb[PASS_SPLIT] = lay.P2 > 1 ? I.gx_split * lay.Q2 * I.pairs : 0;
     // back tile: e1 x column pairs (LDS outer DFT: 16 or 8 x 8, register: 16 x 16)
-    const int64_t te = lay.Q2 >= 64 ? (P->dtype == QMC_F32 ? 16 : 8) : 16;
-    const int64_t tp = lay.Q2 >= 64 ? 8 : 16;
+    const bool lds = lay.Q2 >= 64 || (P->dtype == QMC_F64 && lay.Q2 == 32);
+    const int64_t te = lds ? (P->dtype == QMC_F32 ? 16 : 8) : 16;
+    const int64_t tp = lds ? 8 : 16;
     I.gx_back = (lay.M1 + te - 1) / te;
     I.gy_back = (I.pairs + tp - 1) / tp;
     I.nb[PASS_BACK] = I.gx_back * I.gy_back * lay.P2;
@@ -457,7 +458,13 @@ static int run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
       case 4: QMC_KBB(4); break;
       case 8: QMC_KBB(8); break;
       case 16: QMC_KBB(16); break;
-      case 32: QMC_KBB(32); break;
+      case 32:  // FP64 through LDS, as the single product (the same bits)
+        if constexpr (sizeof(T) == 8) {
+          QMC_KBL(32);
+        } else {
+          QMC_KBB(32);
+        }
+        break;
       case 64: QMC_KBL(64); break;
       case 128:
         if constexpr (sizeof(T) == 4) {

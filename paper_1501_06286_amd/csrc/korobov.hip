@@ -249,7 +249,10 @@ static int korobov_forward(const qmc_korobov_s* U, const T* A, int64_t t, int64_
     }
     if (int rc = ku_split_launch<T, +1>(P, C, nb * pairs, st); rc != QMC_OK) return rc;
     {
-      const int64_t tb = lay.Q2 >= 64 ? 8 : 16;  // back tile (LDS or register outer DFT)
+      // back tile (LDS or register outer DFT; FP64 takes Q2 = 32 through LDS,
+      // as the single product)
+      const bool lds = lay.Q2 >= 64 || (sizeof(T) == 8 && lay.Q2 == 32);
+      const int64_t tb = lds ? 8 : 16;
       const int64_t gx = (lay.M1 + tb - 1) / tb, gy = (pairs + tb - 1) / tb;
       const int64_t per_block = gx * gy * lay.P2;
       T* Xb = X + b0 * (K - 1) * ldx;
@@ -268,7 +271,13 @@ static int korobov_forward(const qmc_korobov_s* U, const T* A, int64_t t, int64_
         case 4: QMC_KBACK(4); break;
         case 8: QMC_KBACK(8); break;
         case 16: QMC_KBACK(16); break;
-        case 32: QMC_KBACK(32); break;
+        case 32:
+          if constexpr (sizeof(T) == 8) {
+            QMC_KBACKL(32);
+          } else {
+            QMC_KBACK(32);
+          }
+          break;
         case 64: QMC_KBACKL(64); break;
         case 128:
           if constexpr (sizeof(T) == 4) {
