@@ -123,7 +123,19 @@ __global__ __launch_bounds__(256) void ku_reduce(const T* __restrict__ Part, int
   if (i >= s * t) return;
   const int64_t j = i / t, k = i % t;
   T acc = accumulate ? dA[j * ldda + k] : (T)0;
-  for (int64_t b = 0; b < nb; ++b) acc += Part[(b * s + j) * t + k];
+  // the parts go out 16 at a time and are added in increasing b
+  const T* p = Part + j * t + k;
+  const int64_t stride = s * t;
+  constexpr int B = 16;
+  int64_t b = 0;
+  for (; b + B <= nb; b += B) {
+    T v[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) v[u] = p[(b + u) * stride];
+#pragma unroll
+    for (int u = 0; u < B; ++u) acc += v[u];
+  }
+  for (; b < nb; ++b) acc += p[b * stride];
   dA[j * ldda + k] = acc;
 }
 
