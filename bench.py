@@ -36,7 +36,7 @@ PAPER_CONTEXT = {
     "fast_entries_per_s": round(64007 * 1000 / 9.827), "std_entries_per_s": round(64007 * 1000 / 8.349),
 }
 HBM_PEAK_GBPS = 8000.0
-# FP32 vector FMA peak without packed FP32 instructions (which this build does
+# FP32 vector FMA peak without packed FP32 instructions (which the library does
 # not use): 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s
 # (157.3 TFLOP/s is the published figure with packed FP32).  FP64 vector: 78.6.
 VALU_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}

@@ -68,7 +68,7 @@ typedef struct qmc_plan_s* qmc_plan_t;
 #define QMC_ERR_WORKSPACE     -6   /* workspace missing or smaller than qmc_workspace_size */
 #define QMC_ERR_OOM           -7   /* device allocation failed while building a plan */
 #define QMC_ERR_HIP           -8   /* a HIP runtime call failed */
-#define QMC_ERR_UNSUPPORTED   -9   /* valid request outside what this build handles */
+#define QMC_ERR_UNSUPPORTED   -9   /* valid request outside what the library handles */
 
 /*
  * qmc_plan_create -- build everything that depends only on the point set.

@@ -82,7 +82,7 @@ const char* qmc_strerror(int code) {
     case QMC_ERR_WORKSPACE: return "workspace missing or too small";
     case QMC_ERR_OOM: return "device allocation failed";
     case QMC_ERR_HIP: return "HIP runtime error";
-    case QMC_ERR_UNSUPPORTED: return "request outside what this build supports";
+    case QMC_ERR_UNSUPPORTED: return "request outside what the library supports";
     default: return "unknown error";
   }
 }
