@@ -26,7 +26,7 @@ struct BatchInst {
   int64_t aT_off, C_off;  // byte offsets into the run's workspace
   const int32_t* it_ptr;
   const int32_t* it_jl;
-  const int32_t* it_e1;
+  const uint16_t* it_e1;
   const int32_t* pow;
   const void* twit;
   const void* twf1;

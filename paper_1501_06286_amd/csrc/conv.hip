@@ -44,7 +44,7 @@ __global__ __launch_bounds__(256) void k_collapse_T(const T* __restrict__ A, int
 template <typename T, int R, bool SPARSE>
 __global__ __launch_bounds__(MidShape<R>::BLOCK)
 __attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void k_middle(
-    const cx<T>* __restrict__ src, int64_t Upad, int64_t rounds, const int32_t* __restrict__ it_e1,
+    const cx<T>* __restrict__ src, int64_t Upad, int64_t rounds, const uint16_t* __restrict__ it_e1,
     const cx<T>* __restrict__ twit, const cx<T>* __restrict__ twf1,
     const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs,
     const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M2, int64_t P,

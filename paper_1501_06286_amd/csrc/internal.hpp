@@ -65,7 +65,7 @@ struct qmc_plan_s {
   void* d_two = nullptr;        // M2*R: conj W_M^{R^2 c w2} in [w2][c] order
   void* d_twit = nullptr;       // M2*Upad: W_M^{slot_u w2} in [w2][u] order
   void* d_twb = nullptr;        // M2  : conj W_{M2}^k, the outer split's twiddles at k = a q mod M2
-  int32_t* d_it_e1 = nullptr;   // Upad: e1 of item u (M1 for padding)
+  uint16_t* d_it_e1 = nullptr;  // Upad: e1 of item u (M1 for padding; M1 <= 4096)
   int32_t* d_it_ptr = nullptr;  // Upad+1: rows of item u are it_jl[it_ptr[u] .. it_ptr[u+1])
   int32_t* d_it_jl = nullptr;   // s   : rows j grouped by item (increasing j)
   int32_t* d_inv_ptr = nullptr;    // L+1 : rows j with l_j = e are inv_j[inv_ptr[e] .. inv_ptr[e+1])
@@ -89,7 +89,7 @@ struct qmc_korobov_s {
   int64_t rounds = 0, Upad = 0;  // common collapse schedule size of every block
   int32_t* d_it_ptr = nullptr;   // blocks*(Upad+1), offsets into the block's s rows
   int32_t* d_it_jl = nullptr;    // blocks*s
-  int32_t* d_it_e1 = nullptr;    // blocks*Upad
+  uint16_t* d_it_e1 = nullptr;   // blocks*Upad
   void* d_twit = nullptr;        // blocks*M2*Upad: W_M^{slot w2} per block
   int32_t* d_rowmap = nullptr;   // L: pow[e] - 1 (row n - 1 of a block)
   int32_t* d_inv_ptr = nullptr;  // blocks*(L+1): per block, CSR of the rows j with l_{b,j} = e

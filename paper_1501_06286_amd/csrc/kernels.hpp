@@ -252,7 +252,7 @@ struct MidSmem {
 template <typename T, int R, bool SPARSE>
 __device__ __forceinline__ void middle_body(
     const cx<T>* __restrict__ src,      // SPARSE: aT [pair][Upad]; dense: B [pair][M2][M1]
-    int64_t Upad, int64_t rounds, const int32_t* __restrict__ it_e1,
+    int64_t Upad, int64_t rounds, const uint16_t* __restrict__ it_e1,
     const cx<T>* __restrict__ twit, const cx<T>* __restrict__ twf1,
     const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs,
     const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M2, int64_t P,
@@ -306,11 +306,12 @@ __device__ __forceinline__ void middle_body(
       for (int i = 0; i < NB; i += PP) {
         const int u = (((r0 + i) / PP * S::F + fo) * S::G + ln) * PP;  // items k, k+1 adjacent
         if constexpr (PP == 2) {
-          const int2 ee = *reinterpret_cast<const int2*>(it_e1 + u);
+          // two 16-bit residues in one 32-bit load (u is even)
+          const uint32_t ee = *reinterpret_cast<const uint32_t*>(it_e1 + u);
           const cx2<T> vv = *reinterpret_cast<const cx2<T>*>(av + u);
           const cx2<T> ww = *reinterpret_cast<const cx2<T>*>(tw + u);
-          e1[i] = ee.x;
-          e1[i + 1] = ee.y;
+          e1[i] = (int)(ee & 0xffffu);
+          e1[i + 1] = (int)(ee >> 16);
           v[i] = vv.a;
           v[i + 1] = vv.b;
           w[i] = ww.a;

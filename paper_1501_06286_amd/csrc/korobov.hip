@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void ku_collapse(const T* __restrict__ A, int6
 template <typename T, int R>
 __global__ __launch_bounds__(MidShape<R>::BLOCK)
 __attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void ku_middle(
-    const cx<T>* __restrict__ aT, int64_t Upad, int64_t rounds, const int32_t* __restrict__ it_e1,
+    const cx<T>* __restrict__ aT, int64_t Upad, int64_t rounds, const uint16_t* __restrict__ it_e1,
     const cx<T>* __restrict__ twit, const cx<T>* __restrict__ twf1,
     const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs,
     const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M1, int64_t M2,

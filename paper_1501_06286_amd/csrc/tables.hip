@@ -627,11 +627,13 @@ int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st) {
 
     // ---- collapse schedule ----------------------------------------------
     Schedule sc = make_schedule(lay, L, s, ell.data());
+    // the residues go to the device as 16-bit values (e1 <= M1 <= 4096)
+    const std::vector<uint16_t> e16(sc.it_e1.begin(), sc.it_e1.end());
     P->rounds = sc.rounds;
     P->Upad = sc.Upad;
     P->d_it_ptr = dev_alloc<int32_t>(P, P->Upad + 1, &err);
     P->d_it_jl = dev_alloc<int32_t>(P, s, &err);
-    P->d_it_e1 = dev_alloc<int32_t>(P, P->Upad, &err);
+    P->d_it_e1 = dev_alloc<uint16_t>(P, P->Upad, &err);
     P->d_inv_ptr = dev_alloc<int32_t>(P, L + 1, &err);
     P->d_inv_j = dev_alloc<int32_t>(P, s, &err);
     if ((rc = err) != QMC_OK) break;
@@ -651,8 +653,8 @@ int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st) {
     if (rc == QMC_OK)
       rc = hip_ok(hipMemcpyAsync(P->d_it_jl, sc.it_jl.data(), s * 4, hipMemcpyHostToDevice, st));
     if (rc == QMC_OK)
-      rc = hip_ok(hipMemcpyAsync(P->d_it_e1, sc.it_e1.data(), P->Upad * 4, hipMemcpyHostToDevice,
-                                 st));
+      rc = hip_ok(hipMemcpyAsync(P->d_it_e1, e16.data(), P->Upad * sizeof(uint16_t),
+                                 hipMemcpyHostToDevice, st));
     if (rc == QMC_OK)
       rc = hip_ok(hipMemcpyAsync(d_slot, sc.it_slot.data(), P->Upad * 4, hipMemcpyHostToDevice,
                                  st));
@@ -731,7 +733,8 @@ int build_korobov_tables(qmc_korobov_s* U, hipStream_t st) {
   U->rounds = rounds;
   U->Upad = scs[0].Upad;
   const int64_t Upad = U->Upad;
-  std::vector<int32_t> it_ptr(nb * (Upad + 1)), it_jl(nb * s), it_e1(nb * Upad), slot(nb * Upad);
+  std::vector<int32_t> it_ptr(nb * (Upad + 1)), it_jl(nb * s), slot(nb * Upad);
+  std::vector<uint16_t> it_e1(nb * Upad);  // 16-bit residues (e1 <= M1 <= 4096)
   for (int64_t b = 0; b < nb; ++b) {
     std::copy(scs[b].it_ptr.begin(), scs[b].it_ptr.end(), it_ptr.begin() + b * (Upad + 1));
     std::copy(scs[b].it_jl.begin(), scs[b].it_jl.end(), it_jl.begin() + b * s);
@@ -743,7 +746,7 @@ int build_korobov_tables(qmc_korobov_s* U, hipStream_t st) {
   const size_t el = P->dtype == QMC_F32 ? sizeof(cx<float>) : sizeof(cx<double>);
   U->d_it_ptr = dev_alloc<int32_t>(P, nb * (Upad + 1), &err);
   U->d_it_jl = dev_alloc<int32_t>(P, nb * s, &err);
-  U->d_it_e1 = dev_alloc<int32_t>(P, nb * Upad, &err);
+  U->d_it_e1 = dev_alloc<uint16_t>(P, nb * Upad, &err);
   U->d_rowmap = dev_alloc<int32_t>(P, L, &err);
   U->d_twit = dev_alloc<char>(P, nb * M2 * Upad * el, &err);
   U->d_inv_ptr = dev_alloc<int32_t>(P, nb * (L + 1), &err);
@@ -760,7 +763,7 @@ int build_korobov_tables(qmc_korobov_s* U, hipStream_t st) {
       rc = hip_ok(hipMemcpyAsync(U->d_it_jl, it_jl.data(), nb * s * 4, hipMemcpyHostToDevice,
                                  st));
     if (rc == QMC_OK)
-      rc = hip_ok(hipMemcpyAsync(U->d_it_e1, it_e1.data(), nb * Upad * 4, hipMemcpyHostToDevice,
+      rc = hip_ok(hipMemcpyAsync(U->d_it_e1, it_e1.data(), nb * Upad * sizeof(uint16_t), hipMemcpyHostToDevice,
                                  st));
     if (rc == QMC_OK)
       rc = hip_ok(hipMemcpyAsync(d_slot, slot.data(), nb * Upad * 4, hipMemcpyHostToDevice, st));
