@@ -192,7 +192,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // rounds of the sparse front whose loads are issued together (a shorter
 // tail batch covers the rest)
-constexpr int MID_RB = 4;
+constexpr int MID_RB = 8;
 
 // Per-thread tables keep each thread's consecutive values in adjacent
 // pairs, so one 16-byte load (FP32) brings two complex values: value h of
