@@ -361,7 +361,11 @@ __device__ __forceinline__ void middle_body(
 #pragma unroll
   for (int f = 1; f < R; ++f) x[f] = cmul(x[f], tw_a[f]);
   const int gl = q % R;
-  load_paired<T, R>(hv, Hs + w2 * M1, q, Q);  // two steps early
+  // the spectrum two steps early; the FP32 dense-front variant, which holds
+  // more registers at this point (it spilled), loads it where it is used
+  // (FP64 keeps the early load: its occupancy is set by LDS, not registers)
+  constexpr bool EARLY_HV = SPARSE || sizeof(T) == 8;
+  if constexpr (EARLY_HV) load_paired<T, R>(hv, Hs + w2 * M1, q, Q);
   __syncthreads();
 #pragma unroll
   for (int f = 0; f < R; ++f) buf[f * PB + q] = x[f];
@@ -390,6 +394,7 @@ __device__ __forceinline__ void middle_body(
     X[2 * pair] = phi0 * x[0].x;
     if (2 * pair + 1 < t) X[2 * pair + 1] = phi0 * x[0].y;
   }
+  if constexpr (!EARLY_HV) load_paired<T, R>(hv, Hs + w2 * M1, q, Q);
 #pragma unroll
   for (int h = 0; h < R; ++h) x[h] = cmul(x[h], hv[h]);
 
