@@ -1,18 +1,39 @@
 #!/usr/bin/env python3
 """Benchmark of the fast QMC matrix product X = Y A on one MI355X.
 
-Workload (one GPU): Gaussian sampling with a general covariance, rank-1
-lattice rule with N = 65537 points (N - 1 = 2^16), s = t = 4096, phi = inverse
-normal CDF applied to {n z_j / N + 1/(2N)}, A = upper Cholesky factor of
-exp(-|i-j|/410), FP32 (and FP64 beside it).  One step = one full qmc_matmul:
-collapse-transpose, fused sparse-DFT / FFT / spectral product / inverse FFT,
-outer inverse DFT with the row un-permutation.  Plan construction (tables,
-spectrum) is excluded from the timed region, as in the paper's experiments.
+Headline workload (one GPU): Gaussian sampling with a general covariance,
+rank-1 lattice rule with N = 65537 points (N - 1 = 2^16), s = t = 4096,
+phi = inverse normal CDF applied to {n z_j / N + 1/(2N)}, A = upper Cholesky
+factor of exp(-|i-j|/410), in FP64 (the precision of the paper's
+experiments), with the same product in FP32 beside it.  One step = one full
+qmc_matmul: collapse-transpose, fused sparse-DFT / FFT / spectral product /
+inverse FFT, outer inverse DFT with the row un-permutation.  Plan
+construction (tables, spectrum) is excluded from the timed region, as in the
+paper's experiments (Section 4).
 
-Prints ONE JSON line:  metric, value (entries/s = N t / time), roofline of the
-dominant kernel (per-kernel HIP-event times measured in the timed region),
-cpu_baseline (the FP64 CPU oracle on a bounded sample of rows), the dense MFMA
-GEMM on the same GPU, and the FP64 path.
+The other legs time the remaining workloads of the same family: the adjoint
+dA = Y^T G, 256 uneven products in one batch, the PDE-field product on a
+polynomial lattice rule (with its epilogue), the union of Korobov rules, the
+large rule N = 1048573 (forward and adjoint), and the dense MFMA GEMM on the
+explicit Y.  The last leg, cpu_baseline, times the FP64 CPU oracle on a
+bounded row sample (median and mean of 5) and compares sampled rows of every
+GPU result with the oracle.
+
+Prints ONE JSON line.  Per leg: the time per step (plain wall clock over the
+timed steps), per-kernel HIP-event times (a second, instrumented pass over
+the same steps), the roofline of the leg's dominant kernel in the units of
+the algorithmic model below, and the whole step's fractions of the HBM and
+vector peaks.
+
+Algorithmic model (per column of X; w bytes per real, L = N - 1):
+  bytes  w (s + N)                       (A read once, X written once)
+  flops  (5 log2 L + 3) L + 2 s          (a forward and an inverse complex
+                                          transform of length L per column
+                                          pair at the nominal 5 n log2 n each,
+                                          the spectral product, and the
+                                          collapse and constant row)
+The dominant kernel of a leg is credited with the flops of the columns one of
+its launches processes.
 """
 import argparse
 import hashlib
@@ -36,37 +57,29 @@ PAPER_CONTEXT = {
     "fast_entries_per_s": round(64007 * 1000 / 9.827), "std_entries_per_s": round(64007 * 1000 / 8.349),
 }
 HBM_PEAK_GBPS = 8000.0
-# FP32 vector FMA peak without packed FP32 instructions (which the library does
-# not use): 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz = 78.6 TFLOP/s
-# (157.3 TFLOP/s is the published figure with packed FP32).  FP64 vector: 78.6.
-VALU_PEAK_TFLOPS = {"f32": 78.6, "f64": 78.6}
+# Published MI355X vector peaks: FP32 157.3 TFLOP/s (counts packed FP32
+# instructions), FP64 78.6.  The library is built without packed FP32, so its
+# attainable FP32 vector rate is 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
+# = 78.6 TFLOP/s, reported beside the published figure.
+VALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+VALU_NONPACKED_TFLOPS = {"f32": 78.6, "f64": 78.6}
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
+LEGS = ("c2", "c2_other", "adjoint", "batched", "pde", "korobov", "c5", "dense", "cpu")
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def kernel_model(plan_info, pairs, t, w, N, s):
-    """Algorithmic bytes and flops per launch of each kernel of one step.
+def wbytes(dtype):
+    return 4 if dtype == "f32" else 8
 
-    Bytes count each operand the kernel must read or write in HBM once
-    (plan tables that stay in cache are not counted); flops are the nominal
-    5 n log2 n per complex DFT of length n, 6 per complex product, 8 per
-    complex multiply-add of the sparse outer DFT."""
-    M, M1, M2 = plan_info["M"], plan_info["M1"], plan_info["M2"]
-    R = int(round(M1 ** (1.0 / 3.0)))
-    U = plan_info["rounds"] * R * R  # scheduled items (s plus padding)
-    el = 2 * w
-    lg = lambda n: math.log2(n) if n > 1 else 0.0
-    out = {
-        "collapse_T": {"bytes": s * t * w + pairs * U * el, "flops": 0.0},
-        "middle": {"bytes": pairs * U * el + pairs * M * el,
-                   "flops": pairs * M2 * (2 * 5 * M1 * lg(M1) + 6 * M1 + 8 * U)},
-        "outer_split": {"bytes": 2 * pairs * M * el, "flops": pairs * M1 * M2 * 5 * lg(M2)},
-        "back": {"bytes": pairs * M * el + N * t * w, "flops": pairs * M1 * M2 * 5 * lg(M2)},
-    }
-    return out
+
+def col_model(N, s, w):
+    """Algorithmic bytes and flops per column of X (see the module docstring)."""
+    L = N - 1
+    lg = math.log2(L) if L > 1 else 0.0
+    return {"bytes": w * (s + N), "flops": (5.0 * lg + 3.0) * L + 2.0 * s}
 
 
 # the sources of the single-plan kernels whose traffic is recorded (device
@@ -117,55 +130,128 @@ def time_steps(fn, steps, torch):
     return time.perf_counter() - t0
 
 
-def roofline_of(name, model, per_launch, avg_s, dtype):
-    """Roofline entry of one kernel: ALU-bound above the ridge point."""
-    m = {k: v / per_launch for k, v in model[name].items()}
-    ai = m["flops"] / max(m["bytes"], 1)
-    ridge = VALU_PEAK_TFLOPS[dtype] * 1e12 / (HBM_PEAK_GBPS * 1e9)
-    if ai > ridge:
-        ach = m["flops"] / avg_s / 1e12
-        return {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_TFLOPS[dtype],
-                "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS[dtype], 4), "kernel": name}
-    ach = m["bytes"] / avg_s / 1e9
-    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBPS, 4), "kernel": name}
+def kernel_times(plan, fn, steps, torch):
+    """The same steps again with HIP events around every kernel launch (on the
+    stream each kernel is launched on): {slot: (total ms, launches)}."""
+    plan.profile(True)
+    time_steps(fn, steps, torch)
+    prof = plan.profile_collect()
+    plan.profile(False)
+    return prof
 
 
-def korobov_model(info, pairs, t, w):
-    """Algorithmic bytes and flops of every kernel for all K - 1 blocks: each
-    block is a lattice product of K points with its own collapse of A."""
-    K = info["K"]
-    one = kernel_model({"M": info["M"], "M1": info["M1"], "M2": info["M2"],
-                        "rounds": info["rounds"]}, pairs, t, w, K - 1, info["s"])
-    return {k: {kk: vv * info["blocks"] for kk, vv in v.items()} for k, v in one.items()}
+def leg_roofline(prof, steps, N, s, t, dtype, workload=None, tuning=None):
+    """Per-kernel table and the roofline of the dominant kernel (the slot with
+    the most time): the algorithmic flops and bytes of the columns one launch
+    processes (t / launches per step), over the kernel's average HIP-event
+    launch time.  The fused FFT kernel's own traffic (its intermediate in
+    and out of cache) is far below its flops at the vector ridge, so it is
+    reported against the vector peak; the bytes figure is given beside it."""
+    w = wbytes(dtype)
+    cm = col_model(N, s, w)
+    kernels = {}
+    for name, (tot, n) in prof.items():
+        kernels[name] = {"avg_ms": round(tot / n, 4), "launches_per_step": n / steps,
+                         "ms_per_step": round(tot / steps, 4)}
+    dom = max(prof, key=lambda k: prof[k][0])
+    tot, n = prof[dom]
+    per_step = n / steps
+    cols = t / per_step
+    avg_s = tot / n * 1e-3
+    fl = cm["flops"] * cols / avg_s / 1e12
+    by = cm["bytes"] * cols / avg_s / 1e9
+    roof = {"bound": "alu", "achieved": round(fl, 3), "peak": VALU_PEAK_TFLOPS[dtype],
+            "unit": "TFLOP/s", "frac": round(fl / VALU_PEAK_TFLOPS[dtype], 4),
+            "traffic": measured_traffic(dom, workload, tuning) if workload else None,
+            "kernel": dom, "avg_launch_ms": round(tot / n, 4), "columns_per_launch": cols,
+            "flops_per_launch": cm["flops"] * cols, "bytes_per_launch": cm["bytes"] * cols,
+            "peak_nonpacked": VALU_NONPACKED_TFLOPS[dtype],
+            "frac_nonpacked": round(fl / VALU_NONPACKED_TFLOPS[dtype], 4),
+            "bytes_GBps": round(by, 1), "bytes_frac_hbm": round(by / HBM_PEAK_GBPS, 4)}
+    return kernels, roof
 
 
-def cpu_baseline(inst, budget_s=12.0):
-    """The FP64 oracle (explicit Y rows, dense product) on a bounded sample."""
+def path_fractions(N, s, t, dtype, ms_step):
+    """The whole step against the peaks: algorithmic bytes over HBM, flops over
+    the published vector peak and the non-packed one."""
+    cm = col_model(N, s, wbytes(dtype))
+    sec = ms_step * 1e-3
+    gbps = cm["bytes"] * t / sec / 1e9
+    tf = cm["flops"] * t / sec / 1e12
+    return {"alg_bytes": cm["bytes"] * t, "alg_flops": cm["flops"] * t,
+            "hbm_GBps": round(gbps, 1), "hbm_frac": round(gbps / HBM_PEAK_GBPS, 4),
+            "TFLOPs": round(tf, 2), "valu_frac": round(tf / VALU_PEAK_TFLOPS[dtype], 4),
+            "valu_frac_nonpacked": round(tf / VALU_NONPACKED_TFLOPS[dtype], 4)}
+
+
+def sample_rows(N, k, seed):
     import numpy as np
-    import oracle
-    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
-    try:
-        from threadpoolctl import threadpool_info
-        bl = [p.get("num_threads") for p in threadpool_info() if p.get("user_api") == "blas"]
-        if bl:
-            threads = int(bl[0])
-    except Exception:
-        pass
-    rng = np.random.default_rng(150106286 + 2000 + 7)
-    probe = 256
-    rows = np.sort(rng.choice(inst.N, size=probe, replace=False))
-    t0 = time.perf_counter()
-    oracle.matmul_rows(inst, rows)
-    dt = time.perf_counter() - t0
-    n = int(min(inst.N, max(probe, probe * budget_s / max(dt, 1e-3))))
-    rows = np.sort(rng.choice(inst.N, size=n, replace=False))
-    t0 = time.perf_counter()
-    oracle.matmul_rows(inst, rows)
-    dt = time.perf_counter() - t0
-    return {"value": n * inst.t / dt, "unit": "entries/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} seeded rows of {inst.N} (all s={inst.s}, t={inst.t}), FP64 explicit Y "
-                      f"+ numpy matmul, {dt:.1f} s"}
+    rg = np.random.default_rng(150106286 + 7000 + seed)
+    rows = set(rg.choice(N, size=min(k, N), replace=False).tolist()) | {0, N - 1}
+    return np.array(sorted(rows))
+
+
+def rows_to_host(X, rows, torch):
+    import numpy as np
+    return X[torch.from_numpy(np.asarray(rows)).to(X.device)].double().cpu().numpy()
+
+
+class Leg:
+    """One timed workload and what the oracle check needs from it."""
+
+    def __init__(self, name):
+        self.name = name
+        self.out = {}
+        self.checks = []  # (label, inst, rows, gpu rows) or ("adjoint", inst, entries, G cols, got)
+
+
+def tune_plan(plan, t, args):
+    if args.no_tune:
+        return plan.get_tuning()
+    from paper_1501_06286_amd import autotune
+    best, _ = autotune.tune(plan, t, reps=3)
+    return best
+
+
+def forward_leg(name, inst, args, torch, q, dev, profile=True, nrows=64):
+    """Time qmc_matmul on one instance; per-kernel events and the roofline."""
+    tdt = torch.float32 if inst.dtype == "f32" else torch.float64
+    plan = q.Plan.from_instance(inst)
+    info = plan.info()
+    log(f"{name}: {inst.name} {inst.dtype} L={info['L']} M={info['M']} M1={info['M1']} "
+        f"M2={info['M2']} rounds={info['rounds']}")
+    tuning = tune_plan(plan, inst.t, args)
+    if args.tuning and name in ("c2", "c2_other"):
+        keys = ("chunk_pairs", "streams", "nt_store", "front", "outer_q", "nt_inter")
+        plan.set_tuning(**dict(zip(keys, [int(v) for v in args.tuning.split(",")])))
+        tuning = plan.get_tuning()
+    log(f"{name}: launch tuning {tuning}")
+    A = torch.from_numpy(inst.A).to(tdt).to(dev)
+    X = torch.empty((inst.N, inst.t), dtype=tdt, device=dev)
+    ws = plan.workspace(inst.t, dev)
+    step = lambda: q.matmul(plan, A, out=X, workspace=ws)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    steps = args.steps
+    el = time_steps(step, steps, torch)
+    ms = 1e3 * el / steps
+    leg = Leg(name)
+    wl = f"{inst.name}_{inst.dtype}"
+    leg.out = {"workload": wl, "dtype": inst.dtype, "N": inst.N, "s": inst.s, "t": inst.t,
+               "M": info["M"], "M1": info["M1"], "M2": info["M2"], "tuning": tuning,
+               "ms_per_step": round(ms, 4), "value": inst.N * inst.t / (el / steps),
+               "unit": "entries/s", "path": path_fractions(inst.N, inst.s, inst.t, inst.dtype, ms)}
+    if profile:
+        prof = kernel_times(plan, step, steps, torch)
+        kern, roof = leg_roofline(prof, steps, inst.N, inst.s, inst.t, inst.dtype, wl, tuning)
+        leg.out["kernels"] = kern
+        leg.out["roofline"] = roof
+    log(f"{name}: {ms:.3f} ms/step, {leg.out['value']:.4e} entries/s, "
+        f"HBM {leg.out['path']['hbm_frac']:.3f}")
+    rows = sample_rows(inst.N, nrows, len(name))
+    leg.checks.append(("X", inst, rows, rows_to_host(X, rows, torch)))
+    return leg, plan, A, X, ws
 
 
 def main():
@@ -173,21 +259,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--dtype", default="f32", choices=["f32", "f64"])
-    ap.add_argument("--s", type=int, default=4096)
-    ap.add_argument("--no-dense", action="store_true")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-f64", action="store_true")
+    ap.add_argument("--dtype", default="f64", choices=["f32", "f64"],
+                    help="headline precision (the other one is timed beside it)")
+    ap.add_argument("--legs", default=",".join(LEGS),
+                    help=f"comma-separated subset of {','.join(LEGS)}")
     ap.add_argument("--no-tune", action="store_true", help="use the default launch tuning")
     ap.add_argument("--tuning", default=None,
-                    help="fixed launch tuning chunk_pairs,streams,nt_store,front[,outer_q,nt_inter] "
-                         "instead of autotuning")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-korobov", action="store_true")
-    ap.add_argument("--no-pde", action="store_true")
+                    help="fixed launch tuning of the C2 legs: "
+                         "chunk_pairs,streams,nt_store,front,outer_q,nt_inter")
     ap.add_argument("--fft-only", action="store_true",
-                    help="time only the FFT path (for profiler runs)")
+                    help="time only the headline FFT product (for profiler runs)")
     ap.add_argument("--dense-only", action="store_true",
                     help="time only the dense MFMA GEMM baseline (for profiler runs)")
     ap.add_argument("--vendor-context", action="store_true",
@@ -201,9 +282,12 @@ def main():
               f"of A are independent, so a multi-GPU run would give each GPU a slice of them "
               f"with a replicated plan and no communication", file=sys.stderr)
         sys.exit(2)
+    legs = set(args.legs.split(","))
+    bad = legs - set(LEGS)
+    if bad:
+        ap.error(f"unknown legs {sorted(bad)}")
     if args.fft_only:
-        args.no_dense = args.no_cpu = args.no_f64 = args.no_batched = args.no_adjoint = True
-        args.no_korobov = args.no_pde = True
+        legs = {"c2"}
     if args.copy_calibration:
         import torch
         n = 1 << 28  # 2^28 float32 = 1 GiB
@@ -221,9 +305,11 @@ def main():
     import qmc_inputs as qi
 
     dev = torch.device("cuda:0")
-    inst = qi.make_c2(args.dtype, s=args.s)
+    hd = args.dtype
+    other = "f32" if hd == "f64" else "f64"
     if args.dense_only:
-        tdt = torch.float32 if args.dtype == "f32" else torch.float64
+        inst = qi.make_c2(hd)
+        tdt = torch.float32 if hd == "f32" else torch.float64
         plan = q.Plan.from_instance(inst)
         A = torch.from_numpy(inst.A).to(tdt).to(dev)
         Y = q.explicit_points(plan)
@@ -235,7 +321,7 @@ def main():
         flops = 2.0 * inst.N * inst.s * inst.t
         out = {"dense_gemm_ms": round(1e3 * ed / args.steps, 3),
                "TFLOPs": round(flops / (ed / args.steps) / 1e12, 2),
-               "workload": inst.name, "dtype": args.dtype}
+               "workload": inst.name, "dtype": hd}
         if args.vendor_context:  # torch.matmul of the same shape, timing context only
             Xv = torch.empty_like(Xd)
             torch.matmul(Y, A, out=Xv)
@@ -244,124 +330,118 @@ def main():
             out["vendor_max_diff"] = float((Xv - Xd).abs().max())
         print(json.dumps(out), flush=True)
         return
+
+    result = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+              "dtype": hd, "data": "synthetic"}
+    all_legs = []
+    main_leg = None
+
+    # ---- headline: C2 at the headline precision ----------------------------
+    inst = qi.make_c2(hd)
     N, s, t = inst.N, inst.s, inst.t
-    w = 4 if args.dtype == "f32" else 8
-    tdt = torch.float32 if args.dtype == "f32" else torch.float64
-    log(f"workload {inst.name} dtype={args.dtype}")
-    plan = q.Plan.from_instance(inst)
-    info = plan.info()
-    log(f"plan: L={info['L']} M={info['M']} M1={info['M1']} M2={info['M2']} rounds={info['rounds']}")
-    A = torch.from_numpy(inst.A).to(tdt).to(dev)
-    X = torch.empty((N, t), dtype=tdt, device=dev)
-    tuning = plan.get_tuning()
-    if args.tuning:
-        keys = ("chunk_pairs", "streams", "nt_store", "front", "outer_q", "nt_inter")
-        vals = [int(v) for v in args.tuning.split(",")]
-        if len(vals) not in (4, 6):
-            ap.error("--tuning takes 4 or 6 comma-separated integers")
-        plan.set_tuning(**dict(zip(keys, vals)))
-        tuning = plan.get_tuning()
-        log(f"fixed launch tuning: {tuning}")
-    elif not args.no_tune:
-        from paper_1501_06286_amd import autotune
-        tuning, _ = autotune.tune(plan, t, reps=3)
-        log(f"autotuned launch: {tuning}")
-    ws = plan.workspace(t, dev)
-    step = lambda: q.matmul(plan, A, out=X, workspace=ws)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log("warmup done")
+    leg, plan, A, X, ws = forward_leg("c2", inst, args, torch, q, dev)
+    all_legs.append(leg)
+    main_leg = leg
+    result.update({"value": leg.out["value"], "unit": "entries/s",
+                   "ms_per_step": leg.out["ms_per_step"],
+                   "config": {"workload": leg.out["workload"], "rule": "rank-1 lattice",
+                              "N": N, "s": s, "t": t,
+                              "phi": "inverse normal CDF, shift 1/(2N)",
+                              "A": "upper Cholesky of exp(-|i-j|/410)", "M": leg.out["M"],
+                              "M1": leg.out["M1"], "M2": leg.out["M2"],
+                              "tuning": leg.out["tuning"]},
+                   "hbm_GBps_algorithmic": leg.out["path"]["hbm_GBps"],
+                   "path": leg.out["path"],
+                   "roofline": leg.out["roofline"], "kernels": leg.out["kernels"],
+                   "paper_context": PAPER_CONTEXT})
 
-    elapsed = time_steps(step, args.steps, torch)
-    ms_step = 1e3 * elapsed / args.steps
-    value = N * t / (elapsed / args.steps)
-    alg_bytes = (s + N) * t * w
-    log(f"FFT path {ms_step:.3f} ms/step, {value:.4e} entries/s")
-    # the same timed steps again with HIP events around every kernel launch
-    # (on the stream each kernel is launched on) for the per-kernel roofline
-    plan.profile(True)
-    elapsed_p = time_steps(step, args.steps, torch)
-    prof = plan.profile_collect()
-    plan.profile(False)
-    log(f"instrumented pass {1e3 * elapsed_p / args.steps:.3f} ms/step")
-
-    pairs = (t + 1) // 2
-    model = kernel_model(info, pairs, t, w, N, s)  # per step (all column pairs)
-    kernels = {}
-    for name, (tot, n) in prof.items():
-        per_step = n / args.steps  # launches of this kernel per step (chunks)
-        avg = tot / n
-        mdl = model.get(name, {"bytes": 0, "flops": 0})
-        kernels[name] = {"avg_ms": round(avg, 4), "launches_per_step": per_step,
-                         "ms_per_step": round(tot / args.steps, 4),
-                         "alg_GBps": round(mdl["bytes"] / per_step / (avg * 1e-3) / 1e9, 1),
-                         "alg_TFLOPs": round(mdl["flops"] / per_step / (avg * 1e-3) / 1e12, 2)}
-    dom = max(prof, key=lambda k: prof[k][0])
-    per_launch = prof[dom][1] / args.steps
-    dmdl = {k: v / per_launch for k, v in model[dom].items()}  # one launch = one chunk
-    davg_s = prof[dom][0] / prof[dom][1] * 1e-3
-    ai = dmdl["flops"] / max(dmdl["bytes"], 1)
-    ridge = VALU_PEAK_TFLOPS[args.dtype] * 1e12 / (HBM_PEAK_GBPS * 1e9)
-    workload = f"c2_gauss_n{N}_s{s}_t{t}_{args.dtype}"
-    traffic = measured_traffic(dom, workload, tuning)  # bytes per launch, same chunking
-    if ai > ridge:
-        ach = dmdl["flops"] / davg_s / 1e12
-        roof = {"bound": "alu", "achieved": round(ach, 3), "peak": VALU_PEAK_TFLOPS[args.dtype],
-                "unit": "TFLOP/s", "frac": round(ach / VALU_PEAK_TFLOPS[args.dtype], 4),
-                "traffic": traffic, "kernel": dom}
-    else:
-        ach = dmdl["bytes"] / davg_s / 1e9
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": traffic, "kernel": dom}
-
-    result = {
-        "metric": METRIC, "value": value, "unit": "entries/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": args.dtype, "data": "synthetic",
-        "config": {"workload": workload, "rule": "rank-1 lattice", "N": N, "s": s, "t": t,
-                   "phi": "inverse normal CDF, shift 1/(2N)",
-                   "A": "upper Cholesky of exp(-|i-j|/410)", "M": info["M"], "M1": info["M1"],
-                   "M2": info["M2"], "tuning": tuning},
-        "hbm_GBps_algorithmic": round(alg_bytes / (elapsed / args.steps) / 1e9, 1),
-        "roofline": roof,
-        "kernels": kernels,
-        "paper_context": PAPER_CONTEXT,
-    }
-
-    if not args.no_f64 and args.dtype == "f32":
-        inst64 = qi.make_c2("f64", s=args.s)
-        p64 = q.Plan.from_instance(inst64)
-        if not args.no_tune:
-            from paper_1501_06286_amd import autotune
-            autotune.tune(p64, t, reps=3)
-        A64 = torch.from_numpy(inst64.A).to(dev)
-        X64 = torch.empty((N, t), dtype=torch.float64, device=dev)
-        ws64 = p64.workspace(t, dev)
-        st64 = lambda: q.matmul(p64, A64, out=X64, workspace=ws64)
-        st64()
-        n64 = max(3, args.steps // 2)
-        e64 = time_steps(st64, n64, torch)
-        result["fp64"] = {"value": N * t / (e64 / n64), "ms_per_step": round(1e3 * e64 / n64, 4),
-                          "hbm_GBps_algorithmic": round((s + N) * t * 8 / (e64 / n64) / 1e9, 1)}
-        log(f"FP64 path {1e3 * e64 / n64:.3f} ms/step")
-        del A64, X64, ws64, p64
-
-    if not args.no_adjoint:
-        G = torch.randn((N, t), dtype=tdt, device=dev)
-        dA = torch.empty((s, t), dtype=tdt, device=dev)
+    if "adjoint" in legs:
+        G = torch.randn((N, t), dtype=A.dtype, device=dev, generator=torch.Generator(dev).manual_seed(7))
+        dA = torch.empty((s, t), dtype=A.dtype, device=dev)
         astep = lambda: q.matmul_adjoint(plan, G, out=dA, workspace=ws)
         astep()
         na = max(3, args.steps // 2)
         ea = time_steps(astep, na, torch)
-        result["adjoint"] = {"value": N * t / (ea / na), "unit": "entries/s (N*t per s)",
-                             "ms_per_step": round(1e3 * ea / na, 4)}
-        log(f"adjoint dA = Y^T G {1e3 * ea / na:.3f} ms/step")
+        ams = 1e3 * ea / na
+        aleg = Leg("adjoint")
+        aleg.out = {"workload": leg.out["workload"], "value": N * t / (ea / na),
+                    "unit": "entries/s (N*t per s)", "ms_per_step": round(ams, 4),
+                    "path": path_fractions(N, s, t, hd, ams)}
+        ent = qi.fd_entries(s, t)
+        ks = sorted({k for _, k in ent})
+        aleg.checks.append(("adjoint", inst, ent, ks,
+                            G[:, ks].double().cpu().numpy(),
+                            np.array([float(dA[j, k]) for j, k in ent])))
+        all_legs.append(aleg)
+        result["adjoint"] = aleg.out
+        log(f"adjoint dA = Y^T G {ams:.3f} ms/step")
         del G, dA
 
-    if not args.no_batched:
-        insts = qi.make_c4(dtype=args.dtype)
+    if "dense" in legs:
+        # the dense MFMA GEMM on the explicit Y of the headline plan, compared
+        # with the FFT product of the same A (X is written by no other leg)
+        Y = q.explicit_points(plan)
+        Xd = torch.empty_like(X)
+        dstep = lambda: q.dense_matmul(plan, Y, A, out=Xd)
+        dstep()
+        nd = 3
+        ed = time_steps(dstep, nd, torch)
+        flops = 2.0 * N * s * t
+        dval = N * t / (ed / nd)
+        scale = float(Y.abs().max()) * A.abs().sum(dim=0)
+        err = float(((Xd - X).abs().max(dim=0).values / scale).max())
+        Xv = torch.empty_like(Xd)
+        vstep = lambda: torch.matmul(Y, A, out=Xv)
+        vstep()
+        ev = time_steps(vstep, nd, torch)
+        dleg = Leg("dense")
+        dleg.out = {"dtype": hd, "value": dval, "ms_per_step": round(1e3 * ed / nd, 3),
+                    "TFLOPs": round(flops / (ed / nd) / 1e12, 2),
+                    "mfma_frac": round(flops / (ed / nd) / 1e12 / MFMA_PEAK_TFLOPS[hd], 4),
+                    "fft_speedup": round(leg.out["value"] / dval, 2),
+                    "max_norm_diff_vs_fft": err,
+                    "vendor_context": {"what": "torch.matmul of the same Y and A",
+                                       "ms_per_step": round(1e3 * ev / nd, 3),
+                                       "TFLOPs": round(flops / (ev / nd) / 1e12, 2)}}
+        rows = sample_rows(N, 16, 99)
+        dleg.checks.append(("X", inst, rows, rows_to_host(Xd, rows, torch)))
+        all_legs.append(dleg)
+        result["dense_gemm"] = dleg.out
+        log(f"dense MFMA GEMM {hd} {1e3 * ed / nd:.2f} ms/step; speed-up "
+            f"{leg.out['value'] / dval:.1f}x; |dense - FFT| {err:.2e}; vendor (context) "
+            f"{1e3 * ev / nd:.2f} ms")
+        del Y, Xd, Xv
+    del plan, A, X, ws
+    torch.cuda.empty_cache()
+
+    # ---- the same product at the other precision -----------------------------
+    if "c2_other" in legs:
+        inst_o = qi.make_c2(other)
+        oleg, p_o, A_o, X_o, ws_o = forward_leg("c2_other", inst_o, args, torch, q, dev)
+        all_legs.append(oleg)
+        result["f32" if other == "f32" else "f64"] = oleg.out
+        if "dense" in legs:
+            Y = q.explicit_points(p_o)
+            Xd = torch.empty_like(X_o)
+            q.dense_matmul(p_o, Y, A_o, out=Xd)
+            ed = time_steps(lambda: q.dense_matmul(p_o, Y, A_o, out=Xd), 3, torch)
+            scale = float(Y.abs().max()) * A_o.abs().sum(dim=0)
+            err = float(((Xd - X_o).abs().max(dim=0).values / scale).max())
+            oleg.out["dense_gemm"] = {
+                "ms_per_step": round(1e3 * ed / 3, 3),
+                "TFLOPs": round(2.0 * N * s * t / (ed / 3) / 1e12, 2),
+                "mfma_frac": round(2.0 * N * s * t / (ed / 3) / 1e12 / MFMA_PEAK_TFLOPS[other], 4),
+                "fft_speedup": round(oleg.out["value"] / (N * t / (ed / 3)), 2),
+                "max_norm_diff_vs_fft": err}
+            log(f"dense MFMA GEMM {other} {1e3 * ed / 3:.2f} ms; |dense - FFT| {err:.2e}")
+            del Y, Xd
+        del p_o, A_o, X_o, ws_o
+        torch.cuda.empty_cache()
+
+    if "batched" in legs:
+        insts = qi.make_c4(dtype="f32")
+        tdt = torch.float32
         bplans = [q.Plan.from_instance(i) for i in insts]
         bA = [torch.from_numpy(i.A).to(tdt).to(dev) for i in insts]
         btune = {}
@@ -372,6 +452,7 @@ def main():
         batch = q.Batch(bplans, bA)
         bchunk = (q.BATCH_CHUNK_DEFAULT, 0)
         if not args.no_tune:
+            from paper_1501_06286_amd import autotune
             bchunk, _ = autotune.tune_batch_chunk(batch)
             log(f"batched run size {bchunk[0] >> 20} MiB of intermediates, nt_inter {bchunk[1]}")
         batch.run()
@@ -387,129 +468,236 @@ def main():
             batch.run()
         eg = time_steps(g.replay, nb, torch)
         ent = sum(i.N * i.t for i in insts)
-        result["batched"] = {"workload": "256 lattice instances, N primes in [1000, 200000], "
-                                         "s in [256, 8192], t in [1, 64], Phi^-1 1/(2N)",
-                             "entries": ent, "value": ent / (eb / nb),
-                             "ms_per_batch": round(1e3 * eb / nb, 4),
-                             "graph_value": ent / (eg / nb),
-                             "graph_ms_per_batch": round(1e3 * eg / nb, 4),
-                             "outer_radix_by_M2": {str(k): v for k, v in btune.items()},
-                             "run_bytes": bchunk[0], "nt_inter": bchunk[1]}
-        log(f"batched 256 products: {1e3 * eb / nb:.3f} ms eager, {1e3 * eg / nb:.3f} ms graph")
+        bbytes = sum(col_model(i.N, i.s, 4)["bytes"] * i.t for i in insts)
+        bflops = sum(col_model(i.N, i.s, 4)["flops"] * i.t for i in insts)
+        bms = 1e3 * eb / nb
+        bleg = Leg("batched")
+        bleg.out = {"workload": "256 lattice instances, N primes in [1000, 200000], "
+                                "s in [256, 8192], t in [1, 64], Phi^-1 1/(2N), f32",
+                    "entries": ent, "value": ent / (eb / nb), "ms_per_batch": round(bms, 4),
+                    "graph_value": ent / (eg / nb), "graph_ms_per_batch": round(1e3 * eg / nb, 4),
+                    "path": {"alg_bytes": bbytes, "alg_flops": bflops,
+                             "hbm_frac": round(bbytes / (eb / nb) / 1e9 / HBM_PEAK_GBPS, 4),
+                             "valu_frac": round(bflops / (eb / nb) / 1e12 / VALU_PEAK_TFLOPS["f32"], 4),
+                             "valu_frac_nonpacked": round(bflops / (eb / nb) / 1e12 / 78.6, 4)},
+                    "outer_radix_by_M2": {str(k): v for k, v in btune.items()},
+                    "run_bytes": bchunk[0], "nt_inter": bchunk[1]}
+        for k in np.random.default_rng(150106286 + 4100).choice(len(insts), 12, replace=False):
+            i = insts[int(k)]
+            rows = sample_rows(i.N, 8, int(k))
+            bleg.checks.append(("X", i, rows, rows_to_host(batch.Xs[int(k)], rows, torch)))
+        all_legs.append(bleg)
+        result["batched"] = bleg.out
+        log(f"batched 256 products: {bms:.3f} ms eager, {1e3 * eg / nb:.3f} ms graph")
         del batch, bA, bplans, g
+        torch.cuda.empty_cache()
 
-    if not args.no_pde:
-        # Section 3.3 on the Gaussian workload: the log-normal coefficient
-        # exp(Y A) written by the same pass
-        ee = time_steps(lambda: q.matmul(plan, A, out=X, workspace=ws, epilogue="exp"), args.steps,
-                        torch)
+    if "pde" in legs:
+        # Section 3.3 on the Gaussian shapes: the log-normal coefficient
+        # exp(Y A) written by the same pass (FP32 plan)
+        c2e = qi.make_c2("f32")
+        pe = q.Plan.from_instance(c2e)
+        tune_plan(pe, c2e.t, args)
+        Ae = torch.from_numpy(c2e.A).float().to(dev)
+        Xe = torch.empty((c2e.N, c2e.t), dtype=torch.float32, device=dev)
+        wse = pe.workspace(c2e.t, dev)
+        q.matmul(pe, Ae, out=Xe, workspace=wse, epilogue="exp")
+        ne = max(3, args.steps // 2)
+        ee = time_steps(lambda: q.matmul(pe, Ae, out=Xe, workspace=wse, epilogue="exp"), ne, torch)
+        ep = time_steps(lambda: q.matmul(pe, Ae, out=Xe, workspace=wse), ne, torch)
+        del pe, Ae, Xe, wse
         # Section 3.2 on the PDE field workload: a = psi_0 + Y A with psi_0 = 1
-        c3 = qi.make_c3(args.dtype)
+        c3 = qi.make_c3("f32")
         p3 = q.Plan.from_instance(c3)
-        if not args.no_tune:
-            from paper_1501_06286_amd import autotune
-            autotune.tune(p3, c3.t, reps=3)
-        A3 = torch.from_numpy(c3.A).to(tdt).to(dev)
-        X3 = torch.empty((c3.N, c3.t), dtype=tdt, device=dev)
+        tune_plan(p3, c3.t, args)
+        A3 = torch.from_numpy(c3.A).float().to(dev)
+        X3 = torch.empty((c3.N, c3.t), dtype=torch.float32, device=dev)
         ws3 = p3.workspace(c3.t, dev)
-        one = torch.ones(c3.t, dtype=tdt, device=dev)
-        q.matmul(p3, A3, out=X3, workspace=ws3)
+        one = torch.ones(c3.t, dtype=torch.float32, device=dev)
+        st3 = lambda: q.matmul(p3, A3, out=X3, workspace=ws3)
+        st3()
         n3 = max(3, args.steps // 2)
-        e3 = time_steps(lambda: q.matmul(p3, A3, out=X3, workspace=ws3), n3, torch)
         e3a = time_steps(lambda: q.matmul(p3, A3, out=X3, workspace=ws3, epilogue="affine",
                                           bias=one), n3, torch)
-        result["pde"] = {
-            "lognormal_exp_epilogue": {"workload": workload, "ms_per_step": round(1e3 * ee / args.steps, 4),
-                                       "plain_ms_per_step": round(ms_step, 4)},
-            "uniform_field": {"workload": f"{c3.name}: GF(2) N=2^16, s=16384, t=4096, phi=y-1/2",
+        e3 = time_steps(st3, n3, torch)
+        ms3 = 1e3 * e3 / n3
+        prof3 = kernel_times(p3, st3, n3, torch)
+        kern3, roof3 = leg_roofline(prof3, n3, c3.N, c3.s, c3.t, "f32", f"{c3.name}_f32",
+                                    p3.get_tuning())
+        pleg = Leg("pde")
+        pleg.out = {
+            "lognormal_exp_epilogue": {"workload": f"{c2e.name}_f32",
+                                       "ms_per_step": round(1e3 * ee / ne, 4),
+                                       "plain_ms_per_step": round(1e3 * ep / ne, 4)},
+            "uniform_field": {"workload": f"{c3.name}_f32: GF(2) N=2^16, s=16384, t=4096, phi=y-1/2",
                               "value": c3.N * c3.t / (e3 / n3), "unit": "entries/s (N*t per s)",
-                              "ms_per_step": round(1e3 * e3 / n3, 4),
+                              "ms_per_step": round(ms3, 4),
                               "affine_epilogue_ms_per_step": round(1e3 * e3a / n3, 4),
-                              "tuning": p3.get_tuning()}}
-        log(f"PDE: exp epilogue {1e3 * ee / args.steps:.3f} ms; field {1e3 * e3 / n3:.3f} ms, "
-            f"with psi_0 {1e3 * e3a / n3:.3f} ms")
+                              "M": p3.info()["M"], "embedded": p3.info()["embedded"],
+                              "tuning": p3.get_tuning(),
+                              "path": path_fractions(c3.N, c3.s, c3.t, "f32", ms3),
+                              "kernels": kern3, "roofline": roof3}}
+        rows = sample_rows(c3.N, 32, 3)
+        pleg.checks.append(("X", c3, rows, rows_to_host(X3, rows, torch)))
+        all_legs.append(pleg)
+        result["pde"] = pleg.out
+        log(f"PDE: exp epilogue {1e3 * ee / ne:.3f} ms (plain {1e3 * ep / ne:.3f}); field "
+            f"{ms3:.3f} ms, with psi_0 {1e3 * e3a / n3:.3f} ms")
         del p3, A3, X3, ws3
+        torch.cuda.empty_cache()
 
-    if not args.no_korobov:
-        kin = qi.make_korobov(args.dtype)
+    if "korobov" in legs:
+        kin = qi.make_korobov("f32")
         U = q.KorobovUnion.from_instance(kin)
         kinfo = U.info()
         if not args.no_tune:
             from paper_1501_06286_amd import autotune
-            kbest, _ = autotune.tune_korobov(U, kin.t)
-        kA = torch.from_numpy(kin.A).to(tdt).to(dev)
-        kX = torch.empty((kin.N, kin.t), dtype=tdt, device=dev)
+            autotune.tune_korobov(U, kin.t)
+        kA = torch.from_numpy(kin.A).float().to(dev)
+        kX = torch.empty((kin.N, kin.t), dtype=torch.float32, device=dev)
         kws = U.workspace(kin.t, dev)
         kstep = lambda: q.korobov_matmul(U, kA, out=kX, workspace=kws)
         kstep()
         nk = max(3, args.steps // 2)
         ek = time_steps(kstep, nk, torch)
-        U.plan.profile(True)
-        time_steps(kstep, nk, torch)
-        kprof = U.plan.profile_collect()
-        U.plan.profile(False)
-        kmodel = korobov_model(kinfo, (kin.t + 1) // 2, kin.t, w)
+        kms = 1e3 * ek / nk
+        kprof = kernel_times(U.plan, kstep, nk, torch)
+        K = kin.modulus
+        # per column: A read once, X written once; flops: K - 1 blocks, each a
+        # convolution of length K - 1 with its own collapse
+        kbytes = 4 * (kin.s + kin.N)
+        kflops = (K - 1) * ((5.0 * math.log2(K - 1) + 3.0) * (K - 1) + 2.0 * kin.s)
         kdom = max(kprof, key=lambda k: kprof[k][0])
-        kroof = roofline_of(kdom, kmodel, kprof[kdom][1] / nk, kprof[kdom][0] / kprof[kdom][1] * 1e-3,
-                            args.dtype)
-        result["korobov_union"] = {
-            "workload": f"union of Korobov lattice rules K={kin.modulus} (N={kin.N}), s={kin.s}, "
-                        f"t={kin.t}, Phi^-1 shift 1/(2K)",
+        cols = kin.t / (kprof[kdom][1] / nk)
+        kavg = kprof[kdom][0] / kprof[kdom][1] * 1e-3
+        kleg = Leg("korobov")
+        kleg.out = {
+            "workload": f"union of Korobov lattice rules K={K} (N={kin.N}), s={kin.s}, "
+                        f"t={kin.t}, Phi^-1 shift 1/(2K), f32",
             "value": kin.N * kin.t / (ek / nk), "unit": "entries/s (N*t per s)",
-            "ms_per_step": round(1e3 * ek / nk, 4), "chunk_blocks": kinfo["chunk_blocks"],
-            "hbm_GBps_algorithmic": round((kin.s + kin.N) * kin.t * w / (ek / nk) / 1e9, 1),
-            "roofline": kroof,
+            "ms_per_step": round(kms, 4), "chunk_blocks": U.info()["chunk_blocks"],
+            "path": {"alg_bytes": kbytes * kin.t, "alg_flops": kflops * kin.t,
+                     "hbm_frac": round(kbytes * kin.t / (kms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                     "valu_frac": round(kflops * kin.t / (kms * 1e-3) / 1e12 / 157.3, 4),
+                     "valu_frac_nonpacked": round(kflops * kin.t / (kms * 1e-3) / 1e12 / 78.6, 4)},
+            "roofline": {"bound": "alu", "kernel": kdom,
+                         "achieved": round(kflops * cols / kavg / 1e12, 3), "peak": 157.3,
+                         "unit": "TFLOP/s", "frac": round(kflops * cols / kavg / 1e12 / 157.3, 4),
+                         "frac_nonpacked": round(kflops * cols / kavg / 1e12 / 78.6, 4)},
             "kernels": {k: {"avg_ms": round(v[0] / v[1], 4), "ms_per_step": round(v[0] / nk, 4)}
                         for k, v in kprof.items()}}
-        log(f"Korobov union {1e3 * ek / nk:.3f} ms/step")
-        if not args.no_adjoint:
-            kG = torch.randn((kin.N, kin.t), dtype=tdt, device=dev)
-            kdA = torch.empty((kin.s, kin.t), dtype=tdt, device=dev)
+        rows = sample_rows(kin.N, 32, 6)
+        kleg.checks.append(("X", kin, rows, rows_to_host(kX, rows, torch)))
+        log(f"Korobov union {kms:.3f} ms/step")
+        if "adjoint" in legs:
+            kG = torch.randn((kin.N, kin.t), dtype=torch.float32, device=dev)
+            kdA = torch.empty((kin.s, kin.t), dtype=torch.float32, device=dev)
             kastep = lambda: q.korobov_matmul_adjoint(U, kG, out=kdA, workspace=kws)
             kastep()
             eka = time_steps(kastep, nk, torch)
-            result["korobov_union"]["adjoint"] = {
-                "value": kin.N * kin.t / (eka / nk), "unit": "entries/s (N*t per s)",
-                "ms_per_step": round(1e3 * eka / nk, 4)}
+            kleg.out["adjoint"] = {"value": kin.N * kin.t / (eka / nk),
+                                   "unit": "entries/s (N*t per s)",
+                                   "ms_per_step": round(1e3 * eka / nk, 4)}
             log(f"Korobov union adjoint {1e3 * eka / nk:.3f} ms/step")
             del kG, kdA
-        if not args.no_cpu:
-            result["korobov_union"]["cpu_baseline"] = cpu_baseline(kin, budget_s=6.0)
+        all_legs.append(kleg)
+        result["korobov_union"] = kleg.out
         del U, kA, kX, kws
+        torch.cuda.empty_cache()
 
-    if not args.no_dense:
-        Y = q.explicit_points(plan)
-        Xd = torch.empty((N, t), dtype=tdt, device=dev)
-        dstep = lambda: q.dense_matmul(plan, Y, A, out=Xd)
-        dstep()
-        nd = 3
-        ed = time_steps(dstep, nd, torch)
-        flops = 2.0 * N * s * t
-        dval = N * t / (ed / nd)
-        err = float((Xd - X).abs().max()) / (float(A.abs().sum(0).max()) * float(Y.abs().max()))
-        # the vendor library's GEMM of the same shape, as timing context only
-        # (torch.matmul; never part of the library's path)
-        Xv = torch.empty_like(Xd)
-        vstep = lambda: torch.matmul(Y, A, out=Xv)
-        vstep()
-        ev = time_steps(vstep, nd, torch)
-        result["dense_gemm"] = {"value": dval, "ms_per_step": round(1e3 * ed / nd, 3),
-                                "TFLOPs": round(flops / (ed / nd) / 1e12, 2),
-                                "mfma_frac": round(flops / (ed / nd) / 1e12 / MFMA_PEAK_TFLOPS[args.dtype], 4),
-                                "fft_speedup": round(value / dval, 2),
-                                "max_norm_diff_vs_fft": err,
-                                "vendor_context": {"what": "torch.matmul of the same Y and A",
-                                                   "ms_per_step": round(1e3 * ev / nd, 3),
-                                                   "TFLOPs": round(flops / (ev / nd) / 1e12, 2)}}
-        log(f"dense MFMA GEMM {1e3 * ed / nd:.2f} ms/step; speed-up {value / dval:.1f}x; "
-            f"vendor GEMM (context) {1e3 * ev / nd:.2f} ms")
-        del Xv
-        del Y, Xd
+    if "c5" in legs:
+        c5 = qi.make_c5("f32")
+        cleg, p5, A5, X5, ws5 = forward_leg("c5", c5, args, torch, q, dev, nrows=32)
+        G5 = torch.from_numpy(c5.G).float().to(dev)
+        dA5 = torch.empty((c5.s, c5.t), dtype=torch.float32, device=dev)
+        st5 = lambda: q.matmul_adjoint(p5, G5, out=dA5, workspace=ws5)
+        st5()
+        n5 = max(3, args.steps // 2)
+        e5 = time_steps(st5, n5, torch)
+        ms5 = 1e3 * e5 / n5
+        prof5 = kernel_times(p5, st5, n5, torch)
+        kern5, roof5 = leg_roofline(prof5, n5, c5.N, c5.s, c5.t, "f32")
+        cleg.out["adjoint"] = {"ms_per_step": round(ms5, 4), "value": c5.N * c5.t / (e5 / n5),
+                               "unit": "entries/s (N*t per s)",
+                               "path": path_fractions(c5.N, c5.s, c5.t, "f32", ms5),
+                               "kernels": kern5, "roofline": roof5}
+        ent = qi.fd_entries(c5.s, c5.t)
+        ks = sorted({k for _, k in ent})
+        cleg.checks.append(("adjoint", c5, ent, ks, c5.G[:, ks],
+                            np.array([float(dA5[j, k]) for j, k in ent])))
+        log(f"C5 adjoint {ms5:.3f} ms/step")
+        all_legs.append(cleg)
+        result["c5"] = cleg.out
+        del p5, A5, X5, ws5, G5, dA5
+        torch.cuda.empty_cache()
 
-    if not args.no_cpu:
-        log("cpu baseline (oracle, bounded sample)")
-        result["cpu_baseline"] = cpu_baseline(inst)
+    if "cpu" in legs:
+        result["cpu_baseline"] = cpu_baseline_and_errors(main_leg.checks[0][1], all_legs)
+        log(f"cpu baseline {result['cpu_baseline']['value']:.3e} entries/s; worst errors "
+            f"{ {l.name: l.out.get('err_vs_oracle') for l in all_legs} }")
     print(json.dumps(result), flush=True)
+
+
+def cpu_baseline_and_errors(inst, legs, budget_s=4.0, reps=5):
+    """The FP64 oracle (explicit Y rows, dense product) timed on a bounded row
+    sample of the headline workload on the host cores: median and mean of
+    `reps` runs.  The same leg then compares the sampled rows (and adjoint
+    entries) of every GPU result with the oracle: the worst normalised error
+    max |got - ref| / (max|Y| ||column||_1) per leg."""
+    import numpy as np
+    import oracle
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    try:
+        from threadpoolctl import threadpool_info
+        bl = [p.get("num_threads") for p in threadpool_info() if p.get("user_api") == "blas"]
+        if bl:
+            threads = int(bl[0])
+    except Exception:
+        pass
+    rng = np.random.default_rng(150106286 + 2000 + 7)
+    probe = 512
+    rows = np.sort(rng.choice(inst.N, size=probe, replace=False))
+    t0 = time.perf_counter()
+    oracle.matmul_rows(inst, rows)
+    dt = time.perf_counter() - t0
+    n = int(min(inst.N, max(probe, probe * budget_s / max(dt, 1e-3))))
+    rows = np.sort(rng.choice(inst.N, size=n, replace=False))
+    times = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        oracle.matmul_rows(inst, rows)
+        times.append(time.perf_counter() - t0)
+    med = float(np.median(times))
+    mean = float(np.mean(times))
+    out = {"value": n * inst.t / med, "unit": "entries/s", "cores": threads, "kind": "oracle",
+           "mean_value": n * inst.t / mean, "runs_s": [round(x, 3) for x in times],
+           "sample": f"{n} seeded rows of {inst.N} (all s={inst.s}, t={inst.t}) of "
+                     f"{inst.name} ({inst.dtype} A), FP64 explicit Y + numpy matmul; "
+                     f"median and mean of {reps} runs"}
+
+    def ymax(i):
+        T = oracle.phi_residue_values(i.rule, i.N, i.phi, i.modulus, i.shift)
+        return float(np.max(np.abs(T)))
+
+    for leg in legs:
+        worst = 0.0
+        for chk in leg.checks:
+            if chk[0] == "X":
+                _, i, rws, got = chk
+                ref = oracle.matmul_rows(i, rws)
+                sc = ymax(i) * np.abs(i.A).sum(axis=0)
+                sc = np.where(sc > 0, sc, 1.0)
+                worst = max(worst, float(np.max(np.max(np.abs(got - ref), axis=0) / sc)))
+            else:
+                _, i, ent, ks, Gk, got = chk
+                col = {k: c for c, k in enumerate(ks)}
+                ref = oracle.adjoint_entries(i, [(j, col[k]) for j, k in ent], G=Gk)
+                sc = ymax(i) * np.abs(Gk).sum(axis=0)
+                worst = max(worst, float(np.max(np.abs(got - ref) /
+                                                np.array([sc[col[k]] for _, k in ent]))))
+        if leg.checks:
+            leg.out["err_vs_oracle"] = worst
+    return out
 
 
 if __name__ == "__main__":

@@ -94,7 +94,9 @@ typedef struct qmc_plan_s* qmc_plan_t;
  *              the equal shift D = shift_num/shift_den in [0,1) added to
  *              every coordinate before phi (Remark 2); 0/1 for none.
  *              QMC_PHI_INVNORM requires a shift that keeps every coordinate
- *              inside (0,1) (e.g. 1/(2N)), otherwise QMC_ERR_ARG.
+ *              inside (0,1) (e.g. 1/(2N)): a shift with N D an integer (D = 0,
+ *              or any multiple of 1/N) puts the coordinate of one residue at 0
+ *              and returns QMC_ERR_ARG.
  *   dtype      QMC_F32 or QMC_F64
  *   stream     HIP stream for the plan-building kernels; the call
  *              synchronises that stream before returning.
@@ -110,7 +112,14 @@ int qmc_plan_create(qmc_plan_t* out, int rule, int64_t N, int64_t s,
 
 void qmc_plan_destroy(qmc_plan_t plan);
 
-/* Plan facts for callers and tests (host pointer to a filled struct). */
+/*
+ * Plan facts for callers and tests (host pointer to a filled struct).  The
+ * transform factorisation is M = M1 x M2 with M1 = R^3 on chip (three
+ * register DFTs of radix R) and the outer length M2 = P2 x Q2 (a split pass of
+ * radix P2 when P2 > 1, the back pass of radix Q2); every length is a power of
+ * two, so these fields are the whole radix plan and no separate list of
+ * radices is reported.
+ */
 typedef struct {
     int64_t N, s, L;        /* points, dimension, group order L = N - 1 */
     int64_t M;              /* circular-convolution length used: L, or a power of two >= 2L-1 */
@@ -216,14 +225,6 @@ int qmc_matmul(qmc_plan_t plan, const void* A, int64_t t, int64_t lda,
                void* stream);
 
 /*
- * qmc_matmul_adjoint -- dA = Y^T G, the transpose product needed to
- * differentiate X = Y A with respect to A.  The nonzero rows of Y in group
- * order form a symmetric (Hankel-circulant) operator, so the same spectrum
- * serves: G's rows are gathered in reflected group order, convolved, and
- * read back at the exponents l_j; the constant row adds phi(x_0) G[0,:].
- *   G   device, N x t (ldg >= t);  dA  device, s x t (ldda >= t), overwritten
- */
-/*
  * qmc_matmul_epilogue -- X = Y A with an elementwise epilogue fused into the
  * writes of X (the downstream steps of Sections 3.2 and 3.3):
  *   QMC_EPI_AFFINE  X[n,c] = scale[c] * (bias[c] + (Y A)[n,c])
@@ -247,6 +248,14 @@ int qmc_matmul_epilogue(qmc_plan_t plan, const void* A, int64_t t, int64_t lda, 
                         int64_t ldx, int epi_kind, const void* bias, const void* scale,
                         void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * qmc_matmul_adjoint -- dA = Y^T G, the transpose product needed to
+ * differentiate X = Y A with respect to A.  The nonzero rows of Y in group
+ * order form a symmetric (Hankel-circulant) operator, so the same spectrum
+ * serves: G's rows are gathered in reflected group order, convolved, and
+ * read back at the exponents l_j; the constant row adds phi(x_0) G[0,:].
+ *   G   device, N x t (ldg >= t);  dA  device, s x t (ldda >= t), overwritten
+ */
 int qmc_matmul_adjoint(qmc_plan_t plan, const void* G, int64_t t, int64_t ldg,
                        void* dA, int64_t ldda, void* workspace, size_t workspace_bytes,
                        void* stream);
@@ -278,7 +287,9 @@ int qmc_dense_matmul(qmc_plan_t plan, const void* Y, int64_t ldy, const void* A,
  * (products with different on-chip transform sizes form separate groups)
  * and makes no host-to-device copies, so it can be captured in a HIP graph
  * and replayed.  Workspace: qmc_batch_workspace_size bytes, caller-owned.
- * Errors: QMC_ERR_ARG (bad arguments or mixed dtypes), QMC_ERR_WORKSPACE.
+ * Errors: QMC_ERR_ARG (bad arguments or mixed dtypes), QMC_ERR_ALIAS (at
+ * create: some X[i] overlaps an A[k] or another X[k]; at run: the workspace
+ * overlaps an operand), QMC_ERR_WORKSPACE.
  *
  * qmc_batch_set_chunk splits each group into runs of consecutive products
  * whose intermediate spectra (pairs x M complex values each) take at most
@@ -309,8 +320,9 @@ int qmc_batch_set_chunk(qmc_batch_t batch, int64_t chunk_bytes, int nt_inter, vo
  * per column, one kind for all (QMC_EPI_*), bias[i] / scale[i] device arrays
  * of t[i] values in the plans' dtype (a NULL array, or a NULL entry, means
  * bias 0 / scale 1).  The vectors must outlive the batch's runs and must not
- * overlap X_i (QMC_ERR_ALIAS).  Re-uploads the descriptors and synchronises
- * `stream`, with the same restrictions as qmc_batch_set_chunk.
+ * overlap any X of the batch (QMC_ERR_ALIAS; the batch is then unchanged).
+ * Re-uploads the descriptors and synchronises `stream`, with the same
+ * restrictions as qmc_batch_set_chunk.
  */
 int qmc_batch_set_epilogue(qmc_batch_t batch, int kind, const void* const* bias,
                            const void* const* scale, void* stream);
@@ -342,8 +354,9 @@ int qmc_matmul_batched(int count, const qmc_plan_t* plans, const void* const* A,
  * ordering for b = beta^(g-1), taken in [0, K-2].
  *
  * qmc_korobov_create -- tables for K, s, phi (as qmc_plan_create; the shift
- *   D = shift_num / shift_den may be 0 for every phi since no coordinate is 0),
- *   dtype.  Synchronous on `stream`.  Device memory grows as (K-1) times the
+ *   D = shift_num / shift_den may be 0 for every phi since no coordinate is 0;
+ *   a nonzero shift with K D an integer puts one coordinate at 0, which the
+ *   inverse normal CDF refuses with QMC_ERR_ARG), dtype.  Synchronous on `stream`.  Device memory grows as (K-1) times the
  *   collapse schedule of s rows.
  *   Errors: QMC_ERR_ARG (K < 3, s < 1, bad phi/dtype/shift), QMC_ERR_NOT_PRIME,
  *   QMC_ERR_OOM, QMC_ERR_HIP.

@@ -14,7 +14,13 @@ product path.
   coefficient of x^i), r(x) = n(x) q_j(x) mod p(x), and the coordinate is
   nu_m(r/p) = sum_{l=1}^m u_l 2^-l where r(x)/p(x) = sum_{l>=1} u_l x^-l.
   Equivalently u_1..u_m are the bits (most significant first) of the
-  quotient floor(r(x) x^m / p(x)).  An equal shift is applied as for lattices.
+  quotient floor(r(x) x^m / p(x)).  The product path of the oracle
+  (``coords_rational``, ``explicit_Y``) takes the digital-net form of the
+  same points: digit l of x_{n,j} is sum_i n_i u_{i+l} (mod 2) with u_k the
+  Laurent digits of q_j(x)/p(x) (the Hankel generating matrix), which is
+  GF(2)-linear in n; ``gf2_coords`` keeps the direct route (product mod p,
+  then the quotient) and the tests check that both agree bit for bit.
+  An equal shift is applied as for lattices.
 * Union of all Korobov lattice point sets with a prime K (Section 2.2, the
   point set of Hua and Wang): for b, n = 1..K-1 the point
   x_{b,n} = ({n b^0 / K}, {n b^1 / K}, ..., {n b^{s-1} / K}); conventional
@@ -139,6 +145,47 @@ def gf2_value_of_residue(m: int, p: int, r: np.ndarray) -> np.ndarray:
     return q
 
 
+def gf2_laurent_digits(p: int, q, count: int) -> np.ndarray:
+    """The first ``count`` digits u_1..u_count of the Laurent expansion
+    q(x)/p(x) = sum_{l>=1} u_l x^-l over GF(2), deg q < deg p, by long
+    division (u_l = 1 when x times the remainder reaches degree m).  Row l-1
+    of the result holds u_l for every q."""
+    m = int(p).bit_length() - 1
+    rem = np.asarray(q, dtype=np.uint64).copy()
+    out = np.zeros((count,) + rem.shape, dtype=np.uint64)
+    pp = np.uint64(p)
+    for l in range(count):
+        rem = rem << np.uint64(1)
+        u = (rem >> np.uint64(m)) & np.uint64(1)
+        rem ^= np.where(u == 1, pp, np.uint64(0))
+        out[l] = u
+    return out
+
+
+def gf2_numerators_digital(m: int, p: int, gen, rows=None) -> np.ndarray:
+    """Integer Q with Q/2^m = nu_m(n(x) q_j(x) / p(x)) for the requested rows,
+    from the digital-net form of the polynomial lattice rule: with n_i the
+    bit i of n and u_k the Laurent digits of q_j/p, the coefficient of
+    x^-l in n(x) q_j(x)/p(x) is sum_i n_i u_{i+l} (mod 2).  Reducing
+    n(x) q_j(x) modulo p(x) first only removes a polynomial part, which has no
+    negative powers, so these are the digits of the point; digit l = 1 is the
+    most significant.  So Q is the XOR over the set bits i of n of the m-bit
+    word (u_{i+1} .. u_{i+m}) (the columns of the Hankel generating matrix)."""
+    q = np.asarray(gen, dtype=np.uint64)
+    N = 1 << m
+    n = np.arange(N, dtype=np.uint64) if rows is None else np.asarray(rows, dtype=np.uint64)
+    u = gf2_laurent_digits(p, q, 2 * m - 1)          # u[k-1] = u_k, shape (2m-1, s)
+    basis = np.zeros((m,) + q.shape, dtype=np.uint64)  # basis[i] = word of n = x^i
+    for i in range(m):
+        for l in range(1, m + 1):
+            basis[i] |= u[i + l - 1] << np.uint64(m - l)
+    Q = np.zeros((len(n),) + q.shape, dtype=np.uint64)
+    for i in range(m):
+        bit = ((n >> np.uint64(i)) & np.uint64(1)) == 1
+        Q ^= np.where(bit[:, None], basis[i][None, :], np.uint64(0))
+    return Q
+
+
 def gf2_coords(m: int, p: int, gen, shift=(0, 1), rows=None) -> np.ndarray:
     """Coordinates nu_m(n(x) q_j(x) / p(x)) (+ Delta, mod 1)."""
     r = gf2_residues(m, p, gen, rows)
@@ -189,22 +236,30 @@ def korobov_union_numerators(K: int, exps, rows=None) -> np.ndarray:
     return n[:, None] * _powmod(b[:, None], e[None, :], K) % K
 
 
-def coords_rational(rule: int, N: int, gen, modulus: int = 0, shift=(0, 1), rows=None):
-    """Exact coordinates K/D of the requested rows (conventional order)."""
+def unshifted_numerators(rule: int, N: int, gen, modulus: int = 0, rows=None):
+    """(numerators, base) of the unshifted coordinates numer/base of the
+    requested rows: n g_j mod N (lattice), the digit value Q of
+    nu_m(n q_j / p) (GF(2), digital-net form), n b^{e_j} mod K (union of
+    Korobov rules, base K).  Every numerator lies in [0, base)."""
     if rule == RULE_LATTICE:
         g = np.asarray(gen, dtype=np.int64)
         n = np.arange(N, dtype=np.int64) if rows is None else np.asarray(rows, dtype=np.int64)
-        return _shifted_numer((n[:, None] * g[None, :]) % N, N, shift)
+        return (n[:, None] * g[None, :]) % N, N
     if rule == RULE_POLY_GF2:
         m = int(N).bit_length() - 1
         assert 1 << m == N, "polynomial lattice rules need N = 2^m"
-        r = gf2_residues(m, modulus, gen, rows)
-        return _shifted_numer(gf2_value_of_residue(m, modulus, r).astype(np.int64), N, shift)
+        return gf2_numerators_digital(m, modulus, gen, rows).astype(np.int64), N
     if rule == RULE_KOROBOV_UNION:
         K = int(modulus)
         assert N == (K - 1) ** 2, "the union of Korobov rules has (K-1)^2 points"
-        return _shifted_numer(korobov_union_numerators(K, gen, rows), K, shift)
+        return korobov_union_numerators(K, gen, rows), K
     raise ValueError(f"unknown rule {rule}")
+
+
+def coords_rational(rule: int, N: int, gen, modulus: int = 0, shift=(0, 1), rows=None):
+    """Exact coordinates K/D of the requested rows (conventional order)."""
+    numer, base = unshifted_numerators(rule, N, gen, modulus, rows)
+    return _shifted_numer(numer, base, shift)
 
 
 def coords(rule: int, N: int, gen, modulus: int = 0, shift=(0, 1), rows=None) -> np.ndarray:
@@ -223,9 +278,16 @@ def coords(rule: int, N: int, gen, modulus: int = 0, shift=(0, 1), rows=None) ->
 def explicit_Y(rule: int, N: int, gen, phi: int, modulus: int = 0, shift=(0, 1),
                rows=None) -> np.ndarray:
     """Y[n, j] = phi(x_{n,j}) in conventional row order, FP64 (phi of the
-    exact rational coordinate, rounded once)."""
-    K, D = coords_rational(rule, N, gen, modulus, shift, rows)
-    return phi_rational(phi, K, D)
+    exact rational coordinate, rounded once).  The shifted coordinate, and so
+    its phi value, depends only on the unshifted numerator in [0, base): when
+    there are more entries than numerators, phi is evaluated once per
+    numerator (the same exact rational, the same rounding) and looked up."""
+    numer, base = unshifted_numerators(rule, N, gen, modulus, rows)
+    if numer.size <= base:
+        K, D = _shifted_numer(numer, base, shift)
+        return phi_rational(phi, K, D)
+    K, D = _shifted_numer(np.arange(base, dtype=np.int64), base, shift)
+    return phi_rational(phi, K, D)[numer]
 
 
 def phi_residue_values(rule: int, N: int, phi: int, modulus: int = 0,

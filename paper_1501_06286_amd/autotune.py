@@ -63,9 +63,28 @@ def _arch() -> str:
         return "unknown"
 
 
+_LIB_SHA = None
+
+
+def _lib_sha() -> str:
+    """Hash of the loaded library file: a tuning timed on other kernels is
+    not reused."""
+    global _LIB_SHA
+    if _LIB_SHA is None:
+        import hashlib
+        import paper_1501_06286_amd as q
+        h = hashlib.sha256()
+        with open(q.LIB_PATH, "rb") as f:
+            for block in iter(lambda: f.read(1 << 20), b""):
+                h.update(block)
+        _LIB_SHA = h.hexdigest()[:16]
+    return _LIB_SHA
+
+
 def cache_key(plan, t: int) -> str:
     i = plan.info()
-    return f"{_arch()}|rule{i['rule']}|L{i['L']}|M{i['M']}|s{i['s']}|t{t}|dtype{i['dtype']}"
+    return (f"{_arch()}|lib{_lib_sha()}|rule{i['rule']}|L{i['L']}|M{i['M']}|s{i['s']}|t{t}"
+            f"|dtype{i['dtype']}")
 
 
 def _load() -> dict:

@@ -42,9 +42,15 @@ int plan_create(qmc_plan_s** out, int rule, int64_t N, int64_t s, const uint64_t
   }
   // the exact coordinate K/D needs D = N * shift_den well inside 63 bits
   if ((__int128)N * shift_den >= ((__int128)1 << 61)) return QMC_ERR_ARG;
-  // the inverse normal CDF needs every coordinate strictly inside (0, 1):
-  // x = 0 occurs for row 0 unless the shift moves it
-  if (row0_used && phi_kind == QMC_PHI_INVNORM && shift_num == 0) return QMC_ERR_ARG;
+  // the inverse normal CDF needs every coordinate strictly inside (0, 1).  The
+  // coordinates of a column are {r/N + D} for the residues r = 0..N-1 (the
+  // digit numerators Q for GF(2)), and {r/N + D} = 0 exactly when N D is an
+  // integer: then the residue r = -N D mod N lands on 0.  That residue is 0
+  // itself only for D = 0, whose zero coordinate is the point of row 0 alone,
+  // which a point set without row 0 (the union of Korobov rules) never uses.
+  if (phi_kind == QMC_PHI_INVNORM && ((__int128)shift_num * N) % shift_den == 0 &&
+      (row0_used || shift_num != 0))
+    return QMC_ERR_ARG;
 
   qmc_plan_s* P = new (std::nothrow) qmc_plan_s();
   if (!P) return QMC_ERR_OOM;

@@ -207,6 +207,10 @@ struct qmc_batch_s {
   // and each one's position in the caller's list
   std::vector<std::pair<int64_t, std::vector<BatchInst>>> byKey;
   std::vector<std::vector<int>> input_index;
+  // every device range the runs read or write (A_i, X_i, epilogue vectors),
+  // checked against the workspace at each run
+  std::vector<std::pair<const void*, size_t>> operands;
+  std::vector<std::pair<const void*, size_t>> epi_operands;
 };
 
 static inline size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -301,9 +305,23 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
     const int64_t la = lda ? lda[i] : t[i], lx = ldx ? ldx[i] : t[i];
     if (la < t[i] || lx < t[i]) return QMC_ERR_ARG;
   }
+  // every X[i] is written while the A[k] and the other X[k] are read or
+  // written: no output may overlap any operand of the batch
+  std::vector<std::pair<const void*, size_t>> ops(2 * (size_t)count);
+  for (int i = 0; i < count; ++i) {
+    ops[2 * i] = {A[i], matrix_extent(plans[i]->s, t[i], lda ? lda[i] : t[i], dtype)};
+    ops[2 * i + 1] = {X[i], matrix_extent(plans[i]->N, t[i], ldx ? ldx[i] : t[i], dtype)};
+  }
+  for (int i = 0; i < count; ++i) {
+    const auto& x = ops[2 * i + 1];
+    for (size_t k = 0; k < ops.size(); ++k)
+      if (k != (size_t)(2 * i + 1) && ranges_overlap(x.first, x.second, ops[k].first, ops[k].second))
+        return QMC_ERR_ALIAS;
+  }
   qmc_batch_s* B = new (std::nothrow) qmc_batch_s();
   if (!B) return QMC_ERR_OOM;
   B->dtype = dtype;
+  B->operands = std::move(ops);
   // products grouped by layout key (R, P2, Q2)
   auto& byKey = B->byKey;
   for (int i = 0; i < count; ++i) {
@@ -380,21 +398,34 @@ int qmc_batch_set_epilogue(qmc_batch_t B, int kind, const void* const* bias,
                            const void* const* scale, void* stream) {
   if (!B || kind < QMC_EPI_NONE || kind > QMC_EPI_EXP) return QMC_ERR_ARG;
   // bias[i], scale[i] belong to the caller's product i (input_index)
+  std::vector<std::pair<const void*, size_t>> epi_ops;
   for (size_t g = 0; g < B->byKey.size(); ++g) {
     for (size_t k = 0; k < B->byKey[g].second.size(); ++k) {
       BatchInst& I = B->byKey[g].second[k];
       const int i = B->input_index[g][k];
       const void* b = (kind && bias) ? bias[i] : nullptr;
       const void* c = (kind && scale) ? scale[i] : nullptr;
-      const size_t xa = matrix_extent(I.L + 1, I.t, I.ldx, B->dtype);  // N = L + 1 rows
       const size_t va = matrix_extent(1, I.t, I.t, B->dtype);
-      if ((b && ranges_overlap(I.X, xa, b, va)) || (c && ranges_overlap(I.X, xa, c, va)))
-        return QMC_ERR_ALIAS;
-      I.epi_kind = kind;
-      I.epi_bias = b;
-      I.epi_scale = c;
+      if (b) epi_ops.push_back({b, va});
+      if (c) epi_ops.push_back({c, va});
     }
   }
+  // no X of the batch may overlap any epilogue vector (checked before any
+  // descriptor changes, so a refused call leaves the batch as it was)
+  for (size_t k = 1; k < B->operands.size(); k += 2)
+    for (const auto& e : epi_ops)
+      if (ranges_overlap(B->operands[k].first, B->operands[k].second, e.first, e.second))
+        return QMC_ERR_ALIAS;
+  for (size_t g = 0; g < B->byKey.size(); ++g) {
+    for (size_t k = 0; k < B->byKey[g].second.size(); ++k) {
+      BatchInst& I = B->byKey[g].second[k];
+      const int i = B->input_index[g][k];
+      I.epi_kind = kind;
+      I.epi_bias = (kind && bias) ? bias[i] : nullptr;
+      I.epi_scale = (kind && scale) ? scale[i] : nullptr;
+    }
+  }
+  B->epi_operands = std::move(epi_ops);
   return build_runs(B, B->chunk_bytes, B->nt_inter, (hipStream_t)stream);
 }
 
@@ -502,6 +533,10 @@ extern "C" {
 int qmc_batch_run(qmc_batch_t B, void* workspace, size_t workspace_bytes, void* stream) {
   if (!B || !B->ready) return QMC_ERR_ARG;
   if (!workspace || workspace_bytes < B->ws_bytes) return QMC_ERR_WORKSPACE;
+  for (const auto& o : B->operands)
+    if (ranges_overlap(workspace, B->ws_bytes, o.first, o.second)) return QMC_ERR_ALIAS;
+  for (const auto& o : B->epi_operands)
+    if (ranges_overlap(workspace, B->ws_bytes, o.first, o.second)) return QMC_ERR_ALIAS;
   hipStream_t st = (hipStream_t)stream;
   for (const auto& g : B->groups) {
     const int rc = B->dtype == QMC_F32 ? run_group<float>(g, (char*)workspace, st)

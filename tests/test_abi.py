@@ -66,6 +66,14 @@ def _create(rule=0, N=7, gen=(1, 5, 3), modulus=0, phi=0, snum=0, sden=1, dtype=
     (dict(dtype=5), -1),
     (dict(phi=9), -1),
     (dict(phi=2), -1),               # inverse normal CDF without a shift hits x = 0
+    # a shift D with N D an integer puts the coordinate of residue -N D mod N
+    # at 0, where the inverse normal CDF is -inf
+    (dict(phi=2, snum=1, sden=7), -1),
+    (dict(phi=2, snum=3, sden=7), -1),
+    (dict(phi=2, snum=2, sden=14), -1),
+    (dict(rule=1, N=16, gen=(1, 2), modulus=0b10011, phi=2), -1),
+    (dict(rule=1, N=16, gen=(1, 2), modulus=0b10011, phi=2, snum=1, sden=4), -1),
+    (dict(rule=1, N=16, gen=(1, 2), modulus=0b10011, phi=2, snum=3, sden=16), -1),
     (dict(snum=3, sden=2), -1),      # shift outside [0, 1)
     (dict(s=0), -1),
     (dict(rule=1, N=12, modulus=0b10011), -1),        # N not a power of two
@@ -102,6 +110,8 @@ def test_null_arguments_rejected():
     (7, 3, 9, 0, 1, 0, -1),      # unknown phi
     (7, 3, 0, 3, 2, 0, -1),      # shift outside [0, 1)
     (7, 3, 0, 0, 1, 5, -1),      # unknown dtype
+    (7, 3, 2, 1, 7, 0, -1),      # inverse normal CDF, shift 1/K: a coordinate is 0
+    (11, 3, 2, 4, 11, 1, -1),    # shift 4/K likewise
 ])
 def test_korobov_create_rejects_before_gpu_work(K, s, phi, snum, sden, dtype, code):
     L = q.lib()

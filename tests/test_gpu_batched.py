@@ -216,3 +216,51 @@ def test_batch_autotune_outer_radix():
     Xs = b.run()
     for p, A, X in zip(plans, As, Xs):
         assert torch.equal(q.matmul(p, A), X)
+
+
+def test_batch_rejects_aliasing():
+    """qmc_batch_create refuses an output X_i that overlaps another product's
+    A_k or X_k, qmc_batch_set_epilogue an epilogue vector inside some X, and
+    qmc_batch_run a workspace that overlaps an operand (QMC_ERR_ALIAS, before
+    any launch).  Every overlapping buffer lies inside one allocation large
+    enough for what the call would write, so a missed check could not write
+    outside it."""
+    torch = torch_cuda()
+    import ctypes
+    import paper_1501_06286_amd as q
+    insts = [qi.small_lattice(101, 10, 3, dtype="f32", seed=1),
+             qi.small_lattice(103, 12, 3, dtype="f32", seed=2)]
+    announce("batch aliasing checks")
+    plans = [plan_of(i) for i in insts]
+    big = torch.zeros(1 << 22, dtype=torch.float32, device="cuda")
+    A0 = big[0:30].view(10, 3)
+    A1 = big[64:100].view(12, 3)
+    A0.copy_(torch.from_numpy(insts[0].A))
+    A1.copy_(torch.from_numpy(insts[1].A))
+    X0 = big[1024:1024 + 303].view(101, 3)
+    X1 = big[2048:2048 + 309].view(103, 3)
+    for bad in ([X0, big[10:10 + 309].view(103, 3)],        # X_1 over A_0
+                [X0, big[1100:1100 + 309].view(103, 3)],    # X_1 over X_0
+                [big[70:70 + 303].view(101, 3), X1]):       # X_0 over A_1
+        with pytest.raises(q.QMCError) as e:
+            q.Batch(plans, [A0, A1], bad)
+        assert e.value.code == -5
+    b = q.Batch(plans, [A0, A1], [X0, X1])
+    with pytest.raises(q.QMCError) as e:
+        b.set_epilogue("affine", biases=[X1[0], None])
+    assert e.value.code == -5
+    L = q.lib()
+    nb = ctypes.c_size_t()
+    assert L.qmc_batch_workspace_size(b._h, ctypes.byref(nb)) == 0
+    need = nb.value
+    assert need < 4 * (big.numel() - 2048 - 4096)
+    for start in (0, 2048):  # over A_0, over X_1
+        ws = big.data_ptr() + 4 * start
+        rc = L.qmc_batch_run(b._h, ctypes.c_void_p(ws), ctypes.c_size_t(need),
+                             ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+        assert rc == -5
+    torch.cuda.synchronize()
+    Xs = b.run()
+    torch.cuda.synchronize()
+    for inst, X in zip(insts, Xs):
+        assert_close(X.double().cpu().numpy(), oracle.matmul(inst), inst.A, inst, "f32", inst.name)

@@ -1,9 +1,14 @@
 """Parity at the full benchmark sizes, in the configuration bench.py times.
 
-The oracle cannot form these products whole, so it computes sampled rows of
-X (and sampled entries of dA) one by one; properties that hold at any size
-(column sums, the adjoint identity, finite differences of a linear map) are
-checked on the whole output.
+The Gaussian workload (N = 65537, s = t = 4096) is compared with the oracle
+on every entry, in FP32 and FP64.  For the PDE field (GF(2), s = 16384,
+t = 4096) and the large rule (N = 1048573, s = 65536, t = 256) the oracle
+computes a row sample chosen through the plan's power table so that every
+residue e1 of the on-chip transform (so every e1 tile of the back pass, with
+random outer indices) appears, plus the first and last group elements; the
+PDE field is also compared whole with the dense MFMA product of the explicit
+Y.  Properties that hold at any size (column sums, the adjoint identity,
+finite differences of a linear map) are checked on the whole output.
 """
 import math
 
@@ -24,9 +29,50 @@ def sample_rows(N, k, seed):
     return np.array(sorted(rows))
 
 
-def _forward_sampled(inst, dtype, nrows=48, tuning=None, autotuned=False):
-    """tuning: a fixed launch tuning; autotuned: the one bench.py's autotuner
-    picks for this plan (the configuration the benchmark times)."""
+def tile_rows(p, seed):
+    """Rows n = pow[e] for group indices e that take every residue
+    e1 = e mod M1 once (outer index e2 drawn at random below L), plus e = 0,
+    e = L - 1 and the constant row 0."""
+    info = p.info()
+    M1, L = info["M1"], info["L"]
+    pw = p.tables()[0]
+    rg = np.random.default_rng(seed)
+    e1 = np.arange(min(M1, L), dtype=np.int64)
+    e2 = rg.integers(0, (L - 1 - e1) // M1 + 1)
+    e = np.concatenate([e1 + M1 * e2, [0, L - 1]])
+    return np.unique(np.concatenate([[0], pw[e].astype(np.int64)]))
+
+
+_FULL = {}
+
+
+def oracle_full(inst):
+    """The oracle's whole X = Y A (FP64), kept for the next test of the same
+    instance (one at a time: 2 GiB at the Gaussian workload)."""
+    key = (inst.name, inst.dtype)
+    if key not in _FULL:
+        _FULL.clear()
+        announce(f"  oracle: all {inst.N} rows of {inst.name} ({inst.dtype} A)")
+        _FULL[key] = oracle.matmul_rows(inst, np.arange(inst.N), chunk=1024)
+    return _FULL[key]
+
+
+def _check_colsums(X, inst, dtype):
+    # column sums: sum_n Y[n, j] = S_phi for every j (each column runs through
+    # all one-dimensional points once), so 1^T X = S_phi 1^T A
+    T = oracle.phi_residue_values(inst.rule, inst.N, inst.phi, inst.modulus, inst.shift)
+    S = float(np.sum(T))
+    colsum = X.double().sum(dim=0).cpu().numpy()
+    bound = S * inst.A.sum(axis=0)
+    scale = ymax(inst) * np.abs(inst.A).sum(axis=0) * math.sqrt(inst.N)
+    assert np.max(np.abs(colsum - bound) / scale) < (1e-10 if dtype == "f64" else 1e-5)
+
+
+def _forward(inst, dtype, rows=None, tuning=None, autotuned=False):
+    """X = Y A on the GPU against the oracle: every row when rows is None,
+    else the given rows.  tuning: a fixed launch tuning; autotuned: the one
+    bench.py's autotuner picks for this plan (the configuration the
+    benchmark times)."""
     torch = torch_cuda()
     import paper_1501_06286_amd as q
     p = plan_of(inst)
@@ -38,28 +84,41 @@ def _forward_sampled(inst, dtype, nrows=48, tuning=None, autotuned=False):
         p.set_tuning(**tuning)
     A = to_dev(inst.A, dtype)
     X = q.matmul(p, A)
-    rows = sample_rows(inst.N, nrows, inst.N + inst.s)
-    got = X[torch.from_numpy(rows).cuda()].double().cpu().numpy()
-    ref = oracle.matmul_rows(inst, rows)
+    if rows is None:
+        got = X.double().cpu().numpy()
+        ref = oracle_full(inst)
+    else:
+        rows = rows(p) if callable(rows) else rows
+        got = X[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+        ref = oracle.matmul_rows(inst, rows)
     worst = assert_close(got, ref, inst.A, inst, dtype, inst.name)
-    # column sums: sum_n Y[n, j] = S_phi for every j (each column runs through
-    # all one-dimensional points once), so 1^T X = S_phi 1^T A
-    T = oracle.phi_residue_values(inst.rule, inst.N, inst.phi, inst.modulus, inst.shift)
-    S = float(np.sum(T))
-    colsum = X.double().sum(dim=0).cpu().numpy()
-    bound = S * inst.A.sum(axis=0)
-    scale = ymax(inst) * np.abs(inst.A).sum(axis=0) * math.sqrt(inst.N)
-    assert np.max(np.abs(colsum - bound) / scale) < (1e-10 if dtype == "f64" else 1e-5)
+    del got
+    _check_colsums(X, inst, dtype)
     return p, A, X, worst
 
 
-@pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("how", ["default", "autotuned", "chunk256_nt"])
+@pytest.mark.parametrize("dtype,how", [(d, h) for d in ("f32", "f64")
+                                       for h in ("default", "autotuned", "chunk256_nt")])
 def test_c2_gaussian_full(dtype, how):
+    """Every one of the 65537 x 4096 entries against the oracle (Section 2.1,
+    eq. (ZPa): the fast product equals the plain one, so every row must)."""
     inst = qi.make_c2(dtype)
-    announce(f"C2 full size {dtype} {how}")
-    _forward_sampled(inst, dtype, autotuned=how == "autotuned",
-                     tuning={"chunk_pairs": 256, "nt_store": 1} if how == "chunk256_nt" else None)
+    announce(f"C2 full size {dtype} {how}: whole output")
+    _forward(inst, dtype, autotuned=how == "autotuned",
+             tuning={"chunk_pairs": 256, "nt_store": 1} if how == "chunk256_nt" else None)
+
+
+def test_c1_plain_lattice_fp64():
+    """The plain-method workload as specified: N = 2003, s = 500, one column,
+    phi = identity without shift, FP64; every entry at 1e-12, and the
+    single column travels as the real part of one complex column pair."""
+    inst = qi.make_c1()
+    assert (inst.N, inst.s, inst.t, inst.phi, inst.shift, inst.dtype) == \
+        (2003, 500, 1, qi.PHI_IDENTITY, (0, 1), "f64")
+    announce("C1 plain lattice N=2003 s=500 t=1 FP64")
+    p, A, X, worst = _forward(inst, "f64")
+    assert p.info()["beta"] == 5  # the smallest primitive root of 2003
+    assert worst <= 1e-12
 
 
 def test_c2_matches_dense_baseline():
@@ -80,42 +139,60 @@ def test_c2_matches_dense_baseline():
 
 @pytest.mark.parametrize("how", ["default", "autotuned"])
 def test_c3_pde_gf2_full(how):
+    """Rows covering every e1 tile against the oracle, and the whole output
+    against the dense MFMA product of the explicit Y (4.3 GB)."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
     inst = qi.make_c3("f32")
-    announce(f"C3 full size (GF(2), m=16, s=16384, t=4096) {how}")
-    _forward_sampled(inst, "f32", nrows=24, autotuned=how == "autotuned")
+    announce(f"C3 full size (GF(2), m=16, s=16384, t=4096) {how}: tile rows")
+    p, A, X, _ = _forward(inst, "f32", rows=lambda p: tile_rows(p, 31),
+                          autotuned=how == "autotuned")
+    if how != "default":
+        return
+    announce("C3 whole output vs the dense MFMA product")
+    Y = q.explicit_points(p)
+    Xd = q.dense_matmul(p, Y, A)
+    scale = float(Y.abs().max()) * A.abs().sum(dim=0)
+    del Y
+    err = float(((X - Xd).abs().max(dim=0).values / scale).max())
+    assert err < 2 * TOL["f32"], err
 
 
 def test_c5_forward_adjoint_fd():
     torch = torch_cuda()
     import paper_1501_06286_amd as q
     inst = qi.make_c5("f32")
-    announce("C5 full size forward")
-    p, A, X, _ = _forward_sampled(inst, "f32", nrows=16)
+    announce("C5 full size forward: tile rows")
+    p, A, X, _ = _forward(inst, "f32", rows=lambda p: tile_rows(p, 55))
     info = p.info()
     assert info["M2"] > 64  # exercises the split outer pass
     announce("C5 adjoint sampled entries")
     G = to_dev(inst.G, "f32")
     dA = q.matmul_adjoint(p, G)
     ent = qi.fd_entries(inst.s, inst.t)
+    assert len(ent) == 32
     got = np.array([float(dA[j, k]) for j, k in ent])
     ref = oracle.adjoint_entries(inst, ent)
     scale = ymax(inst) * np.abs(inst.G).sum(axis=0)
     err = np.abs(got - ref) / np.array([scale[k] for _, k in ent])
     assert np.max(err) <= TOL["f32"], np.max(err)
-    announce("C5 finite differences")
+    announce("C5 finite differences on all 32 seeded entries")
     # L(A) = <X(A), G> is linear in A: a central difference with the step that
     # is actually representable recovers dA up to the FP32 rounding of X
     Gd = G.double()
-    for (j, k) in ent[:8]:
+    Ap = A.clone()
+    Xp = torch.empty_like(X)
+    ws = p.workspace(inst.t, A.device)
+    for (j, k) in ent:
         a0 = float(A[j, k])
         h = 16.0
         up = np.float32(a0 + h)
         dn = np.float32(a0 - h)
-        Ap = A.clone()
         Ap[j, k] = float(up)
-        Lp = float((q.matmul(p, Ap).double() * Gd).sum())
+        Lp = float((q.matmul(p, Ap, out=Xp, workspace=ws).double() * Gd).sum())
         Ap[j, k] = float(dn)
-        Lm = float((q.matmul(p, Ap).double() * Gd).sum())
+        Lm = float((q.matmul(p, Ap, out=Xp, workspace=ws).double() * Gd).sum())
+        Ap[j, k] = a0
         fd = (Lp - Lm) / (float(up) - float(dn))
         assert abs(fd - float(dA[j, k])) <= 2e-3 * (abs(float(dA[j, k])) + scale[k] * 1e-3), (j, k, fd)
 
@@ -127,7 +204,7 @@ def test_split_outer_pass_lattice(dtype):
     assert qi.is_prime(N)
     inst = qi.small_lattice(N, 300, 5, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype)
     announce(f"split outer pass N={N} {dtype}")
-    p, A, X, _ = _forward_sampled(inst, dtype, nrows=32)
+    p, A, X, _ = _forward(inst, dtype, rows=sample_rows(N, 32, N + inst.s))
     assert p.info()["M2"] == 128
     import paper_1501_06286_amd as q
     G = qi.randn((N, inst.t), seed=11, dtype=dtype)
@@ -140,7 +217,7 @@ def test_split_outer_pass_gf2():
     torch_cuda()
     inst = qi.small_gf2(19, 96, 3, dtype="f64")
     announce("split outer pass GF(2) m=19")
-    p, A, X, _ = _forward_sampled(inst, "f64", nrows=24)
+    p, A, X, _ = _forward(inst, "f64", rows=sample_rows(inst.N, 24, inst.N + inst.s))
     assert p.info()["M2"] == 256
 
 
@@ -154,7 +231,7 @@ def test_largest_supported_length(dtype):
     assert qi.is_prime(N)
     inst = qi.small_lattice(N, 8, 3, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype, seed=2)
     announce(f"largest length N={N} {dtype}")
-    p, A, X, _ = _forward_sampled(inst, dtype, nrows=32)
+    p, A, X, _ = _forward(inst, dtype, rows=sample_rows(N, 32, N + inst.s))
     info = p.info()
     assert info["M"] == 1 << 24
     assert info["Q2"] == q2 and info["P2"] == 64

@@ -137,7 +137,70 @@ def test_gf2_known_small_field():
     """
     x = oracle.gf2_coords(2, 0b111, [0b10])
     assert list(x[:, 0]) == [0.0, 0.75, 0.5, 0.25]
+    K, D = oracle.coords_rational(qi.RULE_POLY_GF2, 4, [0b10], modulus=0b111)
+    assert list(K[:, 0] / D) == [0.0, 0.75, 0.5, 0.25]
     assert list(oracle.gf2_digits_coords(2, 0b111, [0b10])[:, 0]) == [0.0, 0.75, 0.5, 0.25]
+
+
+@pytest.mark.parametrize("m", [1, 2, 3, 5, 8, 12, 16])
+def test_gf2_digital_net_form_equals_direct_definition(m):
+    """The digital-net numerators (Hankel generating matrix of the Laurent
+    digits of q/p) equal the direct route r = n q mod p, Q = floor(r x^m / p)
+    bit for bit, on every row for small m and on sampled rows otherwise."""
+    rg = np.random.default_rng(300 + m)
+    p = qi.draw_primitive_poly(m, rg)
+    N = 1 << m
+    q = rg.integers(1, N, size=7)
+    rows = np.arange(N) if m <= 8 else rg.choice(N, size=2000, replace=False)
+    direct = oracle.points.gf2_value_of_residue(m, p, oracle.points.gf2_residues(m, p, q, rows))
+    digital = oracle.points.gf2_numerators_digital(m, p, q, rows)
+    np.testing.assert_array_equal(direct, digital)
+
+
+@pytest.mark.parametrize("rule", [qi.RULE_LATTICE, qi.RULE_POLY_GF2, qi.RULE_KOROBOV_UNION])
+@pytest.mark.parametrize("phi,shift", [(qi.PHI_IDENTITY, (0, 1)), (qi.PHI_CENTERED, (0, 1)),
+                                       (qi.PHI_TENT, (1, 3)), (qi.PHI_INVNORM, "half")])
+def test_phi_table_lookup_is_elementwise_phi(rule, phi, shift):
+    """explicit_Y evaluates phi once per numerator and looks it up when the
+    rows hold more entries than there are numerators: the same bits as phi of
+    every entry's exact coordinate."""
+    if rule == qi.RULE_LATTICE:
+        N, gen, mod, base = 101, np.array([1, 5, 17, 44, 99]), 0, 101
+    elif rule == qi.RULE_POLY_GF2:
+        N, mod = 128, qi.draw_primitive_poly(7, np.random.default_rng(1))
+        gen, base = np.array([1, 3, 77, 127, 64]), 128
+    else:
+        N, gen, mod, base = 100, np.arange(6), 11, 11
+    if shift == "half":
+        shift = (1, 2 * base)
+    Y = oracle.explicit_Y(rule, N, gen, phi, mod, shift)
+    K, D = oracle.coords_rational(rule, N, gen, mod, shift)
+    np.testing.assert_array_equal(Y, oracle.phi_rational(phi, K, D))
+    rows = np.array([0, 1, N - 1, N // 2])  # fewer entries than numerators: no table
+    np.testing.assert_array_equal(oracle.explicit_Y(rule, N, gen, phi, mod, shift, rows), Y[rows])
+
+
+def test_planted_gf2_hankel_index_is_caught():
+    """A digital-net form that reads the Hankel matrix one digit off (u_{i+l-1}
+    or u_{i+l+1}) breaks the GF(4) hand pin and the direct route."""
+    def shifted(off):
+        def numer(m, p, q, rows=None):
+            qq = np.asarray(q, dtype=np.uint64)
+            n = np.arange(1 << m, dtype=np.uint64) if rows is None else np.asarray(rows, np.uint64)
+            u = oracle.points.gf2_laurent_digits(p, qq, 2 * m + 1)
+            out = np.zeros((len(n), len(qq)), dtype=np.uint64)
+            for i in range(m):
+                word = np.zeros(len(qq), dtype=np.uint64)
+                for l in range(1, m + 1):
+                    k = i + l + off  # the right index is u_{i+l}, row i + l - 1
+                    word |= (u[k - 1] if k >= 1 else 0) << np.uint64(m - l)
+                bit = ((n >> np.uint64(i)) & np.uint64(1)) == 1
+                out ^= np.where(bit[:, None], word[None, :], np.uint64(0))
+            return out
+        return numer
+    assert np.array_equal(oracle.points.gf2_numerators_digital(2, 0b111, [0b10])[:, 0], [0, 3, 2, 1])
+    for off in (-1, 1):
+        assert not np.array_equal(shifted(off)(2, 0b111, [0b10])[:, 0], [0, 3, 2, 1])
 
 
 @pytest.mark.parametrize("m", [6, 8, 10])
@@ -181,6 +244,60 @@ def test_column_sum_gf2_centered():
     inst = qi.small_gf2(10, 40, 2, phi=qi.PHI_CENTERED)
     Y = oracle.Y_rows(inst)
     np.testing.assert_allclose(Y.sum(axis=0), -0.5, atol=1e-12)
+
+
+def _tent_pins_pass(tent_fn) -> bool:
+    """Closed forms of the tent map 1 - |2x - 1| (Section 2.1) that a
+    candidate phi_rational-like routine tent_fn(K, D) must meet on the columns
+    of the oracle's point sets:
+
+    * lattice, odd N, g coprime to N: a column runs through every k/N once and
+      sum_{k<N} tent(k/N) = 2 sum_{k<=(N-1)/2} 2k/N = (N^2 - 1)/(2N);
+    * GF(2), N = 2^m: a column runs through every k/2^m once and
+      sum_k tent(k/N) = N/2 (the terms 2k/N for k <= N/2 add up to
+      (N/2 + 1)/2, the terms 2 - 2k/N for k > N/2 to (N/2 - 1)/2);
+    * reflection: tent(1 - x) = tent(x), and for a lattice {(N - n) g / N} =
+      1 - {n g / N} when n g != 0 mod N, so rows n and N - n are equal;
+    * tent(1/2) = 1 and tent(0) = 0 (row 0 of the unshifted lattice)."""
+    for N in (101, 1009):
+        gen = np.random.default_rng(N).integers(1, N, size=9)
+        K, D = oracle.coords_rational(qi.RULE_LATTICE, N, gen)
+        Y = tent_fn(K, D)
+        if not np.allclose(Y.sum(axis=0), (N * N - 1) / (2 * N), rtol=1e-13, atol=0):
+            return False
+        if not np.array_equal(Y[1:], Y[:0:-1]) or np.any(Y[0] != 0.0):
+            return False
+    for m in (6, 9):
+        rg = np.random.default_rng(40 + m)
+        p = qi.draw_primitive_poly(m, rg)
+        q = rg.integers(1, 1 << m, size=5)
+        K, D = oracle.coords_rational(qi.RULE_POLY_GF2, 1 << m, q, modulus=p)
+        if not np.allclose(tent_fn(K, D).sum(axis=0), (1 << m) / 2, rtol=1e-13, atol=0):
+            return False
+    return bool(tent_fn(np.array([1]), 2)[0] == 1.0)
+
+
+def test_tent_closed_forms():
+    """The oracle's tent branch meets the closed forms, through the same
+    product path the GPU parity tests use (explicit Y, dense multiply)."""
+    assert _tent_pins_pass(lambda K, D: oracle.phi_rational(qi.PHI_TENT, K, D))
+    N = 1009
+    inst = qi.small_lattice(N, 33, 3, phi=qi.PHI_TENT)
+    X = oracle.matmul(inst)
+    np.testing.assert_allclose(X.sum(axis=0), (N * N - 1) / (2 * N) * inst.A.sum(axis=0),
+                               rtol=1e-11)
+    np.testing.assert_allclose(X[1:], X[:0:-1], rtol=0, atol=1e-13)
+
+
+def test_tent_planted_mistakes_are_caught():
+    """Plausible slips in the tent branch fail the pins: the complement
+    |2x - 1|, a dropped factor 2 (1 - |x - 1/2|), the ramp 1 - |x - 1| = x,
+    and the half-height tent."""
+    for bad in (lambda K, D: np.abs(2 * K - D) / float(D),
+                lambda K, D: 1.0 - np.abs(K / float(D) - 0.5),
+                lambda K, D: K / float(D),
+                lambda K, D: (D - np.abs(2 * K - D)) / (2.0 * D)):
+        assert not _tent_pins_pass(bad)
 
 
 def test_row_zero_is_phi_of_shift():
