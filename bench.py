@@ -273,6 +273,16 @@ def main():
                     help="time only the dense MFMA GEMM baseline (for profiler runs)")
     ap.add_argument("--vendor-context", action="store_true",
                     help="with --dense-only: also time torch.matmul of the same shape")
+    ap.add_argument("--only", default=None, choices=["c2", "c3", "c4", "c5", "korobov"],
+                    help="time only this workload's product (for profiler runs): c2 at --dtype, "
+                         "the others FP32; with --tuning for single plans, --adjoint for the "
+                         "transpose product, --batch-run-mib for the batch")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="with --only: time dA = Y^T G instead of X = Y A")
+    ap.add_argument("--batch-run-mib", type=int, default=0,
+                    help="with --only c4: MiB of intermediates per run (0: the library default)")
+    ap.add_argument("--korobov-chunk", type=int, default=0,
+                    help="with --only korobov: blocks per run (0: chosen from the shape)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 3 times (reference "
                          "for the FETCH_SIZE / WRITE_SIZE counters)")
@@ -307,6 +317,9 @@ def main():
     dev = torch.device("cuda:0")
     hd = args.dtype
     other = "f32" if hd == "f64" else "f64"
+    if args.only:
+        print(json.dumps(only_run(args, torch, q, qi, dev)), flush=True)
+        return
     if args.dense_only:
         inst = qi.make_c2(hd)
         tdt = torch.float32 if hd == "f32" else torch.float64
@@ -636,6 +649,72 @@ def main():
         log(f"cpu baseline {result['cpu_baseline']['value']:.3e} entries/s; worst errors "
             f"{ {l.name: l.out.get('err_vs_oracle') for l in all_legs} }")
     print(json.dumps(result), flush=True)
+
+
+TUNING_KEYS = ("chunk_pairs", "streams", "nt_store", "front", "outer_q", "nt_inter")
+
+
+def only_run(args, torch, q, qi, dev):
+    """One workload alone, W untimed and K timed steps, for profiler runs: the
+    launch tuning is the given one (--tuning), never re-tuned, so a kernel
+    trace holds only the kernels of the timed configuration."""
+    w = args.only
+    out = {"only": w, "steps": args.steps, "warmup": args.warmup, "adjoint": args.adjoint}
+
+    def run(step):
+        for _ in range(args.warmup):
+            step()
+        el = time_steps(step, args.steps, torch)
+        out["ms_per_step"] = round(1e3 * el / args.steps, 4)
+
+    def randn_dev(shape):
+        g = torch.Generator(dev).manual_seed(7)
+        return torch.randn(shape, dtype=torch.float32, device=dev, generator=g)
+
+    if w in ("c2", "c3", "c5"):
+        inst = {"c2": lambda: qi.make_c2(args.dtype), "c3": lambda: qi.make_c3("f32"),
+                "c5": lambda: qi.make_c5("f32", with_G=False)}[w]()
+        tdt = torch.float32 if inst.dtype == "f32" else torch.float64
+        plan = q.Plan.from_instance(inst)
+        if args.tuning:
+            plan.set_tuning(**dict(zip(TUNING_KEYS, [int(v) for v in args.tuning.split(",")])))
+        out.update({"workload": f"{inst.name}_{inst.dtype}", "tuning": plan.get_tuning(),
+                    "info": {k: plan.info()[k] for k in ("M", "M1", "M2", "P2", "Q2")}})
+        ws = plan.workspace(inst.t, dev)
+        if args.adjoint:
+            G = randn_dev((inst.N, inst.t)).to(tdt)
+            dA = torch.empty((inst.s, inst.t), dtype=tdt, device=dev)
+            run(lambda: q.matmul_adjoint(plan, G, out=dA, workspace=ws))
+        else:
+            A = torch.from_numpy(inst.A).to(tdt).to(dev)
+            X = torch.empty((inst.N, inst.t), dtype=tdt, device=dev)
+            run(lambda: q.matmul(plan, A, out=X, workspace=ws))
+    elif w == "korobov":
+        kin = qi.make_korobov("f32")
+        U = q.KorobovUnion.from_instance(kin)
+        if args.korobov_chunk:
+            U.set_chunk(args.korobov_chunk)
+        out.update({"workload": kin.name, "chunk_blocks": U.info()["chunk_blocks"]})
+        ws = U.workspace(kin.t, dev)
+        if args.adjoint:
+            G = randn_dev((kin.N, kin.t))
+            dA = torch.empty((kin.s, kin.t), dtype=torch.float32, device=dev)
+            run(lambda: q.korobov_matmul_adjoint(U, G, out=dA, workspace=ws))
+        else:
+            A = torch.from_numpy(kin.A).float().to(dev)
+            X = torch.empty((kin.N, kin.t), dtype=torch.float32, device=dev)
+            run(lambda: q.korobov_matmul(U, A, out=X, workspace=ws))
+    else:  # c4: the 256-product batch at the library's default outer radices
+        insts = qi.make_c4(dtype="f32")
+        plans = [q.Plan.from_instance(i) for i in insts]
+        As = [torch.from_numpy(i.A).float().to(dev) for i in insts]
+        batch = q.Batch(plans, As)
+        if args.batch_run_mib:
+            batch.set_chunk(args.batch_run_mib << 20, 0)
+        out.update({"workload": "c4_batched_256_f32", "run_mib": args.batch_run_mib,
+                    "entries": sum(i.N * i.t for i in insts)})
+        run(batch.run)
+    return out
 
 
 def cpu_baseline_and_errors(inst, legs, budget_s=4.0, reps=5):
