@@ -261,6 +261,32 @@ int qmc_matmul_adjoint(qmc_plan_t plan, const void* G, int64_t t, int64_t ldg,
                        void* stream);
 
 /*
+ * qmc_matmul_noalloc -- X = Y A exactly as qmc_matmul computes it (the same
+ * kernels in the same order, so the same bits), for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation.  The call allocates nothing: no
+ * hipMalloc/hipFree, no stream or event creation.  Its workspace is a static
+ * device array of QMC_NOALLOC_SCRATCH_BYTES that every GPU the library runs
+ * on holds from the first load of the library's code on that device until
+ * the process ends.
+ *   A, t, lda, X, ldx, stream   as qmc_matmul; X is written, A only read.
+ * Every launch goes to `stream`, also when the plan's tuning asks for two
+ * streams.  All calls on one GPU share that GPU's one scratch array: calls
+ * that can overlap on a GPU (different streams, host threads or plans) race
+ * and give undefined results; order them on one stream.  The array keeps the
+ * last call's contents; a call reads only scratch bytes it wrote itself.
+ * Errors: QMC_ERR_ARG (bad sizes/NULL, or timing instrumentation switched on
+ * with qmc_profile_enable, which creates events), QMC_ERR_ALIAS (X overlaps
+ * A), QMC_ERR_WORKSPACE (qmc_workspace_size(plan, t) exceeds
+ * QMC_NOALLOC_SCRATCH_BYTES: fewer columns, or a smaller chunk_pairs in the
+ * plan's tuning, brings it under), QMC_ERR_HIP (the scratch address could not
+ * be looked up).
+ */
+#define QMC_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int qmc_matmul_noalloc(qmc_plan_t plan, const void* A, int64_t t, int64_t lda,
+                       void* X, int64_t ldx, void* stream);
+
+/*
  * qmc_explicit_points -- write the N x s matrix Y itself (row stride ldy) in
  * conventional order, Y[n,j] = phi(point of n g_j): the input of the dense
  * baseline.  Y is device memory owned by the caller.

@@ -42,7 +42,7 @@ EXPORTED = [
     "qmc_batch_destroy",
     "qmc_korobov_create", "qmc_korobov_destroy", "qmc_korobov_info", "qmc_korobov_set_chunk",
     "qmc_korobov_workspace_size", "qmc_korobov_plan", "qmc_korobov_matmul",
-    "qmc_korobov_matmul_epilogue", "qmc_korobov_matmul_adjoint",
+    "qmc_korobov_matmul_epilogue", "qmc_korobov_matmul_adjoint", "qmc_matmul_noalloc",
 ]
 PROF_SLOTS = 10
 BATCH_CHUNK_DEFAULT = 256 << 20  # QMC_BATCH_CHUNK_DEFAULT
@@ -100,6 +100,7 @@ def lib() -> ctypes.CDLL:
         L.qmc_workspace_size.argtypes = [vp, i64, ctypes.POINTER(sz)]
         L.qmc_matmul.argtypes = [vp, vp, i64, i64, vp, i64, vp, sz, vp]
         L.qmc_matmul_adjoint.argtypes = [vp, vp, i64, i64, vp, i64, vp, sz, vp]
+        L.qmc_matmul_noalloc.argtypes = [vp, vp, i64, i64, vp, i64, vp]
         L.qmc_matmul_epilogue.argtypes = [vp, vp, i64, i64, vp, i64, ip, vp, vp, vp, sz, vp]
         L.qmc_explicit_points.argtypes = [vp, vp, i64, vp]
         L.qmc_dense_matmul.argtypes = [vp, vp, i64, vp, i64, i64, vp, i64, vp]
@@ -332,6 +333,21 @@ def matmul(plan: Plan, A, out=None, workspace=None, stream=None, epilogue=None, 
                                      ctypes.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
                                      _stream_handle(stream)), "qmc_matmul_epilogue")
     return X
+
+
+def matmul_noalloc(plan: Plan, A, out, stream=None):
+    """X = Y A into the preallocated `out` through qmc_matmul_noalloc: the
+    library's static device scratch serves as workspace, nothing is allocated
+    (same result as matmul)."""
+    _check_tensor(A, plan, plan.s, "A")
+    _check_tensor(out, plan, plan.N, "out")
+    t = A.shape[1]
+    if out.shape[1] != t:
+        raise ValueError(f"out has {out.shape[1]} columns, A has {t}")
+    _check(lib().qmc_matmul_noalloc(plan.handle, ctypes.c_void_p(A.data_ptr()), t, A.stride(0),
+                                    ctypes.c_void_p(out.data_ptr()), out.stride(0),
+                                    _stream_handle(stream)), "qmc_matmul_noalloc")
+    return out
 
 
 def matmul_adjoint(plan: Plan, G, out=None, workspace=None, stream=None):

@@ -334,9 +334,11 @@ static int forward_dense_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t l
   return QMC_OK;
 }
 
+// single: stay on the caller's stream even when the tuning asks for two
+// (the side stream and its events are created on first use)
 template <typename T>
 static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T* X, int64_t ldx,
-                     void* ws, hipStream_t st, const Epi<T>& epi) {
+                     void* ws, hipStream_t st, const Epi<T>& epi, bool single) {
   if (dense_front(P)) return forward_dense_t<T>(P, A, t, lda, X, ldx, ws, st, epi);
   const int64_t pairs = (t + 1) / 2;
   const size_t el = sizeof(cx<T>);
@@ -351,7 +353,7 @@ static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T*
   if (rc != QMC_OK) return rc;
   const int64_t chunk = (P->tune.chunk_pairs > 0 && P->tune.chunk_pairs < pairs)
                             ? P->tune.chunk_pairs : pairs;
-  const bool two = P->tune.streams == 2 && chunk < pairs;
+  const bool two = !single && P->tune.streams == 2 && chunk < pairs;
   hipStream_t sb = st;
   if (two) {
     if ((rc = ensure_side_stream(P)) != QMC_OK) return rc;
@@ -393,8 +395,8 @@ static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T*
 
 template <typename T>
 static int forward_epi_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T* X,
-                         int64_t ldx, void* ws, hipStream_t st, const Epi<T>& epi) {
-  int rc = forward_t<T>(P, A, t, lda, X, ldx, ws, st, epi);
+                         int64_t ldx, void* ws, hipStream_t st, const Epi<T>& epi, bool single) {
+  int rc = forward_t<T>(P, A, t, lda, X, ldx, ws, st, epi, single);
   if (rc != QMC_OK || epi.kind == 0) return rc;
   // row 0 is the fused pass's DC term, in X on the same stream by now
   k_epi_row0<T><<<(unsigned)((t + 255) / 256), 256, 0, st>>>(X, t, epi);
@@ -403,12 +405,14 @@ static int forward_epi_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda
 
 int launch_forward(const qmc_plan_s* P, const void* A, int64_t t, int64_t lda, void* X,
                    int64_t ldx, void* ws, hipStream_t st, int epi_kind, const void* bias,
-                   const void* scale) {
+                   const void* scale, bool single_stream) {
   if (P->dtype == QMC_F32)
     return forward_epi_t<float>(P, (const float*)A, t, lda, (float*)X, ldx, ws, st,
-                                Epi<float>{epi_kind, (const float*)bias, (const float*)scale});
+                                Epi<float>{epi_kind, (const float*)bias, (const float*)scale},
+                                single_stream);
   return forward_epi_t<double>(P, (const double*)A, t, lda, (double*)X, ldx, ws, st,
-                               Epi<double>{epi_kind, (const double*)bias, (const double*)scale});
+                               Epi<double>{epi_kind, (const double*)bias, (const double*)scale},
+                               single_stream);
 }
 
 // dense outer front into B[pair][w2][e1]: the adjoint's gather of G

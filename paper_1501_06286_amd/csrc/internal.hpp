@@ -132,10 +132,12 @@ int plan_create(qmc_plan_s** out, int rule, int64_t N, int64_t s, const uint64_t
 // conv.hip
 bool dense_front(const qmc_plan_s* P);
 size_t workspace_bytes(const qmc_plan_s* P, int64_t t);
-// epi_kind, bias, scale: the epilogue of qmc_matmul_epilogue (0: none)
+// epi_kind, bias, scale: the epilogue of qmc_matmul_epilogue (0: none);
+// single_stream: every launch on st whatever the tuning's stream count
 int launch_forward(const qmc_plan_s* P, const void* A, int64_t t, int64_t lda, void* X,
                    int64_t ldx, void* ws, hipStream_t st, int epi_kind = 0,
-                   const void* bias = nullptr, const void* scale = nullptr);
+                   const void* bias = nullptr, const void* scale = nullptr,
+                   bool single_stream = false);
 int launch_adjoint(const qmc_plan_s* P, const void* G, int64_t t, int64_t ldg, void* dA,
                    int64_t ldda, void* ws, hipStream_t st);
 
