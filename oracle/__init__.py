@@ -24,6 +24,9 @@ multiplication"):
   Z and selection matrix P of eq. (ZPa), worked Example 1), evaluated as a
   plain O(N^2) product Z (P a) with the paper's row order mapped back.
 * ``exact``   -- brute force over exact rationals for tiny N.
+* ``composite`` -- a checker for lattice rules with a non-prime N: the
+  product through the orbits d U(N/d) of the rows and the multilevel
+  circulant over each unit group, with brute-force group structure.
 
 The fast method reaches the plain product exactly in exact arithmetic
 (eq. (ZPa) is an identity and the ordering does not change the quadrature sum,
@@ -39,7 +42,7 @@ from .points import (PHI_IDENTITY, PHI_CENTERED, PHI_INVNORM, PHI_TENT,
                      phi_residue_values, phi_rational)
 from .dense import (matmul, adjoint, matmul_rows, adjoint_entries, Y_rows, epilogue, EPI_NONE,
                     EPI_AFFINE, EPI_EXP)
-from . import literal, exact
+from . import literal, exact, composite
 
 __all__ = [
     "PHI_IDENTITY", "PHI_CENTERED", "PHI_INVNORM", "PHI_TENT",
@@ -48,5 +51,5 @@ __all__ = [
     "phi_residue_values", "phi_rational",
     "matmul", "adjoint", "matmul_rows", "adjoint_entries", "Y_rows", "epilogue", "EPI_NONE",
     "EPI_AFFINE", "EPI_EXP",
-    "literal", "exact",
+    "literal", "exact", "composite",
 ]

@@ -269,6 +269,29 @@ def small_lattice(N: int, s: int, t: int, phi: int = PHI_IDENTITY,
                     phi, shift, dtype, _round_to(A, dtype))
 
 
+def unit_gen(N: int, s: int, gen: np.random.Generator) -> np.ndarray:
+    """s generator components drawn uniformly from the units modulo N (the
+    residues in [1, N-1] coprime to N), for lattice rules with any N."""
+    out = np.empty(0, dtype=np.int64)
+    while len(out) < s:
+        g = gen.integers(1, N, size=2 * (s - len(out)) + 8, dtype=np.int64)
+        keep = np.array([math.gcd(int(v), N) == 1 for v in g], dtype=bool)
+        out = np.concatenate([out, g[keep]])
+    return out[:s].astype(np.uint64)
+
+
+def unit_lattice(N: int, s: int, t: int, phi: int = PHI_IDENTITY,
+                 shift: Tuple[int, int] = (0, 1), dtype: str = "f64",
+                 seed: int = 0) -> Instance:
+    """A seeded lattice instance for any N (prime or not) whose generator
+    components are units modulo N."""
+    gen = np.random.default_rng([SEED_BASE, 10, N, s, t, seed])
+    g = unit_gen(N, s, gen)
+    A = gen.standard_normal((s, t))
+    return Instance(f"unit_lat_n{N}_s{s}_t{t}", RULE_LATTICE, N, s, t, g, 0,
+                    phi, shift, dtype, _round_to(A, dtype))
+
+
 def small_gf2(m: int, s: int, t: int, phi: int = PHI_CENTERED,
               shift: Tuple[int, int] = (0, 1), dtype: str = "f64",
               seed: int = 0) -> Instance:
