@@ -45,7 +45,7 @@ extern "C" {
 typedef struct qmc_plan_s* qmc_plan_t;
 
 /* point-set families */
-#define QMC_RULE_LATTICE  0   /* rank-1 lattice rule, prime N (Section 2.1) */
+#define QMC_RULE_LATTICE  0   /* rank-1 lattice rule (Section 2.1; prime N, or non-prime N by orbits) */
 #define QMC_RULE_POLY_GF2 1   /* polynomial lattice rule over GF(2), N = 2^m, primitive modulus (Remark 1) */
 
 /* the univariate map phi applied to every coordinate (Section 2.1) */
@@ -61,9 +61,9 @@ typedef struct qmc_plan_s* qmc_plan_t;
 /* error codes */
 #define QMC_OK                 0
 #define QMC_ERR_ARG           -1   /* a size, stride, pointer or enum is invalid */
-#define QMC_ERR_NOT_PRIME     -2   /* lattice rule with N not prime */
+#define QMC_ERR_NOT_PRIME     -2   /* the union of Korobov rules with K not prime (lattice rules take any N) */
 #define QMC_ERR_NOT_PRIMITIVE -3   /* GF(2) modulus not primitive of degree m with 2^m = N */
-#define QMC_ERR_GEN_ZERO      -4   /* a generator component is 0 mod N (not in the group) */
+#define QMC_ERR_GEN_ZERO      -4   /* a generator component is not a unit mod N (0, or a common factor) */
 #define QMC_ERR_ALIAS         -5   /* output overlaps an input */
 #define QMC_ERR_WORKSPACE     -6   /* workspace missing or smaller than qmc_workspace_size */
 #define QMC_ERR_OOM           -7   /* device allocation failed while building a plan */
@@ -82,12 +82,14 @@ typedef struct qmc_plan_s* qmc_plan_t;
  *
  *   out        receives the plan handle (host pointer)
  *   rule       QMC_RULE_LATTICE or QMC_RULE_POLY_GF2
- *   N          number of points: prime, 2 <= N < 2^31 (lattice); 2^m with
- *              1 <= m <= 30 (GF(2))
+ *   N          number of points: 2 <= N < 2^31 prime, or non-prime up to
+ *              2^25 (lattice); 2^m with 1 <= m <= 30 (GF(2))
  *   s          dimension, s >= 1
  *   gen        host array of s generator components: g_j in [1, N-1]
- *              (lattice, taken mod N; 0 mod N is QMC_ERR_GEN_ZERO) or GF(2)
- *              polynomial bitmasks q_j in [1, 2^m - 1]
+ *              (lattice, taken mod N; a component that is not a unit mod N
+ *              -- 0, or sharing a prime factor with a non-prime N -- is
+ *              QMC_ERR_GEN_ZERO) or GF(2) polynomial bitmasks q_j in
+ *              [1, 2^m - 1]
  *   modulus    GF(2): the primitive polynomial p with bit m set; lattice: 0
  *   phi_kind   QMC_PHI_*
  *   shift_num, shift_den
@@ -104,6 +106,23 @@ typedef struct qmc_plan_s* qmc_plan_t;
  * power of two >= 2N - 3) must split as M = M1 x M2 with M1 <= 4096 on chip
  * and M2 <= 64 x 64; longer rules (N - 1 > 2^23 when not a power of two, or
  * above 2^24) return QMC_ERR_UNSUPPORTED before any device work.
+ *
+ * Non-prime N (lattice rules; Section 2.1 defers this case to the fast
+ * construction of Nuyens and Cools for non-prime n): with unit generator
+ * components the rows split into the orbits n = d m, d | N, m a unit mod
+ * N/d, on which the coordinates are those of the rule with N/d points.  Each
+ * unit group is a direct product of cyclic groups (one per odd prime power,
+ * one for 4, two for 2^k, k >= 3); with its largest cyclic factor of order L
+ * and the product H of the others, the rows and columns of an orbit split
+ * into |H| x |H| blocks, each a circulant of length L handled like a prime
+ * rule (its own spectrum and collapse), the blocks of one row coset adding
+ * up.  Orbits with L >= 64 and |H| <= 8 take blocks (at most 1024 over all
+ * orbits); the others and row 0 are summed directly (phi(N/d) s t
+ * multiply-adds for an orbit: fast for 2^k, prime powers and products of
+ * few primes, slow for highly composite N with large s t).  Non-prime N above
+ * 2^25 return QMC_ERR_UNSUPPORTED.  Such a plan has no single cyclic
+ * group: qmc_plan_set_row_order(QMC_ROWS_GROUP), the power/logarithm/exponent
+ * tables of qmc_plan_tables and batches return QMC_ERR_UNSUPPORTED.
  * The plan owns its device memory; release it with qmc_plan_destroy.
  */
 int qmc_plan_create(qmc_plan_t* out, int rule, int64_t N, int64_t s,
@@ -121,7 +140,7 @@ void qmc_plan_destroy(qmc_plan_t plan);
  * radices is reported.
  */
 typedef struct {
-    int64_t N, s, L;        /* points, dimension, group order L = N - 1 */
+    int64_t N, s, L;        /* points, dimension, order L of the unit group (N - 1 for prime N) */
     int64_t M;              /* circular-convolution length used: L, or a power of two >= 2L-1 */
     int64_t M1, M2;         /* M = M1 * M2 (on-chip transform length, outer length) */
     int64_t rounds;         /* rounds of the sparse collapse schedule */
@@ -129,6 +148,9 @@ typedef struct {
     int rule, phi_kind, dtype, embedded;
     double phi0;            /* phi of the point of row 0 (the constant first row, Section 2.1) */
     int P2, Q2;             /* outer split M2 = P2 x Q2 of the current tuning */
+    int64_t blocks;         /* non-prime N: circulant blocks (M, M1, M2, P2, Q2, rounds
+                               describe the longest); 0 for prime N and GF(2) */
+    int64_t direct_rows;    /* non-prime N: rows summed directly (row 0, small orbits) */
 } qmc_plan_info_t;
 int qmc_plan_info(qmc_plan_t plan, qmc_plan_info_t* info);
 

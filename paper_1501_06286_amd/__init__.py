@@ -66,7 +66,7 @@ class PlanInfo(ctypes.Structure):
                 ("rounds", ctypes.c_int64), ("beta", ctypes.c_uint64),
                 ("rule", ctypes.c_int), ("phi_kind", ctypes.c_int), ("dtype", ctypes.c_int),
                 ("embedded", ctypes.c_int), ("phi0", ctypes.c_double), ("P2", ctypes.c_int),
-                ("Q2", ctypes.c_int)]
+                ("Q2", ctypes.c_int), ("blocks", ctypes.c_int64), ("direct_rows", ctypes.c_int64)]
 
 
 class KorobovInfo(ctypes.Structure):

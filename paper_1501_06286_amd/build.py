@@ -9,6 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["tables.hip", "conv.hip", "batch.hip", "korobov.hip", "dense.hip", "api.hip",
+           "composite.hip",
            "noalloc.hip"]
 LIB = os.path.join(HERE, "libqmcfast.so")
 ARCH = "gfx950"

@@ -57,6 +57,7 @@ int plan_create(qmc_plan_s** out, int rule, int64_t N, int64_t s, const uint64_t
   P->rule = rule;
   P->N = N;
   P->s = s;
+  P->s_active = s;
   P->L = N - 1;
   P->m = m;
   P->modulus = modulus;
@@ -81,9 +82,9 @@ const char* qmc_strerror(int code) {
   switch (code) {
     case QMC_OK: return "success";
     case QMC_ERR_ARG: return "invalid argument";
-    case QMC_ERR_NOT_PRIME: return "lattice rule needs a prime number of points";
+    case QMC_ERR_NOT_PRIME: return "this point set needs a prime number of points";
     case QMC_ERR_NOT_PRIMITIVE: return "GF(2) modulus is not a primitive polynomial of degree log2(N)";
-    case QMC_ERR_GEN_ZERO: return "generator component is zero modulo N";
+    case QMC_ERR_GEN_ZERO: return "generator component is not a unit modulo N";
     case QMC_ERR_ALIAS: return "output overlaps an input or the workspace";
     case QMC_ERR_WORKSPACE: return "workspace missing or too small";
     case QMC_ERR_OOM: return "device allocation failed";
@@ -112,6 +113,7 @@ static void prof_clear(qmc_plan_t P) {
 
 void qmc_plan_destroy(qmc_plan_t plan) {
   if (!plan) return;
+  destroy_composite(plan);
   prof_clear(plan);
   if (plan->side) {
     (void)hipStreamSynchronize(plan->side);
@@ -125,6 +127,8 @@ void qmc_plan_destroy(qmc_plan_t plan) {
 
 int qmc_profile_enable(qmc_plan_t P, int on) {
   if (!P) return QMC_ERR_ARG;
+  if (P->comp)  // the blocks of a non-prime N record their own launches
+    for (qmc_plan_s* B : composite_blocks(P)) qmc_profile_enable(B, on);
   if (!on) prof_clear(P);
   P->prof_on = on != 0;
   return QMC_OK;
@@ -132,6 +136,24 @@ int qmc_profile_enable(qmc_plan_t P, int on) {
 
 int qmc_profile_collect(qmc_plan_t P, double* total_ms, int64_t* launches) {
   if (!P || !total_ms || !launches) return QMC_ERR_ARG;
+  if (P->comp) {  // summed over the blocks
+    for (int k = 0; k < PROF_NSLOTS; ++k) {
+      total_ms[k] = 0.0;
+      launches[k] = 0;
+    }
+    int rc = QMC_OK;
+    double ms[PROF_NSLOTS];
+    int64_t n[PROF_NSLOTS];
+    for (qmc_plan_s* B : composite_blocks(P)) {
+      const int r = qmc_profile_collect(B, ms, n);
+      if (r != QMC_OK) rc = r;
+      for (int k = 0; k < PROF_NSLOTS; ++k) {
+        total_ms[k] += ms[k];
+        launches[k] += n[k];
+      }
+    }
+    return rc;
+  }
   int rc = QMC_OK;
   for (int k = 0; k < PROF_NSLOTS; ++k) {
     double sum = 0.0;
@@ -166,6 +188,19 @@ int qmc_plan_set_tuning(qmc_plan_t P, const qmc_tuning_t* tu) {
       (tu->nt_store != 0 && tu->nt_store != 1) || tu->front < 0 || tu->front > 2 ||
       tu->nt_inter < 0 || tu->nt_inter > 2)
     return QMC_ERR_ARG;
+  if (P->comp) {
+    // every block takes the tuning; an outer radix a block's length cannot
+    // split falls back to that block's default
+    for (qmc_plan_s* B : composite_blocks(P)) {
+      qmc_tuning_t tb = *tu;
+      Layout lb = B->lay;
+      if (set_outer_split(lb, tb.outer_q, max_outer_q(B->dtype)) != QMC_OK) tb.outer_q = 0;
+      const int rc = qmc_plan_set_tuning(B, &tb);
+      if (rc != QMC_OK) return rc;
+    }
+    P->tune = *tu;
+    return QMC_OK;
+  }
   Layout lay = P->lay;
   const int rc = set_outer_split(lay, tu->outer_q, max_outer_q(P->dtype));
   if (rc != QMC_OK) return rc;
@@ -176,6 +211,8 @@ int qmc_plan_set_tuning(qmc_plan_t P, const qmc_tuning_t* tu) {
 
 int qmc_plan_set_row_order(qmc_plan_t P, int order) {
   if (!P || (order != QMC_ROWS_CONVENTIONAL && order != QMC_ROWS_GROUP)) return QMC_ERR_ARG;
+  // non-prime N has no single cyclic group order
+  if (P->comp && order == QMC_ROWS_GROUP) return QMC_ERR_UNSUPPORTED;
   if (order == QMC_ROWS_GROUP && !P->d_grp) {
     std::vector<int32_t> rows(P->L);
     for (int64_t e = 0; e < P->L; ++e) rows[e] = (int32_t)(e + 1);
@@ -215,12 +252,16 @@ int qmc_plan_info(qmc_plan_t P, qmc_plan_info_t* info) {
   info->phi0 = P->phi0;
   info->P2 = P->lay.P2;
   info->Q2 = P->lay.Q2;
+  info->blocks = P->comp ? (int64_t)composite_blocks(P).size() : 0;
+  info->direct_rows = P->comp ? composite_direct_rows(P) : 0;
   return QMC_OK;
 }
 
 int qmc_plan_tables(qmc_plan_t P, int32_t* pow_out, int32_t* log_out, int32_t* ell_out,
                     double* phi_out) {
   if (!P) return QMC_ERR_ARG;
+  // non-prime N: no single cyclic group, only the value table
+  if (P->comp && (pow_out || log_out || ell_out)) return QMC_ERR_UNSUPPORTED;
   if (pow_out && hipMemcpy(pow_out, P->d_pow, P->L * 4, hipMemcpyDeviceToHost) != hipSuccess)
     return QMC_ERR_HIP;
   if (log_out && hipMemcpy(log_out, P->d_log, P->N * 4, hipMemcpyDeviceToHost) != hipSuccess)

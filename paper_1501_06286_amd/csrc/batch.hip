@@ -302,6 +302,7 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
   for (int i = 0; i < count; ++i) {
     const qmc_plan_s* P = plans[i];
     if (!P || P->dtype != dtype || t[i] < 1 || !A[i] || !X[i]) return QMC_ERR_ARG;
+    if (P->comp) return QMC_ERR_UNSUPPORTED;  // non-prime N: products of several blocks
     const int64_t la = lda ? lda[i] : t[i], lx = ldx ? ldx[i] : t[i];
     if (la < t[i] || lx < t[i]) return QMC_ERR_ARG;
   }

@@ -147,7 +147,7 @@ static int64_t fwd_c_pairs(const qmc_plan_s* P, int64_t pairs) {
 // two break even near s = 4 M1, so the switch is at s > 8 M1)
 bool dense_front(const qmc_plan_s* P) {
   if (P->tune.front != 0) return P->tune.front == 2;
-  return P->s > 8 * P->lay.M1;
+  return P->s_active > 8 * P->lay.M1;
 }
 
 // whether the fused pass writes the intermediate spectrum C with streaming
@@ -166,6 +166,7 @@ static int64_t adj_chunk(const qmc_plan_s* P, int64_t pairs) {
 }
 
 size_t workspace_bytes(const qmc_plan_s* P, int64_t t) {
+  if (P->comp) return composite_workspace_bytes(P, t);
   const size_t el = (P->dtype == QMC_F32) ? sizeof(cx<float>) : sizeof(cx<double>);
   const int64_t pairs = (t + 1) / 2;
   const size_t aT = align256(pairs * P->Upad * el);
@@ -324,7 +325,8 @@ static int forward_dense_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t l
     int rc = launch_outer_front<T>(P, A + 2 * p0, nullptr, lda, tc, np, B, st);
     if (rc != QMC_OK) return rc;
     const Epi<T> ec = chunk_epi(epi, p0);
-    rc = launch_middle<T, false>(P, B, np, C, X + 2 * p0, tc, PROF_MIDDLE, st);
+    // a block of a lattice rule with non-prime N does not hold row 0
+    rc = launch_middle<T, false>(P, B, np, C, P->sub ? nullptr : X + 2 * p0, tc, PROF_MIDDLE, st);
     if (rc != QMC_OK) return rc;
     rc = launch_split<T, +1>(P, C, np, PROF_SPLIT, st);
     if (rc != QMC_OK) return rc;
@@ -371,8 +373,8 @@ static int forward_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T*
       if ((rc = hip_ok(hipStreamWaitEvent(st, P->ev[2 + slot], 0))) != QMC_OK) return rc;
     }
     const Epi<T> ec = chunk_epi(epi, p0);
-    rc = launch_middle<T, true>(P, aT + p0 * P->Upad, np, C, X + 2 * p0, t - 2 * p0,
-                                PROF_MIDDLE, st);
+    rc = launch_middle<T, true>(P, aT + p0 * P->Upad, np, C, P->sub ? nullptr : X + 2 * p0,
+                                t - 2 * p0, PROF_MIDDLE, st);
     if (rc != QMC_OK) return rc;
     rc = launch_split<T, +1>(P, C, np, PROF_SPLIT, st);
     if (rc != QMC_OK) return rc;
@@ -397,7 +399,7 @@ template <typename T>
 static int forward_epi_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda, T* X,
                          int64_t ldx, void* ws, hipStream_t st, const Epi<T>& epi, bool single) {
   int rc = forward_t<T>(P, A, t, lda, X, ldx, ws, st, epi, single);
-  if (rc != QMC_OK || epi.kind == 0) return rc;
+  if (rc != QMC_OK || epi.kind == 0 || epi.kind == EPI_ACC) return rc;
   // row 0 is the fused pass's DC term, in X on the same stream by now
   k_epi_row0<T><<<(unsigned)((t + 255) / 256), 256, 0, st>>>(X, t, epi);
   return hip_ok(hipGetLastError());
@@ -406,6 +408,7 @@ static int forward_epi_t(const qmc_plan_s* P, const T* A, int64_t t, int64_t lda
 int launch_forward(const qmc_plan_s* P, const void* A, int64_t t, int64_t lda, void* X,
                    int64_t ldx, void* ws, hipStream_t st, int epi_kind, const void* bias,
                    const void* scale, bool single_stream) {
+  if (P->comp) return composite_forward(P, A, t, lda, X, ldx, ws, st, epi_kind, bias, scale);
   if (P->dtype == QMC_F32)
     return forward_epi_t<float>(P, (const float*)A, t, lda, (float*)X, ldx, ws, st,
                                 Epi<float>{epi_kind, (const float*)bias, (const float*)scale},
@@ -456,7 +459,8 @@ static int launch_outer_front(const qmc_plan_s* P, const T* A, const T* G, int64
 // 4096, run slower than one chunk).
 template <typename T>
 static int adjoint_t(const qmc_plan_s* P, const T* G, int64_t t, int64_t ldg, T* dA,
-                     int64_t ldda, void* ws, hipStream_t st) {
+                     int64_t ldda, void* ws, hipStream_t st, bool acc) {
+  const Epi<T> epi{acc ? EPI_ACC : 0, nullptr, nullptr};
   const int64_t pairs = (t + 1) / 2;
   const int64_t chunk = adj_chunk(P, pairs);
   cx<T>* B = (cx<T>*)ws;
@@ -470,17 +474,18 @@ static int adjoint_t(const qmc_plan_s* P, const T* G, int64_t t, int64_t ldg, T*
     rc = launch_split<T, +1>(P, C, np, PROF_SPLIT, st);
     if (rc != QMC_OK) return rc;
     rc = launch_back<T, true>(P, C, np, P->d_inv_ptr, P->d_inv_j, G + 2 * p0, dA + 2 * p0, ldda,
-                              tc, st);
+                              tc, st, epi);
     if (rc != QMC_OK) return rc;
   }
   return QMC_OK;
 }
 
 int launch_adjoint(const qmc_plan_s* P, const void* G, int64_t t, int64_t ldg, void* dA,
-                   int64_t ldda, void* ws, hipStream_t st) {
+                   int64_t ldda, void* ws, hipStream_t st, bool acc) {
+  if (P->comp) return composite_adjoint(P, G, t, ldg, dA, ldda, ws, st);
   if (P->dtype == QMC_F32)
-    return adjoint_t<float>(P, (const float*)G, t, ldg, (float*)dA, ldda, ws, st);
-  return adjoint_t<double>(P, (const double*)G, t, ldg, (double*)dA, ldda, ws, st);
+    return adjoint_t<float>(P, (const float*)G, t, ldg, (float*)dA, ldda, ws, st, acc);
+  return adjoint_t<double>(P, (const double*)G, t, ldg, (double*)dA, ldda, ws, st, acc);
 }
 
 }  // namespace qmc

@@ -35,9 +35,18 @@ struct ProfEvents {
 
 }  // namespace qmc
 
+namespace qmc {
+struct CompositePlan;
+}
+
 struct qmc_plan_s {
   int rule = 0;
   int64_t N = 0, s = 0, L = 0;
+  int64_t s_active = 0;      // rows of A the plan reads (s, or a block's share of them)
+  // a lattice rule with non-prime N: its blocks (each one of the plans
+  // below, flagged sub) and the rows summed directly
+  qmc::CompositePlan* comp = nullptr;
+  bool sub = false;          // a block of such a rule: no row 0, group order of L != N - 1
   int m = 0;                 // GF(2): degree
   uint64_t modulus = 0;
   uint64_t beta = 0;
@@ -101,6 +110,30 @@ namespace qmc {
 
 // tables.hip
 int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st);
+// schedule, inverse exponent map and spectral tables of a plan whose layout
+// is set: ell (host, P->s entries, -1 for rows of A outside the product),
+// generator z_k = tphi[zidx[k]] for k < L (device tables)
+int build_conv_tables(qmc_plan_s* P, const int32_t* ell, const int32_t* d_zidx,
+                      const double* d_tphi, hipStream_t st);
+Layout choose_layout(int64_t L, int dtype, int* embedded);
+int launch_phi_table(qmc_plan_s* P, hipStream_t st);
+bool is_prime_u64(uint64_t n);
+std::vector<uint64_t> prime_factors(uint64_t n);
+uint64_t powmod(uint64_t b, uint64_t e, uint64_t n);
+uint64_t smallest_primitive_root(uint64_t N);
+
+// composite.hip: lattice rules with non-prime N
+int build_composite(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st);
+void destroy_composite(qmc_plan_s* P);
+size_t composite_workspace_bytes(const qmc_plan_s* P, int64_t t);
+int composite_forward(const qmc_plan_s* P, const void* A, int64_t t, int64_t lda, void* X,
+                      int64_t ldx, void* ws, hipStream_t st, int epi_kind, const void* bias,
+                      const void* scale);
+int composite_adjoint(const qmc_plan_s* P, const void* G, int64_t t, int64_t ldg, void* dA,
+                      int64_t ldda, void* ws, hipStream_t st);
+// the blocks of a composite plan (for tuning, timing and plan facts)
+const std::vector<qmc_plan_s*>& composite_blocks(const qmc_plan_s* P);
+int64_t composite_direct_rows(const qmc_plan_s* P);
 // split the outer length M2 = P2 Q2 with at most q values per back-pass
 // thread (q = 0: the default); QMC_ERR_ARG if q or the split is invalid
 int set_outer_split(Layout& lay, int q, int qmax);
@@ -138,8 +171,9 @@ int launch_forward(const qmc_plan_s* P, const void* A, int64_t t, int64_t lda, v
                    int64_t ldx, void* ws, hipStream_t st, int epi_kind = 0,
                    const void* bias = nullptr, const void* scale = nullptr,
                    bool single_stream = false);
+// acc: dA += Y^T G (the blocks of a lattice rule with non-prime N add up)
 int launch_adjoint(const qmc_plan_s* P, const void* G, int64_t t, int64_t ldg, void* dA,
-                   int64_t ldda, void* ws, hipStream_t st);
+                   int64_t ldda, void* ws, hipStream_t st, bool acc = false);
 
 // dense.hip
 int launch_explicit_points(const qmc_plan_s* P, void* Y, int64_t ldy, hipStream_t st);

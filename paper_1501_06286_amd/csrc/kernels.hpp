@@ -148,6 +148,10 @@ struct Epi {
   const T* bias = nullptr;
   const T* scale = nullptr;
 };
+// internal epilogue kind: the value is added to what the output entry holds
+// (the blocks of a lattice rule with non-prime N that share output rows, or
+// output rows of dA, add up); bias and scale unused
+constexpr int EPI_ACC = 3;
 // FP32: the hardware base-2 exponential (relative error a few ulp times
 // |v|, far inside the FP32 product's tolerance); FP64: the full-precision one
 __device__ __forceinline__ float exp_t(float v) { return __expf(v); }
@@ -502,7 +506,14 @@ __device__ __forceinline__ void put_row(cx<T> o, int64_t r, int64_t pairw, T* __
   const int64_t col = 2 * pairw;
   const bool both = col + 1 < t;
   T* row = X + r * ldx;
-  const T ox = EPI ? ec.f0(o.x) : o.x, oy = EPI ? ec.f1(o.y) : o.y;
+  T ox, oy;
+  if (EPI && ec.kind == EPI_ACC) {
+    ox = row[col] + o.x;
+    oy = both ? row[col + 1] + o.y : (T)0;
+  } else {
+    ox = EPI ? ec.f0(o.x) : o.x;
+    oy = EPI ? ec.f1(o.y) : o.y;
+  }
   if (v2 && both) {
     store_pair<T, NT>(row + col, ox, oy);
   } else if constexpr (NT) {
@@ -516,20 +527,26 @@ __device__ __forceinline__ void put_row(cx<T> o, int64_t r, int64_t pairw, T* __
 
 // the adjoint's writes for one output e whose rows j (l_j = e) are
 // inv_j[lo .. hi): dA[j] = o + phi(x_0) G[0] (g0, g1: the second term, for
-// columns col and col + 1).  lo, hi and g0, g1 are loaded by the caller
-// together with its other loads, ahead of the transform.
+// columns col and col + 1), or dA[j] += o + ... with acc.  lo, hi and g0, g1
+// are loaded by the caller together with its other loads, ahead of the
+// transform.
 template <typename T>
 __device__ __forceinline__ void put_adj(cx<T> o, int32_t lo, int32_t hi, int64_t col, T g0, T g1,
                                         const int32_t* __restrict__ inv_j, T* __restrict__ X,
-                                        int64_t ldx, int64_t t, bool v2) {
+                                        int64_t ldx, int64_t t, bool v2, bool acc = false) {
   const bool both = col + 1 < t;
   for (int32_t jj = lo; jj < hi; ++jj) {
     T* row = X + (int64_t)inv_j[jj] * ldx;
+    T b0 = (T)0, b1 = (T)0;
+    if (acc) {
+      b0 = row[col];
+      if (both) b1 = row[col + 1];
+    }
     if (v2 && both) {
-      store_pair<T, false>(row + col, o.x + g0, o.y + g1);
+      store_pair<T, false>(row + col, b0 + o.x + g0, b1 + o.y + g1);
     } else {
-      row[col] = o.x + g0;
-      if (both) row[col + 1] = o.y + g1;
+      row[col] = b0 + o.x + g0;
+      if (both) row[col + 1] = b1 + o.y + g1;
     }
   }
 }
@@ -628,7 +645,8 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
           const int64_t e = e1w + M1 * e2;
           if constexpr (ADJ) {
             const int2 r = PRE ? rng[PRE ? c0 + c : 0] : AdjRows<T>::range(inv_ptr, e, e < L);
-            put_adj<T>(sm[c][ew][pw], r.x, r.y, 2 * pairw, ar.g0, ar.g1, inv_j, X, ldx, t, v2);
+            put_adj<T>(sm[c][ew][pw], r.x, r.y, 2 * pairw, ar.g0, ar.g1, inv_j, X, ldx, t, v2,
+                       epi.kind == EPI_ACC);
           } else if (e < L)
             put_row<T, NT, EPI>(sm[c][ew][pw], (int64_t)rowmap[e], pairw, X, ldx, t, v2, ec);
         }
@@ -813,7 +831,8 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
     if constexpr (!ADJ) {
       if (rows[j] >= 0) put_row<T, NT, EPI>(o, rows[j], pairw, X, ldx, t, v2, ec);
     } else {
-      put_adj<T>(o, rng[j].x, rng[j].y, 2 * pairw, ar.g0, ar.g1, inv_j, X, ldx, t, v2);
+      put_adj<T>(o, rng[j].x, rng[j].y, 2 * pairw, ar.g0, ar.g1, inv_j, X, ldx, t, v2,
+                 epi.kind == EPI_ACC);
     }
   }
 }

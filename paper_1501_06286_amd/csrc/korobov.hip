@@ -408,6 +408,8 @@ int qmc_korobov_create(qmc_korobov_t* out, int64_t K, int64_t s, int phi_kind,
   if (!out || K < 3 || s < 1 || K >= ((int64_t)1 << 31) || s > ((int64_t)1 << 30))
     return QMC_ERR_ARG;
   *out = nullptr;
+  // Section 2.2: the union is built on the cyclic group Z_K^*, K prime
+  if (!is_prime_u64((uint64_t)K)) return QMC_ERR_NOT_PRIME;
   std::vector<uint64_t> ones(s, 1);  // the base plan's own generating vector (block b = 1)
   qmc_plan_s* base = nullptr;
   int rc = plan_create(&base, QMC_RULE_LATTICE, K, s, ones.data(), 0, phi_kind, shift_num,

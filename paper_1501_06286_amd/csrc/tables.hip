@@ -19,7 +19,7 @@ namespace qmc {
 // ---------------------------------------------------------------------------
 // host number theory
 // ---------------------------------------------------------------------------
-static bool is_prime_u64(uint64_t n) {
+bool is_prime_u64(uint64_t n) {
   if (n < 2) return false;
   if (n % 2 == 0) return n == 2;
   for (uint64_t f = 3; f * f <= n; f += 2)
@@ -27,7 +27,7 @@ static bool is_prime_u64(uint64_t n) {
   return true;
 }
 
-static std::vector<uint64_t> prime_factors(uint64_t n) {
+std::vector<uint64_t> prime_factors(uint64_t n) {
   std::vector<uint64_t> out;
   for (uint64_t f = 2; f * f <= n; ++f) {
     if (n % f == 0) {
@@ -39,7 +39,7 @@ static std::vector<uint64_t> prime_factors(uint64_t n) {
   return out;
 }
 
-static uint64_t powmod(uint64_t b, uint64_t e, uint64_t n) {
+uint64_t powmod(uint64_t b, uint64_t e, uint64_t n) {
   uint64_t r = 1 % n;
   b %= n;
   while (e) {
@@ -51,7 +51,7 @@ static uint64_t powmod(uint64_t b, uint64_t e, uint64_t n) {
 }
 
 // smallest primitive root of prime N: beta^(L/q) != 1 for every prime q | L
-static uint64_t smallest_primitive_root(uint64_t N) {
+uint64_t smallest_primitive_root(uint64_t N) {
   if (N == 2) return 1;
   const uint64_t L = N - 1;
   std::vector<uint64_t> qs = prime_factors(L);
@@ -381,7 +381,7 @@ static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b -
 // ---------------------------------------------------------------------------
 // layout choice
 // ---------------------------------------------------------------------------
-static Layout choose_layout(int64_t L, int dtype, int* embedded) {
+Layout choose_layout(int64_t L, int dtype, int* embedded) {
   Layout lay;
   int64_t M = 1;
   if ((L & (L - 1)) == 0) {
@@ -444,9 +444,13 @@ Schedule make_schedule(const Layout& lay, int64_t L, int64_t s, const int32_t* e
   const int G = Q < 64 ? Q : 64;
   const int F = Q / G;
   const int PP = pair_pp(R);
-  // distinct slots, each with its rows in increasing j
-  std::vector<std::pair<int64_t, int32_t>> sj(s);
-  for (int64_t j = 0; j < s; ++j) sj[j] = {(L - ell[j]) % L, (int32_t)j};
+  // distinct slots, each with its rows in increasing j (rows with ell < 0 are
+  // not part of the product: a block of a rule with non-prime N)
+  std::vector<std::pair<int64_t, int32_t>> sj;
+  sj.reserve(s);
+  for (int64_t j = 0; j < s; ++j)
+    if (ell[j] >= 0) sj.push_back({(L - ell[j]) % L, (int32_t)j});
+  s = (int64_t)sj.size();
   std::sort(sj.begin(), sj.end());
   std::vector<int64_t> uslot, ufirst;  // slot and first index into sj of each distinct slot
   for (int64_t k = 0; k < s; ++k)
@@ -557,6 +561,101 @@ static int build_spectral_tables(qmc_plan_s* P, const cx<double>* dW, const cx<d
   return QMC_OK;
 }
 
+// The collapse schedule, the inverse map of the exponents and the spectral
+// tables of a plan whose layout is set: ell (host, P->s entries; -1 for rows
+// of A outside the product) and the generator z_k = tphi[zidx[k]], k < L
+// (device tables), embedded in the convolution length M as k_generator
+// describes.
+int build_conv_tables(qmc_plan_s* P, const int32_t* ell, const int32_t* d_zidx,
+                      const double* d_tphi, hipStream_t st) {
+  int err = QMC_OK;
+  const int64_t L = P->L, s = P->s;
+  const Layout& lay = P->lay;
+  std::vector<void*> temps;
+  auto free_temps = [&]() {
+    for (void* p : temps) hipFree(p);
+  };
+  int rc = QMC_OK;
+  do {
+    Schedule sc = make_schedule(lay, L, s, ell);
+    const int64_t sa = (int64_t)sc.it_jl.size();  // rows in the product
+    P->s_active = sa;
+    // the residues go to the device as 16-bit values (e1 <= M1 <= 4096)
+    const std::vector<uint16_t> e16(sc.it_e1.begin(), sc.it_e1.end());
+    P->rounds = sc.rounds;
+    P->Upad = sc.Upad;
+    P->d_it_ptr = dev_alloc<int32_t>(P, P->Upad + 1, &err);
+    P->d_it_jl = dev_alloc<int32_t>(P, sa, &err);
+    P->d_it_e1 = dev_alloc<uint16_t>(P, P->Upad, &err);
+    P->d_inv_ptr = dev_alloc<int32_t>(P, L + 1, &err);
+    P->d_inv_j = dev_alloc<int32_t>(P, sa, &err);
+    if ((rc = err) != QMC_OK) break;
+    int32_t* d_slot = nullptr;
+    if ((rc = hip_ok(hipMalloc(&d_slot, P->Upad * sizeof(int32_t)))) != QMC_OK) break;
+    temps.push_back(d_slot);
+    // inverse of j -> l_j (counting sort, j increasing within each e)
+    std::vector<int32_t> inv_ptr(L + 1, 0), inv_j(std::max<int64_t>(sa, 1));
+    for (int64_t j = 0; j < s; ++j)
+      if (ell[j] >= 0) inv_ptr[ell[j] + 1]++;
+    for (int64_t e = 0; e < L; ++e) inv_ptr[e + 1] += inv_ptr[e];
+    {
+      std::vector<int32_t> pos(inv_ptr.begin(), inv_ptr.end() - 1);
+      for (int64_t j = 0; j < s; ++j)
+        if (ell[j] >= 0) inv_j[pos[ell[j]]++] = (int32_t)j;
+    }
+    rc = hip_ok(hipMemcpyAsync(P->d_it_ptr, sc.it_ptr.data(), (P->Upad + 1) * 4,
+                               hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK && sa > 0)
+      rc = hip_ok(hipMemcpyAsync(P->d_it_jl, sc.it_jl.data(), sa * 4, hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(P->d_it_e1, e16.data(), P->Upad * sizeof(uint16_t),
+                                 hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(d_slot, sc.it_slot.data(), P->Upad * 4, hipMemcpyHostToDevice,
+                                 st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(P->d_inv_ptr, inv_ptr.data(), (L + 1) * 4, hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK && sa > 0)
+      rc = hip_ok(hipMemcpyAsync(P->d_inv_j, inv_j.data(), sa * 4, hipMemcpyHostToDevice, st));
+    // host vectors must outlive the asynchronous copies
+    if (rc == QMC_OK) rc = hip_ok(hipStreamSynchronize(st));
+    if (rc != QMC_OK) break;
+
+    // ---- generator spectrum in FP64 -------------------------------------
+    const int64_t M = lay.M;
+    cx<double>*dW = nullptr, *dA = nullptr, *dB = nullptr;
+    if ((rc = hip_ok(hipMalloc(&dW, M * sizeof(cx<double>)))) != QMC_OK) break;
+    temps.push_back(dW);
+    if ((rc = hip_ok(hipMalloc(&dA, M * sizeof(cx<double>)))) != QMC_OK) break;
+    temps.push_back(dA);
+    if ((rc = hip_ok(hipMalloc(&dB, M * sizeof(cx<double>)))) != QMC_OK) break;
+    temps.push_back(dB);
+    k_twiddle<<<nblk(M), 256, 0, st>>>(dW, M);
+    k_generator<<<nblk(M), 256, 0, st>>>(dA, d_zidx, d_tphi, L, M);
+    cx<double>*src = dA, *dst = dB;
+    for (int64_t Ns = 1; Ns < M; Ns *= 2) {
+      k_fft_r2_pass<<<nblk(M / 2), 256, 0, st>>>(src, dst, M, Ns, dW);
+      std::swap(src, dst);
+    }
+    if ((rc = hip_ok(hipGetLastError())) != QMC_OK) break;
+    if (P->dtype == QMC_F32)
+      rc = build_spectral_tables<float>(P, dW, src, d_slot, st);
+    else
+      rc = build_spectral_tables<double>(P, dW, src, d_slot, st);
+    if (rc != QMC_OK) break;
+    rc = hip_ok(hipStreamSynchronize(st));
+  } while (0);
+  free_temps();
+  return rc;
+}
+
+// phi of every residue's coordinate into P->d_tphi (N entries)
+int launch_phi_table(qmc_plan_s* P, hipStream_t st) {
+  k_phi_table<<<nblk(P->N), 256, 0, st>>>(P->d_tphi, P->rule, P->N, P->m, P->modulus,
+                                           P->phi_kind, P->shift_num, P->shift_den);
+  return hip_ok(hipGetLastError());
+}
+
 int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st) {
   int err = QMC_OK;
   const int64_t N = P->N, L = P->L, s = P->s;
@@ -564,7 +663,8 @@ int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st) {
   // ---- host validation and number theory --------------------------------
   std::vector<uint32_t> gen(s);
   if (P->rule == QMC_RULE_LATTICE) {
-    if (!is_prime_u64((uint64_t)N)) return QMC_ERR_NOT_PRIME;
+    // non-prime N: the orbits of the rows and the blocks of each
+    if (!is_prime_u64((uint64_t)N)) return build_composite(P, gen_host, st);
     for (int64_t j = 0; j < s; ++j) {
       const uint64_t g = gen_host[j] % (uint64_t)N;
       if (g == 0) return QMC_ERR_GEN_ZERO;
@@ -625,70 +725,7 @@ int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st) {
       if (ell[j] < 0 || ell[j] >= L) { rc = QMC_ERR_HIP; break; }
     if (rc != QMC_OK) break;
 
-    // ---- collapse schedule ----------------------------------------------
-    Schedule sc = make_schedule(lay, L, s, ell.data());
-    // the residues go to the device as 16-bit values (e1 <= M1 <= 4096)
-    const std::vector<uint16_t> e16(sc.it_e1.begin(), sc.it_e1.end());
-    P->rounds = sc.rounds;
-    P->Upad = sc.Upad;
-    P->d_it_ptr = dev_alloc<int32_t>(P, P->Upad + 1, &err);
-    P->d_it_jl = dev_alloc<int32_t>(P, s, &err);
-    P->d_it_e1 = dev_alloc<uint16_t>(P, P->Upad, &err);
-    P->d_inv_ptr = dev_alloc<int32_t>(P, L + 1, &err);
-    P->d_inv_j = dev_alloc<int32_t>(P, s, &err);
-    if ((rc = err) != QMC_OK) break;
-    int32_t* d_slot = nullptr;
-    if ((rc = hip_ok(hipMalloc(&d_slot, P->Upad * sizeof(int32_t)))) != QMC_OK) break;
-    temps.push_back(d_slot);
-    // inverse of j -> l_j (counting sort, j increasing within each e)
-    std::vector<int32_t> inv_ptr(L + 1, 0), inv_j(s);
-    for (int64_t j = 0; j < s; ++j) inv_ptr[ell[j] + 1]++;
-    for (int64_t e = 0; e < L; ++e) inv_ptr[e + 1] += inv_ptr[e];
-    {
-      std::vector<int32_t> pos(inv_ptr.begin(), inv_ptr.end() - 1);
-      for (int64_t j = 0; j < s; ++j) inv_j[pos[ell[j]]++] = (int32_t)j;
-    }
-    rc = hip_ok(hipMemcpyAsync(P->d_it_ptr, sc.it_ptr.data(), (P->Upad + 1) * 4,
-                               hipMemcpyHostToDevice, st));
-    if (rc == QMC_OK)
-      rc = hip_ok(hipMemcpyAsync(P->d_it_jl, sc.it_jl.data(), s * 4, hipMemcpyHostToDevice, st));
-    if (rc == QMC_OK)
-      rc = hip_ok(hipMemcpyAsync(P->d_it_e1, e16.data(), P->Upad * sizeof(uint16_t),
-                                 hipMemcpyHostToDevice, st));
-    if (rc == QMC_OK)
-      rc = hip_ok(hipMemcpyAsync(d_slot, sc.it_slot.data(), P->Upad * 4, hipMemcpyHostToDevice,
-                                 st));
-    if (rc == QMC_OK)
-      rc = hip_ok(hipMemcpyAsync(P->d_inv_ptr, inv_ptr.data(), (L + 1) * 4, hipMemcpyHostToDevice, st));
-    if (rc == QMC_OK)
-      rc = hip_ok(hipMemcpyAsync(P->d_inv_j, inv_j.data(), s * 4, hipMemcpyHostToDevice, st));
-    // host vectors must outlive the asynchronous copies
-    if (rc == QMC_OK) rc = hip_ok(hipStreamSynchronize(st));
-    if (rc != QMC_OK) break;
-
-    // ---- generator spectrum in FP64 -------------------------------------
-    const int64_t M = lay.M;
-    cx<double>*dW = nullptr, *dA = nullptr, *dB = nullptr;
-    if ((rc = hip_ok(hipMalloc(&dW, M * sizeof(cx<double>)))) != QMC_OK) break;
-    temps.push_back(dW);
-    if ((rc = hip_ok(hipMalloc(&dA, M * sizeof(cx<double>)))) != QMC_OK) break;
-    temps.push_back(dA);
-    if ((rc = hip_ok(hipMalloc(&dB, M * sizeof(cx<double>)))) != QMC_OK) break;
-    temps.push_back(dB);
-    k_twiddle<<<nblk(M), 256, 0, st>>>(dW, M);
-    k_generator<<<nblk(M), 256, 0, st>>>(dA, P->d_pow, P->d_tphi, L, M);
-    cx<double>*src = dA, *dst = dB;
-    for (int64_t Ns = 1; Ns < M; Ns *= 2) {
-      k_fft_r2_pass<<<nblk(M / 2), 256, 0, st>>>(src, dst, M, Ns, dW);
-      std::swap(src, dst);
-    }
-    if ((rc = hip_ok(hipGetLastError())) != QMC_OK) break;
-    if (P->dtype == QMC_F32)
-      rc = build_spectral_tables<float>(P, dW, src, d_slot, st);
-    else
-      rc = build_spectral_tables<double>(P, dW, src, d_slot, st);
-    if (rc != QMC_OK) break;
-    rc = hip_ok(hipStreamSynchronize(st));
+    rc = build_conv_tables(P, ell.data(), P->d_pow, P->d_tphi, st);
   } while (0);
   free_temps();
   return rc;

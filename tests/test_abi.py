@@ -47,6 +47,7 @@ def test_strerror_strings():
     L = q.lib()
     for code in range(0, -10, -1):
         assert L.qmc_strerror(code)
+    assert b"unit" in L.qmc_strerror(-4)
     assert b"prime" in L.qmc_strerror(-2)
 
 
@@ -60,7 +61,9 @@ def _create(rule=0, N=7, gen=(1, 5, 3), modulus=0, phi=0, snum=0, sden=1, dtype=
 
 
 @pytest.mark.parametrize("kw,code", [
-    (dict(N=9), -2),                 # not prime
+    (dict(N=9), -4),                 # non-prime N: 3 is not a unit mod 9
+    (dict(N=12, gen=(1, 5, 6)), -4), # 6 shares the factor 2 with 12
+    (dict(N=1 << 26, gen=(1, 3)), -9),  # non-prime N above 2^25: refused before device work
     (dict(N=1), -1),                 # too small
     (dict(gen=(1, 7, 3)), -4),       # g = 0 mod 7
     (dict(dtype=5), -1),

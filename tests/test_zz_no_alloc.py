@@ -74,6 +74,13 @@ def test_noalloc_gf2_f32():
     _pair_of_calls(inst, "f32", 4, {})
 
 
+def test_noalloc_non_prime_n():
+    # N = 2^14: blocks of the orbits 2^k and the rows summed directly
+    inst = qi.unit_lattice(1 << 14, 96, 12, phi=qi.PHI_INVNORM, shift=(1, 2 << 14),
+                           dtype="f32", seed=7)
+    _pair_of_calls(inst, "f32", 5, {})
+
+
 def test_noalloc_rejects_what_does_not_fit():
     torch = torch_cuda()
     import paper_1501_06286_amd as q
