@@ -64,7 +64,8 @@ HBM_PEAK_GBPS = 8000.0
 VALU_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
 VALU_NONPACKED_TFLOPS = {"f32": 78.6, "f64": 78.6}
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "f64": 78.6}
-LEGS = ("c2", "c2_other", "adjoint", "batched", "pde", "korobov", "c5", "dense", "cpu")
+LEGS = ("c2", "c2_other", "adjoint", "batched", "pde", "korobov", "c5", "nonprime", "dense",
+        "cpu")
 
 
 def log(msg):
@@ -273,7 +274,7 @@ def main():
                     help="time only the dense MFMA GEMM baseline (for profiler runs)")
     ap.add_argument("--vendor-context", action="store_true",
                     help="with --dense-only: also time torch.matmul of the same shape")
-    ap.add_argument("--only", default=None, choices=["c2", "c3", "c4", "c5", "korobov"],
+    ap.add_argument("--only", default=None, choices=["c2", "c3", "c4", "c5", "korobov", "nonprime"],
                     help="time only this workload's product (for profiler runs): c2 at --dtype, "
                          "the others FP32; with --tuning for single plans, --adjoint for the "
                          "transpose product, --batch-run-mib for the batch")
@@ -644,6 +645,35 @@ def main():
         del p5, A5, X5, ws5, G5, dA5
         torch.cuda.empty_cache()
 
+    if "nonprime" in legs:
+        # the Gaussian-sampling shapes on N = 2^16 points (not prime): orbits of
+        # the rows, unit-group blocks and rows summed directly
+        cn = qi.make_c2_nonprime(hd)
+        nleg, pn, An, Xn, wsn = forward_leg("nonprime", cn, args, torch, q, dev, nrows=48)
+        ninfo = pn.info()
+        nleg.out["blocks"] = ninfo["blocks"]
+        nleg.out["direct_rows"] = ninfo["direct_rows"]
+        Gn = torch.randn((cn.N, cn.t), dtype=An.dtype, device=dev,
+                         generator=torch.Generator(dev).manual_seed(11))
+        dAn = torch.empty((cn.s, cn.t), dtype=An.dtype, device=dev)
+        stn = lambda: q.matmul_adjoint(pn, Gn, out=dAn, workspace=wsn)
+        stn()
+        nn = max(3, args.steps // 2)
+        en = time_steps(stn, nn, torch)
+        nleg.out["adjoint"] = {"ms_per_step": round(1e3 * en / nn, 4),
+                               "value": cn.N * cn.t / (en / nn), "unit": "entries/s (N*t per s)"}
+        ent = qi.fd_entries(cn.s, cn.t)
+        ks = sorted({k for _, k in ent})
+        nleg.checks.append(("adjoint", cn, ent, ks, Gn[:, ks].double().cpu().numpy(),
+                            np.array([float(dAn[j, k]) for j, k in ent])))
+        log(f"non-prime N={cn.N}: {nleg.out['ms_per_step']:.3f} ms forward, "
+            f"{1e3 * en / nn:.3f} ms adjoint ({ninfo['blocks']} blocks, "
+            f"{ninfo['direct_rows']} direct rows)")
+        all_legs.append(nleg)
+        result["nonprime"] = nleg.out
+        del pn, An, Xn, wsn, Gn, dAn
+        torch.cuda.empty_cache()
+
     if "cpu" in legs:
         result["cpu_baseline"] = cpu_baseline_and_errors(main_leg.checks[0][1], all_legs)
         log(f"cpu baseline {result['cpu_baseline']['value']:.3e} entries/s; worst errors "
@@ -671,9 +701,10 @@ def only_run(args, torch, q, qi, dev):
         g = torch.Generator(dev).manual_seed(7)
         return torch.randn(shape, dtype=torch.float32, device=dev, generator=g)
 
-    if w in ("c2", "c3", "c5"):
+    if w in ("c2", "c3", "c5", "nonprime"):
         inst = {"c2": lambda: qi.make_c2(args.dtype), "c3": lambda: qi.make_c3("f32"),
-                "c5": lambda: qi.make_c5("f32", with_G=False)}[w]()
+                "c5": lambda: qi.make_c5("f32", with_G=False),
+                "nonprime": lambda: qi.make_c2_nonprime(args.dtype)}[w]()
         tdt = torch.float32 if inst.dtype == "f32" else torch.float64
         plan = q.Plan.from_instance(inst)
         if args.tuning:

@@ -210,6 +210,18 @@ def make_c2(dtype: str = "f32", s: int = 4096, t: Optional[int] = None,
                     PHI_INVNORM, (1, 2 * N), dtype, _round_to(A, dtype))
 
 
+def make_c2_nonprime(dtype: str = "f32", s: int = 4096, t: Optional[int] = None,
+                     N: int = 65536) -> Instance:
+    """The Gaussian-sampling shapes on a lattice rule whose number of points
+    is not prime (N = 2^16 by default): unit generator components, the same
+    A and phi as make_c2."""
+    t = s if t is None else t
+    g = unit_gen(N, s, rng(6, 0))
+    A = cholesky_exp_upper(s)[:, :t]
+    return Instance(f"c2n_gauss_n{N}_s{s}_t{t}", RULE_LATTICE, N, s, t, g, 0,
+                    PHI_INVNORM, (1, 2 * N), dtype, _round_to(A, dtype))
+
+
 def make_c3(dtype: str = "f32", m: int = 16, s: int = 16384, t: int = 4096) -> Instance:
     p = draw_primitive_poly(m, rng(3, 4))
     N = 1 << m
