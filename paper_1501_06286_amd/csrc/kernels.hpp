@@ -26,9 +26,11 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
   return (xcd < rem) ? xcd * (q + 1) + idx : rem * (q + 1) + (xcd - rem) * q + idx;
 }
 
-// two adjacent values of T as one vector access
+// two (four) adjacent values of T as one vector access
 template <typename T>
 using vec2_t = T __attribute__((ext_vector_type(2)));
+template <typename T>
+using vec4_t = T __attribute__((ext_vector_type(4)));
 
 // whether element pairs (2k, 2k+1) of every row of a row-major matrix are
 // aligned for one vector access
@@ -589,10 +591,14 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
                                           const Epi<T> epi = Epi<T>()) {
   constexpr int PB = 16, EB = 16;
   constexpr int CH = Q < BACK_CH ? Q : BACK_CH;
+  // FP32 forward writes without epilogue: two pairs per 16-byte store when
+  // rows are 16-byte aligned (else per pair, as the other variants)
+  constexpr bool WIDE = !ADJ && !EPI && sizeof(T) == 4 && CH == BACK_CH;
   auto& sm = S.sm;
   const int64_t e1_0 = bx * EB, p0 = by * PB;
   const int el = tid % EB, pl = tid / EB;
   const bool v2 = pairs_aligned(X, ldx);
+  const bool wide = WIDE && ldx % 4 == 0 && reinterpret_cast<uintptr_t>(X) % 16 == 0;
   // the epilogue of the columns this thread writes (EPI only)
   const EpiCols<T> ec(EPI ? epi : Epi<T>(), 2 * (p0 + tid % PB), t);
   const int pw = tid % PB, ew = tid / PB;
@@ -638,7 +644,34 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
 #pragma unroll
       for (int c = 0; c < CH; ++c) sm[c][el][pl] = v[c0 + c];
       __syncthreads();
-      if (pairw < P && e1w < M1) {
+      if constexpr (WIDE) {
+        // thread (two pairs pw0, pw0 + 1; e1; every other c): one 16-byte
+        // store of both pairs per output row, half the store instructions
+        const int pw2 = tid % 8, ew2 = (tid / 8) % EB, ch = tid / (8 * EB);
+        const int64_t pw0 = p0 + 2 * pw2, e1x = e1_0 + ew2, col = 2 * pw0;
+        const bool full = wide && pw0 + 1 < P && col + 3 < t;
+        if (e1x < M1) {
+#pragma unroll
+          for (int cc = 0; cc < CH / 2; ++cc) {
+            const int c = ch + 2 * cc;
+            const int64_t e = e1x + M1 * (a + P2 * (c0 + c));
+            if (e >= L) continue;
+            const int64_t r = rowmap[e];
+            const cx<T> o0 = sm[c][ew2][2 * pw2], o1 = sm[c][ew2][2 * pw2 + 1];
+            if (full) {
+              const vec4_t<T> w = {o0.x, o0.y, o1.x, o1.y};
+              vec4_t<T>* dst = reinterpret_cast<vec4_t<T>*>(X + r * ldx + col);
+              if constexpr (NT)
+                __builtin_nontemporal_store(w, dst);
+              else
+                *dst = w;
+            } else {
+              if (pw0 < P) put_row<T, NT, EPI>(o0, r, pw0, X, ldx, t, v2, ec);
+              if (pw0 + 1 < P) put_row<T, NT, EPI>(o1, r, pw0 + 1, X, ldx, t, v2, ec);
+            }
+          }
+        }
+      } else if (pairw < P && e1w < M1) {
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
           const int64_t e2 = a + P2 * (c0 + c);
