@@ -197,7 +197,12 @@ int qmc_plan_set_row_order(qmc_plan_t plan, int order);
  *                every outer frequency (cost grows with s times M2);
  *                2 = dense: a gather pass collapses A into length-M columns and
  *                transforms the outer index (extra passes over M per pair,
- *                one stream); 0 = dense when s > 8 M1, else sparse
+ *                one stream); 3 = sparse with bucket twiddles: as 1, but an
+ *                item's slot twiddle W_M^{slot w2} is split into its outer
+ *                factor W_{M2}^{e2 w2} (a table of M2 values) and a factor
+ *                W_M^{e1 w2} applied once per bucket after the sums (no
+ *                per-item twiddle table reads); 0 = dense when s > 8 M1,
+ *                else sparse
  *   outer_q      the outer radix: the outer inverse DFT of length M2
  *                (qmc_plan_info) is split as M2 = P2 x Q2 with
  *                Q2 = min(outer_q, M2) values of w2 per output column of the
@@ -215,7 +220,7 @@ int qmc_plan_set_row_order(qmc_plan_t plan, int order);
  *                Infinity Cache for the back pass anyway)
  * The workspace size depends on the tuning: query it after setting it.
  * Returns QMC_ERR_ARG for negative chunks, streams outside {1, 2}, nt_store
- * outside {0, 1}, front outside {0, 1, 2}, an invalid outer_q or nt_inter
+ * outside {0, 1}, front outside {0, 1, 2, 3}, an invalid outer_q or nt_inter
  * outside {0, 1, 2}.
  */
 typedef struct {

@@ -34,8 +34,9 @@ def qmax_of(plan) -> int:
 
 
 def candidates(pairs: int, M2: int = 1, qmax: int = 128) -> List[Dict[str, int]]:
-    """Sparse front: every chunk, one or two streams, plain or non-temporal
-    stores of X.  Dense front (one stream): every chunk, both store kinds.
+    """Sparse front (with item or with bucket twiddles): every chunk, one or
+    two streams, plain or non-temporal stores of X.  Dense front (one
+    stream): every chunk, both store kinds.
     Each with cached or streaming stores of the intermediate and every outer
     radix of ``outer_radices``."""
     chunks = [0] + [c for c in (8, 16, 32, 64, 128, 256, 512, 1024) if c < pairs]
@@ -43,11 +44,12 @@ def candidates(pairs: int, M2: int = 1, qmax: int = 128) -> List[Dict[str, int]]
     out = []
     for q in qs:
         for ni in (1, 2):  # cached or streaming stores of the intermediate
-            for c in chunks:
-                for streams in ((1, 2) if c else (1,)):
-                    for nt in (0, 1):
-                        out.append({"chunk_pairs": c, "streams": streams, "nt_store": nt,
-                                    "front": 1, "outer_q": q, "nt_inter": ni})
+            for front in (1, 3):  # item twiddles, bucket twiddles
+                for c in chunks:
+                    for streams in ((1, 2) if c else (1,)):
+                        for nt in (0, 1):
+                            out.append({"chunk_pairs": c, "streams": streams, "nt_store": nt,
+                                        "front": front, "outer_q": q, "nt_inter": ni})
             for c in chunks:
                 for nt in (0, 1):
                     out.append({"chunk_pairs": c, "streams": 1, "nt_store": nt, "front": 2,

@@ -185,7 +185,7 @@ const char* qmc_profile_slot_name(int slot) {
 int qmc_plan_set_tuning(qmc_plan_t P, const qmc_tuning_t* tu) {
   if (!P || !tu) return QMC_ERR_ARG;
   if (tu->chunk_pairs < 0 || (tu->streams != 1 && tu->streams != 2) ||
-      (tu->nt_store != 0 && tu->nt_store != 1) || tu->front < 0 || tu->front > 2 ||
+      (tu->nt_store != 0 && tu->nt_store != 1) || tu->front < 0 || tu->front > 3 ||
       tu->nt_inter < 0 || tu->nt_inter > 2)
     return QMC_ERR_ARG;
   if (P->comp) {

@@ -41,18 +41,19 @@ __global__ __launch_bounds__(256) void k_collapse_T(const T* __restrict__ A, int
                    threadIdx.x);
 }
 
-template <typename T, int R, bool SPARSE>
+template <typename T, int R, bool SPARSE, bool BTW>
 __global__ __launch_bounds__(MidShape<R>::BLOCK)
 __attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void k_middle(
     const cx<T>* __restrict__ src, int64_t Upad, int64_t rounds, const uint16_t* __restrict__ it_e1,
     const cx<T>* __restrict__ twit, const cx<T>* __restrict__ twf1,
     const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs,
     const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M2, int64_t P,
-    cx<T>* __restrict__ C, T* __restrict__ X, int64_t t, T phi0, int nt_c) {
+    cx<T>* __restrict__ C, T* __restrict__ X, int64_t t, T phi0, int nt_c,
+    const uint16_t* __restrict__ it_e2, const cx<T>* __restrict__ twb) {
   __shared__ MidSmem<T, R> S;
-  middle_body<T, R, SPARSE>(src, Upad, rounds, it_e1, twit, twf1, twf2, Hs, twi3, two, M2,
-                            P, C, X, t, phi0, xcd_remap(blockIdx.x, gridDim.x), S, threadIdx.x,
-                            nt_c != 0);
+  middle_body<T, R, SPARSE, BTW>(src, Upad, rounds, it_e1, twit, twf1, twf2, Hs, twi3, two, M2,
+                                 P, C, X, t, phi0, xcd_remap(blockIdx.x, gridDim.x), S,
+                                 threadIdx.x, nt_c != 0, it_e2, twb);
 }
 
 template <typename T, int P2, int DIR>
@@ -186,12 +187,19 @@ static void launch_middle_r(const qmc_plan_s* P, const cx<T>* src, int64_t pairs
   const int64_t groups = (pairs + S::TPB - 1) / S::TPB;
   const int64_t G = groups * lay.M2;
   ProfScope ps(P, slot, st);
-  k_middle<T, R, SPARSE><<<dim3((unsigned)G), dim3(S::BLOCK), 0, st>>>(
-      src, P->Upad, P->rounds, P->d_it_e1, (const cx<T>*)P->d_twit, (const cx<T>*)P->d_twf1,
-      (const cx<T>*)P->d_twf2, (const cx<T>*)P->d_Hs,
-      (const cx<T>*)P->d_twi3,
-      (const cx<T>*)P->d_two, lay.M2, pairs, C, X, t, (T)P->phi0,
-      nt_inter(P, (SPARSE ? 1 : 2) * pairs * lay.M * (int64_t)sizeof(cx<T>)) ? 1 : 0);
+  const int ntc = nt_inter(P, (SPARSE ? 1 : 2) * pairs * lay.M * (int64_t)sizeof(cx<T>)) ? 1 : 0;
+  // the sparse front with bucket twiddles (tuning front = 3)
+  if (SPARSE && P->tune.front == 3)
+    k_middle<T, R, SPARSE, true><<<dim3((unsigned)G), dim3(S::BLOCK), 0, st>>>(
+        src, P->Upad, P->rounds, P->d_it_e1, nullptr, (const cx<T>*)P->d_twf1,
+        (const cx<T>*)P->d_twf2, (const cx<T>*)P->d_Hs, (const cx<T>*)P->d_twi3,
+        (const cx<T>*)P->d_two, lay.M2, pairs, C, X, t, (T)P->phi0, ntc, P->d_it_e2,
+        (const cx<T>*)P->d_twb);
+  else
+    k_middle<T, R, SPARSE, false><<<dim3((unsigned)G), dim3(S::BLOCK), 0, st>>>(
+        src, P->Upad, P->rounds, P->d_it_e1, (const cx<T>*)P->d_twit, (const cx<T>*)P->d_twf1,
+        (const cx<T>*)P->d_twf2, (const cx<T>*)P->d_Hs, (const cx<T>*)P->d_twi3,
+        (const cx<T>*)P->d_two, lay.M2, pairs, C, X, t, (T)P->phi0, ntc, nullptr, nullptr);
 }
 
 // X != nullptr: forward product, the DC term of each pair goes to row 0

@@ -75,6 +75,7 @@ struct qmc_plan_s {
   void* d_twit = nullptr;       // M2*Upad: W_M^{slot_u w2} in [w2][u] order
   void* d_twb = nullptr;        // M2  : conj W_{M2}^k, the outer split's twiddles at k = a q mod M2
   uint16_t* d_it_e1 = nullptr;  // Upad: e1 of item u (M1 for padding; M1 <= 4096)
+  uint16_t* d_it_e2 = nullptr;  // Upad: e2 = slot / M1 of item u (0 for padding; M2 <= 4096)
   int32_t* d_it_ptr = nullptr;  // Upad+1: rows of item u are it_jl[it_ptr[u] .. it_ptr[u+1])
   int32_t* d_it_jl = nullptr;   // s   : rows j grouped by item (increasing j)
   int32_t* d_inv_ptr = nullptr;    // L+1 : rows j with l_j = e are inv_j[inv_ptr[e] .. inv_ptr[e+1])

@@ -248,14 +248,24 @@ constexpr int mid_waves() {
   return sizeof(T) == 8 ? (R == 16 ? 2 : R == 8 ? 3 : 4) : 4;
 }
 
+// outer lengths whose twiddles the sparse front with bucket twiddles keeps
+// in LDS (longer ones are read from the global table)
+constexpr int MID_TW2 = 256;
+
 template <typename T, int R>
 struct MidSmem {
   cx<T> lds[MidShape<R>::TPB * MidShape<R>::BUFN];
   cx<T> wr2[R * (R + 1)];  // W_{R^2}^{i j} at [i][j], rows padded to R + 1
+  cx<T> tw2[MID_TW2];      // sparse front with bucket twiddles: conj W_{M2}^k, k < M2
 };
 
-// b: logical block of this product (w2 = b mod M2, pair group = b / M2)
-template <typename T, int R, bool SPARSE>
+// b: logical block of this product (w2 = b mod M2, pair group = b / M2).
+// BTW (sparse front only): bucket twiddles.  The slot twiddle of an item,
+// W_M^{slot w2} with slot = e1 + M1 e2, splits as W_M^{e1 w2} W_{M2}^{e2 w2}:
+// the items take the short factor from a table of M2 values (it_e2: e2 per
+// item, twb: conj W_{M2}^k) and every bucket e1 the long one once, after the
+// sums (as the dense front does), instead of loading a twiddle per item.
+template <typename T, int R, bool SPARSE, bool BTW = false>
 __device__ __forceinline__ void middle_body(
     const cx<T>* __restrict__ src,      // SPARSE: aT [pair][Upad]; dense: B [pair][M2][M1]
     int64_t Upad, int64_t rounds, const uint16_t* __restrict__ it_e1,
@@ -263,7 +273,8 @@ __device__ __forceinline__ void middle_body(
     const cx<T>* __restrict__ twf2, const cx<T>* __restrict__ Hs,
     const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M2, int64_t P,
     cx<T>* __restrict__ C, T* __restrict__ X, int64_t t, T phi0, int64_t b, MidSmem<T, R>& SM,
-    int tid, bool nt_c = false) {
+    int tid, bool nt_c = false, const uint16_t* __restrict__ it_e2 = nullptr,
+    const cx<T>* __restrict__ twb = nullptr) {
   typedef MidShape<R> S;
   constexpr int Q = S::Q, M1 = R * R * R, PB = R * (R + 1);
   cx<T>* lds = SM.lds;
@@ -285,6 +296,13 @@ __device__ __forceinline__ void middle_body(
   // read after the barriers of step 1); twf2 holds value g of thread a
   for (int i = tid; i < R * R; i += S::BLOCK)
     SM.wr2[(i % R) * (R + 1) + i / R] = twf2[paired_index(i / R, i % R, R, pair_pp(R))];
+  // bucket twiddles: the short factors in LDS (read after the front's first
+  // barrier); longer outer lengths read the global table
+  const bool tw2_lds = BTW && M2 <= MID_TW2;
+  if constexpr (BTW) {
+    if (tw2_lds)
+      for (int i = tid; i < M2; i += S::BLOCK) SM.tw2[i] = twb[i];
+  }
 
   // ---- front: B[e1] for this w2, in registers of thread e1' = q ----------
   if constexpr (SPARSE) {
@@ -298,7 +316,8 @@ __device__ __forceinline__ void middle_body(
     // slot).
     // Inactive transforms read pair 0 and store nothing that is used.
     const cx<T>* av = src + (active ? pair : 0) * Upad;
-    const cx<T>* tw = twit + w2 * Upad;
+    const cx<T>* tw = BTW ? nullptr : twit + w2 * Upad;
+    const int64_t m2mask = M2 - 1;
     const int nr = (int)rounds;
     int cur = M1;
     cx<T> acc = zero;
@@ -315,22 +334,36 @@ __device__ __forceinline__ void middle_body(
           // two 16-bit residues in one 32-bit load (u is even)
           const uint32_t ee = *reinterpret_cast<const uint32_t*>(it_e1 + u);
           const cx2<T> vv = *reinterpret_cast<const cx2<T>*>(av + u);
-          const cx2<T> ww = *reinterpret_cast<const cx2<T>*>(tw + u);
           e1[i] = (int)(ee & 0xffffu);
           e1[i + 1] = (int)(ee >> 16);
           v[i] = vv.a;
           v[i + 1] = vv.b;
-          w[i] = ww.a;
-          w[i + 1] = ww.b;
+          if constexpr (BTW) {
+            const uint32_t ff = *reinterpret_cast<const uint32_t*>(it_e2 + u);
+            // conj W_{M2}^{e2 w2}
+            const int64_t k0 = ((int64_t)(ff & 0xffffu) * w2) & m2mask;
+            const int64_t k1 = ((int64_t)(ff >> 16) * w2) & m2mask;
+            w[i] = tw2_lds ? SM.tw2[k0] : twb[k0];
+            w[i + 1] = tw2_lds ? SM.tw2[k1] : twb[k1];
+          } else {
+            const cx2<T> ww = *reinterpret_cast<const cx2<T>*>(tw + u);
+            w[i] = ww.a;
+            w[i + 1] = ww.b;
+          }
         } else {
           e1[i] = it_e1[u];
           v[i] = av[u];
-          w[i] = tw[u];
+          if constexpr (BTW) {
+            const int64_t k = ((int64_t)it_e2[u] * w2) & m2mask;
+            w[i] = tw2_lds ? SM.tw2[k] : twb[k];
+          } else {
+            w[i] = tw[u];
+          }
         }
       }
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
-        const cx<T> c = cmul(v[i], w[i]);
+        const cx<T> c = BTW ? cmulc(v[i], w[i]) : cmul(v[i], w[i]);
         if (e1[i] != cur) {
           buf[cur] = acc;
           cur = e1[i];
@@ -347,6 +380,15 @@ __device__ __forceinline__ void middle_body(
     __syncthreads();
 #pragma unroll
     for (int c = 0; c < R; ++c) x[c] = buf[q + Q * c];
+    if constexpr (BTW) {
+      // the long factor W_M^{e1 w2} of bucket e1 = q + Q c, as the dense front
+      const cx<T> tq = twi3[w2 * M1 + paired_index(q / R, q % R, Q, pair_pp(R))];
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        x[c] = cmulc(x[c], tq);
+        if (c > 0) x[c] = cmulc(x[c], two[w2 * R + c]);
+      }
+    }
   } else {
     // dense outer DFT already done: B[pair][w2][e1], times W_M^{e1 w2}
     const cx<T>* bv = src + ((active ? pair : 0) * M2 + w2) * M1;

@@ -587,8 +587,13 @@ int build_conv_tables(qmc_plan_s* P, const int32_t* ell, const int32_t* d_zidx,
     P->d_it_ptr = dev_alloc<int32_t>(P, P->Upad + 1, &err);
     P->d_it_jl = dev_alloc<int32_t>(P, sa, &err);
     P->d_it_e1 = dev_alloc<uint16_t>(P, P->Upad, &err);
+    P->d_it_e2 = dev_alloc<uint16_t>(P, P->Upad, &err);
     P->d_inv_ptr = dev_alloc<int32_t>(P, L + 1, &err);
     P->d_inv_j = dev_alloc<int32_t>(P, sa, &err);
+    // e2 = slot / M1 of every item (the outer index of its slot, 0 for padding)
+    std::vector<uint16_t> e2(P->Upad);
+    for (int64_t u = 0; u < P->Upad; ++u)
+      e2[u] = sc.it_slot[u] >= 0 ? (uint16_t)(sc.it_slot[u] / lay.M1) : (uint16_t)0;
     if ((rc = err) != QMC_OK) break;
     int32_t* d_slot = nullptr;
     if ((rc = hip_ok(hipMalloc(&d_slot, P->Upad * sizeof(int32_t)))) != QMC_OK) break;
@@ -609,6 +614,9 @@ int build_conv_tables(qmc_plan_s* P, const int32_t* ell, const int32_t* d_zidx,
       rc = hip_ok(hipMemcpyAsync(P->d_it_jl, sc.it_jl.data(), sa * 4, hipMemcpyHostToDevice, st));
     if (rc == QMC_OK)
       rc = hip_ok(hipMemcpyAsync(P->d_it_e1, e16.data(), P->Upad * sizeof(uint16_t),
+                                 hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK)
+      rc = hip_ok(hipMemcpyAsync(P->d_it_e2, e2.data(), P->Upad * sizeof(uint16_t),
                                  hipMemcpyHostToDevice, st));
     if (rc == QMC_OK)
       rc = hip_ok(hipMemcpyAsync(d_slot, sc.it_slot.data(), P->Upad * 4, hipMemcpyHostToDevice,

@@ -14,7 +14,8 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 @pytest.mark.parametrize("chunk,streams,nt,front", [
     (0, 1, 1, 1), (5, 1, 0, 1), (5, 2, 0, 1), (7, 2, 1, 1), (16, 2, 0, 1), (1, 2, 1, 1),
-    (0, 1, 0, 2), (5, 1, 1, 2), (16, 1, 0, 2), (1, 1, 0, 2), (3, 2, 0, 2)])
+    (0, 1, 0, 2), (5, 1, 1, 2), (16, 1, 0, 2), (1, 1, 0, 2), (3, 2, 0, 2),
+    (0, 1, 1, 3), (5, 1, 0, 3), (7, 2, 1, 3)])
 def test_tuned_forward(chunk, streams, nt, front, dtype):
     torch = torch_cuda()
     import paper_1501_06286_amd as q
@@ -59,7 +60,7 @@ def test_tuning_rejects_bad_values():
     torch_cuda()
     import paper_1501_06286_amd as q
     p = plan_of(qi.small_lattice(101, 5, 2))
-    for bad in ({"chunk_pairs": -1}, {"streams": 3}, {"nt_store": 2}, {"front": 3},
+    for bad in ({"chunk_pairs": -1}, {"streams": 3}, {"nt_store": 2}, {"front": 4},
                 {"front": -1}, {"nt_inter": 3}, {"nt_inter": -1}):
         with pytest.raises(q.QMCError):
             p.set_tuning(**bad)
@@ -198,3 +199,43 @@ def test_lds_back_tiles(q, t, dtype):
     assert_close(X.double().cpu().numpy(), oracle.matmul(inst), inst.A, inst, dtype, "forward")
     Gr = G.astype(np.float32).astype(np.float64) if dtype == "f32" else G
     assert_close(dA.double().cpu().numpy(), oracle.adjoint(inst, Gr), Gr, inst, dtype, "adjoint")
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("case", ["gauss", "gf2", "m2_512", "m2_4096", "tiny"])
+def test_bucket_twiddle_front(case, dtype):
+    """The sparse front with bucket twiddles (front 3) against the oracle and
+    the item-twiddle front: outer lengths with the short factors in LDS
+    (M2 = 16, 32) and read from the global table (M2 = 512, 4096), and R < 16."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    if case == "gauss":
+        inst = qi.small_lattice(65537, 700, 6, phi=qi.PHI_INVNORM, shift=(1, 2 * 65537),
+                                dtype=dtype)
+    elif case == "gf2":
+        inst = qi.small_gf2(16, 900, 5, dtype=dtype)
+    elif case == "m2_512":
+        N = 1048573
+        inst = qi.small_lattice(N, 300, 3, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype)
+    elif case == "m2_4096":
+        N = 8388593
+        inst = qi.small_lattice(N, 40, 2, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype)
+    else:
+        inst = qi.small_lattice(1009, 50, 7, phi=qi.PHI_CENTERED, dtype=dtype)
+    announce(f"bucket twiddles {case} {dtype}")
+    p = plan_of(inst)
+    A = to_dev(inst.A, dtype)
+    p.set_tuning(front=1)
+    X1 = q.matmul(p, A)
+    p.set_tuning(front=3)
+    X3 = q.matmul(p, A)
+    torch.cuda.synchronize()
+    N = inst.N
+    rg = np.random.default_rng(N)
+    rows = np.unique(np.concatenate([[0, 1, N - 1], rg.choice(N, size=min(N, 400), replace=False)]))
+    got = X3[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+    assert_close(got, oracle.matmul_rows(inst, rows), inst.A, inst, dtype, f"front 3 {case}")
+    scale = float(np.max(np.abs(oracle.phi_residue_values(inst.rule, N, inst.phi, inst.modulus,
+                                                          inst.shift))))
+    d = float((X3 - X1).abs().max()) / (scale * float(np.abs(inst.A).sum(axis=0).max()))
+    assert d <= (1e-12 if dtype == "f64" else 1e-5)
