@@ -676,6 +676,9 @@ def main():
 
     if "cpu" in legs:
         result["cpu_baseline"] = cpu_baseline_and_errors(main_leg.checks[0][1], all_legs)
+        # the headline's own error against the FP64 oracle (max over the
+        # checked rows of |X - X_oracle| / (max|Y| ||A[:, k]||_1))
+        result["err_vs_oracle"] = main_leg.out.get("err_vs_oracle")
         log(f"cpu baseline {result['cpu_baseline']['value']:.3e} entries/s; worst errors "
             f"{ {l.name: l.out.get('err_vs_oracle') for l in all_legs} }")
     print(json.dumps(result), flush=True)

@@ -103,7 +103,9 @@ typedef struct qmc_plan_s* qmc_plan_t;
  *   stream     HIP stream for the plan-building kernels; the call
  *              synchronises that stream before returning.
  * The convolution length M (N - 1 when that is a power of two, else the
- * power of two >= 2N - 3) must split as M = M1 x M2 with M1 <= 4096 on chip
+ * shortest power of two or 3 x 2^k >= 2N - 3, see qmc_plan_info; the union
+ * of Korobov rules takes powers of two only) must split as M = M1 x M2 with
+ * M1 <= 4096 on chip
  * and M2 <= 64 x 64; longer rules (N - 1 > 2^23 when not a power of two, or
  * above 2^24) return QMC_ERR_UNSUPPORTED before any device work.
  *
@@ -135,13 +137,16 @@ void qmc_plan_destroy(qmc_plan_t plan);
  * Plan facts for callers and tests (host pointer to a filled struct).  The
  * transform factorisation is M = M1 x M2 with M1 = R^3 on chip (three
  * register DFTs of radix R) and the outer length M2 = P2 x Q2 (a split pass of
- * radix P2 when P2 > 1, the back pass of radix Q2); every length is a power of
- * two, so these fields are the whole radix plan and no separate list of
- * radices is reported.
+ * radix P2 when P2 > 1, the back pass of radix Q2).  R and P2 are powers of
+ * two; Q2 (and M2) is a power of two or 3 x 2^i, whose register DFTs take
+ * one radix-3 stage and then radix-4 and radix-2 stages.  These fields are
+ * the whole radix plan, so no separate list of radices is reported.
  */
 typedef struct {
     int64_t N, s, L;        /* points, dimension, order L of the unit group (N - 1 for prime N) */
-    int64_t M;              /* circular-convolution length used: L, or a power of two >= 2L-1 */
+    int64_t M;              /* circular-convolution length used: L, or the shortest power
+                               of two >= 2L-1, or 3 x 2^k >= 2L-1 when that is shorter
+                               (M >= 3 x 4096 and M2 no longer than one back pass) */
     int64_t M1, M2;         /* M = M1 * M2 (on-chip transform length, outer length) */
     int64_t rounds;         /* rounds of the sparse collapse schedule */
     uint64_t beta;          /* primitive element (lattice: smallest primitive root; GF(2): x = 2) */
@@ -201,18 +206,21 @@ int qmc_plan_set_row_order(qmc_plan_t plan, int order);
  *                item's slot twiddle W_M^{slot w2} is split into its outer
  *                factor W_{M2}^{e2 w2} (a table of M2 values) and a factor
  *                W_M^{e1 w2} applied once per bucket after the sums (no
- *                per-item twiddle table reads); 0 = dense when s > 8 M1,
+ *                per-item twiddle table reads; M2 a power of two, other
+ *                outer lengths run 3 as 1); 0 = dense when s > 8 M1,
  *                else sparse
  *   outer_q      the outer radix: the outer inverse DFT of length M2
  *                (qmc_plan_info) is split as M2 = P2 x Q2 with
  *                Q2 = min(outer_q, M2) values of w2 per output column of the
  *                back pass and one extra split pass when P2 > 1; Q2 <= 32 is
- *                held in registers (FP64: up to 16), the larger ones in LDS
- *                (128: FP32 plans only).
- *                A power of two <= 128 with P2 <= 64, or 0 for the default:
- *                all of M2 when that fits one back pass (M2 <= 128 in FP32,
- *                64 in FP64: no split pass), else 32, or M2/64 when larger.
- *                The dense fronts' forward split uses min(Q2, 64)
+ *                held in registers (FP64: up to 24), the larger ones in LDS
+ *                (96 and 128: FP32 plans only).
+ *                A power of two <= 128, or for M2 = 3 x 2^j a value 3 x 2^i
+ *                <= 96, with P2 = M2 / Q2 a power of two <= 64; or 0 for the
+ *                default: all of M2 when that fits one back pass (M2 <= 128
+ *                in FP32, 64 in FP64: no split pass), else 32, or M2/64 when
+ *                larger.  The dense fronts' forward split uses Q2 up to 64,
+ *                else Q2 / 2
  *   nt_inter     stores of the intermediate spectrum by the fused pass: 1 =
  *                cached, 2 = streaming (non-temporal), 0 = streaming when one
  *                launch's intermediates (with the dense fronts: both

@@ -24,7 +24,7 @@ static bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 
 int plan_create(qmc_plan_s** out, int rule, int64_t N, int64_t s, const uint64_t* gen,
                 uint64_t modulus, int phi_kind, int64_t shift_num, int64_t shift_den, int dtype,
-                bool row0_used, hipStream_t stream) {
+                bool row0_used, bool mixed_outer, hipStream_t stream) {
   if (!out || !gen || s < 1) return QMC_ERR_ARG;
   *out = nullptr;
   if (rule != QMC_RULE_LATTICE && rule != QMC_RULE_POLY_GF2) return QMC_ERR_ARG;
@@ -65,6 +65,7 @@ int plan_create(qmc_plan_s** out, int rule, int64_t N, int64_t s, const uint64_t
   P->shift_num = shift_num;
   P->shift_den = shift_den;
   P->dtype = dtype;
+  P->mixed_outer = mixed_outer;
   const int rc = build_tables(P, gen, stream);
   if (rc != QMC_OK) {
     qmc_plan_destroy(P);
@@ -97,7 +98,7 @@ const char* qmc_strerror(int code) {
 int qmc_plan_create(qmc_plan_t* out, int rule, int64_t N, int64_t s, const uint64_t* gen,
                     uint64_t modulus, int phi_kind, int64_t shift_num, int64_t shift_den,
                     int dtype, void* stream) {
-  return plan_create(out, rule, N, s, gen, modulus, phi_kind, shift_num, shift_den, dtype, true,
+  return plan_create(out, rule, N, s, gen, modulus, phi_kind, shift_num, shift_den, dtype, true, true,
                      (hipStream_t)stream);
 }
 

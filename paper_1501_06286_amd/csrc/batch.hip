@@ -361,7 +361,7 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
     I.gx_split = (lay.M1 + 63) / 64;
     I.nb[PASS_SPLIT] = lay.P2 > 1 ? I.gx_split * lay.Q2 * I.pairs : 0;
     // back tile: e1 x column pairs (LDS outer DFT: 16 or 8 x 8, register: 16 x 16)
-    const bool lds = lay.Q2 >= 64 || (P->dtype == QMC_F64 && lay.Q2 == 32);
+    const bool lds = back_in_lds(lay.Q2, P->dtype == QMC_F64);
     const int64_t te = lds ? (P->dtype == QMC_F32 ? 16 : 8) : 16;
     const int64_t tp = lds ? 8 : 16;
     I.gx_back = (lay.M1 + te - 1) / te;
@@ -490,6 +490,17 @@ static int run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
       case 4: QMC_KBB(4); break;
       case 8: QMC_KBB(8); break;
       case 16: QMC_KBB(16); break;
+      case 3: QMC_KBB(3); break;
+      case 6: QMC_KBB(6); break;
+      case 12: QMC_KBB(12); break;
+      case 24: QMC_KBB(24); break;
+      case 48: QMC_KBL(48); break;
+      case 96:
+        if constexpr (sizeof(T) == 4) {
+          QMC_KBL(96);
+          break;
+        }
+        return QMC_ERR_UNSUPPORTED;
       case 32:  // FP64 through LDS, as the single product (the same bits)
         if constexpr (sizeof(T) == 8) {
           QMC_KBL(32);

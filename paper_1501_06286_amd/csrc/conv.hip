@@ -188,8 +188,9 @@ static void launch_middle_r(const qmc_plan_s* P, const cx<T>* src, int64_t pairs
   const int64_t G = groups * lay.M2;
   ProfScope ps(P, slot, st);
   const int ntc = nt_inter(P, (SPARSE ? 1 : 2) * pairs * lay.M * (int64_t)sizeof(cx<T>)) ? 1 : 0;
-  // the sparse front with bucket twiddles (tuning front = 3)
-  if (SPARSE && P->tune.front == 3)
+  // the sparse front with bucket twiddles (tuning front = 3; its twiddle
+  // index needs M2 a power of two, other M2 take the item twiddles)
+  if (SPARSE && P->tune.front == 3 && (lay.M2 & (lay.M2 - 1)) == 0)
     k_middle<T, R, SPARSE, true><<<dim3((unsigned)G), dim3(S::BLOCK), 0, st>>>(
         src, P->Upad, P->rounds, P->d_it_e1, nullptr, (const cx<T>*)P->d_twf1,
         (const cx<T>*)P->d_twf2, (const cx<T>*)P->d_Hs, (const cx<T>*)P->d_twi3,
@@ -244,10 +245,10 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
                        hipStream_t st, const Epi<T>& epi = Epi<T>()) {
   const Layout& lay = P->lay;
   ProfScope ps(P, ADJ ? PROF_ADJ_BACK : PROF_BACK, st);
-  // the outer factor through LDS, tiles of TE e1 x 8 pairs: Q2 = 64 and 128,
-  // and 32 in FP64 (its register variant takes all 256 registers and spills;
-  // in FP32 the register variant is the faster one)
-  if (lay.Q2 >= 64 || (sizeof(T) == 8 && lay.Q2 == 32)) {
+  // the outer factor through LDS, tiles of TE e1 x 8 pairs: Q2 = 48, 64, 96
+  // and 128, and 32 in FP64 (its register variant takes all 256 registers and
+  // spills; in FP32 the register variant is the faster one)
+  if (back_in_lds(lay.Q2, sizeof(T) == 8)) {
     constexpr int TE = back_lds_te<T>();
     dim3 gl((unsigned)((lay.M1 + TE - 1) / TE), (unsigned)((pairs + 7) / 8), (unsigned)lay.P2);
 #define QMC_BACKL(QQ)                                                                        \
@@ -255,11 +256,17 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
       <<<gl, BackLdsShape<QQ, TE, back_lds_nw<T, QQ, ADJ>()>::BLOCK, 0, st>>>(                \
           C, lay.M1, lay.M2, lay.P2, P->L, pairs, (const cx<T>*)P->d_twb, out_rows(P), inv_ptr, \
           inv_j, G0, (T)P->phi0, X, ldx, t, epi)
-    if (lay.Q2 == 64) {
+    if (lay.Q2 == 48) {
+      QMC_BACKL(48);
+    } else if (lay.Q2 == 64) {
       QMC_BACKL(64);
     } else if constexpr (sizeof(T) == 4) {
-      if (lay.Q2 != 128) return QMC_ERR_UNSUPPORTED;
-      QMC_BACKL(128);
+      if (lay.Q2 == 96) {
+        QMC_BACKL(96);
+      } else {
+        if (lay.Q2 != 128) return QMC_ERR_UNSUPPORTED;
+        QMC_BACKL(128);
+      }
     } else {
       if (lay.Q2 != 32) return QMC_ERR_UNSUPPORTED;
       QMC_BACKL(32);
@@ -278,6 +285,10 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
     case 8: QMC_BACK(8); break;
     case 16: QMC_BACK(16); break;
     case 32: QMC_BACK(32); break;
+    case 3: QMC_BACK(3); break;
+    case 6: QMC_BACK(6); break;
+    case 12: QMC_BACK(12); break;
+    case 24: QMC_BACK(24); break;
     default: return QMC_ERR_UNSUPPORTED;
   }
 #undef QMC_BACK
@@ -452,6 +463,11 @@ static int launch_outer_front(const qmc_plan_s* P, const T* A, const T* G, int64
       case 16: QMC_OFRONT(16); break;
       case 32: QMC_OFRONT(32); break;
       case 64: QMC_OFRONT(64); break;
+      case 3: QMC_OFRONT(3); break;
+      case 6: QMC_OFRONT(6); break;
+      case 12: QMC_OFRONT(12); break;
+      case 24: QMC_OFRONT(24); break;
+      case 48: QMC_OFRONT(48); break;
       default: return QMC_ERR_UNSUPPORTED;
     }
 #undef QMC_OFRONT

@@ -2,8 +2,8 @@
 //
 // The circular convolutions of the fast QMC product (Section 2.1, eq. (ZPa):
 // Y' a = Z (P a) with Z circulant) are evaluated with FFTs.  Short DFTs
-// (length <= 64) run entirely in one lane's registers with compile-time
-// twiddle constants; longer transforms are built from them with LDS
+// (length 2^k <= 64 or 3 x 2^k <= 96) run entirely in one lane's registers
+// with compile-time twiddle constants; longer transforms are built from them with LDS
 // exchanges between lanes (kernels.hpp).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -43,7 +43,7 @@ template <typename T>
 __device__ __forceinline__ cx<T> mul_mi(cx<T> a) { return {a.y, -a.x}; }
 
 // ---------------------------------------------------------------------------
-// compile-time twiddle constants: cos and sin of 2 pi k / 64
+// compile-time twiddle constants: cos and sin of 2 pi k / 64 and 2 pi k / 192
 // ---------------------------------------------------------------------------
 constexpr double kTwoPi = 6.283185307179586476925286766559;
 
@@ -79,18 +79,23 @@ constexpr void sincos_turns(long num, long den, double& s, double& c) {
     default: s = -c0; c = s0; break;
   }
 }
-struct TwTab64 {
-  double c[64];
-  double s[64];
+template <int D>
+struct TwTab {
+  double c[D];
+  double s[D];
 };
-constexpr TwTab64 make_tw64() {
-  TwTab64 t{};
-  for (int k = 0; k < 64; ++k) sincos_turns(k, 64, t.s[k], t.c[k]);
+template <int D>
+constexpr TwTab<D> make_tw() {
+  TwTab<D> t{};
+  for (int k = 0; k < D; ++k) sincos_turns(k, D, t.s[k], t.c[k]);
   return t;
 }
-__device__ constexpr TwTab64 kTw64 = make_tw64();
+// roots of unity of order 64 (every power-of-two length up to 64) and 192
+// (the lengths 3 x 2^k up to 192 of the mixed-radix DFTs)
+__device__ constexpr TwTab<64> kTw64 = make_tw<64>();
+__device__ constexpr TwTab<192> kTw192 = make_tw<192>();
 
-// a * W^num with W = exp(DIR * 2 pi i / den), den a power of two <= 64.
+// a * W^num with W = exp(DIR * 2 pi i / den), den dividing 64 or 192.
 // num and den are compile-time constants after unrolling: exact quarter and
 // eighth turns become sign changes and one shared 1/sqrt(2) scaling.
 template <typename T, int DIR>
@@ -103,9 +108,11 @@ __device__ __forceinline__ cx<T> twiddle_const(cx<T> a, int num, int den) {
     bool plus_i = (q == 1) == (DIR > 0);
     return plus_i ? mul_i(a) : mul_mi(a);
   }
-  const int k = num * (64 / den);
-  const T c = (T)kTw64.c[k];
-  const T s = (T)(DIR > 0 ? kTw64.s[k] : -kTw64.s[k]);
+  const bool p2 = 64 % den == 0;
+  const int k = p2 ? num * (64 / den) : num * (192 / den);
+  const T c = (T)(p2 ? kTw64.c[k] : kTw192.c[k]);
+  const T sv = (T)(p2 ? kTw64.s[k] : kTw192.s[k]);
+  const T s = DIR > 0 ? sv : -sv;
   if ((8 * num) % den == 0) {
     // (+-1 +- i)/sqrt(2): rotate by a quarter-turn-free eighth turn
     const T h = (T)0.70710678118654752440;
@@ -119,10 +126,10 @@ __device__ __forceinline__ cx<T> twiddle_const(cx<T> a, int num, int den) {
 }
 
 // ---------------------------------------------------------------------------
-// register DFT of length N (power of two, N <= 64), natural order in and out,
-// Stockham formulation with radix-4 stages (and one radix-2 stage when
-// log2 N is odd).  DIR = -1: forward exp(-2 pi i jk/N); DIR = +1: inverse,
-// unscaled.
+// register DFT of length N (2^k <= 64, or 3 x 2^k <= 96), natural order in
+// and out, Stockham formulation: one radix-3 stage first when 3 divides N,
+// then radix-4 stages (and one radix-2 stage when the power of two is an odd
+// power).  DIR = -1: forward exp(-2 pi i jk/N); DIR = +1: inverse, unscaled.
 // ---------------------------------------------------------------------------
 template <typename T, int DIR>
 __device__ __forceinline__ void bfly2(cx<T>& a0, cx<T>& a1) {
@@ -140,11 +147,24 @@ __device__ __forceinline__ void bfly4(cx<T>& a0, cx<T>& a1, cx<T>& a2, cx<T>& a3
   a3 = t1 - t3;
 }
 
+// length 3: with W = exp(DIR 2 pi i / 3) = -1/2 + DIR i sqrt(3)/2,
+//   y0 = a0 + (a1 + a2),  y1,2 = a0 - (a1 + a2)/2 +- DIR i sqrt(3)/2 (a1 - a2)
+template <typename T, int DIR>
+__device__ __forceinline__ void bfly3(cx<T>& a0, cx<T>& a1, cx<T>& a2) {
+  const T h = (T)0.86602540378443864676;  // sqrt(3)/2
+  const cx<T> t1 = a1 + a2, t2 = a1 - a2;
+  const cx<T> m = {fmaT(t1.x, (T)-0.5, a0.x), fmaT(t1.y, (T)-0.5, a0.y)};
+  const cx<T> n = DIR > 0 ? cx<T>{-t2.y * h, t2.x * h} : cx<T>{t2.y * h, -t2.x * h};
+  a0 = a0 + t1;
+  a1 = m + n;
+  a2 = m - n;
+}
+
 template <typename T, int N, int DIR, int Ns>
 struct RegFftStage {
   static __device__ __forceinline__ void run(cx<T>* v) {
     if constexpr (Ns < N) {
-      constexpr int r = ((N / Ns) % 4 == 0) ? 4 : 2;
+      constexpr int r = (Ns == 1 && N % 3 == 0) ? 3 : ((N / Ns) % 4 == 0) ? 4 : 2;
       cx<T> out[N];
 #pragma unroll
       for (int j = 0; j < N / r; ++j) {
@@ -156,6 +176,8 @@ struct RegFftStage {
         for (int q = 1; q < r; ++q) a[q] = twiddle_const<T, DIR>(a[q], q * k, Ns * r);
         if constexpr (r == 4)
           bfly4<T, DIR>(a[0], a[1], a[2], a[3]);
+        else if constexpr (r == 3)
+          bfly3<T, DIR>(a[0], a[1], a[2]);
         else
           bfly2<T, DIR>(a[0], a[1]);
         const int base = (j / Ns) * Ns * r + k;
@@ -171,7 +193,9 @@ struct RegFftStage {
 
 template <typename T, int N, int DIR>
 __device__ __forceinline__ void reg_fft(cx<T>* v) {
-  static_assert(N >= 1 && N <= 64 && (N & (N - 1)) == 0, "register DFT length");
+  constexpr int P = N % 3 == 0 ? N / 3 : N;  // the power-of-two part
+  static_assert(N >= 1 && (P & (P - 1)) == 0 && (N == P ? N <= 64 : N <= 96),
+                "register DFT length");
   RegFftStage<T, N, DIR, 1>::run(v);
 }
 

@@ -13,11 +13,11 @@ namespace qmc {
 // Decomposition of the circular convolution of length M = M1 * M2
 // (M1 = R * R on chip, M2 outer).
 struct Layout {
-  int64_t M = 1, M1 = 1, M2 = 1;
+  int64_t M = 1, M1 = 1, M2 = 1;  // M2 = 2^j, or 3 x 2^j (then M1 = 16^3)
   int R = 1;        // M1 = R * R * R, R <= 16
-  int P2 = 1;       // outer inverse split M2 = P2 * Q2 (P2 = 1: single back pass)
-  int Q2 = 1;       // values of w2 per output column of the back pass (<= 64 in registers,
-                    // 64 and 128 through LDS)
+  int P2 = 1;       // outer inverse split M2 = P2 * Q2 (P2 = 1: single back pass; a power of two)
+  int Q2 = 1;       // values of w2 per output column of the back pass (up to 32 in registers,
+                    // 48 and more through LDS; holds the factor 3 of M2)
   int Pf = 1;       // outer forward split of the dense fronts M2 = Pf * Qf (Qf <= 64)
   int Qf = 1;
 };
@@ -54,6 +54,7 @@ struct qmc_plan_s {
   int64_t shift_num = 0, shift_den = 1;
   int dtype = QMC_F32;
   int embedded = 0;          // 1: L is not a power of two, convolution embedded in M >= 2L-1
+  bool mixed_outer = true;   // the embedding may take M = 3 x 2^k (outer length 3 x 2^j)
   double phi0 = 0.0;
   qmc::Layout lay;
   int64_t rounds = 0;        // sparse collapse schedule: rounds per front slice
@@ -116,7 +117,10 @@ int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st);
 // generator z_k = tphi[zidx[k]] for k < L (device tables)
 int build_conv_tables(qmc_plan_s* P, const int32_t* ell, const int32_t* d_zidx,
                       const double* d_tphi, hipStream_t st);
-Layout choose_layout(int64_t L, int dtype, int* embedded);
+// M = L when L is a power of two, else the shortest power of two >= 2L-1 or
+// (mixed) the shortest 3 x 2^k >= 2L-1 when that is shorter and its outer
+// length fits one back pass
+Layout choose_layout(int64_t L, int dtype, int* embedded, bool mixed);
 int launch_phi_table(qmc_plan_s* P, hipStream_t st);
 bool is_prime_u64(uint64_t n);
 std::vector<uint64_t> prime_factors(uint64_t n);
@@ -158,10 +162,11 @@ void pad_schedule(Schedule& sc, int64_t rounds, int64_t M1, int R);
 bool ranges_overlap(const void* a, size_t abytes, const void* b, size_t bbytes);
 size_t matrix_extent(int64_t rows, int64_t cols, int64_t ld, int dtype);
 // row0_used = false: the point of row 0 never enters a product (the union of
-// Korobov rules), so phi may be unbounded there
+// Korobov rules), so phi may be unbounded there; mixed_outer = false: the
+// convolution length stays a power of two (the union's kernels)
 int plan_create(qmc_plan_s** out, int rule, int64_t N, int64_t s, const uint64_t* gen,
                 uint64_t modulus, int phi_kind, int64_t shift_num, int64_t shift_den, int dtype,
-                bool row0_used, hipStream_t stream);
+                bool row0_used, bool mixed_outer, hipStream_t stream);
 
 // conv.hip
 bool dense_front(const qmc_plan_s* P);

@@ -260,7 +260,7 @@ struct MidSmem {
 };
 
 // b: logical block of this product (w2 = b mod M2, pair group = b / M2).
-// BTW (sparse front only): bucket twiddles.  The slot twiddle of an item,
+// BTW (sparse front only, M2 a power of two): bucket twiddles.  The slot twiddle of an item,
 // W_M^{slot w2} with slot = e1 + M1 e2, splits as W_M^{e1 w2} W_{M2}^{e2 w2}:
 // the items take the short factor from a table of M2 values (it_e2: e2 per
 // item, twb: conj W_{M2}^k) and every bucket e1 the long one once, after the
@@ -278,9 +278,16 @@ __device__ __forceinline__ void middle_body(
   typedef MidShape<R> S;
   constexpr int Q = S::Q, M1 = R * R * R, PB = R * (R + 1);
   cx<T>* lds = SM.lds;
-  // M2 is a power of two (M and M1 are): mask and shift, no division
-  const int64_t w2 = b & (M2 - 1);
-  const int64_t pg = b >> __builtin_ctzll((unsigned long long)M2);
+  // b = w2 + M2 pg: mask and shift when M2 is a power of two, else one
+  // 32-bit division (M2 = 3 x 2^k; b is below the grid size)
+  int64_t w2, pg;
+  if ((M2 & (M2 - 1)) == 0) {
+    w2 = b & (M2 - 1);
+    pg = b >> __builtin_ctzll((unsigned long long)M2);
+  } else {
+    pg = (int64_t)((uint32_t)b / (uint32_t)M2);
+    w2 = b - pg * M2;
+  }
   const int tr = tid / Q, q = tid % Q;
   const int64_t pair = pg * S::TPB + tr;
   const bool active = pair < P;
@@ -510,7 +517,7 @@ __device__ __forceinline__ void split_body(cx<T>* __restrict__ C, int64_t M1, in
   reg_fft<T, P2, DIR>(v);
   if constexpr (DIR > 0) {
 #pragma unroll
-    for (int a = 1; a < P2; ++a) v[a] = cmul(v[a], twb[(a * q) & (M2 - 1)]);
+    for (int a = 1; a < P2; ++a) v[a] = cmul(v[a], twb[a * q]);  // a q < P2 Q2 = M2
   }
 #pragma unroll
   for (int a = 0; a < P2; ++a) base[(q + (int64_t)Q2 * a) * M1] = v[a];
@@ -526,6 +533,13 @@ __device__ __forceinline__ void split_body(cx<T>* __restrict__ C, int64_t M1, in
 // adjoint-front passes; small enough that a back workgroup fits beside
 // four fused-kernel workgroups on one CU
 constexpr int BACK_CH = 8;
+// the largest divisor of Q that is at most cap (Q = 2^k or 3 x 2^k: the
+// chunks of a length-Q column moved through LDS together)
+constexpr int chunk_of(int Q, int cap) {
+  int c = Q < cap ? Q : cap;
+  while (Q % c) --c;
+  return c;
+}
 template <typename T>
 struct BackSmem {
   cx<T> sm[BACK_CH][16][17];
@@ -632,7 +646,7 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
                                           int64_t by, int64_t a, BackSmem<T>& S, int tid,
                                           const Epi<T> epi = Epi<T>()) {
   constexpr int PB = 16, EB = 16;
-  constexpr int CH = Q < BACK_CH ? Q : BACK_CH;
+  constexpr int CH = chunk_of(Q, BACK_CH);
   // FP32 forward writes without epilogue: two pairs per 16-byte store when
   // rows are 16-byte aligned (else per pair, as the other variants)
   constexpr bool WIDE = !ADJ && !EPI && sizeof(T) == 4 && CH == BACK_CH;
@@ -746,7 +760,8 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
 // ---------------------------------------------------------------------------
 template <int Q, int TE = 8, int NW_ = 4>
 struct BackLdsShape {
-  static constexpr int F1 = 8;
+  // Q = 2^k: F1 = 8; Q = 3 x 2^k: F1 = Q / 8 (6 or 12), F2 = 8
+  static constexpr int F1 = Q % 3 == 0 ? Q / 8 : 8;
   static constexpr int F2 = Q / F1;
   static constexpr int TP = 8;        // column pairs per tile
   static constexpr int K = TE * TP;   // columns per tile (TE values of e1)
@@ -794,10 +809,18 @@ constexpr int back_lds_te() {
 
 // threads per column of the LDS back pass: 8 (1024- or 512-thread
 // workgroups, half the registers per thread and twice the waves of 4), but 4
-// for the FP32 adjoint at Q = 64, which measured faster so
+// for the FP32 adjoint at Q = 64, which measured faster so; for Q = 3 x 2^k
+// the most that divides both factors (2 for Q = 48, 4 for Q = 96)
 template <typename T, int Q, bool ADJ>
 constexpr int back_lds_nw() {
-  return (Q == 32 || (ADJ && sizeof(T) == 4 && Q == 64)) ? 4 : 8;
+  return Q == 48 ? 2 : Q == 96 ? 4 : (Q == 32 || (ADJ && sizeof(T) == 4 && Q == 64)) ? 4 : 8;
+}
+
+// whether the back pass of outer radix Q goes through LDS: Q >= 48 (64, 128
+// and 48, 96), and Q = 32 in FP64 (its register variant takes all 256
+// registers and spills; in FP32 the register variant is the faster one)
+__host__ __device__ constexpr bool back_in_lds(int Q, bool f64) {
+  return Q >= 48 || (f64 && Q == 32);
 }
 
 template <typename T, int Q, int TE = 8>
@@ -877,7 +900,7 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
       reg_fft<T, F1, +1>(v[it]);
 #pragma unroll
       for (int c = 1; c < F1; ++c)
-        v[it][c] = cmul(v[it][c], twb[(int64_t)(u * c) * tstep & (M2 - 1)]);
+        v[it][c] = cmul(v[it][c], twb[(int64_t)(u * c) * tstep]);  // u c < Q
 #pragma unroll
       for (int c = 0; c < F1; ++c) lds[(u + F2 * c) * K + kc] = v[it][c];
     }
@@ -991,7 +1014,6 @@ __device__ __forceinline__ void outer_front_body(const Gather& gather, int64_t M
                                                  cx<T>* __restrict__ B, int64_t bx, int64_t by,
                                                  int64_t a, BackSmem<T>& S, int tid) {
   constexpr int PB = 16, EB = 16;
-  constexpr int CH = Q < BACK_CH ? Q : BACK_CH;
   auto& sm = S.sm;
   const int64_t e1_0 = bx * EB, p0 = by * PB;
   const int pw = tid % PB, ew = tid / PB;     // gather mapping (pair-fast)
@@ -1000,7 +1022,8 @@ __device__ __forceinline__ void outer_front_body(const Gather& gather, int64_t M
   // GQ values of the thread's gather column are loaded before the first wait
   // (all of them up to 16; beyond that the registers go to the transform)
   // and then transposed through LDS CH at a time
-  constexpr int GQ = Q <= 16 ? Q : 16;
+  constexpr int GQ = chunk_of(Q, 16);
+  constexpr int CH = chunk_of(GQ, BACK_CH);
   cx<T> v[Q];
 #pragma unroll
   for (int g0 = 0; g0 < Q; g0 += GQ) {
@@ -1030,7 +1053,7 @@ __device__ __forceinline__ void outer_front_body(const Gather& gather, int64_t M
   reg_fft<T, Q, -1>(v);
   if (P2 > 1) {
 #pragma unroll
-    for (int q = 1; q < Q; ++q) v[q] = cmulc(v[q], twb[(a * q) & (M2 - 1)]);
+    for (int q = 1; q < Q; ++q) v[q] = cmulc(v[q], twb[a * q]);  // a q < M2
   }
   const int64_t e1 = e1_0 + el, pair = p0 + pl;
   if (pair < P && e1 < M1) {

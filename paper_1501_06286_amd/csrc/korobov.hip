@@ -412,8 +412,9 @@ int qmc_korobov_create(qmc_korobov_t* out, int64_t K, int64_t s, int phi_kind,
   if (!is_prime_u64((uint64_t)K)) return QMC_ERR_NOT_PRIME;
   std::vector<uint64_t> ones(s, 1);  // the base plan's own generating vector (block b = 1)
   qmc_plan_s* base = nullptr;
+  // the union's kernels take power-of-two outer lengths only
   int rc = plan_create(&base, QMC_RULE_LATTICE, K, s, ones.data(), 0, phi_kind, shift_num,
-                       shift_den, dtype, false, (hipStream_t)stream);
+                       shift_den, dtype, false, false, (hipStream_t)stream);
   if (rc != QMC_OK) return rc;
   qmc_korobov_s* U = new (std::nothrow) qmc_korobov_s();
   if (!U) {

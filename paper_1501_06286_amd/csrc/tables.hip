@@ -262,7 +262,8 @@ __global__ void k_twiddle(cx<double>* W, int64_t M) {
   W[k] = {c, -s};
 }
 
-// one radix-2 Stockham pass of a forward FP64 DFT of length M over global memory
+// one radix-2 Stockham pass of a forward FP64 DFT of length M over global
+// memory (M = 2^k, or 3 x 2^k after one radix-3 pass)
 __global__ void k_fft_r2_pass(const cx<double>* in, cx<double>* out, int64_t M, int64_t Ns,
                               const cx<double>* W) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -273,6 +274,23 @@ __global__ void k_fft_r2_pass(const cx<double>* in, cx<double>* out, int64_t M, 
   const int64_t base = (j / Ns) * 2 * Ns + k;
   out[base] = a0 + a1;
   out[base + Ns] = a0 - a1;
+}
+
+// the radix-3 Stockham pass of a forward FP64 DFT of length M = 3 x 2^k
+// (the first pass, Ns = 1, of those lengths)
+__global__ void k_fft_r3_pass(const cx<double>* in, cx<double>* out, int64_t M, int64_t Ns,
+                              const cx<double>* W) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M / 3) return;
+  const int64_t k = j % Ns, step = M / (3 * Ns);
+  cx<double> a0 = in[j], a1 = in[j + M / 3], a2 = in[j + 2 * (M / 3)];
+  a1 = cmul(a1, W[k * step]);
+  a2 = cmul(a2, W[2 * k * step]);
+  bfly3<double, -1>(a0, a1, a2);
+  const int64_t base = (j / Ns) * 3 * Ns + k;
+  out[base] = a0;
+  out[base + Ns] = a1;
+  out[base + 2 * Ns] = a2;
 }
 
 template <typename T>
@@ -306,7 +324,7 @@ __global__ void k_tw_f1(cx<T>* twf1, const cx<double>* W, int R, int64_t M, int6
   const int Q = R * R;
   if (i >= R * Q) return;
   const int64_t f = i / Q, e = i % Q;
-  twf1[paired_index(f, e, Q, pair_pp(R))] = to_t<T>(W[(e * f * M2) & (M - 1)]);
+  twf1[paired_index(f, e, Q, pair_pp(R))] = to_t<T>(W[(e * f * M2) % M]);
 }
 
 // twf2: thread a, value g: W_{R^2}^{a g} = W_M^{a g M / R^2}
@@ -315,7 +333,7 @@ __global__ void k_tw_f2(cx<T>* twf2, const cx<double>* W, int R, int64_t M) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= R * R) return;
   const int64_t g = i / R, a = i % R;
-  twf2[paired_index(g, a, R, pair_pp(R))] = to_t<T>(W[(a * g * (M / ((int64_t)R * R))) & (M - 1)]);
+  twf2[paired_index(g, a, R, pair_pp(R))] = to_t<T>(W[(a * g * (M / ((int64_t)R * R))) % M]);
 }
 
 // twi3: block w2, thread a + R f, value bb: conj W_M^{e1' (f M2 + w2)} with
@@ -326,7 +344,7 @@ __global__ void k_tw_i3(cx<T>* twi3, const cx<double>* W, int R, int64_t M, int6
   if (i >= M) return;
   const int64_t M1 = M / M2, Q = (int64_t)R * R;
   const int64_t f = i % R, e = (i / R) % Q, w2 = i / M1;
-  const cx<double> w = W[(e * (f * M2 + w2)) & (M - 1)];
+  const cx<double> w = W[(e * (f * M2 + w2)) % M];
   const int64_t a = e % R, bb = e / R;
   twi3[w2 * M1 + paired_index(bb, a + R * f, Q, pair_pp(R))] = to_t<T>({w.x, -w.y});
 }
@@ -337,7 +355,7 @@ __global__ void k_tw_outer(cx<T>* two, const cx<double>* W, int R, int64_t M, in
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= M2 * R) return;
   const int64_t c = i % R, w2 = i / R;
-  const cx<double> w = W[((int64_t)R * R * c * w2) & (M - 1)];
+  const cx<double> w = W[((int64_t)R * R * c * w2) % M];
   two[i] = to_t<T>({w.x, -w.y});
 }
 
@@ -350,7 +368,7 @@ __global__ void k_tw_items(cx<T>* twit, const cx<double>* W, const int32_t* slot
   if (i >= nb * M2 * Upad) return;
   const int64_t u = i % Upad, w2 = (i / Upad) % M2, b = i / (Upad * M2);
   const int32_t k = slot[b * Upad + u];
-  twit[i] = (k < 0) ? cx<T>{(T)0, (T)0} : to_t<T>(W[((int64_t)k * w2) & (M - 1)]);
+  twit[i] = (k < 0) ? cx<T>{(T)0, (T)0} : to_t<T>(W[((int64_t)k * w2) % M]);
 }
 
 // rowmap[e] = pow[e] - 1
@@ -365,7 +383,7 @@ template <typename T>
 __global__ void k_tw_back(cx<T>* twb, const cx<double>* W, int64_t M, int64_t M2) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= M2) return;
-  const cx<double> w = W[(k * (M / M2)) & (M - 1)];
+  const cx<double> w = W[k * (M / M2)];
   twb[k] = to_t<T>({w.x, -w.y});
 }
 
@@ -381,7 +399,7 @@ static inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b -
 // ---------------------------------------------------------------------------
 // layout choice
 // ---------------------------------------------------------------------------
-Layout choose_layout(int64_t L, int dtype, int* embedded) {
+Layout choose_layout(int64_t L, int dtype, int* embedded, bool mixed) {
   Layout lay;
   int64_t M = 1;
   if ((L & (L - 1)) == 0) {
@@ -390,11 +408,18 @@ Layout choose_layout(int64_t L, int dtype, int* embedded) {
   } else {
     while (M < 2 * L - 1) M <<= 1;
     *embedded = 1;
+    // the shortest embedding: 3 x 2^k when it is shorter than the power of
+    // two and its outer length M / 16^3 = 3 x 2^j fits one back pass
+    // (M2 <= the dtype's longest outer radix: no split pass)
+    int64_t M3 = 3;
+    while (M3 < 2 * L - 1) M3 <<= 1;
+    if (mixed && M3 < M && M3 >= 3 * 4096 && M3 / 4096 <= max_outer_q(dtype)) M = M3;
   }
   lay.M = M;
   const int rmax = 16;
+  const int64_t M_2 = M % 3 == 0 ? M / 3 : M;  // the power-of-two part of M
   int R = 1;
-  while (2 * R <= rmax && (int64_t)(2 * R) * (2 * R) * (2 * R) <= M) R *= 2;
+  while (2 * R <= rmax && (int64_t)(2 * R) * (2 * R) * (2 * R) <= M_2) R *= 2;
   lay.R = R;
   lay.M1 = (int64_t)R * R * R;
   lay.M2 = M / lay.M1;
@@ -405,19 +430,27 @@ Layout choose_layout(int64_t L, int dtype, int* embedded) {
 
 int set_outer_split(Layout& lay, int q, int qmax) {
   // The outer inverse DFT of the back pass takes Q2 values of w2 per output
-  // column and the split pass P2 = M2 / Q2 (at most 64).  Q2 <= 32 stays in
-  // registers (32: occupancy 3), 64 and 128 go through LDS (qmax: what the
-  // LDS tile of the dtype allows).  The default q = 0 takes the whole of M2
-  // when it fits one back pass (M2 <= qmax: no split pass; the LDS back pass
-  // costs less than a split pass plus a register back pass), else 32, more
-  // only when M2 > 32 * 64 (with a split pass anyway, the register back pass
-  // is the faster one).  The dense fronts' forward split keeps at most 64
-  // values per thread in registers: Qf = min(Q2, 64).
-  if (q < 0 || q > qmax || (q & (q - 1))) return QMC_ERR_ARG;
+  // column and the split pass P2 = M2 / Q2 (a power of two, at most 64).
+  // Q2 <= 32 stays in registers (32: occupancy 3), 48 and more go through LDS
+  // (qmax: what the LDS tile of the dtype allows).  The default q = 0 takes
+  // the whole of M2 when it fits one back pass (M2 <= qmax: no split pass;
+  // the LDS back pass costs less than a split pass plus a register back
+  // pass), else 32, more only when M2 > 32 * 64 (with a split pass anyway,
+  // the register back pass is the faster one).  The dense fronts' forward
+  // split keeps at most 64 values per thread in registers: Qf = Q2 up to 64,
+  // else Q2 / 2.  For M2 = 3 x 2^j the factor 3 stays in Q2 and Qf (a
+  // radix-3 stage of their register DFTs): q must then be 3 x 2^i.
+  auto radix_ok = [](int64_t v) {
+    const int64_t p = v % 3 == 0 ? v / 3 : v;
+    return v >= 1 && (p & (p - 1)) == 0;
+  };
+  if (q < 0 || q > qmax || (q > 0 && !radix_ok(q))) return QMC_ERR_ARG;
   const int64_t qdef = lay.M2 <= qmax ? lay.M2 : std::max<int64_t>(32, lay.M2 / 64);
   const int64_t Q2 = std::min<int64_t>(q > 0 ? q : qdef, lay.M2);
-  if (Q2 > qmax || lay.M2 / Q2 > 64) return QMC_ERR_ARG;
-  const int64_t Qf = std::min<int64_t>(Q2, 64);
+  if (Q2 > qmax || lay.M2 % Q2 != 0) return QMC_ERR_ARG;
+  const int64_t P2 = lay.M2 / Q2;
+  if (P2 > 64 || (P2 & (P2 - 1))) return QMC_ERR_ARG;  // also: 3 | M2 needs 3 | Q2
+  const int64_t Qf = Q2 <= 64 ? Q2 : Q2 / 2;
   if (lay.M2 / Qf > 64) return QMC_ERR_ARG;
   lay.Q2 = (int)Q2;
   lay.P2 = (int)(lay.M2 / Q2);
@@ -641,7 +674,13 @@ int build_conv_tables(qmc_plan_s* P, const int32_t* ell, const int32_t* d_zidx,
     k_twiddle<<<nblk(M), 256, 0, st>>>(dW, M);
     k_generator<<<nblk(M), 256, 0, st>>>(dA, d_zidx, d_tphi, L, M);
     cx<double>*src = dA, *dst = dB;
-    for (int64_t Ns = 1; Ns < M; Ns *= 2) {
+    int64_t Ns = 1;
+    if (M % 3 == 0) {  // M = 3 x 2^k: the radix-3 pass first
+      k_fft_r3_pass<<<nblk(M / 3), 256, 0, st>>>(src, dst, M, Ns, dW);
+      std::swap(src, dst);
+      Ns = 3;
+    }
+    for (; Ns < M; Ns *= 2) {
       k_fft_r2_pass<<<nblk(M / 2), 256, 0, st>>>(src, dst, M, Ns, dW);
       std::swap(src, dst);
     }
@@ -688,7 +727,7 @@ int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st) {
     }
     P->beta = (P->m == 1) ? 1 : 2;
   }
-  P->lay = choose_layout(L, P->dtype, &P->embedded);
+  P->lay = choose_layout(L, P->dtype, &P->embedded, P->mixed_outer);
   const Layout& lay = P->lay;
   if (lay.P2 < 1) return QMC_ERR_UNSUPPORTED;  // outer length beyond the longest split
 

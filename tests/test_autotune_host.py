@@ -32,3 +32,25 @@ def test_outer_radices_keep_the_register_back_with_a_split():
     assert autotune.outer_radices(16, 128) == [0]
     # C5-like M2 = 512: a split is needed whatever the radix
     assert autotune.outer_radices(512, 128) == [0, 16, 64, 128]
+
+
+def test_outer_radices_of_mixed_lengths():
+    # M2 = 3 x 2^j: the factor 3 stays in the back pass, P2 = M2 / q a power
+    # of two; the default (all of M2 up to the dtype's limit) is not repeated
+    for qmax in (64, 128):
+        for j in range(0, 6):
+            M2 = 3 << j
+            qs = autotune.outer_radices(M2, qmax)
+            assert qs[0] == 0 and len(set(qs)) == len(qs)
+            for q in qs[1:]:
+                assert q % 3 == 0 and M2 % q == 0 and (M2 // q) & (M2 // q - 1) == 0
+                assert q <= qmax and q < M2 and M2 // q <= 64
+    assert autotune.outer_radices(96, 128) == [0, 12, 24, 48]
+    assert autotune.outer_radices(48, 64) == [0, 12, 24]
+    assert autotune.outer_radices(12, 128) == [0]
+
+
+def test_bucket_twiddles_only_for_power_of_two_outer_lengths():
+    fronts = lambda M2: {c["front"] for c in autotune.candidates(64, M2, 128)}
+    assert fronts(64) == {1, 2, 3}
+    assert fronts(96) == {1, 2}

@@ -49,7 +49,7 @@ def test_batch_lds_back(dtype):
     register-back products: each matches the oracle and its single product."""
     torch = torch_cuda()
     import paper_1501_06286_amd as q
-    N = 139999
+    N = 200003
     insts = [qi.small_lattice(N, 100, t, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype,
                               seed=20 + t) for t in (3, 19, 1)]
     insts.append(qi.small_lattice(8209, 300, 9, phi=qi.PHI_INVNORM, shift=(1, 16418),
@@ -102,7 +102,7 @@ def test_batch_epilogue(epi, dtype):
     torch = torch_cuda()
     import paper_1501_06286_amd as q
     insts = _instances(dtype, seed=21)
-    N = 139999
+    N = 200003
     insts.append(qi.small_lattice(N, 100, 19, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype,
                                   seed=22))
     announce(f"batch epilogue {epi} {dtype}")

@@ -33,7 +33,7 @@ CASES = [  # (kind, N or m, s, t, tuning)
     ("lattice", 8209, 400, 33, {"chunk_pairs": 4, "streams": 2}),
     ("lattice", 139999, 100, 6, {"front": 2}),
     ("lattice", 65537, 300, 4, {"front": 2, "chunk_pairs": 1}),
-    ("lattice", 139999, 100, 19, {"outer_q": 64}),  # the LDS back pass, ragged pair tile
+    ("lattice", 200003, 100, 19, {"outer_q": 64}),  # the LDS back pass, ragged pair tile
     ("gf2", 12, 500, 5, {}),
 ]
 

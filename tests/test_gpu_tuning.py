@@ -118,7 +118,7 @@ def test_outer_radix(q, front, dtype):
     holds the outer factor in LDS (128: FP32 only, and FP32's default)."""
     torch = torch_cuda()
     import paper_1501_06286_amd as q_
-    inst = qi.small_lattice(139999, 100, 5, phi=qi.PHI_INVNORM, shift=(1, 279998), dtype=dtype,
+    inst = qi.small_lattice(200003, 100, 5, phi=qi.PHI_INVNORM, shift=(1, 400006), dtype=dtype,
                             seed=9)
     announce(f"outer radix q={q} front={front} {dtype}")
     p = plan_of(inst)
@@ -144,15 +144,15 @@ def test_outer_radix(q, front, dtype):
 def test_outer_radix_rejects_bad_values():
     torch_cuda()
     import paper_1501_06286_amd as q
-    p = plan_of(qi.small_lattice(139999, 20, 2))  # M2 = 128
-    for bad in (3, 256, 1, -2):  # not a power of two, above 128, P2 = 128 > 64, negative
+    p = plan_of(qi.small_lattice(200003, 20, 2))  # M2 = 128
+    for bad in (3, 256, 1, -2):  # a factor 3 that M2 lacks, above 128, P2 = 128 > 64, negative
         with pytest.raises(q.QMCError):
             p.set_tuning(outer_q=bad)
     assert p.info()["Q2"] == 32  # FP64 default, unchanged by the rejected calls
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-@pytest.mark.parametrize("N", [100003, 139999])
+@pytest.mark.parametrize("N", [100003, 200003])
 def test_default_outer_split(N, dtype):
     """The default split: one back pass over all of M2 when it fits (M2 = 64:
     both dtypes; M2 = 128: FP32), else Q2 = 32 after a split pass (FP64 at
@@ -187,7 +187,7 @@ def test_lds_back_tiles(q, t, dtype):
     import paper_1501_06286_amd as q_
     if q == 128 and dtype == "f64":
         pytest.skip("Q2 = 128 is FP32 only (rejected for FP64 in test_outer_radix)")
-    N = 139999
+    N = 200003
     inst = qi.small_lattice(N, 60, t, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype, seed=4)
     announce(f"lds back q={q} t={t} {dtype}")
     p = plan_of(inst)

@@ -63,7 +63,7 @@ def test_noalloc_two_stream_tuning_runs_on_one_stream():
 
 def test_noalloc_dense_front_embedded_f64():
     # N - 1 not a power of two (embedded convolution), dense outer front, FP64
-    N = 139999
+    N = 200003
     inst = qi.small_lattice(N, 300, 6, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype="f64",
                             seed=5)
     _pair_of_calls(inst, "f64", 3, {"front": 2})
