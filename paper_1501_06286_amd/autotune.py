@@ -131,6 +131,21 @@ def time_config(plan, A, X, cfg: Dict[str, int], reps: int = 3) -> float:
     return e0.elapsed_time(e1) / reps
 
 
+def refine(plan, A, X, results, reps: int, top: int = 4, rounds: int = 5) -> Dict[str, int]:
+    """The first sweep's few fastest tunings (often within a few percent of
+    each other) timed again in turns, several rounds: the one with the least
+    median time, so that the choice does not follow one noisy sample."""
+    order = sorted(results, key=lambda r: r[1])[:top]
+    if len(order) < 2:
+        return order[0][0]
+    times = [[] for _ in order]
+    for _ in range(rounds):
+        for i, (cfg, _) in enumerate(order):
+            times[i].append(time_config(plan, A, X, cfg, reps))
+    med = [sorted(ts)[len(ts) // 2] for ts in times]
+    return order[min(range(len(order)), key=lambda i: med[i])][0]
+
+
 def tune(plan, t: int, reps: int = 3, use_cache: bool = True,
          cands: Optional[List[Dict[str, int]]] = None) -> Tuple[Dict[str, int], List]:
     """Pick and set the fastest tuning for (plan, t).  Returns (best, timings)."""
@@ -146,7 +161,7 @@ def tune(plan, t: int, reps: int = 3, use_cache: bool = True,
     results = []
     for cfg in (cands or candidates((t + 1) // 2, plan.info()["M2"], qmax_of(plan))):
         results.append((cfg, time_config(plan, A, X, cfg, reps)))
-    best = min(results, key=lambda r: r[1])[0]
+    best = refine(plan, A, X, results, reps)
     plan.set_tuning(**best)
     if use_cache:
         cache = _load()

@@ -56,6 +56,17 @@ __attribute__((amdgpu_waves_per_eu(mid_waves<T, R>()))) void k_middle(
                                  threadIdx.x, nt_c != 0, it_e2, twb);
 }
 
+template <typename T, int R, bool SPARSE>
+__global__ __launch_bounds__(MidShape<R>::BLOCK)
+__attribute__((amdgpu_waves_per_eu(mid_sum_waves<T, R>()))) void k_middle_sum(
+    const MidTerms<T> terms, const cx<T>* __restrict__ twf1, const cx<T>* __restrict__ twf2,
+    const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M2, int64_t P,
+    cx<T>* __restrict__ C, int nt_c) {
+  __shared__ MidSmem<T, R> S;
+  middle_sum_body<T, R, SPARSE>(terms, twf1, twf2, twi3, two, M2, P, C,
+                                xcd_remap(blockIdx.x, gridDim.x), S, threadIdx.x, nt_c != 0);
+}
+
 template <typename T, int P2, int DIR>
 __global__ __launch_bounds__(64) void k_outer_split(cx<T>* __restrict__ C, int64_t M1, int64_t M2,
                                                     int Q2, const cx<T>* __restrict__ twb) {
@@ -510,6 +521,197 @@ int launch_adjoint(const qmc_plan_s* P, const void* G, int64_t t, int64_t ldg, v
   if (P->dtype == QMC_F32)
     return adjoint_t<float>(P, (const float*)G, t, ldg, (float*)dA, ldda, ws, st, acc);
   return adjoint_t<double>(P, (const double*)G, t, ldg, (double*)dA, ldda, ws, st, acc);
+}
+
+}  // namespace qmc
+
+namespace qmc {
+// ---------------------------------------------------------------------------
+// sums of blocks (lattice rules with non-prime N)
+// ---------------------------------------------------------------------------
+template <typename T, int R, bool SPARSE>
+static void launch_middle_sum_r(const qmc_plan_s* P0, const MidTerms<T>& terms, int64_t pairs,
+                                cx<T>* C, int slot, hipStream_t st) {
+  const Layout& lay = P0->lay;
+  typedef MidShape<R> S;
+  const int64_t G = ((pairs + S::TPB - 1) / S::TPB) * lay.M2;
+  ProfScope ps(P0, slot, st);
+  const int ntc = nt_inter(P0, pairs * lay.M * (int64_t)sizeof(cx<T>)) ? 1 : 0;
+  k_middle_sum<T, R, SPARSE><<<dim3((unsigned)G), dim3(S::BLOCK), 0, st>>>(
+      terms, (const cx<T>*)P0->d_twf1, (const cx<T>*)P0->d_twf2, (const cx<T>*)P0->d_twi3,
+      (const cx<T>*)P0->d_two, lay.M2, pairs, C, ntc);
+}
+
+// src[k]: term k's input (SPARSE: its aT; dense: its B) for these pairs
+template <typename T, bool SPARSE>
+static int launch_middle_sum(const qmc_plan_s* const* blk, int n, cx<T>* const* src,
+                             int64_t pairs, cx<T>* C, int slot, hipStream_t st) {
+  MidTerms<T> terms{};
+  terms.n = n;
+  for (int k = 0; k < n; ++k)
+    terms.t[k] = {src[k], blk[k]->d_it_e1, (const cx<T>*)blk[k]->d_twit,
+                  (const cx<T>*)blk[k]->d_Hs, blk[k]->Upad, blk[k]->rounds};
+  switch (blk[0]->lay.R) {
+    case 1: launch_middle_sum_r<T, 1, SPARSE>(blk[0], terms, pairs, C, slot, st); break;
+    case 2: launch_middle_sum_r<T, 2, SPARSE>(blk[0], terms, pairs, C, slot, st); break;
+    case 4: launch_middle_sum_r<T, 4, SPARSE>(blk[0], terms, pairs, C, slot, st); break;
+    case 8: launch_middle_sum_r<T, 8, SPARSE>(blk[0], terms, pairs, C, slot, st); break;
+    case 16: launch_middle_sum_r<T, 16, SPARSE>(blk[0], terms, pairs, C, slot, st); break;
+    default: return QMC_ERR_UNSUPPORTED;
+  }
+  return hip_ok(hipGetLastError());
+}
+
+static bool sum_ok(const qmc_plan_s* const* blk, int n) {
+  if (n < 1 || n > MID_MAX_TERMS) return false;
+  for (int k = 1; k < n; ++k) {
+    const Layout &a = blk[0]->lay, &b = blk[k]->lay;
+    if (a.M != b.M || a.M2 != b.M2 || a.R != b.R || blk[k]->dtype != blk[0]->dtype) return false;
+  }
+  return true;
+}
+
+static int64_t sum_chunk(const qmc_plan_s* P0, int64_t pairs) {
+  return (P0->tune.chunk_pairs > 0 && P0->tune.chunk_pairs < pairs) ? P0->tune.chunk_pairs
+                                                                     : pairs;
+}
+
+size_t collapse_bytes(const qmc_plan_s* B, int64_t t) {
+  const size_t el = (B->dtype == QMC_F32) ? sizeof(cx<float>) : sizeof(cx<double>);
+  return align256(((t + 1) / 2) * B->Upad * el);
+}
+
+size_t sum_workspace_bytes(const qmc_plan_s* const* blk, int n, int64_t t, bool adjoint,
+                           bool collapsed) {
+  const size_t el = (blk[0]->dtype == QMC_F32) ? sizeof(cx<float>) : sizeof(cx<double>);
+  const int64_t pairs = (t + 1) / 2, chunk = sum_chunk(blk[0], pairs);
+  const size_t slab = align256(chunk * blk[0]->lay.M * el);  // one B or C of a chunk
+  if (adjoint || dense_front(blk[0])) return (size_t)(n + 1) * slab;
+  size_t w = slab;
+  if (!collapsed)
+    for (int k = 0; k < n; ++k) w += collapse_bytes(blk[k], t);
+  return w;
+}
+
+int launch_collapse(const qmc_plan_s* B, const void* A, int64_t t, int64_t lda, void* aT,
+                    hipStream_t st) {
+  const int64_t pairs = (t + 1) / 2;
+  dim3 gT((unsigned)((B->Upad + 63) / 64), (unsigned)((pairs + 15) / 16));
+  ProfScope ps(B, PROF_COLLAPSE, st);
+  if (B->dtype == QMC_F32)
+    k_collapse_T<float><<<gT, 256, 0, st>>>((const float*)A, lda, t, pairs, B->d_it_ptr,
+                                            B->d_it_jl, B->Upad, (cx<float>*)aT);
+  else
+    k_collapse_T<double><<<gT, 256, 0, st>>>((const double*)A, lda, t, pairs, B->d_it_ptr,
+                                             B->d_it_jl, B->Upad, (cx<double>*)aT);
+  return hip_ok(hipGetLastError());
+}
+
+// X rows of the blocks' common row coset = sum_k Y_k A: every term's
+// collapse (sparse fronts) or outer front (dense), one fused pass that sums
+// the spectral products, the split and one back pass that writes the rows
+// collapsed[k] (sparse fronts only, may be null): term k's collapse of A,
+// made by the caller (blocks of several row cosets share it)
+template <typename T>
+static int forward_sum_t(const qmc_plan_s* const* blk, int n, const T* A, int64_t t, int64_t lda,
+                         T* X, int64_t ldx, void* ws, hipStream_t st,
+                         void* const* collapsed) {
+  const qmc_plan_s* P0 = blk[0];
+  const int64_t pairs = (t + 1) / 2, chunk = sum_chunk(P0, pairs);
+  const size_t el = sizeof(cx<T>);
+  const size_t slab = align256(chunk * P0->lay.M * el);
+  const bool dense = dense_front(P0);
+  if (dense) collapsed = nullptr;
+  cx<T>* in[MID_MAX_TERMS];
+  char* p = (char*)ws;
+  for (int k = 0; k < n; ++k) {
+    if (collapsed) {
+      in[k] = (cx<T>*)collapsed[k];
+    } else {
+      in[k] = (cx<T>*)p;
+      p += dense ? slab : align256(pairs * blk[k]->Upad * el);
+    }
+  }
+  cx<T>* C = (cx<T>*)p;
+  int rc = QMC_OK;
+  if (!dense && !collapsed)
+    for (int k = 0; k < n && rc == QMC_OK; ++k) rc = launch_collapse(blk[k], A, t, lda, in[k], st);
+  for (int64_t p0 = 0; p0 < pairs && rc == QMC_OK; p0 += chunk) {
+    const int64_t np = std::min(chunk, pairs - p0), tc = t - 2 * p0;
+    cx<T>* src[MID_MAX_TERMS];
+    for (int k = 0; k < n && rc == QMC_OK; ++k) {
+      if (dense) {
+        rc = launch_outer_front<T>(blk[k], A + 2 * p0, nullptr, lda, tc, np, in[k], st);
+        src[k] = in[k];
+      } else {
+        src[k] = in[k] + p0 * blk[k]->Upad;
+      }
+    }
+    if (rc == QMC_OK)
+      rc = dense ? launch_middle_sum<T, false>(blk, n, src, np, C, PROF_MIDDLE, st)
+                 : launch_middle_sum<T, true>(blk, n, src, np, C, PROF_MIDDLE, st);
+    if (rc == QMC_OK) rc = launch_split<T, +1>(P0, C, np, PROF_SPLIT, st);
+    if (rc == QMC_OK) rc = back_dispatch<T>(P0, C, np, X + 2 * p0, ldx, tc, st, Epi<T>());
+  }
+  return rc;
+}
+
+// the adjoint of an orbit's blocks blk[r * ncol + c] (row coset r, column
+// coset c), per chunk of column pairs: the outer front of G on every row
+// coset once, then per column coset the sum over its row cosets' products
+template <typename T>
+static int adjoint_grid_t(const qmc_plan_s* const* blk, int nrow, int ncol, const T* G,
+                          int64_t t, int64_t ldg, T* dA, int64_t ldda, void* ws,
+                          hipStream_t st) {
+  const qmc_plan_s* P0 = blk[0];
+  const int64_t pairs = (t + 1) / 2, chunk = sum_chunk(P0, pairs);
+  const size_t slab = align256(chunk * P0->lay.M * sizeof(cx<T>));
+  cx<T>* Br[MID_MAX_TERMS];
+  for (int r = 0; r < nrow; ++r) Br[r] = (cx<T>*)((char*)ws + r * slab);
+  cx<T>* C = (cx<T>*)((char*)ws + nrow * slab);
+  const Epi<T> acc{EPI_ACC, nullptr, nullptr};
+  int rc = QMC_OK;
+  for (int64_t p0 = 0; p0 < pairs && rc == QMC_OK; p0 += chunk) {
+    const int64_t np = std::min(chunk, pairs - p0), tc = t - 2 * p0;
+    for (int r = 0; r < nrow && rc == QMC_OK; ++r)
+      rc = launch_outer_front<T>(blk[r * ncol], nullptr, G + 2 * p0, ldg, tc, np, Br[r], st);
+    for (int c = 0; c < ncol && rc == QMC_OK; ++c) {
+      const qmc_plan_s* terms[MID_MAX_TERMS];
+      for (int r = 0; r < nrow; ++r) terms[r] = blk[r * ncol + c];
+      rc = launch_middle_sum<T, false>(terms, nrow, Br, np, C, PROF_ADJ_MIDDLE, st);
+      if (rc == QMC_OK) rc = launch_split<T, +1>(terms[0], C, np, PROF_SPLIT, st);
+      if (rc == QMC_OK)
+        rc = launch_back<T, true>(terms[0], C, np, terms[0]->d_inv_ptr, terms[0]->d_inv_j,
+                                  G + 2 * p0, dA + 2 * p0, ldda, tc, st, acc);
+    }
+  }
+  return rc;
+}
+
+int launch_adjoint_grid(const qmc_plan_s* const* blk, int nrow, int ncol, const void* G,
+                        int64_t t, int64_t ldg, void* dA, int64_t ldda, void* ws,
+                        hipStream_t st) {
+  if (nrow < 1 || ncol < 1 || nrow > MID_MAX_TERMS) return QMC_ERR_UNSUPPORTED;
+  for (int i = 1; i < nrow * ncol; ++i) {  // one layout for all
+    const qmc_plan_s* two[2] = {blk[0], blk[i]};
+    if (!sum_ok(two, 2)) return QMC_ERR_UNSUPPORTED;
+  }
+  if (blk[0]->dtype == QMC_F32)
+    return adjoint_grid_t<float>(blk, nrow, ncol, (const float*)G, t, ldg, (float*)dA, ldda, ws,
+                                 st);
+  return adjoint_grid_t<double>(blk, nrow, ncol, (const double*)G, t, ldg, (double*)dA, ldda,
+                                ws, st);
+}
+
+int launch_forward_sum(const qmc_plan_s* const* blk, int n, const void* A, int64_t t,
+                       int64_t lda, void* X, int64_t ldx, void* ws, hipStream_t st,
+                       void* const* collapsed) {
+  if (!sum_ok(blk, n)) return QMC_ERR_UNSUPPORTED;
+  if (blk[0]->dtype == QMC_F32)
+    return forward_sum_t<float>(blk, n, (const float*)A, t, lda, (float*)X, ldx, ws, st,
+                                collapsed);
+  return forward_sum_t<double>(blk, n, (const double*)A, t, lda, (double*)X, ldx, ws, st,
+                               collapsed);
 }
 
 }  // namespace qmc

@@ -180,6 +180,25 @@ int launch_forward(const qmc_plan_s* P, const void* A, int64_t t, int64_t lda, v
 // acc: dA += Y^T G (the blocks of a lattice rule with non-prime N add up)
 int launch_adjoint(const qmc_plan_s* P, const void* G, int64_t t, int64_t ldg, void* dA,
                    int64_t ldda, void* ws, hipStream_t st, bool acc = false);
+// sums of n <= MID_MAX_TERMS blocks with one layout (the blocks of a lattice
+// rule with non-prime N) that share their output rows: X rows written
+// (collapsed: the terms' collapses of A when the caller made them, sparse
+// fronts only; else null)
+int launch_forward_sum(const qmc_plan_s* const* blk, int n, const void* A, int64_t t,
+                       int64_t lda, void* X, int64_t ldx, void* ws, hipStream_t st,
+                       void* const* collapsed = nullptr);
+size_t sum_workspace_bytes(const qmc_plan_s* const* blk, int n, int64_t t, bool adjoint,
+                           bool collapsed = false);
+// the adjoint of an orbit's blocks blk[r * ncol + c] (row coset r <
+// MID_MAX_TERMS, column coset c): G's outer front once per row coset, a sum
+// per column coset; workspace (nrow + 1) chunk x M values
+int launch_adjoint_grid(const qmc_plan_s* const* blk, int nrow, int ncol, const void* G,
+                        int64_t t, int64_t ldg, void* dA, int64_t ldda, void* ws,
+                        hipStream_t st);
+// the collapse of A on a plan's schedule (pairs x Upad values) and its size
+int launch_collapse(const qmc_plan_s* B, const void* A, int64_t t, int64_t lda, void* aT,
+                    hipStream_t st);
+size_t collapse_bytes(const qmc_plan_s* B, int64_t t);
 
 // dense.hip
 int launch_explicit_points(const qmc_plan_s* P, void* Y, int64_t ldy, hipStream_t st);

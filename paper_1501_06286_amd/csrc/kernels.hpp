@@ -496,6 +496,207 @@ __device__ __forceinline__ void middle_body(
 }
 
 // ---------------------------------------------------------------------------
+// F for a sum of circulant products that share the output rows (the blocks
+// of one row coset of a lattice rule with non-prime N, forward; or of one
+// column coset, adjoint): sum_k H(z_k) a_k = IDFT(sum_k Zhat_k DFT(a_k)).
+// Each term's input goes through the front and the forward steps of
+// middle_body, its spectral product is accumulated in registers, and one
+// inverse transform follows: the inverse steps and the intermediate's
+// stores are paid once instead of once per term.  Item twiddles only (no
+// bucket twiddles), no DC term (the blocks hold no row 0).
+// ---------------------------------------------------------------------------
+template <typename T>
+struct MidTerm {
+  const cx<T>* src;        // SPARSE: aT [pair][Upad]; dense: B [pair][M2][M1]
+  const uint16_t* it_e1;   // SPARSE: the term's schedule
+  const cx<T>* twit;       // SPARSE: item twiddles [M2][Upad]
+  const cx<T>* Hs;         // the term's spectrum / M (per-thread layout)
+  int64_t Upad, rounds;
+};
+constexpr int MID_MAX_TERMS = 8;
+template <typename T>
+struct MidTerms {
+  MidTerm<T> t[MID_MAX_TERMS];
+  int n;
+};
+
+// waves per SIMD the sum kernel is compiled for: the accumulated products
+// take R more complex registers than middle_body, so FP32 at R = 16 gets three
+// waves' budget (170 registers) instead of four
+template <typename T, int R>
+constexpr int mid_sum_waves() {
+  return (sizeof(T) == 4 && R == 16) ? 3 : mid_waves<T, R>();
+}
+
+template <typename T, int R, bool SPARSE>
+__device__ __forceinline__ void middle_sum_body(
+    const MidTerms<T>& terms, const cx<T>* __restrict__ twf1, const cx<T>* __restrict__ twf2,
+    const cx<T>* __restrict__ twi3, const cx<T>* __restrict__ two, int64_t M2, int64_t P,
+    cx<T>* __restrict__ C, int64_t b, MidSmem<T, R>& SM, int tid, bool nt_c) {
+  typedef MidShape<R> S;
+  constexpr int Q = S::Q, M1 = R * R * R, PB = R * (R + 1);
+  cx<T>* lds = SM.lds;
+  int64_t w2, pg;
+  if ((M2 & (M2 - 1)) == 0) {
+    w2 = b & (M2 - 1);
+    pg = b >> __builtin_ctzll((unsigned long long)M2);
+  } else {
+    pg = (int64_t)((uint32_t)b / (uint32_t)M2);
+    w2 = b - pg * M2;
+  }
+  const int tr = tid / Q, q = tid % Q;
+  const int64_t pair = pg * S::TPB + tr;
+  const bool active = pair < P;
+  cx<T>* buf = lds + tr * S::BUFN;
+  const cx<T> zero = {(T)0, (T)0};
+  cx<T> x[R], acc[R], tw_a[R], tw_b[R], hv[R];
+  for (int i = tid; i < R * R; i += S::BLOCK)
+    SM.wr2[(i % R) * (R + 1) + i / R] = twf2[paired_index(i / R, i % R, R, pair_pp(R))];
+  const int gl = q % R;
+  cx<T>* grp = buf + (q / R) * PB;
+  const cx<T>* wrow = SM.wr2 + gl * (R + 1);
+  // The tables are loaded where they are used (not ahead as in middle_body):
+  // the accumulated products hold R more complex registers.
+  const int nt = terms.n;
+  for (int k = 0; k < nt; ++k) {
+    const MidTerm<T> tm = terms.t[k];
+    if (k > 0) __syncthreads();  // the previous term's exchanges have left buf
+    if constexpr (SPARSE) {
+      for (int i = q; i <= M1; i += Q) buf[i] = zero;
+      __syncthreads();
+      const int fo = q / S::G, ln = q % S::G;
+      const cx<T>* av = tm.src + (active ? pair : 0) * tm.Upad;
+      const cx<T>* tw = tm.twit + w2 * tm.Upad;
+      const int nr = (int)tm.rounds;
+      int cur = M1;
+      cx<T> sum = zero;
+      constexpr int PP = pair_pp(R);
+      auto rounds_from = [&](int r0, auto nb) {
+        constexpr int NB = decltype(nb)::value;
+        int e1[NB];
+        cx<T> v[NB], w[NB];
+#pragma unroll
+        for (int i = 0; i < NB; i += PP) {
+          const int u = (((r0 + i) / PP * S::F + fo) * S::G + ln) * PP;
+          if constexpr (PP == 2) {
+            const uint32_t ee = *reinterpret_cast<const uint32_t*>(tm.it_e1 + u);
+            const cx2<T> vv = *reinterpret_cast<const cx2<T>*>(av + u);
+            const cx2<T> ww = *reinterpret_cast<const cx2<T>*>(tw + u);
+            e1[i] = (int)(ee & 0xffffu);
+            e1[i + 1] = (int)(ee >> 16);
+            v[i] = vv.a;
+            v[i + 1] = vv.b;
+            w[i] = ww.a;
+            w[i + 1] = ww.b;
+          } else {
+            e1[i] = tm.it_e1[u];
+            v[i] = av[u];
+            w[i] = tw[u];
+          }
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const cx<T> c = cmul(v[i], w[i]);
+          if (e1[i] != cur) {
+            buf[cur] = sum;
+            cur = e1[i];
+            sum = c;
+          } else {
+            sum = sum + c;
+          }
+        }
+      };
+      int r0 = 0;
+      for (; r0 + MID_RB <= nr; r0 += MID_RB)
+        rounds_from(r0, std::integral_constant<int, MID_RB>{});
+      for (; r0 < nr; r0 += PP) rounds_from(r0, std::integral_constant<int, PP>{});
+      buf[cur] = sum;
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < R; ++c) x[c] = buf[q + Q * c];
+    } else {
+      const cx<T>* bv = tm.src + ((active ? pair : 0) * M2 + w2) * M1;
+      // conj W_M^{q w2}: the long outer twiddle of column e1 = q + Q c
+      const cx<T> tq = twi3[w2 * M1 + paired_index(q / R, q % R, Q, pair_pp(R))];
+#pragma unroll
+      for (int c = 0; c < R; ++c) {
+        cx<T> v = active ? bv[q + Q * c] : zero;
+        v = cmulc(v, tq);
+        if (c > 0) v = cmulc(v, two[w2 * R + c]);
+        x[c] = v;
+      }
+    }
+    // ---- forward steps 1-3, as middle_body ----------------------------------
+    load_paired<T, R>(tw_a, twf1, q, Q);
+    reg_fft<T, R, -1>(x);
+#pragma unroll
+    for (int f = 1; f < R; ++f) x[f] = cmul(x[f], tw_a[f]);
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < R; ++f) buf[f * PB + q] = x[f];
+    __syncthreads();
+#pragma unroll
+    for (int bb = 0; bb < R; ++bb) x[bb] = grp[gl + R * bb];
+    reg_fft<T, R, -1>(x);
+#pragma unroll
+    for (int g = 1; g < R; ++g) x[g] = cmul(x[g], wrow[g]);
+    wave_lds_sync();
+#pragma unroll
+    for (int g = 0; g < R; ++g) grp[g * (R + 1) + gl] = x[g];
+    wave_lds_sync();
+#pragma unroll
+    for (int a = 0; a < R; ++a) x[a] = grp[gl * (R + 1) + a];
+    reg_fft<T, R, -1>(x);
+    // ---- this term's spectral product, accumulated ---------------------------
+    load_paired<T, R>(hv, tm.Hs + w2 * M1, q, Q);
+#pragma unroll
+    for (int h = 0; h < R; ++h) {
+      const cx<T> p = cmul(x[h], hv[h]);
+      acc[h] = k == 0 ? p : acc[h] + p;
+    }
+  }
+  // ---- inverse steps and the stores of C, as middle_body ----------------------
+#pragma unroll
+  for (int h = 0; h < R; ++h) x[h] = acc[h];
+  reg_fft<T, R, +1>(x);
+#pragma unroll
+  for (int a = 1; a < R; ++a) x[a] = cmulc(x[a], wrow[a]);
+  wave_lds_sync();
+#pragma unroll
+  for (int a = 0; a < R; ++a) grp[a * (R + 1) + gl] = x[a];
+  wave_lds_sync();
+#pragma unroll
+  for (int g = 0; g < R; ++g) x[g] = grp[gl * (R + 1) + g];
+  reg_fft<T, R, +1>(x);
+  load_paired<T, R>(tw_b, twi3 + w2 * M1, q, Q);
+#pragma unroll
+  for (int bb = 0; bb < R; ++bb) x[bb] = cmul(x[bb], tw_b[bb]);
+#pragma unroll
+  for (int c = 1; c < R; ++c) tw_a[c] = two[w2 * R + c];
+  __syncthreads();
+#pragma unroll
+  for (int bb = 0; bb < R; ++bb) buf[(gl + R * bb) * (R + 1) + q / R] = x[bb];
+  __syncthreads();
+#pragma unroll
+  for (int f = 0; f < R; ++f) x[f] = buf[q * (R + 1) + f];
+  reg_fft<T, R, +1>(x);
+#pragma unroll
+  for (int c = 1; c < R; ++c) x[c] = cmul(x[c], tw_a[c]);
+  if (active) {
+    cx<T>* cp = C + (pair * M2 + w2) * M1;
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      if (nt_c) {
+        const vec2_t<T> w = {x[c].x, x[c].y};
+        __builtin_nontemporal_store(w, reinterpret_cast<vec2_t<T>*>(cp + q + Q * c));
+      } else {
+        cp[q + Q * c] = x[c];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // outer split (only when the tuning splits M2 = P2 * Q2 with P2 > 1), in place
 // on C[pair][w2][e1]:
 //   DIR = +1 (forward product, first half of the inverse over w2):
