@@ -558,6 +558,9 @@ __device__ __forceinline__ void middle_sum_body(
   // The tables are loaded where they are used (not ahead as in middle_body):
   // the accumulated products hold R more complex registers.
   const int nt = terms.n;
+#pragma unroll
+  for (int h = 0; h < R; ++h) acc[h] = zero;
+#pragma unroll 1
   for (int k = 0; k < nt; ++k) {
     const MidTerm<T> tm = terms.t[k];
     if (k > 0) __syncthreads();  // the previous term's exchanges have left buf
@@ -651,8 +654,8 @@ __device__ __forceinline__ void middle_sum_body(
     load_paired<T, R>(hv, tm.Hs + w2 * M1, q, Q);
 #pragma unroll
     for (int h = 0; h < R; ++h) {
-      const cx<T> p = cmul(x[h], hv[h]);
-      acc[h] = k == 0 ? p : acc[h] + p;
+      acc[h].x = fmaT(x[h].x, hv[h].x, fmaT(-x[h].y, hv[h].y, acc[h].x));
+      acc[h].y = fmaT(x[h].x, hv[h].y, fmaT(x[h].y, hv[h].x, acc[h].y));
     }
   }
   // ---- inverse steps and the stores of C, as middle_body ----------------------
