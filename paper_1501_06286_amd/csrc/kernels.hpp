@@ -971,7 +971,10 @@ struct BackLdsShape {
   static constexpr int K = TE * TP;   // columns per tile (TE values of e1)
   static constexpr int NW = NW_;      // threads per column
   static constexpr int BLOCK = NW * K;
-  static_assert(F1 * F2 == Q && F2 % NW == 0 && F1 % NW == 0, "outer factor split");
+  // pass-1 and pass-2 tasks per thread (the last one guarded when NW does
+  // not divide a factor: Q = 48 and 96 with 8 threads per column)
+  static constexpr int T1 = (F2 + NW - 1) / NW, T2 = (F1 + NW - 1) / NW;
+  static_assert(F1 * F2 == Q && Q % NW == 0, "outer factor split");
   static_assert(TE == 8 || TE == 16, "tile width");
   // LDS column of (e1 offset el, pair offset pl): with 16 e1 per tile the
   // rows of e1 are rotated by 4 per two pairs, so that the output reads (8
@@ -1013,11 +1016,10 @@ constexpr int back_lds_te() {
 
 // threads per column of the LDS back pass: 8 (1024- or 512-thread
 // workgroups, half the registers per thread and twice the waves of 4), but 4
-// for the FP32 adjoint at Q = 64, which measured faster so; for Q = 3 x 2^k
-// the most that divides both factors (2 for Q = 48, 4 for Q = 96)
+// for the FP32 adjoint at Q = 64, which measured faster so
 template <typename T, int Q, bool ADJ>
 constexpr int back_lds_nw() {
-  return Q == 48 ? 2 : Q == 96 ? 4 : (Q == 32 || (ADJ && sizeof(T) == 4 && Q == 64)) ? 4 : 8;
+  return (Q == 32 || (ADJ && sizeof(T) == 4 && Q == 64)) ? 4 : 8;
 }
 
 // whether the back pass of outer radix Q goes through LDS: Q >= 48 (64, 128
@@ -1046,8 +1048,8 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
                                               const Epi<T> epi = Epi<T>()) {
   typedef BackLdsShape<Q, TE, NW_> B;
   constexpr int F1 = B::F1, F2 = B::F2, TP = B::TP, K = B::K, NW = B::NW;
-  constexpr int T1 = F2 / NW, T2 = F1 / NW;  // pass-1 and pass-2 tasks per thread
-  constexpr int NO = Q / NW;                 // output values per thread
+  constexpr int T1 = B::T1, T2 = B::T2;  // pass-1 and pass-2 tasks per thread
+  constexpr int NO = Q / NW;             // output values per thread
   cx<T>* lds = S.v;
   const int64_t e1_0 = bx * TE, p0 = by * TP;
   const int w = tid / K;  // this thread's first task
@@ -1090,7 +1092,7 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
 #pragma unroll
       for (int j = 0; j < F1; ++j) {
         cx<T> c = {(T)0, (T)0};
-        if (ok) {  // C is dead after this read
+        if (ok && (F2 % NW == 0 || u < F2)) {  // C is dead after this read
           const vec2_t<T> x = __builtin_nontemporal_load(
               reinterpret_cast<const vec2_t<T>*>(base + (int64_t)(u + F2 * j) * M1));
           c = {x.x, x.y};
@@ -1101,6 +1103,7 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
 #pragma unroll
     for (int it = 0; it < T1; ++it) {
       const int u = w + NW * it;
+      if (F2 % NW != 0 && u >= F2) continue;
       reg_fft<T, F1, +1>(v[it]);
 #pragma unroll
       for (int c = 1; c < F1; ++c)
@@ -1114,6 +1117,7 @@ __device__ __forceinline__ void back_lds_body(const cx<T>* __restrict__ C, int64
 #pragma unroll
   for (int it = 0; it < T2; ++it) {
     const int c = w + NW * it;
+    if (F1 % NW != 0 && c >= F1) continue;
     cx<T> v[F2];
 #pragma unroll
     for (int u = 0; u < F2; ++u) v[u] = lds[(u + F2 * c) * K + kc];
