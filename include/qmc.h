@@ -103,7 +103,7 @@ typedef struct qmc_plan_s* qmc_plan_t;
  *   stream     HIP stream for the plan-building kernels; the call
  *              synchronises that stream before returning.
  * The convolution length M (N - 1 when that is a power of two, else the
- * shortest power of two or 3 x 2^k >= 2N - 3, see qmc_plan_info; the union
+ * shortest power of two, 3 x 2^k or 5 x 2^k >= 2N - 3, see qmc_plan_info; the union
  * of Korobov rules takes powers of two only) must split as M = M1 x M2 with
  * M1 <= 4096 on chip
  * and M2 <= 64 x 64; longer rules (N - 1 > 2^23 when not a power of two, or
@@ -138,14 +138,14 @@ void qmc_plan_destroy(qmc_plan_t plan);
  * transform factorisation is M = M1 x M2 with M1 = R^3 on chip (three
  * register DFTs of radix R) and the outer length M2 = P2 x Q2 (a split pass of
  * radix P2 when P2 > 1, the back pass of radix Q2).  R and P2 are powers of
- * two; Q2 (and M2) is a power of two or 3 x 2^i, whose register DFTs take
- * one radix-3 stage and then radix-4 and radix-2 stages.  These fields are
+ * two; Q2 (and M2) is a power of two, 3 x 2^i or 5 x 2^i, whose register
+ * DFTs take one radix-3 or radix-5 stage and then radix-4 and radix-2 stages.  These fields are
  * the whole radix plan, so no separate list of radices is reported.
  */
 typedef struct {
     int64_t N, s, L;        /* points, dimension, order L of the unit group (N - 1 for prime N) */
     int64_t M;              /* circular-convolution length used: L, or the shortest power
-                               of two >= 2L-1, or 3 x 2^k >= 2L-1 when that is shorter
+                               of two >= 2L-1, or 3 x 2^k or 5 x 2^k >= 2L-1 when shorter
                                (M >= 3 x 4096 and M2 no longer than one back pass) */
     int64_t M1, M2;         /* M = M1 * M2 (on-chip transform length, outer length) */
     int64_t rounds;         /* rounds of the sparse collapse schedule */
@@ -215,8 +215,8 @@ int qmc_plan_set_row_order(qmc_plan_t plan, int order);
  *                back pass and one extra split pass when P2 > 1; Q2 <= 32 is
  *                held in registers (FP64: up to 24), the larger ones in LDS
  *                (96 and 128: FP32 plans only).
- *                A power of two <= 128, or for M2 = 3 x 2^j a value 3 x 2^i
- *                <= 96, with P2 = M2 / Q2 a power of two <= 64; or 0 for the
+ *                A power of two <= 128, or for M2 = f x 2^j (f = 3, 5) a value
+ *                f x 2^i <= 96, with P2 = M2 / Q2 a power of two <= 64; or 0 for the
  *                default: all of M2 when that fits one back pass (M2 <= 128
  *                in FP32, 64 in FP64: no split pass), else 32, or M2/64 when
  *                larger.  The dense fronts' forward split uses Q2 up to 64,

@@ -23,11 +23,12 @@ def outer_radices(M2: int, qmax: int = 128) -> List[int]:
     all of M2 in one back pass when M2 <= qmax, else 32 values of w2 per
     back-pass output column), and the other splits: 16 and 32 in registers,
     the LDS back pass's 64 and 128 (up to qmax, the dtype's limit), as far as
-    the split allows; for M2 = 3 x 2^j the same with the factor 3 kept in the
-    back pass (12, 24, 48, 96).  A value equal to the default is not tried
-    twice."""
+    the split allows; for M2 = 3 x 2^j or 5 x 2^j the same with that factor
+    kept in the back pass (12, 24, 48, 96 or 10, 20, 40, 80).  A value equal
+    to the default is not tried twice."""
     qdef = M2 if M2 <= qmax else max(32, M2 // 64)
-    base = (12, 24, 48, 96) if M2 % 3 == 0 else (16, 32, 64, 128)
+    base = ((12, 24, 48, 96) if M2 % 3 == 0 else (10, 20, 40, 80) if M2 % 5 == 0
+            else (16, 32, 64, 128))
     return [0] + [q for q in base
                   if M2 > 16 and q < M2 and M2 % q == 0 and M2 // q <= 64 and q <= qmax
                   and q != qdef]
@@ -43,7 +44,8 @@ def candidates(pairs: int, M2: int = 1, qmax: int = 128) -> List[Dict[str, int]]
     stream): every chunk, both store kinds.
     Each with cached or streaming stores of the intermediate and every outer
     radix of ``outer_radices``.  Bucket twiddles need M2 a power of two (for
-    M2 = 3 x 2^j the library runs front 3 as front 1: not tried twice)."""
+    M2 = 3 x 2^j or 5 x 2^j the library runs front 3 as front 1: not tried
+    twice)."""
     chunks = [0] + [c for c in (8, 16, 32, 64, 128, 256, 512, 1024) if c < pairs]
     qs = outer_radices(M2, qmax)
     fronts = (1, 3) if M2 & (M2 - 1) == 0 else (1,)

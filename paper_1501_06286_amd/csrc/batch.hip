@@ -494,7 +494,17 @@ static int run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
       case 6: QMC_KBB(6); break;
       case 12: QMC_KBB(12); break;
       case 24: QMC_KBB(24); break;
+      case 5: QMC_KBB(5); break;
+      case 10: QMC_KBB(10); break;
+      case 20: QMC_KBB(20); break;
+      case 40: QMC_KBL(40); break;
       case 48: QMC_KBL(48); break;
+      case 80:
+        if constexpr (sizeof(T) == 4) {
+          QMC_KBL(80);
+          break;
+        }
+        return QMC_ERR_UNSUPPORTED;
       case 96:
         if constexpr (sizeof(T) == 4) {
           QMC_KBL(96);

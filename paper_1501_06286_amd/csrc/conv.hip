@@ -256,9 +256,9 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
                        hipStream_t st, const Epi<T>& epi = Epi<T>()) {
   const Layout& lay = P->lay;
   ProfScope ps(P, ADJ ? PROF_ADJ_BACK : PROF_BACK, st);
-  // the outer factor through LDS, tiles of TE e1 x 8 pairs: Q2 = 48, 64, 96
-  // and 128, and 32 in FP64 (its register variant takes all 256 registers and
-  // spills; in FP32 the register variant is the faster one)
+  // the outer factor through LDS, tiles of TE e1 x 8 pairs: Q2 = 40, 48, 64,
+  // 80, 96 and 128, and 32 in FP64 (its register variant takes all 256
+  // registers and spills; in FP32 the register variant is the faster one)
   if (back_in_lds(lay.Q2, sizeof(T) == 8)) {
     constexpr int TE = back_lds_te<T>();
     dim3 gl((unsigned)((lay.M1 + TE - 1) / TE), (unsigned)((pairs + 7) / 8), (unsigned)lay.P2);
@@ -267,12 +267,16 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
       <<<gl, BackLdsShape<QQ, TE, back_lds_nw<T, QQ, ADJ>()>::BLOCK, 0, st>>>(                \
           C, lay.M1, lay.M2, lay.P2, P->L, pairs, (const cx<T>*)P->d_twb, out_rows(P), inv_ptr, \
           inv_j, G0, (T)P->phi0, X, ldx, t, epi)
-    if (lay.Q2 == 48) {
+    if (lay.Q2 == 40) {
+      QMC_BACKL(40);
+    } else if (lay.Q2 == 48) {
       QMC_BACKL(48);
     } else if (lay.Q2 == 64) {
       QMC_BACKL(64);
     } else if constexpr (sizeof(T) == 4) {
-      if (lay.Q2 == 96) {
+      if (lay.Q2 == 80) {
+        QMC_BACKL(80);
+      } else if (lay.Q2 == 96) {
         QMC_BACKL(96);
       } else {
         if (lay.Q2 != 128) return QMC_ERR_UNSUPPORTED;
@@ -300,6 +304,9 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
     case 6: QMC_BACK(6); break;
     case 12: QMC_BACK(12); break;
     case 24: QMC_BACK(24); break;
+    case 5: QMC_BACK(5); break;
+    case 10: QMC_BACK(10); break;
+    case 20: QMC_BACK(20); break;
     default: return QMC_ERR_UNSUPPORTED;
   }
 #undef QMC_BACK
@@ -479,6 +486,10 @@ static int launch_outer_front(const qmc_plan_s* P, const T* A, const T* G, int64
       case 12: QMC_OFRONT(12); break;
       case 24: QMC_OFRONT(24); break;
       case 48: QMC_OFRONT(48); break;
+      case 5: QMC_OFRONT(5); break;
+      case 10: QMC_OFRONT(10); break;
+      case 20: QMC_OFRONT(20); break;
+      case 40: QMC_OFRONT(40); break;
       default: return QMC_ERR_UNSUPPORTED;
     }
 #undef QMC_OFRONT

@@ -13,7 +13,7 @@ namespace qmc {
 // Decomposition of the circular convolution of length M = M1 * M2
 // (M1 = R * R on chip, M2 outer).
 struct Layout {
-  int64_t M = 1, M1 = 1, M2 = 1;  // M2 = 2^j, or 3 x 2^j (then M1 = 16^3)
+  int64_t M = 1, M1 = 1, M2 = 1;  // M2 = 2^j, or 3 x 2^j or 5 x 2^j (then M1 = 16^3)
   int R = 1;        // M1 = R * R * R, R <= 16
   int P2 = 1;       // outer inverse split M2 = P2 * Q2 (P2 = 1: single back pass; a power of two)
   int Q2 = 1;       // values of w2 per output column of the back pass (up to 32 in registers,
@@ -54,7 +54,7 @@ struct qmc_plan_s {
   int64_t shift_num = 0, shift_den = 1;
   int dtype = QMC_F32;
   int embedded = 0;          // 1: L is not a power of two, convolution embedded in M >= 2L-1
-  bool mixed_outer = true;   // the embedding may take M = 3 x 2^k (outer length 3 x 2^j)
+  bool mixed_outer = true;   // the embedding may take M = 3 x 2^k or 5 x 2^k
   double phi0 = 0.0;
   qmc::Layout lay;
   int64_t rounds = 0;        // sparse collapse schedule: rounds per front slice
@@ -118,7 +118,7 @@ int build_tables(qmc_plan_s* P, const uint64_t* gen_host, hipStream_t st);
 int build_conv_tables(qmc_plan_s* P, const int32_t* ell, const int32_t* d_zidx,
                       const double* d_tphi, hipStream_t st);
 // M = L when L is a power of two, else the shortest power of two >= 2L-1 or
-// (mixed) the shortest 3 x 2^k >= 2L-1 when that is shorter and its outer
+// (mixed) the shortest 3 x 2^k or 5 x 2^k >= 2L-1 when that is shorter and its outer
 // length fits one back pass
 Layout choose_layout(int64_t L, int dtype, int* embedded, bool mixed);
 int launch_phi_table(qmc_plan_s* P, hipStream_t st);

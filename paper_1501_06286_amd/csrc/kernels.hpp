@@ -279,7 +279,7 @@ __device__ __forceinline__ void middle_body(
   constexpr int Q = S::Q, M1 = R * R * R, PB = R * (R + 1);
   cx<T>* lds = SM.lds;
   // b = w2 + M2 pg: mask and shift when M2 is a power of two, else one
-  // 32-bit division (M2 = 3 x 2^k; b is below the grid size)
+  // 32-bit division (M2 = 3 x 2^k or 5 x 2^k; b is below the grid size)
   int64_t w2, pg;
   if ((M2 & (M2 - 1)) == 0) {
     w2 = b & (M2 - 1);
@@ -737,8 +737,8 @@ __device__ __forceinline__ void split_body(cx<T>* __restrict__ C, int64_t M1, in
 // adjoint-front passes; small enough that a back workgroup fits beside
 // four fused-kernel workgroups on one CU
 constexpr int BACK_CH = 8;
-// the largest divisor of Q that is at most cap (Q = 2^k or 3 x 2^k: the
-// chunks of a length-Q column moved through LDS together)
+// the largest divisor of Q that is at most cap (Q = 2^k, 3 x 2^k or 5 x 2^k:
+// the chunks of a length-Q column moved through LDS together)
 constexpr int chunk_of(int Q, int cap) {
   int c = Q < cap ? Q : cap;
   while (Q % c) --c;
@@ -964,8 +964,8 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
 // ---------------------------------------------------------------------------
 template <int Q, int TE = 8, int NW_ = 4>
 struct BackLdsShape {
-  // Q = 2^k: F1 = 8; Q = 3 x 2^k: F1 = Q / 8 (6 or 12), F2 = 8
-  static constexpr int F1 = Q % 3 == 0 ? Q / 8 : 8;
+  // Q = 2^k: F1 = 8; Q = 3 x 2^k or 5 x 2^k: F1 = Q / 8 (5, 6, 10 or 12), F2 = 8
+  static constexpr int F1 = (Q % 3 == 0 || Q % 5 == 0) ? Q / 8 : 8;
   static constexpr int F2 = Q / F1;
   static constexpr int TP = 8;        // column pairs per tile
   static constexpr int K = TE * TP;   // columns per tile (TE values of e1)
@@ -1022,11 +1022,11 @@ constexpr int back_lds_nw() {
   return (Q == 32 || (ADJ && sizeof(T) == 4 && Q == 64)) ? 4 : 8;
 }
 
-// whether the back pass of outer radix Q goes through LDS: Q >= 48 (64, 128
-// and 48, 96), and Q = 32 in FP64 (its register variant takes all 256
-// registers and spills; in FP32 the register variant is the faster one)
+// whether the back pass of outer radix Q goes through LDS: Q >= 40 (64, 128
+// and 40, 48, 80, 96), and Q = 32 in FP64 (its register variant takes all
+// 256 registers and spills; in FP32 the register variant is the faster one)
 __host__ __device__ constexpr bool back_in_lds(int Q, bool f64) {
-  return Q >= 48 || (f64 && Q == 32);
+  return Q >= 40 || (f64 && Q == 32);
 }
 
 template <typename T, int Q, int TE = 8>

@@ -263,7 +263,7 @@ __global__ void k_twiddle(cx<double>* W, int64_t M) {
 }
 
 // one radix-2 Stockham pass of a forward FP64 DFT of length M over global
-// memory (M = 2^k, or 3 x 2^k after one radix-3 pass)
+// memory (M = 2^k, or f x 2^k after one radix-f pass, f = 3, 5)
 __global__ void k_fft_r2_pass(const cx<double>* in, cx<double>* out, int64_t M, int64_t Ns,
                               const cx<double>* W) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -274,6 +274,21 @@ __global__ void k_fft_r2_pass(const cx<double>* in, cx<double>* out, int64_t M, 
   const int64_t base = (j / Ns) * 2 * Ns + k;
   out[base] = a0 + a1;
   out[base + Ns] = a0 - a1;
+}
+
+// the radix-5 Stockham pass of a forward FP64 DFT of length M = 5 x 2^k
+// (the first pass, Ns = 1, of those lengths)
+__global__ void k_fft_r5_pass(const cx<double>* in, cx<double>* out, int64_t M, int64_t Ns,
+                              const cx<double>* W) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M / 5) return;
+  const int64_t k = j % Ns, step = M / (5 * Ns), f = M / 5;
+  cx<double> a[5];
+  for (int q = 0; q < 5; ++q) a[q] = in[j + q * f];
+  for (int q = 1; q < 5; ++q) a[q] = cmul(a[q], W[q * k * step]);
+  bfly5<double, -1>(a[0], a[1], a[2], a[3], a[4]);
+  const int64_t base = (j / Ns) * 5 * Ns + k;
+  for (int q = 0; q < 5; ++q) out[base + q * Ns] = a[q];
 }
 
 // the radix-3 Stockham pass of a forward FP64 DFT of length M = 3 x 2^k
@@ -408,16 +423,18 @@ Layout choose_layout(int64_t L, int dtype, int* embedded, bool mixed) {
   } else {
     while (M < 2 * L - 1) M <<= 1;
     *embedded = 1;
-    // the shortest embedding: 3 x 2^k when it is shorter than the power of
-    // two and its outer length M / 16^3 = 3 x 2^j fits one back pass
-    // (M2 <= the dtype's longest outer radix: no split pass)
-    int64_t M3 = 3;
-    while (M3 < 2 * L - 1) M3 <<= 1;
-    if (mixed && M3 < M && M3 >= 3 * 4096 && M3 / 4096 <= max_outer_q(dtype)) M = M3;
+    // the shortest embedding: f x 2^k (f = 3, 5) when it is shorter than the
+    // power of two and its outer length M / 16^3 = f x 2^j fits one back
+    // pass (M2 <= the dtype's longest outer radix: no split pass)
+    for (const int64_t f : {3, 5}) {
+      int64_t Mf = f;
+      while (Mf < 2 * L - 1) Mf <<= 1;
+      if (mixed && Mf < M && Mf >= f * 4096 && Mf / 4096 <= max_outer_q(dtype)) M = Mf;
+    }
   }
   lay.M = M;
   const int rmax = 16;
-  const int64_t M_2 = M % 3 == 0 ? M / 3 : M;  // the power-of-two part of M
+  const int64_t M_2 = M % 3 == 0 ? M / 3 : M % 5 == 0 ? M / 5 : M;  // the power-of-two part
   int R = 1;
   while (2 * R <= rmax && (int64_t)(2 * R) * (2 * R) * (2 * R) <= M_2) R *= 2;
   lay.R = R;
@@ -438,10 +455,10 @@ int set_outer_split(Layout& lay, int q, int qmax) {
   // pass), else 32, more only when M2 > 32 * 64 (with a split pass anyway,
   // the register back pass is the faster one).  The dense fronts' forward
   // split keeps at most 64 values per thread in registers: Qf = Q2 up to 64,
-  // else Q2 / 2.  For M2 = 3 x 2^j the factor 3 stays in Q2 and Qf (a
-  // radix-3 stage of their register DFTs): q must then be 3 x 2^i.
+  // else Q2 / 2.  For M2 = f x 2^j (f = 3, 5) the factor f stays in Q2 and
+  // Qf (a radix-f stage of their register DFTs): q must then be f x 2^i.
   auto radix_ok = [](int64_t v) {
-    const int64_t p = v % 3 == 0 ? v / 3 : v;
+    const int64_t p = v % 3 == 0 ? v / 3 : v % 5 == 0 ? v / 5 : v;
     return v >= 1 && (p & (p - 1)) == 0;
   };
   if (q < 0 || q > qmax || (q > 0 && !radix_ok(q))) return QMC_ERR_ARG;
@@ -449,7 +466,7 @@ int set_outer_split(Layout& lay, int q, int qmax) {
   const int64_t Q2 = std::min<int64_t>(q > 0 ? q : qdef, lay.M2);
   if (Q2 > qmax || lay.M2 % Q2 != 0) return QMC_ERR_ARG;
   const int64_t P2 = lay.M2 / Q2;
-  if (P2 > 64 || (P2 & (P2 - 1))) return QMC_ERR_ARG;  // also: 3 | M2 needs 3 | Q2
+  if (P2 > 64 || (P2 & (P2 - 1))) return QMC_ERR_ARG;  // also: 3 or 5 | M2 needs it in Q2
   const int64_t Qf = Q2 <= 64 ? Q2 : Q2 / 2;
   if (lay.M2 / Qf > 64) return QMC_ERR_ARG;
   lay.Q2 = (int)Q2;
@@ -679,6 +696,10 @@ int build_conv_tables(qmc_plan_s* P, const int32_t* ell, const int32_t* d_zidx,
       k_fft_r3_pass<<<nblk(M / 3), 256, 0, st>>>(src, dst, M, Ns, dW);
       std::swap(src, dst);
       Ns = 3;
+    } else if (M % 5 == 0) {  // M = 5 x 2^k: the radix-5 pass first
+      k_fft_r5_pass<<<nblk(M / 5), 256, 0, st>>>(src, dst, M, Ns, dW);
+      std::swap(src, dst);
+      Ns = 5;
     }
     for (; Ns < M; Ns *= 2) {
       k_fft_r2_pass<<<nblk(M / 2), 256, 0, st>>>(src, dst, M, Ns, dW);

@@ -26,5 +26,6 @@ void both() {
 int main() {
   both<1>(); both<2>(); both<4>(); both<8>(); both<16>(); both<32>(); both<64>();
   both<3>(); both<6>(); both<12>(); both<24>(); both<48>(); both<96>();
+  both<5>(); both<10>(); both<20>(); both<40>(); both<80>();
   return 0;
 }

@@ -45,6 +45,12 @@ def test_outer_radices_of_mixed_lengths():
             for q in qs[1:]:
                 assert q % 3 == 0 and M2 % q == 0 and (M2 // q) & (M2 // q - 1) == 0
                 assert q <= qmax and q < M2 and M2 // q <= 64
+    for qmax in (64, 128):
+        for j in range(0, 5):
+            M2 = 5 << j
+            for q in autotune.outer_radices(M2, qmax)[1:]:
+                assert q % 5 == 0 and M2 % q == 0 and (M2 // q) & (M2 // q - 1) == 0
+    assert autotune.outer_radices(80, 128) == [0, 10, 20, 40]
     assert autotune.outer_radices(96, 128) == [0, 12, 24, 48]
     assert autotune.outer_radices(48, 64) == [0, 12, 24]
     assert autotune.outer_radices(12, 128) == [0]
@@ -54,3 +60,4 @@ def test_bucket_twiddles_only_for_power_of_two_outer_lengths():
     fronts = lambda M2: {c["front"] for c in autotune.candidates(64, M2, 128)}
     assert fronts(64) == {1, 2, 3}
     assert fronts(96) == {1, 2}
+    assert fronts(80) == {1, 2}

@@ -200,7 +200,7 @@ def test_c5_forward_adjoint_fd():
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
 def test_split_outer_pass_lattice(dtype):
     """N = 200003 (L = 2 * 100001 not a power of two): M = 2^19, M2 = 128 > 64
-    (3 x 2^17 < 2L - 1, so no shorter mixed length)."""
+    (3 x 2^17 and 5 x 2^16 < 2L - 1, so no shorter mixed length)."""
     N = 200003
     assert qi.is_prime(N)
     inst = qi.small_lattice(N, 300, 5, phi=qi.PHI_INVNORM, shift=(1, 2 * N), dtype=dtype)

@@ -1,8 +1,9 @@
 """The register DFTs of the kernels (csrc/cx.hpp: Stockham stages of radix
-4 and 2, and one radix-3 stage for the lengths 3 x 2^k of the outer
-transform) built for the host with g++ and compared with numpy's FFT on a
-fixed input: forward exp(-2 pi i jk/N) and the unscaled inverse, every
-length the kernels instantiate (2^k <= 64, 3 x 2^k <= 96)."""
+4 and 2, and one radix-3 or radix-5 stage for the lengths 3 x 2^k and
+5 x 2^k of the outer transform) built for the host with g++ and compared
+with numpy's FFT on a fixed input: forward exp(-2 pi i jk/N) and the
+unscaled inverse, every length the kernels instantiate (2^k <= 64,
+3 x 2^k <= 96, 5 x 2^k <= 80)."""
 import os
 import shutil
 import subprocess
@@ -11,7 +12,7 @@ import numpy as np
 import pytest
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LENGTHS = [1, 2, 4, 8, 16, 32, 64, 3, 6, 12, 24, 48, 96]
+LENGTHS = [1, 2, 4, 8, 16, 32, 64, 3, 6, 12, 24, 48, 96, 5, 10, 20, 40, 80]
 
 
 @pytest.fixture(scope="module")
