@@ -118,7 +118,9 @@ typedef struct qmc_plan_s* qmc_plan_t;
  * and the product H of the others, the rows and columns of an orbit split
  * into |H| x |H| blocks, each a circulant of length L handled like a prime
  * rule (its own spectrum and collapse), the blocks of one row coset adding
- * up.  Orbits with L >= 64 and |H| <= 8 take blocks (at most 1024 over all
+ * up (summed on their spectra: one inverse transform and one pass writing
+ * the rows per row coset; the adjoint likewise per column coset).  Orbits
+ * with L >= 64 and |H| <= 8 take blocks (at most 1024 over all
  * orbits); the others and row 0 are summed directly (phi(N/d) s t
  * multiply-adds for an orbit: fast for 2^k, prime powers and products of
  * few primes, slow for highly composite N with large s t).  Non-prime N above
