@@ -346,20 +346,22 @@ int qmc_dense_matmul(qmc_plan_t plan, const void* Y, int64_t ldy, const void* A,
  * matrices A[i] (s_i x t[i], row stride lda[i], or t[i] if lda is NULL) and
  * X[i] (N_i x t[i], ldx[i] or t[i]); it uploads one descriptor per product
  * and synchronises `stream`.  The plans and buffers must outlive the batch.
- * qmc_batch_run enqueues one persistent launch per pass over all products
- * (products with different on-chip transform sizes form separate groups)
- * and makes no host-to-device copies, so it can be captured in a HIP graph
- * and replayed.  Workspace: qmc_batch_workspace_size bytes, caller-owned.
+ * qmc_batch_run enqueues, per run of products (below), one persistent launch
+ * of each pass over the run's products: the collapse over all of them, the
+ * fused pass once per on-chip transform size, the split once per split
+ * radix and the back pass once per outer radix (the kernels are compiled
+ * per size and radix).  It makes no host-to-device copies, so it can be
+ * captured in a HIP graph and replayed.  Workspace: qmc_batch_workspace_size bytes, caller-owned.
  * Errors: QMC_ERR_ARG (bad arguments or mixed dtypes), QMC_ERR_ALIAS (at
  * create: some X[i] overlaps an A[k] or another X[k]; at run: the workspace
  * overlaps an operand), QMC_ERR_WORKSPACE.
  *
- * qmc_batch_set_chunk splits each group into runs of consecutive products
- * whose intermediate spectra (pairs x M complex values each) take at most
- * chunk_bytes together, one set of launches per run, so that the
- * intermediate can stay in the Infinity Cache between the passes that write
- * and read it (a product larger than chunk_bytes runs alone; 0 = one run per
- * group).  nt_inter chooses the stores of the intermediates as in
+ * qmc_batch_set_chunk cuts the products (ordered by transform size and
+ * radix) into runs of consecutive products whose intermediate spectra
+ * (pairs x M complex values each) take at most chunk_bytes together, so
+ * that the intermediate can stay in the Infinity Cache between the passes
+ * that write and read it (a product larger than chunk_bytes runs alone; 0 =
+ * one run of all products).  nt_inter chooses the stores of the intermediates as in
  * qmc_tuning_t (0: streaming for runs whose intermediates exceed 128 MiB).  A
  * new batch starts with QMC_BATCH_CHUNK_DEFAULT and nt_inter 0.  The runs
  * share the workspace, whose size changes with the chunk: query it

@@ -423,9 +423,11 @@ def matmul_batched(plans: Sequence[Plan], As: Sequence, outs: Optional[Sequence]
 
 
 class Batch:
-    """Many products X_i = Y_i A_i bound once; run() is one persistent launch
-    per pass over all of them and can be captured in a graph
-    (torch.cuda.graph) and replayed.  The plans and tensors must stay alive."""
+    """Many products X_i = Y_i A_i bound once; run() is, per run of products
+    sized to the Infinity Cache, one persistent launch of each pass over the
+    run (per transform size and radix where the kernels differ) and can be
+    captured in a graph (torch.cuda.graph) and replayed.  The plans and
+    tensors must stay alive."""
 
     def __init__(self, plans: Sequence[Plan], As: Sequence, Xs: Optional[Sequence] = None,
                  stream=None, chunk_bytes: Optional[int] = None):

@@ -36,6 +36,7 @@ struct BatchInst {
   const void* two;
   const void* twb;
   int64_t Upad, rounds, M1, M2, P2, Q2, L;
+  int64_t R;  // on-chip radix (M1 = R^3)
   double phi0;
   int64_t off[NPASS];  // first logical block of this product in each pass
   int64_t nb[NPASS];   // logical blocks of this product in each pass
@@ -193,16 +194,19 @@ struct qmc_batch_s {
   int64_t chunk_bytes = 0;
   int nt_inter = 0;  // stores of the intermediates: 0 auto, 1 cached, 2 streaming
   bool ready = false;  // the runs are built (a failed regrouping leaves none)
-  // one run of products of one layout: a set of launches, one per pass
+  // one launch of a run: one pass over the run's products that share the
+  // pass's template parameter (collapse: all; fused pass: R; split: P2 > 1;
+  // back pass: Q2), with their descriptors
   struct Group {
-    int R = 0, P2 = 1, Q2 = 1;
+    int pass = 0;
+    int key = 0;   // R, P2 or Q2 of the launch's products
     int nt_c = 0;  // streaming stores of the run's intermediate (too large for the cache)
-    int epi = 0;   // some product of the run has an epilogue
+    int epi = 0;   // some product of the launch has an epilogue
     int n = 0;
     BatchInst* d_desc = nullptr;
-    int64_t total[NPASS] = {0, 0, 0, 0};
+    int64_t total = 0;  // logical blocks of the pass
   };
-  std::vector<Group> groups;
+  std::vector<Group> groups;  // every run's launches, runs in order
   // the products by layout key (R, P2, Q2), in input order, for regrouping,
   // and each one's position in the caller's list
   std::vector<std::pair<int64_t, std::vector<BatchInst>>> byKey;
@@ -221,67 +225,96 @@ static void free_runs(qmc_batch_s* B) {
   B->groups.clear();
 }
 
-// Splits every layout group into runs of consecutive products whose
-// intermediate spectra C together take at most `chunk` bytes (0: one run per
-// group; a product larger than `chunk` runs alone), so that C can stay in the
-// 256 MB Infinity Cache between the fused pass that writes it and the back
-// pass that reads it.  The runs execute one after another on one stream and
-// share the workspace from offset 0.  Uploads the descriptors and
-// synchronises `st`.
+// Cuts the products (ordered by layout key (R, P2, Q2), input order within a
+// key) into runs of consecutive products whose intermediate spectra C
+// together take at most `chunk` bytes (0: one run of all; a product larger
+// than `chunk` runs alone), so that C can stay in the 256 MB Infinity Cache
+// between the fused pass that writes it and the back pass that reads it.
+// A run is one launch of the collapse over all its products, one fused-pass
+// launch per on-chip size R, one split launch per split radix P2 > 1 and one
+// back-pass launch per outer radix Q2.  The runs execute one after another on
+// one stream and share the workspace from offset 0.  Uploads the
+// descriptors and synchronises `st`.
 static int build_runs(qmc_batch_s* B, int64_t chunk, int nt_inter, hipStream_t st) {
   free_runs(B);
   B->ready = false;
   const size_t el = B->dtype == QMC_F32 ? sizeof(cx<float>) : sizeof(cx<double>);
+  std::vector<BatchInst> all;  // byKey is in first-appearance order: sort by key
+  {
+    std::vector<size_t> order(B->byKey.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    std::sort(order.begin(), order.end(),
+              [&](size_t a, size_t b) { return B->byKey[a].first < B->byKey[b].first; });
+    for (size_t k : order) all.insert(all.end(), B->byKey[k].second.begin(), B->byKey[k].second.end());
+  }
+  // one launch of pass p over the products v[i] with sel(i)
+  auto add_launch = [&](std::vector<BatchInst>& v, int p, int key, int nt_c, auto sel) -> int {
+    std::vector<BatchInst> d;
+    for (size_t i = 0; i < v.size(); ++i)
+      if (sel(v[i])) d.push_back(v[i]);
+    qmc_batch_s::Group g;
+    g.pass = p;
+    g.key = key;
+    g.nt_c = nt_c;
+    int64_t o = 0;
+    for (BatchInst& I : d) {
+      I.off[p] = o;
+      o += I.nb[p];
+      g.epi |= I.epi_kind != 0;
+    }
+    g.total = o;
+    g.n = (int)d.size();
+    if (o == 0) return QMC_OK;  // nothing to launch (a split pass of no product)
+    if (hipMalloc(&g.d_desc, d.size() * sizeof(BatchInst)) != hipSuccess) return QMC_ERR_OOM;
+    B->groups.push_back(g);
+    int rc = hip_ok(hipMemcpyAsync(g.d_desc, d.data(), d.size() * sizeof(BatchInst),
+                                   hipMemcpyHostToDevice, st));
+    if (rc == QMC_OK) rc = hip_ok(hipStreamSynchronize(st));  // d is freed next
+    return rc;
+  };
   size_t ws = 0;
-  for (auto& kv : B->byKey) {
-    const std::vector<BatchInst>& all = kv.second;
-    for (size_t i0 = 0; i0 < all.size();) {
-      size_t i1 = i0;
-      int64_t cbytes = 0;
-      while (i1 < all.size()) {
-        const int64_t c = all[i1].pairs * all[i1].M1 * all[i1].M2 * (int64_t)el;
-        if (chunk > 0 && i1 > i0 && cbytes + c > chunk) break;
-        cbytes += c;
-        ++i1;
-      }
-      std::vector<BatchInst> v(all.begin() + i0, all.begin() + i1);
-      i0 = i1;
-      size_t off = 0;
-      for (BatchInst& I : v) {
-        I.aT_off = (int64_t)off;
-        off += al256(I.pairs * I.Upad * el);
-        I.C_off = (int64_t)off;
-        off += al256(I.pairs * I.M1 * I.M2 * el);
-      }
-      ws = std::max(ws, off);
-      qmc_batch_s::Group g;
-      g.R = (int)(kv.first >> 32);
-      g.P2 = (int)((kv.first >> 16) & 0xffff);
-      g.Q2 = (int)(kv.first & 0xffff);
-      g.n = (int)v.size();
-      // streaming stores of C when it cannot stay in the cache anyway
-      g.nt_c = nt_inter ? (nt_inter == 2) : (cbytes > ((int64_t)128 << 20));
-      for (const BatchInst& I : v) g.epi |= I.epi_kind != 0;
-      for (int p = 0; p < NPASS; ++p) {
-        int64_t o = 0;
-        for (BatchInst& I : v) {
-          I.off[p] = o;
-          o += I.nb[p];
-        }
-        g.total[p] = o;
-      }
-      if (hipMalloc(&g.d_desc, v.size() * sizeof(BatchInst)) != hipSuccess) {
-        free_runs(B);
-        return QMC_ERR_OOM;
-      }
-      B->groups.push_back(g);
-      int rc = hip_ok(hipMemcpyAsync(g.d_desc, v.data(), v.size() * sizeof(BatchInst),
-                                     hipMemcpyHostToDevice, st));
-      if (rc == QMC_OK) rc = hip_ok(hipStreamSynchronize(st));  // v is freed next
-      if (rc != QMC_OK) {
-        free_runs(B);
-        return rc;
-      }
+  for (size_t i0 = 0; i0 < all.size();) {
+    size_t i1 = i0;
+    int64_t cbytes = 0;
+    while (i1 < all.size()) {
+      const int64_t c = all[i1].pairs * all[i1].M1 * all[i1].M2 * (int64_t)el;
+      if (chunk > 0 && i1 > i0 && cbytes + c > chunk) break;
+      cbytes += c;
+      ++i1;
+    }
+    std::vector<BatchInst> v(all.begin() + i0, all.begin() + i1);
+    i0 = i1;
+    size_t off = 0;
+    for (BatchInst& I : v) {
+      I.aT_off = (int64_t)off;
+      off += al256(I.pairs * I.Upad * el);
+      I.C_off = (int64_t)off;
+      off += al256(I.pairs * I.M1 * I.M2 * el);
+    }
+    ws = std::max(ws, off);
+    // streaming stores of C when it cannot stay in the cache anyway
+    const int nt_c = nt_inter ? (nt_inter == 2) : (cbytes > ((int64_t)128 << 20));
+    std::vector<int64_t> Rs, P2s, Q2s;
+    for (const BatchInst& I : v) {
+      const int64_t R = I.R;
+      if (std::find(Rs.begin(), Rs.end(), R) == Rs.end()) Rs.push_back(R);
+      if (I.P2 > 1 && std::find(P2s.begin(), P2s.end(), I.P2) == P2s.end()) P2s.push_back(I.P2);
+      if (std::find(Q2s.begin(), Q2s.end(), I.Q2) == Q2s.end()) Q2s.push_back(I.Q2);
+    }
+    int rc = add_launch(v, PASS_COLLAPSE, 0, nt_c, [](const BatchInst&) { return true; });
+    for (int64_t R : Rs)
+      if (rc == QMC_OK)
+        rc = add_launch(v, PASS_MIDDLE, (int)R, nt_c, [R](const BatchInst& I) { return I.R == R; });
+    for (int64_t P2 : P2s)
+      if (rc == QMC_OK)
+        rc = add_launch(v, PASS_SPLIT, (int)P2, nt_c,
+                        [P2](const BatchInst& I) { return I.P2 == P2; });
+    for (int64_t Q2 : Q2s)
+      if (rc == QMC_OK)
+        rc = add_launch(v, PASS_BACK, (int)Q2, nt_c, [Q2](const BatchInst& I) { return I.Q2 == Q2; });
+    if (rc != QMC_OK) {
+      free_runs(B);
+      return rc;
     }
   }
   B->ws_bytes = ws;
@@ -349,6 +382,7 @@ int qmc_batch_create(qmc_batch_t* out, int count, const qmc_plan_t* plans, const
     I.Upad = P->Upad;
     I.rounds = P->rounds;
     I.M1 = lay.M1;
+    I.R = lay.R;
     I.M2 = lay.M2;
     I.P2 = lay.P2;
     I.Q2 = lay.Q2;
@@ -449,102 +483,103 @@ static inline unsigned grid_for(int64_t total, int64_t cap) {
   return (unsigned)std::max<int64_t>(1, std::min(total, cap));
 }
 
-template <typename T, int R>
-static int run_group_r(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
-  // persistent grids: a few resident workgroups per CU (256 CUs)
-  if (g.total[PASS_COLLAPSE])
-    kb_collapse<T><<<grid_for(g.total[PASS_COLLAPSE], 2048), 256, 0, st>>>(
-        g.d_desc, g.n, g.total[PASS_COLLAPSE], ws);
-  if (g.total[PASS_MIDDLE])
-    kb_middle<T, R><<<grid_for(g.total[PASS_MIDDLE], 1024), MidShape<R>::BLOCK, 0, st>>>(
-        g.d_desc, g.n, g.total[PASS_MIDDLE], ws, g.nt_c);
-  if (g.total[PASS_SPLIT]) {
-    const unsigned gs = grid_for(g.total[PASS_SPLIT], 4096);
-#define QMC_KBS(PP) kb_split<T, PP><<<gs, 64, 0, st>>>(g.d_desc, g.n, g.total[PASS_SPLIT], ws)
-    switch (g.P2) {
-      case 2: QMC_KBS(2); break;
-      case 4: QMC_KBS(4); break;
-      case 8: QMC_KBS(8); break;
-      case 16: QMC_KBS(16); break;
-      case 32: QMC_KBS(32); break;
-      case 64: QMC_KBS(64); break;
-      default: return QMC_ERR_UNSUPPORTED;
+// one launch of a run (persistent grids: a few resident workgroups per CU)
+template <typename T>
+static int run_launch(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
+  const int64_t tot = g.total;
+  switch (g.pass) {
+    case PASS_COLLAPSE:
+      kb_collapse<T><<<grid_for(tot, 2048), 256, 0, st>>>(g.d_desc, g.n, tot, ws);
+      break;
+    case PASS_MIDDLE: {
+      const unsigned gm = grid_for(tot, 1024);
+#define QMC_KBM(RR) \
+  kb_middle<T, RR><<<gm, MidShape<RR>::BLOCK, 0, st>>>(g.d_desc, g.n, tot, ws, g.nt_c)
+      switch (g.key) {
+        case 1: QMC_KBM(1); break;
+        case 2: QMC_KBM(2); break;
+        case 4: QMC_KBM(4); break;
+        case 8: QMC_KBM(8); break;
+        case 16: QMC_KBM(16); break;
+        default: return QMC_ERR_UNSUPPORTED;
+      }
+#undef QMC_KBM
+      break;
     }
+    case PASS_SPLIT: {
+      const unsigned gs = grid_for(tot, 4096);
+#define QMC_KBS(PP) kb_split<T, PP><<<gs, 64, 0, st>>>(g.d_desc, g.n, tot, ws)
+      switch (g.key) {
+        case 2: QMC_KBS(2); break;
+        case 4: QMC_KBS(4); break;
+        case 8: QMC_KBS(8); break;
+        case 16: QMC_KBS(16); break;
+        case 32: QMC_KBS(32); break;
+        case 64: QMC_KBS(64); break;
+        default: return QMC_ERR_UNSUPPORTED;
+      }
 #undef QMC_KBS
-  }
-  if (g.total[PASS_BACK]) {
-    const unsigned gb = grid_for(g.total[PASS_BACK], 1024);
-#define QMC_KBB(QQ)                                                                           \
-  (g.epi ? kb_back<T, QQ, true><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws)     \
-         : kb_back<T, QQ, false><<<gb, 256, 0, st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws))
+      break;
+    }
+    default: {  // PASS_BACK
+      const unsigned gb = grid_for(tot, 1024);
+#define QMC_KBB(QQ)                                                                  \
+  (g.epi ? kb_back<T, QQ, true><<<gb, 256, 0, st>>>(g.d_desc, g.n, tot, ws)         \
+         : kb_back<T, QQ, false><<<gb, 256, 0, st>>>(g.d_desc, g.n, tot, ws))
 #define QMC_KBL(QQ)                                                                  \
   (g.epi ? kb_back_lds<T, QQ, true>                                                  \
                <<<gb, BackLdsShape<QQ, back_lds_te<T>(), back_lds_nw<T, QQ, false>()>::BLOCK, 0, \
-                  st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws)                       \
+                  st>>>(g.d_desc, g.n, tot, ws)                                      \
          : kb_back_lds<T, QQ, false>                                                 \
                <<<gb, BackLdsShape<QQ, back_lds_te<T>(), back_lds_nw<T, QQ, false>()>::BLOCK, 0, \
-                  st>>>(g.d_desc, g.n, g.total[PASS_BACK], ws))
-    switch (g.Q2) {
-      case 1: QMC_KBB(1); break;
-      case 2: QMC_KBB(2); break;
-      case 4: QMC_KBB(4); break;
-      case 8: QMC_KBB(8); break;
-      case 16: QMC_KBB(16); break;
-      case 3: QMC_KBB(3); break;
-      case 6: QMC_KBB(6); break;
-      case 12: QMC_KBB(12); break;
-      case 24: QMC_KBB(24); break;
-      case 5: QMC_KBB(5); break;
-      case 10: QMC_KBB(10); break;
-      case 20: QMC_KBB(20); break;
-      case 40: QMC_KBL(40); break;
-      case 48: QMC_KBL(48); break;
-      case 80:
-        if constexpr (sizeof(T) == 4) {
-          QMC_KBL(80);
+                  st>>>(g.d_desc, g.n, tot, ws))
+      switch (g.key) {
+        case 1: QMC_KBB(1); break;
+        case 2: QMC_KBB(2); break;
+        case 4: QMC_KBB(4); break;
+        case 8: QMC_KBB(8); break;
+        case 16: QMC_KBB(16); break;
+        case 3: QMC_KBB(3); break;
+        case 6: QMC_KBB(6); break;
+        case 12: QMC_KBB(12); break;
+        case 24: QMC_KBB(24); break;
+        case 5: QMC_KBB(5); break;
+        case 10: QMC_KBB(10); break;
+        case 20: QMC_KBB(20); break;
+        case 40: QMC_KBL(40); break;
+        case 48: QMC_KBL(48); break;
+        case 80:
+          if constexpr (sizeof(T) == 4) {
+            QMC_KBL(80);
+            break;
+          }
+          return QMC_ERR_UNSUPPORTED;
+        case 96:
+          if constexpr (sizeof(T) == 4) {
+            QMC_KBL(96);
+            break;
+          }
+          return QMC_ERR_UNSUPPORTED;
+        case 32:  // FP64 through LDS, as the single product (the same bits)
+          if constexpr (sizeof(T) == 8) {
+            QMC_KBL(32);
+          } else {
+            QMC_KBB(32);
+          }
           break;
-        }
-        return QMC_ERR_UNSUPPORTED;
-      case 96:
-        if constexpr (sizeof(T) == 4) {
-          QMC_KBL(96);
-          break;
-        }
-        return QMC_ERR_UNSUPPORTED;
-      case 32:  // FP64 through LDS, as the single product (the same bits)
-        if constexpr (sizeof(T) == 8) {
-          QMC_KBL(32);
-        } else {
-          QMC_KBB(32);
-        }
-        break;
-      case 64: QMC_KBL(64); break;
-      case 128:
-        if constexpr (sizeof(T) == 4) {
-          QMC_KBL(128);
-          break;
-        }
-        return QMC_ERR_UNSUPPORTED;
-      default: return QMC_ERR_UNSUPPORTED;
-    }
+        case 64: QMC_KBL(64); break;
+        case 128:
+          if constexpr (sizeof(T) == 4) {
+            QMC_KBL(128);
+            break;
+          }
+          return QMC_ERR_UNSUPPORTED;
+        default: return QMC_ERR_UNSUPPORTED;
+      }
 #undef QMC_KBL
 #undef QMC_KBB
+    }
   }
-  return QMC_OK;
-}
-
-template <typename T>
-static int run_group(const qmc_batch_s::Group& g, char* ws, hipStream_t st) {
-  int rc = QMC_ERR_UNSUPPORTED;
-  switch (g.R) {
-    case 1: rc = run_group_r<T, 1>(g, ws, st); break;
-    case 2: rc = run_group_r<T, 2>(g, ws, st); break;
-    case 4: rc = run_group_r<T, 4>(g, ws, st); break;
-    case 8: rc = run_group_r<T, 8>(g, ws, st); break;
-    case 16: rc = run_group_r<T, 16>(g, ws, st); break;
-    default: break;
-  }
-  if (rc != QMC_OK) return rc;
   return hip_ok(hipGetLastError());
 }
 
@@ -561,8 +596,8 @@ int qmc_batch_run(qmc_batch_t B, void* workspace, size_t workspace_bytes, void* 
     if (ranges_overlap(workspace, B->ws_bytes, o.first, o.second)) return QMC_ERR_ALIAS;
   hipStream_t st = (hipStream_t)stream;
   for (const auto& g : B->groups) {
-    const int rc = B->dtype == QMC_F32 ? run_group<float>(g, (char*)workspace, st)
-                                       : run_group<double>(g, (char*)workspace, st);
+    const int rc = B->dtype == QMC_F32 ? run_launch<float>(g, (char*)workspace, st)
+                                       : run_launch<double>(g, (char*)workspace, st);
     if (rc != QMC_OK) return rc;
   }
   return QMC_OK;
