@@ -1,9 +1,9 @@
 """A seeded sweep over many small lattice rules (prime and non-prime N up to
-2^17, so every layout kind appears: direct and embedded lengths, outer
+2^18, so every layout kind appears: direct and embedded lengths, outer
 lengths 2^j, 3 x 2^j and 5 x 2^j, on-chip radices 1-16, orbits summed as
-blocks or directly), each product and adjoint compared with the CPU
-oracle's plain Y A and Y^T G on the same inputs, to tau max|Y| ||A[:, k]||_1
-(tau = 1e-12 FP64, 1e-5 FP32)."""
+blocks or directly) and polynomial lattice rules over GF(2), each product
+and adjoint compared with the CPU oracle's plain Y A and Y^T G on the same
+inputs, to tau max|Y| ||A[:, k]||_1 (tau = 1e-12 FP64, 1e-5 FP32)."""
 import numpy as np
 import pytest
 
@@ -53,3 +53,33 @@ def test_sweep_forward_adjoint(N, s, t, phi, dtype, seed):
     G = qi.randn((N, t), seed=seed, dtype=dtype)
     dA = q.matmul_adjoint(p, to_dev(G, dtype)).double().cpu().numpy()
     assert_close(dA, oracle.adjoint(inst, G), G, inst, dtype, f"adjoint N={N}")
+
+
+def _gf2_cases(count=20, seed=2027):
+    rg = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        m = int(rg.integers(1, 18))
+        s = int(rg.integers(1, 120))
+        t = int(rg.integers(1, 8))
+        phi = int(rg.integers(0, len(PHIS)))
+        out.append((m, s, t, phi, "f64" if i % 2 else "f32", i))
+    return out
+
+
+@pytest.mark.parametrize("m,s,t,phi,dtype,seed", _gf2_cases())
+def test_sweep_gf2(m, s, t, phi, dtype, seed):
+    """Polynomial lattice rules over GF(2), N = 2^m, m = 1..17 (cyclic group
+    of order 2^m - 1, always embedded for m >= 2)."""
+    torch_cuda()
+    import paper_1501_06286_amd as q
+    kind, shift = PHIS[phi]
+    N = 1 << m
+    inst = qi.small_gf2(m, s, t, phi=kind, shift=shift(N), dtype=dtype, seed=seed)
+    announce(f"sweep GF(2) m={m} s={s} t={t} phi={kind} {dtype}")
+    p = plan_of(inst)
+    X = q.matmul(p, to_dev(inst.A, dtype)).double().cpu().numpy()
+    assert_close(X, oracle.matmul(inst), inst.A, inst, dtype, f"forward m={m}")
+    G = qi.randn((N, t), seed=seed, dtype=dtype)
+    dA = q.matmul_adjoint(p, to_dev(G, dtype)).double().cpu().numpy()
+    assert_close(dA, oracle.adjoint(inst, G), G, inst, dtype, f"adjoint m={m}")
