@@ -244,12 +244,12 @@ def tune_batch(plans, As, reps: int = 3, qs=None) -> Tuple[Dict[int, int], List]
     return best, timings
 
 
-def tune_batch_chunk(batch, reps: int = 3, chunks_mib=(128, 256, 384, 512),
+def tune_batch_chunk(batch, reps: int = 3, chunks_mib=(128, 256, 384, 512, 1024, 0),
                      nts=(0, 2)) -> Tuple[Tuple[int, int], List]:
-    """Pick the run size of a batch (intermediates per run, in MiB) and the
-    store kind of its intermediates (automatic or streaming) by timing whole
-    runs of the batch; sets the fastest and returns ((chunk_bytes, nt_inter),
-    timings)."""
+    """Pick the run size of a batch (intermediates per run, in MiB; 0 = one
+    run of all products) and the store kind of its intermediates (automatic
+    or streaming) by timing whole runs of the batch; sets the fastest and
+    returns ((chunk_bytes, nt_inter), timings)."""
     import torch
     results = []
     for mib in chunks_mib:
