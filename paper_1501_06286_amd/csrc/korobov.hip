@@ -22,9 +22,9 @@ __global__ __launch_bounds__(256) void ku_collapse(const T* __restrict__ A, int6
                                                    int64_t Upad, cx<T>* __restrict__ aT,
                                                    int64_t gx, int64_t per_block,
                                                    int64_t total) {
-  // a grid of a few workgroups per CU striding over the tiles of all blocks
-  // (the tiles are small: one workgroup per tile would be bound by the
-  // workgroup dispatch rate)
+  // a grid of a fixed number of workgroups striding over the tiles of all
+  // blocks (the tiles are small: one workgroup per tile would be bound by
+  // the workgroup dispatch rate)
   __shared__ CollapseSmem<T> S;
   for (int64_t id = blockIdx.x; id < total; id += gridDim.x) {
     const int64_t b = id / per_block, lb = id % per_block;
@@ -247,7 +247,10 @@ static int korobov_forward(const qmc_korobov_s* U, const T* A, int64_t t, int64_
       const int64_t gx = (U->Upad + 63) / 64, per_block = gx * ((pairs + 15) / 16);
       ProfScope ps(P, PROF_COLLAPSE, st);
       const int64_t total = nb * per_block;
-      ku_collapse<T><<<dim3((unsigned)std::min<int64_t>(total, 2048)), 256, 0, st>>>(
+      // 8192 workgroups, more than fit on the GPU at once: a tile is a chain
+      // of dependent small loads, and a full machine keeps more chains in
+      // flight (2048 workgroups: 2.5% slower at K = 1021)
+      ku_collapse<T><<<dim3((unsigned)std::min<int64_t>(total, 8192)), 256, 0, st>>>(
           A, lda, t, pairs, U->s, U->d_it_ptr + b0 * (U->Upad + 1), U->d_it_jl + b0 * U->s,
           U->Upad, aT, gx, per_block, total);
     }
