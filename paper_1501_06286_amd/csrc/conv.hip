@@ -73,8 +73,8 @@ __global__ __launch_bounds__(64) void k_outer_split(cx<T>* __restrict__ C, int64
   split_body<T, P2, DIR>(C, M1, M2, Q2, twb, blockIdx.x, blockIdx.y, blockIdx.z, threadIdx.x);
 }
 
-template <typename T, int Q, bool ADJ, bool NT, bool EPI>
-__global__ __launch_bounds__(256)
+template <typename T, int Q, bool ADJ, bool NT, bool EPI, int EB = 16, int PB = 16>
+__global__ __launch_bounds__(EB * PB)
 __attribute__((amdgpu_waves_per_eu(back_waves<T, Q>()))) void k_back(const cx<T>* __restrict__ C, int64_t M1, int64_t M2,
                                               int64_t P2, int64_t L, int64_t P,
                                               const int32_t* __restrict__ rowmap,
@@ -83,9 +83,10 @@ __attribute__((amdgpu_waves_per_eu(back_waves<T, Q>()))) void k_back(const cx<T>
                                               const T* __restrict__ G0, T phi0,
                                               T* __restrict__ X, int64_t ldx, int64_t t,
                                               Epi<T> epi) {
-  __shared__ BackSmem<T> S;
-  back_body<T, Q, ADJ, NT, EPI>(C, M1, M2, P2, L, P, rowmap, inv_ptr, inv_j, G0, phi0, X, ldx,
-                                t, blockIdx.x, blockIdx.y, blockIdx.z, S, threadIdx.x, epi);
+  __shared__ BackSmem<T, EB, PB> S;
+  back_body<T, Q, ADJ, NT, EPI, EB, PB>(C, M1, M2, P2, L, P, rowmap, inv_ptr, inv_j, G0, phi0,
+                                        X, ldx, t, blockIdx.x, blockIdx.y, blockIdx.z, S,
+                                        threadIdx.x, epi);
 }
 
 template <typename T, int Q, bool ADJ, bool NT, bool EPI, int TE, int NW>
@@ -288,6 +289,17 @@ static int launch_back(const qmc_plan_s* P, const cx<T>* C, int64_t pairs, const
     }
 #undef QMC_BACKL
     return hip_ok(hipGetLastError());
+  }
+  if constexpr (sizeof(T) == 8 && !ADJ) {
+    // FP64 forward at Q2 = 16 (the Gaussian workload): tiles of 64 e1 x 8
+    // pairs (measured: the product 1.80 -> 1.76 ms; no gain for the adjoint)
+    if (lay.Q2 == 16) {
+      dim3 g8((unsigned)((lay.M1 + 63) / 64), (unsigned)((pairs + 7) / 8), (unsigned)lay.P2);
+      k_back<T, 16, false, NT, EPI, 64, 8><<<g8, 512, 0, st>>>(
+          C, lay.M1, lay.M2, lay.P2, P->L, pairs, out_rows(P), inv_ptr, inv_j, G0, (T)P->phi0, X,
+          ldx, t, epi);
+      return hip_ok(hipGetLastError());
+    }
   }
   dim3 grid((unsigned)((lay.M1 + 15) / 16), (unsigned)((pairs + 15) / 16), (unsigned)lay.P2);
 #define QMC_BACK(QQ)                                                                          \

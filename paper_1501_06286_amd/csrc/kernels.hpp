@@ -732,6 +732,10 @@ __device__ __forceinline__ void split_body(cx<T>* __restrict__ C, int64_t M1, in
 // thread (pair, e1, a): loads C[pair][q + Q a][e1], q < Q, produces e2 = a + P2 b.
 //   forward: X[pow[e]][2 pair .. 2 pair + 1] = out[e] for e < L
 //   adjoint: dA[j][...] = out[e] + phi0 G[0][...] for every j with l_j = e
+// A workgroup takes a tile of EB e1 x PB column pairs (one thread each), so
+// it reads C in runs of EB values and writes each output row's PB pairs as
+// one segment: 16 x 16 (256-byte runs and segments in FP64), or 64 x 8 for
+// the FP64 forward product (1 KB runs of C, one whole 128-byte line per row).
 // ---------------------------------------------------------------------------
 // values per thread exchanged per round through LDS in the back and
 // adjoint-front passes; small enough that a back workgroup fits beside
@@ -744,9 +748,9 @@ constexpr int chunk_of(int Q, int cap) {
   while (Q % c) --c;
   return c;
 }
-template <typename T>
+template <typename T, int EB = 16, int PB = 16>
 struct BackSmem {
-  cx<T> sm[BACK_CH][16][17];
+  cx<T> sm[BACK_CH][EB][PB + 1];
 };
 
 template <typename T, bool NT>
@@ -839,7 +843,7 @@ constexpr int back_waves() {
   return (sizeof(T) == 8 && Q == 32) ? 2 : 1;
 }
 
-template <typename T, int Q, bool ADJ, bool NT, bool EPI = false>
+template <typename T, int Q, bool ADJ, bool NT, bool EPI = false, int EB = 16, int PB = 16>
 __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M1, int64_t M2,
                                           int64_t P2, int64_t L, int64_t P,
                                           const int32_t* __restrict__ rowmap,
@@ -847,9 +851,8 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
                                           const int32_t* __restrict__ inv_j,
                                           const T* __restrict__ G0, T phi0,
                                           T* __restrict__ X, int64_t ldx, int64_t t, int64_t bx,
-                                          int64_t by, int64_t a, BackSmem<T>& S, int tid,
-                                          const Epi<T> epi = Epi<T>()) {
-  constexpr int PB = 16, EB = 16;
+                                          int64_t by, int64_t a, BackSmem<T, EB, PB>& S,
+                                          int tid, const Epi<T> epi = Epi<T>()) {
   constexpr int CH = chunk_of(Q, BACK_CH);
   // FP32 forward writes without epilogue: two pairs per 16-byte store when
   // rows are 16-byte aligned (else per pair, as the other variants)
@@ -907,7 +910,7 @@ __device__ __forceinline__ void back_body(const cx<T>* __restrict__ C, int64_t M
       if constexpr (WIDE) {
         // thread (two pairs pw0, pw0 + 1; e1; every other c): one 16-byte
         // store of both pairs per output row, half the store instructions
-        const int pw2 = tid % 8, ew2 = (tid / 8) % EB, ch = tid / (8 * EB);
+        const int pw2 = tid % (PB / 2), ew2 = (tid / (PB / 2)) % EB, ch = tid / ((PB / 2) * EB);
         const int64_t pw0 = p0 + 2 * pw2, e1x = e1_0 + ew2, col = 2 * pw0;
         const bool full = wide && pw0 + 1 < P && col + 3 < t;
         if (e1x < M1) {
