@@ -136,7 +136,8 @@ def time_config(plan, A, X, cfg: Dict[str, int], reps: int = 3) -> float:
 def refine(plan, A, X, results, reps: int, top: int = 4, rounds: int = 5) -> Dict[str, int]:
     """The first sweep's few fastest tunings (often within a few percent of
     each other) timed again in turns, several rounds: the one with the least
-    median time, so that the choice does not follow one noisy sample."""
+    median time, so that the choice does not follow one noisy sample; a
+    one-stream tuning within 1% of it is preferred."""
     order = sorted(results, key=lambda r: r[1])[:top]
     if len(order) < 2:
         return order[0][0]
@@ -145,7 +146,12 @@ def refine(plan, A, X, results, reps: int, top: int = 4, rounds: int = 5) -> Dic
         for i, (cfg, _) in enumerate(order):
             times[i].append(time_config(plan, A, X, cfg, reps))
     med = [sorted(ts)[len(ts) // 2] for ts in times]
-    return order[min(range(len(order)), key=lambda i: med[i])][0]
+    best = min(range(len(order)), key=lambda i: med[i])
+    # within 1% of the fastest, one stream wins: its passes do not overlap,
+    # so their launch times (and the per-kernel rooflines) are their own
+    one = [i for i in range(len(order))
+           if order[i][0].get("streams", 1) == 1 and med[i] <= 1.01 * med[best]]
+    return order[min(one, key=lambda i: med[i]) if one else best][0]
 
 
 def tune(plan, t: int, reps: int = 3, use_cache: bool = True,
