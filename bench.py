@@ -215,11 +215,20 @@ class Leg:
         self.checks = []  # (label, inst, rows, gpu rows) or ("adjoint", inst, entries, G cols, got)
 
 
-def tune_plan(plan, t, args):
+def tune_plan(plan, t, args, one_stream=False):
+    """The autotuner's choice for (plan, t).  one_stream: among the tunings
+    that run every pass on the caller's stream only, so that the per-kernel
+    launch times a roofline divides by hold no other pass running beside
+    them (the two-stream pipelines measured within 1-2% of them)."""
     if args.no_tune:
         return plan.get_tuning()
     from paper_1501_06286_amd import autotune
-    best, _ = autotune.tune(plan, t, reps=3)
+    cands = None
+    if one_stream:
+        info = plan.info()
+        cands = [c for c in autotune.candidates((t + 1) // 2, info["M2"], autotune.qmax_of(plan))
+                 if c["streams"] == 1]
+    best, _ = autotune.tune(plan, t, reps=3, cands=cands)
     return best
 
 
@@ -230,7 +239,7 @@ def forward_leg(name, inst, args, torch, q, dev, profile=True, nrows=64):
     info = plan.info()
     log(f"{name}: {inst.name} {inst.dtype} L={info['L']} M={info['M']} M1={info['M1']} "
         f"M2={info['M2']} rounds={info['rounds']}")
-    tuning = tune_plan(plan, inst.t, args)
+    tuning = tune_plan(plan, inst.t, args, one_stream=profile)
     if args.tuning and name in ("c2", "c2_other"):
         keys = ("chunk_pairs", "streams", "nt_store", "front", "outer_q", "nt_inter")
         plan.set_tuning(**dict(zip(keys, [int(v) for v in args.tuning.split(",")])))

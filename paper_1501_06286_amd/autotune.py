@@ -10,6 +10,7 @@ by the GPU architecture and the plan's shape (rule, L, M, s, t, dtype).
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 from typing import Dict, List, Optional, Tuple
@@ -160,6 +161,8 @@ def tune(plan, t: int, reps: int = 3, use_cache: bool = True,
     """Pick and set the fastest tuning for (plan, t).  Returns (best, timings)."""
     import torch
     key = cache_key(plan, t)
+    if cands is not None:  # a choice among other candidates is cached apart
+        key += "|cands" + hashlib.sha1(json.dumps(cands, sort_keys=True).encode()).hexdigest()[:12]
     cache = _load() if use_cache else {}
     if use_cache and key in cache:
         best = cache[key]["best"]
