@@ -277,7 +277,9 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=30,
+                    help="untimed steps before the timed ones, per leg (the first few after a "
+                         "re-tuning run slower while the clocks and the fresh workspace settle)")
     ap.add_argument("--dtype", default="f64", choices=["f32", "f64"],
                     help="headline precision (the other one is timed beside it)")
     ap.add_argument("--legs", default=",".join(LEGS),
