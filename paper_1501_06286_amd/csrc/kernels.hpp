@@ -298,7 +298,15 @@ __device__ __forceinline__ void middle_body(
   // The first twiddles and the spectrum are loaded ahead of use, so their
   // latency hides behind the front and the steps in between.
   cx<T> tw_a[R], tw_b[R], hv[R];
-  if constexpr (SPARSE) load_paired<T, R>(tw_a, twf1, q, Q);  // the dense front's loads come first
+  // FP64: the step twiddles of a thread are powers of one root (W_{M1}^{q f}
+  // over f; conj W_M^{(a + R bb)(f M2 + w2)} over bb), made by recurrence from
+  // one or two table values instead of R loads each
+  constexpr bool TW_REC = sizeof(T) == 8 && R >= 2;
+  cx<T> za;
+  if constexpr (SPARSE) {  // the dense front's loads come first
+    if constexpr (TW_REC) za = twf1[paired_index(1, q, Q, pair_pp(R))];
+    else load_paired<T, R>(tw_a, twf1, q, Q);
+  }
   // the R x R roots W_{R^2}^{a g} of the middle steps live in LDS (first
   // read after the barriers of step 1); twf2 holds value g of thread a
   for (int i = tid; i < R * R; i += S::BLOCK)
@@ -408,13 +416,23 @@ __device__ __forceinline__ void middle_body(
       if (c > 0) v = cmulc(v, two[w2 * R + c]);
       x[c] = v;
     }
-    load_paired<T, R>(tw_a, twf1, q, Q);
+    if constexpr (TW_REC) za = twf1[paired_index(1, q, Q, pair_pp(R))];
+    else load_paired<T, R>(tw_a, twf1, q, Q);
   }
 
   // ---- forward step 1: thread e1' = q, DFT over c -> f --------------------
   reg_fft<T, R, -1>(x);
+  if constexpr (TW_REC) {
+    cx<T> wf = za;
 #pragma unroll
-  for (int f = 1; f < R; ++f) x[f] = cmul(x[f], tw_a[f]);
+    for (int f = 1; f < R; ++f) {
+      x[f] = cmul(x[f], wf);
+      if (f + 1 < R) wf = cmul(wf, za);
+    }
+  } else {
+#pragma unroll
+    for (int f = 1; f < R; ++f) x[f] = cmul(x[f], tw_a[f]);
+  }
   const int gl = q % R;
   // the spectrum two steps early; the FP32 dense-front variant, which holds
   // more registers at this point (it spilled), loads it where it is used
@@ -466,9 +484,23 @@ __device__ __forceinline__ void middle_body(
   for (int g = 0; g < R; ++g) x[g] = grp[gl * (R + 1) + g];
   reg_fft<T, R, +1>(x);
   // value bb: conj W_M^{(a + R bb)(f M2 + w2)}
-  load_paired<T, R>(tw_b, twi3 + w2 * M1, q, Q);
+  if constexpr (TW_REC) {
+    // values 0 and 1 of the thread's row (adjacent); their ratio is the root
+    const cx2<T> kk = *reinterpret_cast<const cx2<T>*>(twi3 + w2 * M1 + 2 * q);
+    const cx<T> zb = cmulc(kk.b, kk.a);
+    cx<T> wb = kk.b;
+    x[0] = cmul(x[0], kk.a);
+    x[1] = cmul(x[1], kk.b);
 #pragma unroll
-  for (int bb = 0; bb < R; ++bb) x[bb] = cmul(x[bb], tw_b[bb]);
+    for (int bb = 2; bb < R; ++bb) {
+      wb = cmul(wb, zb);
+      x[bb] = cmul(x[bb], wb);
+    }
+  } else {
+    load_paired<T, R>(tw_b, twi3 + w2 * M1, q, Q);
+#pragma unroll
+    for (int bb = 0; bb < R; ++bb) x[bb] = cmul(x[bb], tw_b[bb]);
+  }
 #pragma unroll
   for (int c = 1; c < R; ++c) tw_a[c] = two[w2 * R + c];
   __syncthreads();
@@ -550,6 +582,7 @@ __device__ __forceinline__ void middle_sum_body(
   cx<T>* buf = lds + tr * S::BUFN;
   const cx<T> zero = {(T)0, (T)0};
   cx<T> x[R], acc[R], tw_a[R], tw_b[R], hv[R];
+  constexpr bool TW_REC = sizeof(T) == 8 && R >= 2;  // as in middle_body
   for (int i = tid; i < R * R; i += S::BLOCK)
     SM.wr2[(i % R) * (R + 1) + i / R] = twf2[paired_index(i / R, i % R, R, pair_pp(R))];
   const int gl = q % R;
@@ -671,9 +704,23 @@ __device__ __forceinline__ void middle_sum_body(
 #pragma unroll
   for (int g = 0; g < R; ++g) x[g] = grp[gl * (R + 1) + g];
   reg_fft<T, R, +1>(x);
-  load_paired<T, R>(tw_b, twi3 + w2 * M1, q, Q);
+  if constexpr (TW_REC) {
+    // values 0 and 1 of the thread's row (adjacent); their ratio is the root
+    const cx2<T> kk = *reinterpret_cast<const cx2<T>*>(twi3 + w2 * M1 + 2 * q);
+    const cx<T> zb = cmulc(kk.b, kk.a);
+    cx<T> wb = kk.b;
+    x[0] = cmul(x[0], kk.a);
+    x[1] = cmul(x[1], kk.b);
 #pragma unroll
-  for (int bb = 0; bb < R; ++bb) x[bb] = cmul(x[bb], tw_b[bb]);
+    for (int bb = 2; bb < R; ++bb) {
+      wb = cmul(wb, zb);
+      x[bb] = cmul(x[bb], wb);
+    }
+  } else {
+    load_paired<T, R>(tw_b, twi3 + w2 * M1, q, Q);
+#pragma unroll
+    for (int bb = 0; bb < R; ++bb) x[bb] = cmul(x[bb], tw_b[bb]);
+  }
 #pragma unroll
   for (int c = 1; c < R; ++c) tw_a[c] = two[w2 * R + c];
   __syncthreads();
