@@ -43,6 +43,23 @@ def test_korobov_union_matches_oracle(K, s, t, phi, shift, dtype):
     assert_close(X.double().cpu().numpy(), oracle.matmul(inst), inst.A, inst, dtype, inst.name)
 
 
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("t", [33, 100, 129, 250, 301])
+def test_korobov_union_wide_outputs(t, dtype):
+    """Many output columns: the collapse takes 2, 4 or 8 groups of 16 column
+    pairs per tile (t = 33: 17 pairs, two groups, the second ragged; 301:
+    151 pairs, a second tile row of two groups), element by element against
+    the oracle, with colliding exponents (s > K - 1)."""
+    torch = torch_cuda()
+    import paper_1501_06286_amd as q
+    inst = qi.small_korobov(31, 70, t, phi=qi.PHI_INVNORM, shift=(1, 62), dtype=dtype, seed=t)
+    announce(f"korobov union wide t={t} {dtype}")
+    U = _union(inst, dtype)
+    X = q.korobov_matmul(U, to_dev(inst.A, dtype))
+    torch.cuda.synchronize()
+    assert_close(X.double().cpu().numpy(), oracle.matmul(inst), inst.A, inst, dtype, inst.name)
+
+
 @pytest.mark.parametrize("chunk", [1, 7, 100, 0])
 def test_korobov_chunks_give_the_same_bits(chunk):
     torch = torch_cuda()
