@@ -234,6 +234,7 @@ def tune_plan(plan, t, args, one_stream=False):
 
 def forward_leg(name, inst, args, torch, q, dev, profile=True, nrows=64):
     """Time qmc_matmul on one instance; per-kernel events and the roofline."""
+    import numpy as np
     tdt = torch.float32 if inst.dtype == "f32" else torch.float64
     plan = q.Plan.from_instance(inst)
     info = plan.info()
@@ -270,6 +271,25 @@ def forward_leg(name, inst, args, torch, q, dev, profile=True, nrows=64):
         f"HBM {leg.out['path']['hbm_frac']:.3f}")
     rows = sample_rows(inst.N, nrows, len(name))
     leg.checks.append(("X", inst, rows, rows_to_host(X, rows, torch)))
+    if profile and tuning.get("streams", 1) == 1 and 0 < tuning.get("chunk_pairs", 0) < (inst.t + 1) // 2:
+        # the same chunks pipelined on two streams (the back pass of one chunk
+        # beside the fused pass of the next): whole-product time only, since
+        # the two passes' launches then overlap and their per-kernel times
+        # no longer bound one kernel each
+        plan.set_tuning(**dict(tuning, streams=2))
+        ws2 = plan.workspace(inst.t, dev)
+        step2 = lambda: q.matmul(plan, A, out=X, workspace=ws2)
+        for _ in range(min(args.warmup, 10)):
+            step2()
+        el2 = time_steps(step2, steps, torch)
+        same = bool(np.array_equal(rows_to_host(X, rows, torch), leg.checks[-1][3]))
+        plan.set_tuning(**tuning)
+        del ws2
+        ms2 = 1e3 * el2 / steps
+        leg.out["two_streams"] = {"tuning": dict(tuning, streams=2), "ms_per_step": round(ms2, 4),
+                                  "value": inst.N * inst.t / (el2 / steps),
+                                  "rows_identical": same}
+        log(f"{name}: the same chunks on two streams {ms2:.3f} ms/step (rows identical: {same})")
     return leg, plan, A, X, ws
 
 
