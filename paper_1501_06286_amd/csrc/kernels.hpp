@@ -230,6 +230,32 @@ __device__ __forceinline__ void load_paired(cx<T> (&v)[R], const cx<T>* __restri
   }
 }
 
+// x[bb] *= value bb of thread q's row of the inverse middle step's twiddles
+// (conj W_M^{(a + R bb)(f M2 + w2)}, a paired table).  REC (FP64): the values
+// are powers of one root, made by recurrence from values 0 and 1 (adjacent
+// in the row; their ratio is the root) instead of R loads
+template <typename T, int R, bool REC>
+__device__ __forceinline__ void inverse_step_twiddles(cx<T> (&x)[R], const cx<T>* __restrict__ row,
+                                                      int q, int Q) {
+  if constexpr (REC) {
+    const cx2<T> kk = *reinterpret_cast<const cx2<T>*>(row + 2 * q);
+    const cx<T> zb = cmulc(kk.b, kk.a);
+    cx<T> wb = kk.b;
+    x[0] = cmul(x[0], kk.a);
+    x[1] = cmul(x[1], kk.b);
+#pragma unroll
+    for (int bb = 2; bb < R; ++bb) {
+      wb = cmul(wb, zb);
+      x[bb] = cmul(x[bb], wb);
+    }
+  } else {
+    cx<T> tw[R];
+    load_paired<T, R>(tw, row, q, Q);
+#pragma unroll
+    for (int bb = 0; bb < R; ++bb) x[bb] = cmul(x[bb], tw[bb]);
+  }
+}
+
 template <int R>
 struct MidShape {
   static constexpr int Q = R * R;                  // threads per transform
@@ -297,7 +323,7 @@ __device__ __forceinline__ void middle_body(
 
   // The first twiddles and the spectrum are loaded ahead of use, so their
   // latency hides behind the front and the steps in between.
-  cx<T> tw_a[R], tw_b[R], hv[R];
+  cx<T> tw_a[R], hv[R];
   // FP64: the step twiddles of a thread are powers of one root (W_{M1}^{q f}
   // over f; conj W_M^{(a + R bb)(f M2 + w2)} over bb), made by recurrence from
   // one or two table values instead of R loads each
@@ -484,23 +510,7 @@ __device__ __forceinline__ void middle_body(
   for (int g = 0; g < R; ++g) x[g] = grp[gl * (R + 1) + g];
   reg_fft<T, R, +1>(x);
   // value bb: conj W_M^{(a + R bb)(f M2 + w2)}
-  if constexpr (TW_REC) {
-    // values 0 and 1 of the thread's row (adjacent); their ratio is the root
-    const cx2<T> kk = *reinterpret_cast<const cx2<T>*>(twi3 + w2 * M1 + 2 * q);
-    const cx<T> zb = cmulc(kk.b, kk.a);
-    cx<T> wb = kk.b;
-    x[0] = cmul(x[0], kk.a);
-    x[1] = cmul(x[1], kk.b);
-#pragma unroll
-    for (int bb = 2; bb < R; ++bb) {
-      wb = cmul(wb, zb);
-      x[bb] = cmul(x[bb], wb);
-    }
-  } else {
-    load_paired<T, R>(tw_b, twi3 + w2 * M1, q, Q);
-#pragma unroll
-    for (int bb = 0; bb < R; ++bb) x[bb] = cmul(x[bb], tw_b[bb]);
-  }
+  inverse_step_twiddles<T, R, TW_REC>(x, twi3 + w2 * M1, q, Q);
 #pragma unroll
   for (int c = 1; c < R; ++c) tw_a[c] = two[w2 * R + c];
   __syncthreads();
@@ -581,7 +591,7 @@ __device__ __forceinline__ void middle_sum_body(
   const bool active = pair < P;
   cx<T>* buf = lds + tr * S::BUFN;
   const cx<T> zero = {(T)0, (T)0};
-  cx<T> x[R], acc[R], tw_a[R], tw_b[R], hv[R];
+  cx<T> x[R], acc[R], tw_a[R], hv[R];
   constexpr bool TW_REC = sizeof(T) == 8 && R >= 2;  // as in middle_body
   for (int i = tid; i < R * R; i += S::BLOCK)
     SM.wr2[(i % R) * (R + 1) + i / R] = twf2[paired_index(i / R, i % R, R, pair_pp(R))];
@@ -704,23 +714,7 @@ __device__ __forceinline__ void middle_sum_body(
 #pragma unroll
   for (int g = 0; g < R; ++g) x[g] = grp[gl * (R + 1) + g];
   reg_fft<T, R, +1>(x);
-  if constexpr (TW_REC) {
-    // values 0 and 1 of the thread's row (adjacent); their ratio is the root
-    const cx2<T> kk = *reinterpret_cast<const cx2<T>*>(twi3 + w2 * M1 + 2 * q);
-    const cx<T> zb = cmulc(kk.b, kk.a);
-    cx<T> wb = kk.b;
-    x[0] = cmul(x[0], kk.a);
-    x[1] = cmul(x[1], kk.b);
-#pragma unroll
-    for (int bb = 2; bb < R; ++bb) {
-      wb = cmul(wb, zb);
-      x[bb] = cmul(x[bb], wb);
-    }
-  } else {
-    load_paired<T, R>(tw_b, twi3 + w2 * M1, q, Q);
-#pragma unroll
-    for (int bb = 0; bb < R; ++bb) x[bb] = cmul(x[bb], tw_b[bb]);
-  }
+  inverse_step_twiddles<T, R, TW_REC>(x, twi3 + w2 * M1, q, Q);
 #pragma unroll
   for (int c = 1; c < R; ++c) tw_a[c] = two[w2 * R + c];
   __syncthreads();
