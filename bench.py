@@ -279,7 +279,7 @@ def forward_leg(name, inst, args, torch, q, dev, profile=True, nrows=64):
         plan.set_tuning(**dict(tuning, streams=2))
         ws2 = plan.workspace(inst.t, dev)
         step2 = lambda: q.matmul(plan, A, out=X, workspace=ws2)
-        for _ in range(min(args.warmup, 10)):
+        for _ in range(args.warmup):
             step2()
         el2 = time_steps(step2, steps, torch)
         same = bool(np.array_equal(rows_to_host(X, rows, torch), leg.checks[-1][3]))
